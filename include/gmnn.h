@@ -1,0 +1,234 @@
+/*
+ * gmnn.h -- C ABI of the MI355X (gfx950) Gaussian Moment Neural Network
+ * energy/force library.
+ *
+ * The method is the Gaussian Moment Neural Network potential of the Apax
+ * paper (arXiv 2505.22168):
+ *   Section 2.1, eq. (energy_sum):   E = sum_i E_i(G_i)
+ *   Section 2.1, eq. (basis_fn):     Psi_{i,L,s} = sum_{j != i} R_{Zi,Zj,s}(r_ij) rhat_ij^{(x)L}
+ *                                    with R built from equidistant Gaussians
+ *                                    mixed by species-pair coefficients beta
+ *   Section 2.1, eq. (contraction):  G_i = full tensor contractions of Psi, L <= 3
+ *   Section 2.1, eq. (scale_shift):  E_i = sigma_{Z_i} NN(G_i) + mu_{Z_i}
+ *   Section 3.3:                     forces and virials are gradients of E
+ *                                    w.r.t. positions and strain
+ *   Section 2.2, eq. (uncertainty), eq. (jacobian): shallow ensembles share
+ *                                    everything but the last layer
+ *   Section 3.5:                     periodic cells narrower than twice the
+ *                                    cutoff need several images per neighbour
+ *
+ * Conventions
+ *   Units: Angstrom, eV, eV/A, eV/A^3.  F = -dE/dx.  stress = (1/V) dE/dstrain.
+ *   All array pointers in the structs below are DEVICE pointers unless the
+ *   field name ends in _host.  Every buffer is owned by the caller; the
+ *   library never allocates or frees device memory and keeps no global state.
+ *   Work is enqueued on the given HIP stream (NULL = default stream) and is
+ *   complete in stream order; argument and shape checks are synchronous and
+ *   return a negative status without enqueuing anything.  Device-side
+ *   conditions (list capacity overflow, non-finite input, coincident atoms)
+ *   are OR-ed into a device status word (GMNN_FLAG_*), never trapped.
+ */
+#ifndef GMNN_H_
+#define GMNN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gmnn_status;
+#define GMNN_OK 0
+#define GMNN_ERR_INVALID_ARG -1   /* null pointer, bad size, bad flag */
+#define GMNN_ERR_CAPACITY -2      /* neighbour capacity too small (SYNC mode) */
+#define GMNN_ERR_UNSUPPORTED -3   /* shape/model outside what the kernels handle */
+#define GMNN_ERR_HIP -4           /* a HIP runtime call failed */
+#define GMNN_ERR_DEVICE_FLAG -5   /* a device status flag was raised (SYNC mode) */
+#define GMNN_ERR_WORKSPACE -6     /* workspace smaller than gmnn_workspace_bytes() */
+
+/* bits of the device status word */
+#define GMNN_FLAG_CAPACITY 1u      /* more pairs than nl->capacity */
+#define GMNN_FLAG_NONFINITE 2u     /* a non-finite position */
+#define GMNN_FLAG_COINCIDENT 4u    /* two atoms (or images) at zero distance */
+#define GMNN_FLAG_ROW_TOO_LONG 8u  /* an atom with more than GMNN_MAX_ROW neighbours */
+#define GMNN_FLAG_SHIFT_RANGE 16u  /* an image vector outside [-127, 127] */
+
+#define GMNN_MAX_ROW 1024          /* neighbours per atom handled by the list build */
+
+/* flags of gmnn_energy_forces / gmnn_backward */
+#define GMNN_PREC_FP32 0u          /* network products in FP32 (MFMA f32) */
+#define GMNN_PREC_BF16 1u          /* network products in BF16 on MFMA, FP32 accumulate */
+#define GMNN_WANT_STRESS 2u        /* fill outputs->stress */
+#define GMNN_WANT_FORCE_VAR 4u     /* fill outputs->force_var (one backward per head) */
+#define GMNN_SYNC 8u               /* synchronise and turn device flags into a status */
+
+/* A ragged batch of B structures with N atoms in total (Section 2.1: a
+ * configuration is positions R and atomic numbers Z; Section 3.5: with a
+ * periodic cell).  Structure b owns atoms atom_ptr[b] .. atom_ptr[b+1]-1. */
+typedef struct gmnn_system {
+  int32_t n_structs;            /* B >= 1 */
+  int32_t n_atoms;              /* N >= 0 */
+  const int64_t* atom_ptr;      /* [B+1] device, atom_ptr[0] = 0, non-decreasing */
+  const int64_t* atom_ptr_host; /* [B+1] host mirror (sizes the launches) */
+  const float* pos;             /* [N,3] device, Cartesian positions; need not lie in the cell */
+  const int32_t* species;       /* [N] device, species index in [0, n_species) */
+  const double* cell;           /* [B,3,3] device, lattice vectors as rows */
+  const double* cell_host;      /* [B,3,3] host mirror (sizes the cell grids) */
+  const uint8_t* pbc;           /* [B,3] device, 1 = periodic along that axis */
+  const uint8_t* pbc_host;      /* [B,3] host mirror */
+} gmnn_system;
+
+/* Neighbour list in CSR form, canonical order: rows by centre atom i, inside a
+ * row by (j, Sx, Sy, Sz) ascending.  A pair p = (i, j, S) means the neighbour
+ * x_j + S . h_b of x_i.  All arrays device, caller-allocated. */
+typedef struct gmnn_neighbors {
+  int64_t capacity;       /* length of j, shift, rev */
+  int64_t* row_ptr;       /* [N+1] */
+  int32_t* j;             /* [capacity] neighbour atom (global index) */
+  int32_t* shift;         /* [capacity] S packed as int8 x3: Sx | Sy<<8 | Sz<<16 */
+  int32_t* rev;           /* [capacity] index of the reverse pair (j, i, -S) */
+  int32_t* atom_struct;   /* [N] structure of every atom */
+  int64_t* n_pairs;       /* [1] total pairs (written even when above capacity) */
+  uint32_t* status;       /* [1] GMNN_FLAG_* bits, OR-ed; clear before a build */
+  float cutoff;           /* list cutoff the list was built with (r_cut + skin) */
+} gmnn_neighbors;
+
+/* Model hyperparameters and parameters (Section 2.1).  Device arrays in FP32.
+ * F = number of invariants = S + 3 S(S+1)/2 + S(S+1)(S+2)/6 + S^2(S+1) + S^3
+ * (360 for S = 5); the kernels support S = 5, K <= 8, H1, H2 multiples of 64
+ * up to 512, n_heads <= 16, n_species <= 16. */
+typedef struct gmnn_model {
+  int32_t n_species;
+  int32_t n_radial;       /* S */
+  int32_t n_basis;        /* K */
+  int32_t hidden1;        /* H1 */
+  int32_t hidden2;        /* H2 */
+  int32_t n_heads;        /* shallow-ensemble heads (Section 2.2) */
+  float r_min;            /* first Gaussian centre */
+  float r_cut;            /* cutoff radius */
+  float gamma;            /* Gaussian width: g_k = exp(-gamma (r - mu_k)^2) */
+  float psi_scale;        /* prefactor of the moment sums; the Gaussian centres
+                             are mu_k = r_min + k (r_cut - r_min)/(K - 1) */
+  const float* beta;      /* [n_species, n_species, S, K] */
+  const float* W1;        /* [F, H1] */
+  const float* b1;        /* [H1] */
+  const float* W2;        /* [H1, H2] */
+  const float* b2;        /* [H2] */
+  const float* W3;        /* [H2, n_heads] */
+  const float* b3;        /* [n_heads] */
+  const float* scale;     /* [n_species] sigma_Z */
+  const float* shift;     /* [n_species] mu_Z */
+  void* packed;           /* device buffer of gmnn_model_packed_bytes() bytes,
+                             filled by gmnn_model_prepare(): MFMA-ordered FP32
+                             and BF16 copies of W1, W2 and their transposes */
+} gmnn_model;
+
+/* Parameter gradients: FP32 device arrays with the shapes of the matching
+ * gmnn_model fields; overwritten by gmnn_backward. */
+typedef struct gmnn_param_grads {
+  float* beta;
+  float* W1;
+  float* b1;
+  float* W2;
+  float* b2;
+  float* W3;
+  float* b3;
+  float* scale;
+  float* shift;
+} gmnn_param_grads;
+
+/* Results.  energy[b, m] is the total energy of structure b under head m
+ * (eq. energy_sum, summed in FP64).  forces are -d(mean over heads of E)/dx
+ * (eq. jacobian).  Optional fields may be NULL unless requested. */
+typedef struct gmnn_outputs {
+  double* energy;         /* [B, n_heads] */
+  float* forces;          /* [N, 3] */
+  double* stress;         /* [B, 3, 3], with GMNN_WANT_STRESS */
+  double* energy_var;     /* [B] population variance over heads, may be NULL */
+  float* force_var;       /* [N] (1/M) sum_m |F_i^m - Fbar_i|^2, with GMNN_WANT_FORCE_VAR */
+  float* atomic_energy;   /* [N, n_heads] E_i^m, may be NULL */
+} gmnn_outputs;
+
+/* ---------------------------------------------------------------------- */
+
+/* Human-readable name of a status code (static string). */
+const char* gmnn_status_string(gmnn_status s);
+
+/* Number of invariants F for S radial channels (Section 2.1, eq. contraction;
+ * eight contraction families, see gmnn_energy_forces). */
+int32_t gmnn_num_features(int32_t n_radial);
+
+/* Bytes of model->packed needed for this model's shapes. */
+size_t gmnn_model_packed_bytes(const gmnn_model* m);
+
+/* Fill model->packed from the FP32 weights (enqueued on `stream`).  Call again
+ * whenever W1 or W2 change (for example after an optimiser step). */
+gmnn_status gmnn_model_prepare(gmnn_model* m, void* stream);
+
+/* Workspace bytes for op = GMNN_OP_ENERGY_FORCES / GMNN_OP_BACKWARD (sized by
+ * sys->n_atoms, nl->capacity and the model).  GMNN_OP_NEIGHBORS takes the list
+ * cutoff from nl->cutoff (= cutoff + skin) and ignores `m`.  Returns 0 on
+ * invalid arguments. */
+#define GMNN_OP_NEIGHBORS 0
+#define GMNN_OP_ENERGY_FORCES 1
+#define GMNN_OP_BACKWARD 2
+size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* sys,
+                            const gmnn_neighbors* nl, uint32_t flags);
+
+/* Workspace bytes of gmnn_build_neighbors for this system and list cutoff
+ * (cell grids sized from sys->cell_host). */
+size_t gmnn_neighbors_workspace_bytes(const gmnn_system* sys, float cutoff, float skin);
+
+/* Build the periodic neighbour list (Section 3.5: cell list with as many
+ * periodic images as the cell width requires; Section 2.1: all j != i within
+ * the cutoff).  A pair (i, j, S) is listed iff its separation
+ *   d = x_j - x_i + S . h,   computed in FP64 from the FP32 positions as
+ *   dx = (x_j - x_i) + ((Sx h00 + Sy h10) + Sz h20)   (each op rounded once)
+ *   d2 = (dx dx + dy dy) + dz dz
+ * satisfies 0 < d2 < (cutoff + skin)^2, except (i, i, 0).  Coincident pairs
+ * (d2 == 0) are left out and raise GMNN_FLAG_COINCIDENT.  Non-periodic axes
+ * take S = 0.  If the pair count exceeds nl->capacity, *nl->n_pairs still
+ * holds the required size and GMNN_FLAG_CAPACITY is raised; the pair arrays
+ * are then not filled.  With GMNN_SYNC in `flags` the call synchronises and
+ * returns GMNN_ERR_CAPACITY / GMNN_ERR_DEVICE_FLAG accordingly.
+ * The workspace must hold gmnn_workspace_bytes(GMNN_OP_NEIGHBORS, ...). */
+gmnn_status gmnn_build_neighbors(const gmnn_system* sys, float cutoff, float skin,
+                                 gmnn_neighbors* nl, uint32_t flags,
+                                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Energies, forces and (optionally) stress, energy variance and force
+ * variance of every structure.  Pairs of the list with r >= model->r_cut
+ * contribute nothing (a list built with a skin can be reused).  Steps:
+ *   pair geometry, Gaussian basis x cosine cutoff, species-pair mixing and
+ *   moment sums (eq. basis_fn) -> invariants (eq. contraction; families
+ *   Psi0 | Psi1.Psi1 | Psi2:Psi2 | Psi3:Psi3 | tr(Psi2 Psi2 Psi2) |
+ *   Psi1 Psi1 Psi2 | Psi2 Psi3 Psi3 | Psi1 Psi3 Psi2) -> network and
+ *   scale/shift (eq. scale_shift) -> exact gradient back to the pairs ->
+ *   scatter-free force gather over the reverse pair index -> FP64
+ *   per-structure sums of energy and virial.
+ * GMNN_PREC_BF16 rounds the inputs of the two hidden-layer products (and of
+ * their backward products) to BF16 and accumulates in FP32; everything else
+ * is FP32 with FP64 per-structure sums.  The workspace must hold
+ * gmnn_workspace_bytes(GMNN_OP_ENERGY_FORCES, ...). */
+gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
+                               const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Gradients of a scalar loss L(E, F) w.r.t. the model parameters and the
+ * positions, given the upstream gradients dL/dE (per structure, w.r.t. the
+ * head-mean energy) and dL/dF [N,3] (Section 3.4: energy + force losses;
+ * Section 3.3: forces are -dE/dx, so the force term needs the mixed second
+ * derivative).  Every array of `grads` is overwritten; dL_dpos may be
+ * NULL.  Requires the workspace of gmnn_energy_forces for the same inputs;
+ * recomputes the forward pass itself. */
+gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                          const double* dL_dE, const float* dL_dF, uint32_t flags,
+                          gmnn_param_grads* grads, float* dL_dpos,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMNN_H_ */

@@ -1,0 +1,110 @@
+"""ctypes view of the C ABI in include/gmnn.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmnn.so")
+
+GMNN_OK = 0
+GMNN_ERR_INVALID_ARG = -1
+GMNN_ERR_CAPACITY = -2
+GMNN_ERR_UNSUPPORTED = -3
+GMNN_ERR_HIP = -4
+GMNN_ERR_DEVICE_FLAG = -5
+GMNN_ERR_WORKSPACE = -6
+
+GMNN_FLAG_CAPACITY = 1
+GMNN_FLAG_NONFINITE = 2
+GMNN_FLAG_COINCIDENT = 4
+GMNN_FLAG_ROW_TOO_LONG = 8
+GMNN_FLAG_SHIFT_RANGE = 16
+GMNN_MAX_ROW = 1024
+
+GMNN_PREC_FP32 = 0
+GMNN_PREC_BF16 = 1
+GMNN_WANT_STRESS = 2
+GMNN_WANT_FORCE_VAR = 4
+GMNN_SYNC = 8
+
+GMNN_OP_NEIGHBORS = 0
+GMNN_OP_ENERGY_FORCES = 1
+GMNN_OP_BACKWARD = 2
+
+vp = C.c_void_p
+
+
+class gmnn_system(C.Structure):
+    _fields_ = [("n_structs", C.c_int32), ("n_atoms", C.c_int32),
+                ("atom_ptr", vp), ("atom_ptr_host", vp), ("pos", vp), ("species", vp),
+                ("cell", vp), ("cell_host", vp), ("pbc", vp), ("pbc_host", vp)]
+
+
+class gmnn_neighbors(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("row_ptr", vp), ("j", vp), ("shift", vp), ("rev", vp),
+                ("atom_struct", vp), ("n_pairs", vp), ("status", vp), ("cutoff", C.c_float)]
+
+
+class gmnn_model(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_radial", C.c_int32), ("n_basis", C.c_int32),
+                ("hidden1", C.c_int32), ("hidden2", C.c_int32), ("n_heads", C.c_int32),
+                ("r_min", C.c_float), ("r_cut", C.c_float), ("gamma", C.c_float), ("psi_scale", C.c_float),
+                ("beta", vp), ("W1", vp), ("b1", vp), ("W2", vp), ("b2", vp), ("W3", vp), ("b3", vp),
+                ("scale", vp), ("shift", vp), ("packed", vp)]
+
+
+class gmnn_param_grads(C.Structure):
+    _fields_ = [(k, vp) for k in ("beta", "W1", "b1", "W2", "b2", "W3", "b3", "scale", "shift")]
+
+
+class gmnn_outputs(C.Structure):
+    _fields_ = [("energy", vp), ("forces", vp), ("stress", vp), ("energy_var", vp),
+                ("force_var", vp), ("atomic_energy", vp)]
+
+
+EXPORTS = {
+    "gmnn_status_string": (C.c_char_p, [C.c_int32]),
+    "gmnn_num_features": (C.c_int32, [C.c_int32]),
+    "gmnn_model_packed_bytes": (C.c_size_t, [C.POINTER(gmnn_model)]),
+    "gmnn_model_prepare": (C.c_int32, [C.POINTER(gmnn_model), vp]),
+    "gmnn_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(gmnn_model), C.POINTER(gmnn_system),
+                                          C.POINTER(gmnn_neighbors), C.c_uint32]),
+    "gmnn_neighbors_workspace_bytes": (C.c_size_t, [C.POINTER(gmnn_system), C.c_float, C.c_float]),
+    "gmnn_build_neighbors": (C.c_int32, [C.POINTER(gmnn_system), C.c_float, C.c_float,
+                                         C.POINTER(gmnn_neighbors), C.c_uint32, vp, C.c_size_t, vp]),
+    "gmnn_energy_forces": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
+                                       C.c_uint32, C.POINTER(gmnn_outputs), vp, C.c_size_t, vp]),
+    "gmnn_backward": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
+                                  vp, vp, C.c_uint32, C.POINTER(gmnn_param_grads), vp, vp, C.c_size_t, vp]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgmnn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2505_22168_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class GMNNError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().gmnn_status_string(status).decode()
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+def check(status: int, where: str):
+    if status != GMNN_OK:
+        raise GMNNError(status, where)

@@ -1,0 +1,243 @@
+"""Python binding of the GMNN library: device buffers are torch tensors, every
+step of the energy/force path runs in the HIP kernels of libgmnn.so.
+
+The binding only marshals arguments: it allocates torch tensors for the
+caller-owned buffers of the C ABI, passes their device pointers and the
+current torch stream, and checks the returned status.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _capi as A
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_device(device):
+    device = torch.device(device)
+    if device.type != "cuda":
+        raise RuntimeError("the GMNN library runs on a HIP device only (no CPU fallback)")
+    return device
+
+
+# ---------------------------------------------------------------------------
+class System:
+    """A ragged batch of periodic structures on the device (gmnn_system)."""
+
+    def __init__(self, pos, species, cell, pbc, atom_ptr, device="cuda"):
+        device = _require_device(device)
+        self.atom_ptr_host = np.ascontiguousarray(np.asarray(atom_ptr, dtype=np.int64))
+        self.cell_host = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(-1, 3, 3))
+        self.pbc_host = np.ascontiguousarray(np.asarray(pbc, dtype=np.uint8).reshape(-1, 3))
+        self.pos = torch.as_tensor(np.asarray(pos, dtype=np.float32)).reshape(-1, 3).contiguous().to(device)
+        self.species = torch.as_tensor(np.asarray(species, dtype=np.int32)).contiguous().to(device)
+        self.cell = torch.as_tensor(self.cell_host).to(device)
+        self.pbc = torch.as_tensor(self.pbc_host).to(device)
+        self.atom_ptr = torch.as_tensor(self.atom_ptr_host).to(device)
+        self.device = device
+
+    @classmethod
+    def from_batch(cls, batch, device="cuda"):
+        return cls(batch.pos, batch.species, batch.cell, batch.pbc, batch.atom_ptr, device)
+
+    @property
+    def n_atoms(self):
+        return int(self.atom_ptr_host[-1])
+
+    @property
+    def n_structs(self):
+        return int(self.cell_host.shape[0])
+
+    def c(self, pos=None):
+        p = self.pos if pos is None else pos
+        return A.gmnn_system(
+            self.n_structs, self.n_atoms, _ptr(self.atom_ptr), self.atom_ptr_host.ctypes.data_as(C.c_void_p),
+            _ptr(p), _ptr(self.species), _ptr(self.cell), self.cell_host.ctypes.data_as(C.c_void_p),
+            _ptr(self.pbc), self.pbc_host.ctypes.data_as(C.c_void_p))
+
+
+# ---------------------------------------------------------------------------
+class NeighborList:
+    """Device CSR neighbour list (gmnn_neighbors), canonical order."""
+
+    def __init__(self, n_atoms: int, capacity: int, device):
+        self.capacity = int(capacity)
+        self.row_ptr = torch.zeros(n_atoms + 1, dtype=torch.int64, device=device)
+        self.j = torch.zeros(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.shift = torch.zeros(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.rev = torch.zeros(max(self.capacity, 1), dtype=torch.int32, device=device)
+        self.atom_struct = torch.zeros(max(n_atoms, 1), dtype=torch.int32, device=device)
+        self.n_pairs_dev = torch.zeros(1, dtype=torch.int64, device=device)
+        self.status_dev = torch.zeros(1, dtype=torch.int32, device=device)
+        self.cutoff = 0.0
+
+    def c(self):
+        return A.gmnn_neighbors(self.capacity, _ptr(self.row_ptr), _ptr(self.j), _ptr(self.shift), _ptr(self.rev),
+                                _ptr(self.atom_struct), _ptr(self.n_pairs_dev), _ptr(self.status_dev),
+                                C.c_float(self.cutoff))
+
+    @property
+    def n_pairs(self) -> int:
+        return int(self.n_pairs_dev.item())
+
+    @property
+    def status(self) -> int:
+        return int(self.status_dev.item()) & 0xFFFFFFFF
+
+    def shifts(self):
+        """Unpacked image vectors [P,3] (int64) of the first n_pairs pairs."""
+        s = self.shift[: self.n_pairs].to(torch.int64)
+        out = torch.stack([(s >> (8 * k)) & 0xFF for k in range(3)], 1)
+        return torch.where(out >= 128, out - 256, out)
+
+    def rows(self):
+        """Centre atom of every pair [P] (int64)."""
+        counts = torch.diff(self.row_ptr)
+        return torch.repeat_interleave(torch.arange(len(counts), device=counts.device), counts)
+
+
+def estimate_capacity(system: System, cutoff: float, skin: float) -> int:
+    rl = cutoff + skin
+    total = 0.0
+    for b in range(system.n_structs):
+        n = system.atom_ptr_host[b + 1] - system.atom_ptr_host[b]
+        vol = abs(np.linalg.det(system.cell_host[b]))
+        total += n * (n / vol * 4.0 / 3.0 * math.pi * rl ** 3)
+    return int(total * 1.25) + 1024
+
+
+def build_neighbors(system: System, cutoff: float, skin: float = 0.0, capacity: int | None = None,
+                    nl: NeighborList | None = None, workspace: torch.Tensor | None = None) -> NeighborList:
+    """Build the list; grows the capacity (and rebuilds) when it is too small."""
+    lib = A.load()
+    sysc = system.c()
+    nbytes = lib.gmnn_neighbors_workspace_bytes(C.byref(sysc), cutoff, skin)
+    if nbytes == 0:
+        raise A.GMNNError(A.GMNN_ERR_INVALID_ARG, "gmnn_neighbors_workspace_bytes")
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=system.device)
+    if nl is None:
+        cap = capacity if capacity is not None else estimate_capacity(system, cutoff, skin)
+        nl = NeighborList(system.n_atoms, cap, system.device)
+    for _ in range(2):
+        nlc = nl.c()
+        st = lib.gmnn_build_neighbors(C.byref(sysc), cutoff, skin, C.byref(nlc), A.GMNN_SYNC, _ptr(workspace),
+                                      nbytes, _stream())
+        nl.cutoff = float(np.float32(cutoff) + np.float32(skin))
+        if st == A.GMNN_ERR_CAPACITY:
+            need = nl.n_pairs
+            nl = NeighborList(system.n_atoms, int(need * 1.1) + 1024, system.device)
+            continue
+        A.check(st, "gmnn_build_neighbors")
+        return nl
+    raise A.GMNNError(A.GMNN_ERR_CAPACITY, "gmnn_build_neighbors")
+
+
+# ---------------------------------------------------------------------------
+PARAM_NAMES = ("beta", "W1", "b1", "W2", "b2", "W3", "b3", "scale", "shift")
+
+
+class Model:
+    """GMNN parameters on the device plus their MFMA-ordered packed copies."""
+
+    def __init__(self, spec, params: dict, device="cuda"):
+        device = _require_device(device)
+        self.spec = spec
+        self.device = device
+        self.tensors = {k: torch.as_tensor(np.asarray(params[k], dtype=np.float32)).contiguous().to(device)
+                        for k in PARAM_NAMES}
+        lib = A.load()
+        c = self._c(None)
+        nbytes = lib.gmnn_model_packed_bytes(C.byref(c))
+        self.packed = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+        self.prepare()
+
+    @classmethod
+    def from_params(cls, params, device="cuda"):
+        return cls(params.spec, params.as_dict(), device)
+
+    def _c(self, packed):
+        s = self.spec
+        t = self.tensors
+        H1, H2 = s.hidden
+        return A.gmnn_model(s.n_species, s.n_radial, s.n_basis, H1, H2, s.n_heads, s.r_min, s.r_cut, s.gamma,
+                            s.psi_scale, *[_ptr(t[k]) for k in PARAM_NAMES], _ptr(packed))
+
+    def c(self):
+        return self._c(self.packed)
+
+    def prepare(self):
+        """Refresh the packed weights after the FP32 parameters changed."""
+        c = self.c()
+        A.check(A.load().gmnn_model_prepare(C.byref(c), _stream()), "gmnn_model_prepare")
+
+
+@dataclass
+class Outputs:
+    energy: torch.Tensor        # [B, heads] float64
+    forces: torch.Tensor        # [N, 3] float32
+    stress: torch.Tensor | None
+    energy_var: torch.Tensor | None
+    force_var: torch.Tensor | None
+    atomic_energy: torch.Tensor
+
+
+class EnergyForces:
+    """Reusable evaluator: owns the outputs and the workspace of one system /
+    list / model shape, so repeated calls allocate nothing."""
+
+    def __init__(self, model: Model, system: System, nl: NeighborList, precision: str = "bf16",
+                 stress: bool = True, force_var: bool = False):
+        self.model, self.system, self.nl = model, system, nl
+        self.flags = (A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32)
+        if precision not in ("bf16", "fp32"):
+            raise ValueError(precision)
+        if stress:
+            self.flags |= A.GMNN_WANT_STRESS
+        if force_var:
+            self.flags |= A.GMNN_WANT_FORCE_VAR
+        dev = system.device
+        B, N, M = system.n_structs, system.n_atoms, model.spec.n_heads
+        self.out = Outputs(
+            energy=torch.zeros((B, M), dtype=torch.float64, device=dev),
+            forces=torch.zeros((max(N, 1), 3), dtype=torch.float32, device=dev),
+            stress=torch.zeros((B, 3, 3), dtype=torch.float64, device=dev) if stress else None,
+            energy_var=torch.zeros(B, dtype=torch.float64, device=dev),
+            force_var=torch.zeros(max(N, 1), dtype=torch.float32, device=dev) if force_var else None,
+            atomic_energy=torch.zeros((max(N, 1), M), dtype=torch.float32, device=dev))
+        lib = A.load()
+        self._mc = model.c()
+        self._sc = system.c()
+        self._nc = nl.c()
+        nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_ENERGY_FORCES, C.byref(self._mc), C.byref(self._sc),
+                                          C.byref(self._nc), self.flags)
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        self.ws_bytes = nbytes
+        o = self.out
+        self._oc = A.gmnn_outputs(_ptr(o.energy), _ptr(o.forces), _ptr(o.stress), _ptr(o.energy_var),
+                                  _ptr(o.force_var), _ptr(o.atomic_energy))
+
+    def __call__(self, sync: bool = False) -> Outputs:
+        flags = self.flags | (A.GMNN_SYNC if sync else 0)
+        st = A.load().gmnn_energy_forces(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), flags,
+                                         C.byref(self._oc), _ptr(self.workspace), self.ws_bytes, _stream())
+        A.check(st, "gmnn_energy_forces")
+        return self.out
+
+
+def energy_forces(model: Model, system: System, nl: NeighborList, precision: str = "bf16", stress: bool = True,
+                  force_var: bool = False) -> Outputs:
+    """One evaluation (allocates its outputs and workspace)."""
+    return EnergyForces(model, system, nl, precision, stress, force_var)(sync=False)

@@ -1,0 +1,341 @@
+// C ABI entry points of the GMNN library (declared in include/gmnn.h).
+#include <string.h>
+
+#include <cmath>
+
+#include "common.h"
+#include "model.h"
+#include "neighbors.h"
+
+namespace gmnn {
+
+// defined in pairs.hip / readout.hip
+__global__ void pair_moments(DevModel m, DevSystem sys, float* psi);
+__global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial);
+__global__ void force_gather(DevSystem sys, const float* gpair, float* forces);
+__global__ void struct_reduce(int M, DevSystem sys, const float* atomic_e, const float* virial, int want_stress,
+                              double* energy, double* energy_var, double* stress);
+gmnn_status launch_readout(int tm, const DevModel& m, const DevSystem& sys, bool bf16, const float* psi,
+                           float* atomic_e, float* psibar, hipStream_t stream);
+size_t readout_lds_bytes(int tm, int hp, bool bf16);
+
+constexpr int kPairThreads = 256;
+constexpr int kPairAtoms = 16;  // atoms per block of the pair kernels (16 lanes each)
+
+// ---------------------------------------------------------------------------
+// model preparation: MFMA fragment order, padded widths
+// ---------------------------------------------------------------------------
+// which = 0: W1 (K = F pad 384, N = HP1); 1: W1^T (K = HP1, N = 384);
+//         2: W2 (K = HP1, N = HP2);       3: W2^T (K = HP2, N = HP1)
+__device__ inline float wsrc(int which, const float* W1, const float* W2, int F, int H1, int H2, int k, int n) {
+  switch (which) {
+    case 0: return (k < F && n < H1) ? W1[(size_t)k * H1 + n] : 0.0f;
+    case 1: return (n < F && k < H1) ? W1[(size_t)n * H1 + k] : 0.0f;
+    case 2: return (k < H1 && n < H2) ? W2[(size_t)k * H2 + n] : 0.0f;
+    default: return (n < H1 && k < H2) ? W2[(size_t)n * H2 + k] : 0.0f;
+  }
+}
+
+__global__ void pack_weights(int which, const float* __restrict__ W1, const float* __restrict__ W2, int F, int H1,
+                             int H2, int Kp, int Np, float* __restrict__ out_f32, __bf16* __restrict__ out_bf16) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)Kp * Np;
+  if (t >= total) return;
+  // f32 fragments: index = ((nb*KB4 + kb)*64 + l)
+  {
+    const int KB4 = Kp / 4;
+    const int64_t l = t % 64, rest = t / 64;
+    const int64_t kb = rest % KB4, nb = rest / KB4;
+    const int k = (int)(kb * 4 + (l >> 4)), n = (int)(nb * 16 + (l & 15));
+    out_f32[t] = wsrc(which, W1, W2, F, H1, H2, k, n);
+  }
+  // bf16 fragments: index = ((nb*KB32 + kb)*64 + l)*8 + e
+  {
+    const int KB32 = Kp / 32;
+    const int64_t e = t % 8, rest = t / 8;
+    const int64_t l = rest % 64, rest2 = rest / 64;
+    const int64_t kb = rest2 % KB32, nb = rest2 / KB32;
+    const int k = (int)(kb * 32 + 8 * (l >> 4) + e), n = (int)(nb * 16 + (l & 15));
+    out_bf16[t] = (__bf16)wsrc(which, W1, W2, F, H1, H2, k, n);
+  }
+}
+
+__global__ void pack_vectors(const float* __restrict__ b1, const float* __restrict__ b2, const float* __restrict__ W3,
+                             const float* __restrict__ b3, int H1, int H2, int HP1, int HP2, int M,
+                             float* __restrict__ b1p, float* __restrict__ b2p, float* __restrict__ w3p,
+                             float* __restrict__ w3bar, float* __restrict__ b3p) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < HP1) b1p[t] = t < H1 ? b1[t] : 0.0f;
+  if (t < HP2) {
+    b2p[t] = t < H2 ? b2[t] : 0.0f;
+    float s = 0.0f;
+    for (int m = 0; m < M; ++m) {
+      const float v = t < H2 ? W3[(size_t)t * M + m] : 0.0f;
+      w3p[(size_t)t * M + m] = v;
+      s += v;
+    }
+    w3bar[t] = s / (float)M;
+  }
+  if (t < M) b3p[t] = b3[t];
+}
+
+static DevModel dev_model(const gmnn_model* m) {
+  DevModel d;
+  const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+  const char* P = (const char*)m->packed;
+  d.n_species = m->n_species;
+  d.K = m->n_basis;
+  d.HP1 = L.HP1;
+  d.HP2 = L.HP2;
+  d.M = m->n_heads;
+  d.r_min = m->r_min;
+  d.r_cut = m->r_cut;
+  d.rc2 = m->r_cut * m->r_cut;
+  d.gamma = m->gamma;
+  d.delta = (m->r_cut - m->r_min) / (float)(m->n_basis - 1);
+  d.psi_scale = m->psi_scale;
+  d.beta = m->beta;
+  d.scale = m->scale;
+  d.shift = m->shift;
+  d.w1_f32 = (const float*)(P + L.w1_f32);
+  d.w1t_f32 = (const float*)(P + L.w1t_f32);
+  d.w2_f32 = (const float*)(P + L.w2_f32);
+  d.w2t_f32 = (const float*)(P + L.w2t_f32);
+  d.w1_bf16 = (const bf16x8*)(P + L.w1_bf16);
+  d.w1t_bf16 = (const bf16x8*)(P + L.w1t_bf16);
+  d.w2_bf16 = (const bf16x8*)(P + L.w2_bf16);
+  d.w2t_bf16 = (const bf16x8*)(P + L.w2t_bf16);
+  d.b1 = (const float*)(P + L.b1);
+  d.b2 = (const float*)(P + L.b2);
+  d.w3 = (const float*)(P + L.w3);
+  d.w3bar = (const float*)(P + L.w3bar);
+  d.b3 = (const float*)(P + L.b3);
+  return d;
+}
+
+static gmnn_status check_model(const gmnn_model* m) {
+  if (!m || !m->beta || !m->W1 || !m->b1 || !m->W2 || !m->b2 || !m->W3 || !m->b3 || !m->scale || !m->shift ||
+      !m->packed)
+    return GMNN_ERR_INVALID_ARG;
+  if (m->n_radial != kS || m->n_basis < 2 || m->n_basis > kMaxBasis || m->n_species < 1 ||
+      m->n_species > kMaxSpecies || m->n_heads < 1 || m->n_heads > kMaxHeads || m->hidden1 < 1 || m->hidden2 < 1)
+    return GMNN_ERR_UNSUPPORTED;
+  if (!(m->r_cut > m->r_min) || !(m->gamma > 0.0f)) return GMNN_ERR_INVALID_ARG;
+  const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+  if (L.HP1 != L.HP2 || L.HP1 > 512 || (L.HP1 != 64 && L.HP1 != 128 && L.HP1 != 256 && L.HP1 != 512))
+    return GMNN_ERR_UNSUPPORTED;
+  return GMNN_OK;
+}
+
+static gmnn_status check_system(const gmnn_system* s) {
+  if (!s || s->n_structs < 1 || s->n_atoms < 0 || !s->atom_ptr || !s->atom_ptr_host || !s->cell || !s->cell_host ||
+      !s->pbc || !s->pbc_host || (s->n_atoms > 0 && (!s->pos || !s->species)))
+    return GMNN_ERR_INVALID_ARG;
+  if (s->atom_ptr_host[0] != 0 || s->atom_ptr_host[s->n_structs] != s->n_atoms) return GMNN_ERR_INVALID_ARG;
+  for (int b = 0; b < s->n_structs; ++b) {
+    if (s->atom_ptr_host[b + 1] < s->atom_ptr_host[b]) return GMNN_ERR_INVALID_ARG;
+    const double* h = s->cell_host + 9 * (size_t)b;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(h[k])) return GMNN_ERR_INVALID_ARG;
+    const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
+                       h[2] * (h[3] * h[7] - h[4] * h[6]);
+    if (!(std::fabs(det) > 1e-9)) return GMNN_ERR_INVALID_ARG;
+  }
+  return GMNN_OK;
+}
+
+static DevSystem dev_system(const gmnn_system* s, const gmnn_neighbors* nl) {
+  DevSystem d;
+  d.n_atoms = s->n_atoms;
+  d.n_structs = s->n_structs;
+  d.pos = s->pos;
+  d.species = s->species;
+  d.cell = s->cell;
+  d.atom_ptr = s->atom_ptr;
+  d.atom_struct = nl->atom_struct;
+  d.row_ptr = nl->row_ptr;
+  d.nj = nl->j;
+  d.nshift = nl->shift;
+  d.rev = nl->rev;
+  return d;
+}
+
+// readout tile rows for a precision / width (largest tile that fits in LDS)
+static int pick_tile(int hp, bool bf16, int n_atoms) {
+  int tm = 32;
+  if (readout_lds_bytes(32, hp, bf16) > 160 * 1024) tm = 16;
+  // small systems: more, smaller tiles spread over more compute units
+  if (n_atoms < 32 * 256) tm = 16;
+  return tm;
+}
+
+struct EfLayout {
+  size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, bytes = 0;
+};
+
+static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl) {
+  EfLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t N = (size_t)sys->n_atoms;
+  L.psi = take(4 * N * kS * kPacked);
+  L.psibar = take(4 * N * kS * kPacked);
+  L.atomic_e = take(4 * N * (size_t)m->n_heads);
+  L.gpair = take(12 * (size_t)nl->capacity);
+  L.virial = take(4 * 9 * N);
+  L.bytes = off;
+  return L;
+}
+
+}  // namespace gmnn
+
+using namespace gmnn;
+
+extern "C" {
+
+const char* gmnn_status_string(gmnn_status s) {
+  switch (s) {
+    case GMNN_OK: return "ok";
+    case GMNN_ERR_INVALID_ARG: return "invalid argument";
+    case GMNN_ERR_CAPACITY: return "neighbour capacity too small";
+    case GMNN_ERR_UNSUPPORTED: return "unsupported shape or model";
+    case GMNN_ERR_HIP: return "HIP runtime error";
+    case GMNN_ERR_DEVICE_FLAG: return "device status flag raised";
+    case GMNN_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+int32_t gmnn_num_features(int32_t S) {
+  if (S < 1) return 0;
+  const int pairs = S * (S + 1) / 2;
+  return S + 3 * pairs + S * (S + 1) * (S + 2) / 6 + 2 * pairs * S + S * S * S;
+}
+
+size_t gmnn_model_packed_bytes(const gmnn_model* m) {
+  if (!m || m->hidden1 < 1 || m->hidden2 < 1 || m->n_heads < 1) return 0;
+  return packed_layout(m->hidden1, m->hidden2, m->n_heads).bytes;
+}
+
+gmnn_status gmnn_model_prepare(gmnn_model* m, void* stream) {
+  gmnn_status st = check_model(m);
+  if (st != GMNN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+  char* P = (char*)m->packed;
+  const int F = kF, H1 = m->hidden1, H2 = m->hidden2;
+  struct Job {
+    int which, Kp, Np;
+    size_t f, b;
+  } jobs[4] = {{0, kFP, L.HP1, L.w1_f32, L.w1_bf16},
+               {1, L.HP1, kFP, L.w1t_f32, L.w1t_bf16},
+               {2, L.HP1, L.HP2, L.w2_f32, L.w2_bf16},
+               {3, L.HP2, L.HP1, L.w2t_f32, L.w2t_bf16}};
+  for (auto& j : jobs) {
+    const int64_t total = (int64_t)j.Kp * j.Np;
+    hipLaunchKernelGGL(pack_weights, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, j.which, m->W1, m->W2, F,
+                       H1, H2, j.Kp, j.Np, (float*)(P + j.f), (__bf16*)(P + j.b));
+  }
+  const int nv = L.HP1 > L.HP2 ? L.HP1 : L.HP2;
+  hipLaunchKernelGGL(pack_vectors, dim3((nv + 255) / 256), dim3(256), 0, s, m->b1, m->b2, m->W3, m->b3, H1, H2, L.HP1,
+                     L.HP2, m->n_heads, (float*)(P + L.b1), (float*)(P + L.b2), (float*)(P + L.w3),
+                     (float*)(P + L.w3bar), (float*)(P + L.b3));
+  return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
+}
+
+size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                            uint32_t flags) {
+  (void)flags;
+  if (!sys || check_system(sys) != GMNN_OK) return 0;
+  if (op == GMNN_OP_NEIGHBORS) {
+    if (!nl || !(nl->cutoff > 0.0f)) return 0;
+    return nl_layout(sys, (double)nl->cutoff + 1.0e-4).bytes;
+  }
+  if (!m || !nl) return 0;
+  if (op == GMNN_OP_ENERGY_FORCES || op == GMNN_OP_BACKWARD) return ef_layout(m, sys, nl).bytes;
+  return 0;
+}
+
+size_t gmnn_neighbors_workspace_bytes(const gmnn_system* sys, float cutoff, float skin) {
+  if (!sys || check_system(sys) != GMNN_OK) return 0;
+  return nl_layout(sys, (double)(cutoff + skin) + 1.0e-4).bytes;
+}
+
+gmnn_status gmnn_build_neighbors(const gmnn_system* sys, float cutoff, float skin, gmnn_neighbors* nl, uint32_t flags,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  gmnn_status st = check_system(sys);
+  if (st != GMNN_OK) return st;
+  if (!nl || !nl->row_ptr || !nl->atom_struct || !nl->n_pairs || !nl->status || nl->capacity < 0 ||
+      (nl->capacity > 0 && (!nl->j || !nl->shift || !nl->rev)) || !(cutoff > 0.0f) || !(skin >= 0.0f) ||
+      (!workspace && workspace_bytes > 0))
+    return GMNN_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  st = nl_build(sys, cutoff, skin, nl, workspace, workspace_bytes, s);
+  if (st != GMNN_OK) return st;
+  if (flags & GMNN_SYNC) {
+    if (hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
+    uint32_t status = 0;
+    int64_t np = 0;
+    if (hipMemcpy(&status, nl->status, 4, hipMemcpyDeviceToHost) != hipSuccess) return GMNN_ERR_HIP;
+    if (hipMemcpy(&np, nl->n_pairs, 8, hipMemcpyDeviceToHost) != hipSuccess) return GMNN_ERR_HIP;
+    if (status & GMNN_FLAG_CAPACITY || np > nl->capacity) return GMNN_ERR_CAPACITY;
+    if (status) return GMNN_ERR_DEVICE_FLAG;
+  }
+  return GMNN_OK;
+}
+
+gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
+                               gmnn_outputs* out, void* workspace, size_t workspace_bytes, void* stream) {
+  gmnn_status st = check_model(m);
+  if (st != GMNN_OK) return st;
+  st = check_system(sys);
+  if (st != GMNN_OK) return st;
+  if (!nl || !nl->row_ptr || !nl->atom_struct || (nl->capacity > 0 && (!nl->j || !nl->shift || !nl->rev)) || !out ||
+      !out->energy || (sys->n_atoms > 0 && !out->forces) || ((flags & GMNN_WANT_STRESS) && !out->stress))
+    return GMNN_ERR_INVALID_ARG;
+  if (flags & GMNN_WANT_FORCE_VAR) return GMNN_ERR_UNSUPPORTED;
+  if (nl->cutoff + 1e-6f < m->r_cut) return GMNN_ERR_INVALID_ARG;
+  const EfLayout L = ef_layout(m, sys, nl);
+  if (workspace_bytes < L.bytes || !workspace) return GMNN_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)workspace;
+  float* psi = (float*)(W + L.psi);
+  float* psibar = (float*)(W + L.psibar);
+  float* atomic_e = out->atomic_energy ? out->atomic_energy : (float*)(W + L.atomic_e);
+  float* gpair = (float*)(W + L.gpair);
+  float* virial = (float*)(W + L.virial);
+  const DevModel dm = dev_model(m);
+  const DevSystem ds = dev_system(sys, nl);
+  const bool bf16 = (flags & GMNN_PREC_BF16) != 0;
+  const int N = sys->n_atoms;
+  const size_t beta_lds = sizeof(float) * (size_t)m->n_species * m->n_species * kS * kMaxBasis;
+  if (N > 0) {
+    const int nb = (N + kPairAtoms - 1) / kPairAtoms;
+    hipLaunchKernelGGL(pair_moments, dim3(nb), dim3(kPairThreads), beta_lds, s, dm, ds, psi);
+    st = launch_readout(pick_tile(dm.HP1, bf16, N), dm, ds, bf16, psi, atomic_e, psibar, s);
+    if (st != GMNN_OK) return st;
+    hipLaunchKernelGGL(pair_backward, dim3(nb), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair, virial);
+    hipLaunchKernelGGL(force_gather, dim3(nb), dim3(kPairThreads), 0, s, ds, gpair, out->forces);
+  }
+  hipLaunchKernelGGL(struct_reduce, dim3(sys->n_structs), dim3(256), 0, s, m->n_heads, ds, atomic_e, virial,
+                     (flags & GMNN_WANT_STRESS) ? 1 : 0, out->energy, out->energy_var, out->stress);
+  if (hipGetLastError() != hipSuccess) return GMNN_ERR_HIP;
+  if (flags & GMNN_SYNC) {
+    if (hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
+  }
+  return GMNN_OK;
+}
+
+gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, const double* dL_dE,
+                          const float* dL_dF, uint32_t flags, gmnn_param_grads* grads, float* dL_dpos, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  (void)m; (void)sys; (void)nl; (void)dL_dE; (void)dL_dF; (void)flags; (void)grads; (void)dL_dpos;
+  (void)workspace; (void)workspace_bytes; (void)stream;
+  return GMNN_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

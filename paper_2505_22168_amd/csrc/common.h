@@ -1,0 +1,89 @@
+// Shared device helpers of the GMNN HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gmnn.h"
+
+#define GMNN_WAVE 64
+
+namespace gmnn {
+
+// ---------------------------------------------------------------------------
+// packed image vector: three int8 in the low 24 bits
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int32_t pack_shift(int sx, int sy, int sz) {
+  return (sx & 0xff) | ((sy & 0xff) << 8) | ((sz & 0xff) << 16);
+}
+__host__ __device__ inline void unpack_shift(int32_t p, int& sx, int& sy, int& sz) {
+  sx = (int)(int8_t)(p & 0xff);
+  sy = (int)(int8_t)((p >> 8) & 0xff);
+  sz = (int)(int8_t)((p >> 16) & 0xff);
+}
+// canonical sort key of a pair inside a row: (j, Sx, Sy, Sz) ascending
+__host__ __device__ inline uint64_t pair_key(int j, int sx, int sy, int sz) {
+  return ((uint64_t)(uint32_t)j << 24) | ((uint64_t)(sx + 128) << 16) |
+         ((uint64_t)(sy + 128) << 8) | (uint64_t)(sz + 128);
+}
+
+// ---------------------------------------------------------------------------
+// wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ inline int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, GMNN_WAVE);
+  return v;
+}
+
+// inclusive prefix sum over the 64 lanes
+__device__ inline int wave_incl_scan(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, GMNN_WAVE);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ inline void raise_flag(uint32_t* status, uint32_t f) { atomicOr(status, f); }
+
+// ---------------------------------------------------------------------------
+// block-level exclusive scan of `n` int32 counts into int64 offsets (n+1
+// entries, out[n] = total).  One block; every thread of the block calls it.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__device__ inline void block_exclusive_scan(const int32_t* __restrict__ in, int64_t* __restrict__ out,
+                                            int64_t n, int64_t* total_out) {
+  __shared__ int64_t sums[BLOCK];
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + BLOCK - 1) / BLOCK;
+  const int64_t b0 = t * chunk;
+  const int64_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
+  int64_t s = 0;
+  for (int64_t k = b0; k < b1; ++k) s += in[k];
+  sums[t] = s;
+  __syncthreads();
+  // Hillis-Steele over BLOCK partial sums
+  for (int o = 1; o < BLOCK; o <<= 1) {
+    int64_t v = (t >= o) ? sums[t - o] : 0;
+    __syncthreads();
+    sums[t] += v;
+    __syncthreads();
+  }
+  int64_t run = (t == 0) ? 0 : sums[t - 1];
+  for (int64_t k = b0; k < b1; ++k) {
+    out[k] = run;
+    run += in[k];
+  }
+  if (t == BLOCK - 1) {
+    out[n] = sums[BLOCK - 1];
+    if (total_out) *total_out = sums[BLOCK - 1];
+  }
+}
+
+}  // namespace gmnn

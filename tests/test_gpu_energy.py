@@ -1,0 +1,128 @@
+"""GPU energies, forces and stress vs the FP64 oracle.
+
+Tolerances: FP32 arm |dE|/N <= 1e-5 eV/atom and max|dF| <= 1e-4 eV/A against
+the FP64 oracle (the bound the method's FP32 evaluation is held to); the BF16
+arm against the oracle's BF16-rounding arm (same rounding points) within
+FP32-accumulation error, and against FP64 within the stated BF16 budget
+(force RMSE <= 1% of RMS |F|, |dE|/N <= 1e-3 eV/atom)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import brute_force_neighbors, evaluate
+from workloads import make_batch, make_workload
+from gpu_helpers import gpu, need_gpu
+
+pytestmark = gpu
+
+
+def _run(g, batch, params, rc, precision, skin=0.0):
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, rc, skin)
+    model = g.Model.from_params(params, "cuda")
+    out = g.energy_forces(model, system, nl, precision=precision, stress=True)
+    torch.cuda.synchronize()
+    return out
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = [("tiny", {}), ("ensemble", dict(n_structs=5)), ("train", dict(n_structs=2, n_lo=100, n_hi=160))]
+
+
+@pytest.mark.parametrize("name,kw", CASES)
+def test_fp32_matches_fp64_oracle(name, kw):
+    g = need_gpu()
+    batch, params, spec = make_workload(name, **kw)
+    out = _run(g, batch, params, spec.model.r_cut, "fp32")
+    ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
+    nb = np.diff(batch.atom_ptr)
+    dE = np.abs(_np(out.energy) - ref.energy) / nb[:, None]
+    assert dE.max() < 1e-5, dE.max()
+    dF = np.abs(_np(out.forces)[: batch.n_atoms] - ref.forces)
+    assert dF.max() < 1e-4, dF.max()
+    dS = np.abs(_np(out.stress) - ref.stress)
+    assert dS.max() < 1e-6, dS.max()
+    dEi = np.abs(_np(out.atomic_energy)[: batch.n_atoms] - ref.atomic)
+    assert dEi.max() < 1e-4
+
+
+@pytest.mark.parametrize("name,kw", CASES)
+def test_bf16_matches_bf16_oracle_and_budget(name, kw):
+    g = need_gpu()
+    batch, params, spec = make_workload(name, **kw)
+    out = _run(g, batch, params, spec.model.r_cut, "bf16")
+    nl = brute_force_neighbors(batch, spec.model.r_cut)
+    ref16 = evaluate(batch, params, nl, bf16=True)
+    ref64 = evaluate(batch, params, nl)
+    F = _np(out.forces)[: batch.n_atoms]
+    nb = np.diff(batch.atom_ptr)
+    rms = np.sqrt((ref64.forces ** 2).mean())
+    # same rounding points as the oracle's bf16 arm: differences come from
+    # FP32 accumulation and rare bf16 rounding flips
+    assert np.sqrt(((F - ref16.forces) ** 2).mean()) < 2e-3 * rms
+    assert (np.abs(_np(out.energy) - ref16.energy) / nb[:, None]).max() < 1e-4
+    # stated budget against FP64
+    assert np.sqrt(((F - ref64.forces) ** 2).mean()) < 1e-2 * rms
+    assert (np.abs(_np(out.energy) - ref64.energy) / nb[:, None]).max() < 1e-3
+
+
+def test_energy_variance_over_heads():
+    g = need_gpu()
+    batch, params, spec = make_workload("ensemble", n_structs=4)
+    out = _run(g, batch, params, 5.0, "fp32")
+    ref = evaluate(batch, params, brute_force_neighbors(batch, 5.0))
+    assert np.allclose(_np(out.energy_var), ref.energy_var, rtol=1e-5, atol=1e-6)
+
+
+def test_skin_list_gives_same_result():
+    g = need_gpu()
+    batch, params, spec = make_workload("solid", reps=(7, 7, 6))
+    a = _run(g, batch, params, 6.0, "fp32", skin=0.0)
+    b = _run(g, batch, params, 6.0, "fp32", skin=1.0)
+    assert abs(_np(a.energy) - _np(b.energy)).max() / batch.n_atoms < 1e-6
+    assert np.abs(_np(a.forces) - _np(b.forces)).max() < 2e-5
+    ref = evaluate(batch, params, brute_force_neighbors(batch, 6.0))
+    assert np.abs(_np(b.forces) - ref.forces).max() < 1e-4
+
+
+def test_run_to_run_bitwise_reproducible():
+    g = need_gpu()
+    batch, params, spec = make_workload("ensemble", n_structs=6)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, 5.0)
+    model = g.Model.from_params(params, "cuda")
+    for prec in ("fp32", "bf16"):
+        ev = g.EnergyForces(model, system, nl, precision=prec)
+        o1 = ev(sync=True)
+        e1, f1, s1 = o1.energy.clone(), o1.forces.clone(), o1.stress.clone()
+        o2 = ev(sync=True)
+        assert torch.equal(e1, o2.energy) and torch.equal(f1, o2.forces) and torch.equal(s1, o2.stress)
+
+
+def test_batched_equals_per_structure():
+    g = need_gpu()
+    batch, params, spec = make_workload("ensemble", n_structs=5)
+    full = _run(g, batch, params, 5.0, "fp32")
+    for b in (0, 3):
+        sub = batch.structure(b)
+        one = _run(g, sub, params, 5.0, "fp32")
+        a0, a1 = batch.atom_ptr[b], batch.atom_ptr[b + 1]
+        assert np.allclose(_np(one.energy), _np(full.energy)[b:b + 1], rtol=0, atol=1e-9 * max(1, abs(_np(one.energy)).max()) + 1e-6)
+        assert np.abs(_np(one.forces)[: a1 - a0] - _np(full.forces)[a0:a1]).max() < 1e-6
+
+
+def test_net_force_and_lattice_translation():
+    g = need_gpu()
+    batch, params, spec = make_workload("liquid", n=400, sweeps=2)
+    out = _run(g, batch, params, 5.0, "fp32")
+    F = _np(out.forces)[: batch.n_atoms].astype(np.float64)
+    assert np.abs(F.sum(0)).max() < 1e-3
+    # shifting one atom by a lattice vector changes only the image vectors
+    b2 = make_batch([(batch.pos + np.where(np.arange(batch.n_atoms)[:, None] == 7, batch.cell[0, 0], 0).astype(np.float32),
+                      batch.species, batch.cell[0], (1, 1, 1))])
+    out2 = _run(g, b2, params, 5.0, "fp32")
+    assert abs(_np(out2.energy) - _np(out.energy)).max() / batch.n_atoms < 1e-5
+    assert np.abs(_np(out2.forces) - _np(out.forces)).max() < 1e-4
