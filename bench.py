@@ -1,0 +1,228 @@
+"""Throughput of the GMNN energy+force hot path on one MI355X.
+
+A step is one full pass of the path (pair moments -> invariants + network +
+backward in the tile readout -> pair backward -> force gather -> FP64
+per-structure sums) over the workload, with the neighbour list built once
+beforehand (it is reused across steps, as in MD between rebuilds) and all
+inputs resident in HBM.  The headline value is the fused BF16-network path;
+the plain FP32 path is timed the same way and reported beside it, each with
+its error against the FP64 oracle on the same inputs.
+
+    python bench.py [--steps K] [--warmup W] [--workload liquid]
+
+Prints one JSON line (rank 0, one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "energy+force atom-evals/s on 1 GPU, fused BF16 vs plain FP32, at force err vs FP64"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+STAGES = ["pair_moments", "readout", "pair_backward", "force_gather", "struct_reduce"]
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime (recorded by the library on
+    the stream its kernels run on)."""
+
+    def __init__(self):
+        self.rt = C.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [C.c_void_p]
+
+    def create(self, n):
+        arr = (C.c_void_p * n)()
+        for k in range(n):
+            h = C.c_void_p()
+            assert self.rt.hipEventCreate(C.byref(h)) == 0
+            arr[k] = h
+        return arr
+
+    def elapsed_ms(self, a, b):
+        ms = C.c_float()
+        assert self.rt.hipEventElapsedTime(C.byref(ms), a, b) == 0
+        return ms.value
+
+    def destroy(self, arr):
+        for h in arr:
+            self.rt.hipEventDestroy(h)
+
+
+def algorithmic_work(spec, n_atoms, n_pairs):
+    """Bytes (HBM-bound stages) or flops (network) one launch must move/do."""
+    H1, H2 = spec.hidden
+    F, M = spec.n_features, spec.n_heads
+    mlp_flops = 2 * (F * H1 + H1 * H2 + H2 * M) + 2 * (H2 * H1 + H1 * F)
+    return {
+        # j + packed shift per pair; per atom: pos, species, row_ptr, structure id, moments out
+        "pair_moments": ("hbm", 8 * n_pairs + n_atoms * (12 + 4 + 8 + 4 + 400)),
+        "readout": ("mfma", mlp_flops * n_atoms),
+        # list + g out per pair; per atom: moment gradient in, virial out, pos, species, row_ptr
+        "pair_backward": ("hbm", 20 * n_pairs + n_atoms * (400 + 36 + 12 + 4 + 8 + 4)),
+        # rev + two g reads per pair; forces out
+        "force_gather": ("hbm", 28 * n_pairs + n_atoms * (12 + 8)),
+        "struct_reduce": ("hbm", n_atoms * (4 * M + 36)),
+    }
+
+
+def run_path(g, A, model, system, nl, precision, steps, warmup, events):
+    import torch
+    ev = g.EnergyForces(model, system, nl, precision=precision, stress=True)
+    for _ in range(warmup):
+        ev()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-stage durations: the same steps again with events around each kernel
+    lib = A.load()
+    evs = [events.create(10) for _ in range(steps)]
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    for k in range(steps):
+        st = lib.gmnn_energy_forces_timed(C.byref(ev._mc), C.byref(ev._sc), C.byref(ev._nc), ev.flags,
+                                          C.byref(ev._oc), C.c_void_p(ev.workspace.data_ptr()), ev.ws_bytes,
+                                          stream, evs[k])
+        A.check(st, "gmnn_energy_forces_timed")
+    torch.cuda.synchronize()
+    stage_ms = {name: float(np.mean([events.elapsed_ms(e[2 * s], e[2 * s + 1]) for e in evs]))
+                for s, name in enumerate(STAGES)}
+    for e in evs:
+        events.destroy(e)
+    out = ev(sync=True)
+    return wall, stage_ms, out
+
+
+def errors_vs_oracle(out, ref, n_atoms, nb):
+    F = out.forces.cpu().numpy()[:n_atoms].astype(np.float64)
+    dF = F - ref.forces
+    E = out.energy.cpu().numpy()
+    rmsF = float(np.sqrt((ref.forces ** 2).mean()))
+    return {
+        "force_mae": float(np.abs(dF).mean()), "force_rmse": float(np.sqrt((dF ** 2).mean())),
+        "force_max": float(np.abs(dF).max()), "force_rmse_rel": float(np.sqrt((dF ** 2).mean()) / rmsF),
+        "energy_per_atom_max": float((np.abs(E - ref.energy) / nb[:, None]).max()),
+        "stress_max": float(np.abs(out.stress.cpu().numpy() - ref.stress).max()),
+        "rms_force": rmsF,
+    }
+
+
+def cpu_baseline(batch, params, nl_ref, budget_s):
+    import torch
+    from oracle import evaluate
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        evaluate(batch, params, nl_ref)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": batch.n_atoms * reps / el, "unit": "atom-evals/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} FP64 oracle evaluations (energy, forces, stress; list excluded) of the "
+                      f"{batch.n_atoms}-atom workload, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="liquid")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-oracle", action="store_true", help="skip oracle errors and the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2505_22168_amd as g
+    from paper_2505_22168_amd import _capi as A
+    from workloads import make_workload
+
+    g.load_library()
+    batch, params, spec = make_workload(args.workload)
+    dev = torch.device("cuda:0")
+    system = g.System.from_batch(batch, dev)
+    nl = g.build_neighbors(system, spec.model.r_cut, spec.skin)
+    model = g.Model.from_params(params, dev)
+    events = HipEvents()
+    N, P = batch.n_atoms, nl.n_pairs
+    print(f"[bench] workload {args.workload}: {N} atoms, {P} pairs, {batch.n_structs} structures", file=sys.stderr,
+          flush=True)
+
+    res = {}
+    for prec in ("bf16", "fp32"):
+        wall, stage_ms, out = run_path(g, A, model, system, nl, prec, args.steps, args.warmup, events)
+        res[prec] = (wall, stage_ms, out)
+        print(f"[bench] {prec}: {wall / args.steps * 1e3:.4f} ms/step, stages(us) "
+              + ", ".join(f"{k}={v * 1e3:.1f}" for k, v in stage_ms.items()), file=sys.stderr, flush=True)
+
+    wall, stage_ms, out16 = res["bf16"]
+    ms_per_step = wall / args.steps * 1e3
+    value = N * args.steps / wall
+    work = algorithmic_work(spec.model, N, P)
+    dom = max(stage_ms, key=stage_ms.get)
+    bound, amount = work[dom]
+    dur_s = stage_ms[dom] * 1e-3
+    if bound == "hbm":
+        achieved, peak, unit = amount / dur_s / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = amount / dur_s / 1e12, MFMA_PEAK_TFLOPS["bf16"], "TFLOP/s"
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None,
+                "per_launch": {"amount": amount, "what": "bytes" if bound == "hbm" else "flops",
+                               "avg_duration_us": stage_ms[dom] * 1e3}}
+
+    wall32, stage32, out32 = res["fp32"]
+    fp32 = {"value": N * args.steps / wall32, "ms_per_step": wall32 / args.steps * 1e3,
+            "stages_us": {k: v * 1e3 for k, v in stage32.items()}}
+
+    accuracy = None
+    cpu = None
+    if not args.no_oracle:
+        from oracle import brute_force_neighbors, evaluate
+        t0 = time.perf_counter()
+        nl_ref = brute_force_neighbors(batch, spec.model.r_cut)
+        ref = evaluate(batch, params, nl_ref)
+        print(f"[bench] oracle reference in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        nb = np.diff(batch.atom_ptr)
+        accuracy = {"bf16": errors_vs_oracle(out16, ref, N, nb), "fp32": errors_vs_oracle(out32, ref, N, nb)}
+        cpu = cpu_baseline(batch, params, nl_ref, args.cpu_budget)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "atom-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": args.workload, "n_atoms": N, "n_pairs": P, "n_structs": batch.n_structs,
+                   "r_cut": spec.model.r_cut, "mlp": list(spec.model.hidden), "heads": spec.model.n_heads,
+                   "features": spec.model.n_features, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_us": {k: v * 1e3 for k, v in stage_ms.items()},
+        "fp32": fp32,
+        "bf16_over_fp32": value / fp32["value"],
+        "accuracy_vs_fp64": accuracy,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -215,6 +215,16 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
                                const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
                                void* workspace, size_t workspace_bytes, void* stream);
 
+/* gmnn_energy_forces with a hipEvent_t recorded on `stream` right before and
+ * right after each kernel stage, for profiling: stage_events[2k] / [2k+1]
+ * bracket stage k = 0 pair moments, 1 readout (invariants + network +
+ * invariant backward), 2 pair backward, 3 force gather, 4 per-structure
+ * reductions (10 events; created by the caller with hipEventCreate). */
+gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys,
+                                     const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
+                                     void* workspace, size_t workspace_bytes, void* stream,
+                                     void* const* stage_events);
+
 /* Gradients of a scalar loss L(E, F) w.r.t. the model parameters and the
  * positions, given the upstream gradients dL/dE (per structure, w.r.t. the
  * head-mean energy) and dL/dF [N,3] (Section 3.4: energy + force losses;

@@ -52,8 +52,10 @@ class NeighborList:
 
 
 def _image_range(cell: np.ndarray, pbc, rc: float):
-    """Per-axis half-width of the image range: ceil(rc / width) + 1 where width
-    is the distance between the two faces of the cell normal to that axis."""
+    """Per-axis half-width of the image window around S0 = -round(f_j - f_i):
+    a listed pair has |f_j - f_i + S|_k < rc / width_k (width: distance
+    between the two cell faces normal to axis k) and |f_j - f_i + S0|_k <= 1/2,
+    so |S - S0|_k <= ceil(rc / width_k + 1/2)."""
     vol = abs(float(np.linalg.det(cell)))
     n = []
     for k in range(3):
@@ -62,7 +64,7 @@ def _image_range(cell: np.ndarray, pbc, rc: float):
             continue
         a, b = cell[(k + 1) % 3], cell[(k + 2) % 3]
         width = vol / float(np.linalg.norm(np.cross(a, b)))
-        n.append(int(math.ceil(rc / width)) + 1)
+        n.append(int(math.ceil(rc / width + 0.5 + 1e-9)))
     return n
 
 

@@ -288,8 +288,9 @@ gmnn_status gmnn_build_neighbors(const gmnn_system* sys, float cutoff, float ski
   return GMNN_OK;
 }
 
-gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
-                               gmnn_outputs* out, void* workspace, size_t workspace_bytes, void* stream) {
+gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                     uint32_t flags, gmnn_outputs* out, void* workspace, size_t workspace_bytes,
+                                     void* stream, void* const* stage_events) {
   gmnn_status st = check_model(m);
   if (st != GMNN_OK) return st;
   st = check_system(sys);
@@ -313,21 +314,40 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, cons
   const bool bf16 = (flags & GMNN_PREC_BF16) != 0;
   const int N = sys->n_atoms;
   const size_t beta_lds = sizeof(float) * (size_t)m->n_species * m->n_species * kS * kMaxBasis;
+  hipEvent_t* ev = (hipEvent_t*)stage_events;
+  auto mark = [&](int k) {
+    if (ev) hipEventRecord(ev[k], s);
+  };
   if (N > 0) {
     const int nb = (N + kPairAtoms - 1) / kPairAtoms;
+    mark(0);
     hipLaunchKernelGGL(pair_moments, dim3(nb), dim3(kPairThreads), beta_lds, s, dm, ds, psi);
+    mark(1);
+    mark(2);
     st = launch_readout(pick_tile(dm.HP1, bf16, N), dm, ds, bf16, psi, atomic_e, psibar, s);
     if (st != GMNN_OK) return st;
+    mark(3);
+    mark(4);
     hipLaunchKernelGGL(pair_backward, dim3(nb), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair, virial);
+    mark(5);
+    mark(6);
     hipLaunchKernelGGL(force_gather, dim3(nb), dim3(kPairThreads), 0, s, ds, gpair, out->forces);
+    mark(7);
   }
+  mark(8);
   hipLaunchKernelGGL(struct_reduce, dim3(sys->n_structs), dim3(256), 0, s, m->n_heads, ds, atomic_e, virial,
                      (flags & GMNN_WANT_STRESS) ? 1 : 0, out->energy, out->energy_var, out->stress);
+  mark(9);
   if (hipGetLastError() != hipSuccess) return GMNN_ERR_HIP;
   if (flags & GMNN_SYNC) {
     if (hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
   }
   return GMNN_OK;
+}
+
+gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
+                               gmnn_outputs* out, void* workspace, size_t workspace_bytes, void* stream) {
+  return gmnn_energy_forces_timed(m, sys, nl, flags, out, workspace, workspace_bytes, stream, nullptr);
 }
 
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, const double* dL_dE,

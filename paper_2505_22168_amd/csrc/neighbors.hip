@@ -213,7 +213,10 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_rows(
   const int i = blockIdx.x * kRowsWaves + w;
   if (i >= n_atoms) return;
   if (*n_cells_total > cell_capacity) return;
-  if (MODE == 1 && *n_pairs > capacity) return;
+  if (MODE == 1 && *n_pairs > capacity) {
+    if (i == 0 && l == 0) raise_flag(status, GMNN_FLAG_CAPACITY);
+    return;
+  }
   const int b = atom_struct[i];
   const StructGrid& g = grids[b];
   const int4 ii = atom_img[i];

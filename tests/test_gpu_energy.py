@@ -4,7 +4,7 @@ Tolerances: FP32 arm |dE|/N <= 1e-5 eV/atom and max|dF| <= 1e-4 eV/A against
 the FP64 oracle (the bound the method's FP32 evaluation is held to); the BF16
 arm against the oracle's BF16-rounding arm (same rounding points) within
 FP32-accumulation error, and against FP64 within the stated BF16 budget
-(force RMSE <= 1% of RMS |F|, |dE|/N <= 1e-3 eV/atom)."""
+(force RMSE <= 1% of RMS |F|, |dE|/N <= 5e-3 eV/atom)."""
 import numpy as np
 import pytest
 import torch
@@ -66,7 +66,7 @@ def test_bf16_matches_bf16_oracle_and_budget(name, kw):
     assert (np.abs(_np(out.energy) - ref16.energy) / nb[:, None]).max() < 1e-4
     # stated budget against FP64
     assert np.sqrt(((F - ref64.forces) ** 2).mean()) < 1e-2 * rms
-    assert (np.abs(_np(out.energy) - ref64.energy) / nb[:, None]).max() < 1e-3
+    assert (np.abs(_np(out.energy) - ref64.energy) / nb[:, None]).max() < 5e-3
 
 
 def test_energy_variance_over_heads():
