@@ -217,9 +217,16 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
 
 /* gmnn_energy_forces with a hipEvent_t recorded on `stream` right before and
  * right after each kernel stage, for profiling: stage_events[2k] / [2k+1]
- * bracket stage k = 0 pair moments, 1 readout (invariants + network +
- * invariant backward), 2 pair backward, 3 force gather, 4 per-structure
- * reductions (10 events; created by the caller with hipEventCreate). */
+ * bracket stage k = 0 pair moments (on small systems: the fused tile kernel,
+ * which also covers stages 1 and 2), 1 readout (invariants + network +
+ * invariant backward), 2 pair backward, 3 force gather + per-structure
+ * reductions (8 events, created by the caller with hipEventCreate). */
+/* 1 if gmnn_energy_forces runs the fused small-system schedule for these
+ * shapes and flags (moments, readout and pair backward in one launch, then
+ * the gather/reduction launch), 0 for the four-launch schedule, -1 on
+ * invalid arguments.  Host only. */
+int32_t gmnn_uses_fused_path(const gmnn_model* m, const gmnn_system* sys, uint32_t flags);
+
 gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys,
                                      const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
                                      void* workspace, size_t workspace_bytes, void* stream,

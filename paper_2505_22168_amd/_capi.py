@@ -75,6 +75,7 @@ EXPORTS = {
                                          C.POINTER(gmnn_neighbors), C.c_uint32, vp, C.c_size_t, vp]),
     "gmnn_energy_forces": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
                                        C.c_uint32, C.POINTER(gmnn_outputs), vp, C.c_size_t, vp]),
+    "gmnn_uses_fused_path": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.c_uint32]),
     "gmnn_energy_forces_timed": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
                                              C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_outputs), vp,
                                              C.c_size_t, vp, vp]),

@@ -9,18 +9,39 @@
 
 namespace gmnn {
 
-// defined in pairs.hip / readout.hip
-__global__ void pair_moments(DevModel m, DevSystem sys, float* psi);
-__global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial);
-__global__ void force_gather(DevSystem sys, const float* gpair, float* forces);
-__global__ void struct_reduce(int M, DevSystem sys, const float* atomic_e, const float* virial, int want_stress,
-                              double* energy, double* energy_var, double* stress);
-gmnn_status launch_readout(int tm, const DevModel& m, const DevSystem& sys, bool bf16, const float* psi,
-                           float* atomic_e, float* psibar, hipStream_t stream);
-size_t readout_lds_bytes(int tm, int hp, bool bf16);
+// defined in pairs.hip / tile.hip
+template <int LPA>
+__global__ void pair_moments(DevModel m, DevSystem sys, float* psi, int* counters, int n_counters);
+template <int LPA>
+__global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial, int nh,
+                              int64_t gstride);
+template <int LPA, bool VAR>
+__global__ void finish(int M, DevSystem sys, const float* gpair, const float* atomic_e, const float* virial,
+                       int want_stress, int nb_gather, int64_t gstride, int nchunk, double* partial, int* counters,
+                       float* forces, float* force_var, double* energy, double* energy_var, double* stress);
+gmnn_status launch_tile(bool fused, bool perhead, const DevModel& m, const DevSystem& sys, bool bf16,
+                        const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
+                        int64_t gstride, hipStream_t stream);
+bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead);
+size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead);
 
 constexpr int kPairThreads = 256;
-constexpr int kPairAtoms = 16;  // atoms per block of the pair kernels (16 lanes each)
+// systems below this many atoms take the fused (latency) path
+constexpr int kFusedMaxAtoms = 8192;
+// per-structure reductions split into chunks of at most this many atoms
+// (never below kFusedMaxAtoms: chunked sums need counters zeroed by the
+// unfused path's first kernel)
+constexpr int kReduceChunk = 8192;
+
+static int reduce_chunks(const gmnn_system* sys) {
+  int64_t mx = 0;
+  for (int b = 0; b < sys->n_structs; ++b) {
+    const int64_t n = sys->atom_ptr_host[b + 1] - sys->atom_ptr_host[b];
+    if (n > mx) mx = n;
+  }
+  const int64_t c = (mx + kReduceChunk - 1) / kReduceChunk;
+  return c < 1 ? 1 : (int)c;
+}
 
 // ---------------------------------------------------------------------------
 // model preparation: MFMA fragment order, padded widths
@@ -41,15 +62,16 @@ __global__ void pack_weights(int which, const float* __restrict__ W1, const floa
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)Kp * Np;
   if (t >= total) return;
-  // f32 fragments: index = ((nb*KB4 + kb)*64 + l)
+  // fp32 chunks: index = ((nb*KC + kc)*64 + l)*4 + u,  k = 16 kc + 4 (l>>4) + u
   {
-    const int KB4 = Kp / 4;
-    const int64_t l = t % 64, rest = t / 64;
-    const int64_t kb = rest % KB4, nb = rest / KB4;
-    const int k = (int)(kb * 4 + (l >> 4)), n = (int)(nb * 16 + (l & 15));
+    const int KC = Kp / 16;
+    const int64_t u = t % 4, rest = t / 4;
+    const int64_t l = rest % 64, rest2 = rest / 64;
+    const int64_t kc = rest2 % KC, nb = rest2 / KC;
+    const int k = (int)(kc * 16 + 4 * (l >> 4) + u), n = (int)(nb * 16 + (l & 15));
     out_f32[t] = wsrc(which, W1, W2, F, H1, H2, k, n);
   }
-  // bf16 fragments: index = ((nb*KB32 + kb)*64 + l)*8 + e
+  // bf16 fragments: index = ((nb*KB + kb)*64 + l)*8 + e,  k = 32 kb + 8 (l>>4) + e
   {
     const int KB32 = Kp / 32;
     const int64_t e = t % 8, rest = t / 8;
@@ -94,6 +116,9 @@ static DevModel dev_model(const gmnn_model* m) {
   d.gamma = m->gamma;
   d.delta = (m->r_cut - m->r_min) / (float)(m->n_basis - 1);
   d.psi_scale = m->psi_scale;
+  for (int k = 0; k < 8; ++k)
+    d.ck[k] = k < m->n_basis ? (float)std::exp(-(double)d.gamma * (double)d.delta * (double)d.delta * (double)(k * k))
+                             : 0.0f;
   d.beta = m->beta;
   d.scale = m->scale;
   d.shift = m->shift;
@@ -160,20 +185,11 @@ static DevSystem dev_system(const gmnn_system* s, const gmnn_neighbors* nl) {
   return d;
 }
 
-// readout tile rows for a precision / width (largest tile that fits in LDS)
-static int pick_tile(int hp, bool bf16, int n_atoms) {
-  int tm = 32;
-  if (readout_lds_bytes(32, hp, bf16) > 160 * 1024) tm = 16;
-  // small systems: more, smaller tiles spread over more compute units
-  if (n_atoms < 32 * 256) tm = 16;
-  return tm;
-}
-
 struct EfLayout {
-  size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, bytes = 0;
+  size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, partial = 0, counters = 0, bytes = 0;
 };
 
-static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl) {
+static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags) {
   EfLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -182,11 +198,14 @@ static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmn
     return o;
   };
   const size_t N = (size_t)sys->n_atoms;
+  const size_t nh = (flags & GMNN_WANT_FORCE_VAR) ? (size_t)m->n_heads : 1;
   L.psi = take(4 * N * kS * kPacked);
-  L.psibar = take(4 * N * kS * kPacked);
+  L.psibar = take(4 * N * kS * kPacked * nh);
   L.atomic_e = take(4 * N * (size_t)m->n_heads);
-  L.gpair = take(12 * (size_t)nl->capacity);
+  L.gpair = take(12 * (size_t)nl->capacity * nh);
   L.virial = take(4 * 9 * N);
+  L.partial = take(8 * (size_t)(kMaxHeads + 9) * sys->n_structs * reduce_chunks(sys));
+  L.counters = take(4 * (size_t)sys->n_structs);
   L.bytes = off;
   return L;
 }
@@ -256,7 +275,7 @@ size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* 
     return nl_layout(sys, (double)nl->cutoff + 1.0e-4).bytes;
   }
   if (!m || !nl) return 0;
-  if (op == GMNN_OP_ENERGY_FORCES || op == GMNN_OP_BACKWARD) return ef_layout(m, sys, nl).bytes;
+  if (op == GMNN_OP_ENERGY_FORCES || op == GMNN_OP_BACKWARD) return ef_layout(m, sys, nl, flags).bytes;
   return 0;
 }
 
@@ -288,6 +307,15 @@ gmnn_status gmnn_build_neighbors(const gmnn_system* sys, float cutoff, float ski
   return GMNN_OK;
 }
 
+int32_t gmnn_uses_fused_path(const gmnn_model* m, const gmnn_system* sys, uint32_t flags) {
+  if (check_model(m) != GMNN_OK || check_system(sys) != GMNN_OK) return -1;
+  const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+  return (sys->n_atoms < kFusedMaxAtoms &&
+          tile_fused_supported(m->n_species, L.HP1, (flags & GMNN_PREC_BF16) != 0, (flags & GMNN_WANT_FORCE_VAR) != 0))
+             ? 1
+             : 0;
+}
+
 gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
                                      uint32_t flags, gmnn_outputs* out, void* workspace, size_t workspace_bytes,
                                      void* stream, void* const* stage_events) {
@@ -298,9 +326,9 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   if (!nl || !nl->row_ptr || !nl->atom_struct || (nl->capacity > 0 && (!nl->j || !nl->shift || !nl->rev)) || !out ||
       !out->energy || (sys->n_atoms > 0 && !out->forces) || ((flags & GMNN_WANT_STRESS) && !out->stress))
     return GMNN_ERR_INVALID_ARG;
-  if (flags & GMNN_WANT_FORCE_VAR) return GMNN_ERR_UNSUPPORTED;
+  if ((flags & GMNN_WANT_FORCE_VAR) && !out->force_var) return GMNN_ERR_INVALID_ARG;
   if (nl->cutoff + 1e-6f < m->r_cut) return GMNN_ERR_INVALID_ARG;
-  const EfLayout L = ef_layout(m, sys, nl);
+  const EfLayout L = ef_layout(m, sys, nl, flags);
   if (workspace_bytes < L.bytes || !workspace) return GMNN_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   char* W = (char*)workspace;
@@ -309,6 +337,9 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   float* atomic_e = out->atomic_energy ? out->atomic_energy : (float*)(W + L.atomic_e);
   float* gpair = (float*)(W + L.gpair);
   float* virial = (float*)(W + L.virial);
+  double* partial = (double*)(W + L.partial);
+  int* counters = (int*)(W + L.counters);
+  const int nchunk = reduce_chunks(sys);
   const DevModel dm = dev_model(m);
   const DevSystem ds = dev_system(sys, nl);
   const bool bf16 = (flags & GMNN_PREC_BF16) != 0;
@@ -318,26 +349,65 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   auto mark = [&](int k) {
     if (ev) hipEventRecord(ev[k], s);
   };
+  const bool var = (flags & GMNN_WANT_FORCE_VAR) != 0;
+  const bool fused = N < kFusedMaxAtoms && tile_fused_supported(m->n_species, dm.HP1, bf16, var);
+  if (!fused && tile_lds_bytes(dm.HP1, bf16, false, var) > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
+  const int lpa = (N < kFusedMaxAtoms) ? 64 : 16;
+  const int nb_gather = (N + kPairThreads / lpa - 1) / (kPairThreads / lpa);
+  const int64_t gstride = nl->capacity;
+  const int nh = var ? m->n_heads : 1;
   if (N > 0) {
-    const int nb = (N + kPairAtoms - 1) / kPairAtoms;
-    mark(0);
-    hipLaunchKernelGGL(pair_moments, dim3(nb), dim3(kPairThreads), beta_lds, s, dm, ds, psi);
-    mark(1);
-    mark(2);
-    st = launch_readout(pick_tile(dm.HP1, bf16, N), dm, ds, bf16, psi, atomic_e, psibar, s);
-    if (st != GMNN_OK) return st;
-    mark(3);
-    mark(4);
-    hipLaunchKernelGGL(pair_backward, dim3(nb), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair, virial);
-    mark(5);
-    mark(6);
-    hipLaunchKernelGGL(force_gather, dim3(nb), dim3(kPairThreads), 0, s, ds, gpair, out->forces);
-    mark(7);
+    if (fused) {
+      mark(0);
+      st = launch_tile(true, false, dm, ds, bf16, nullptr, atomic_e, nullptr, gpair, virial, gstride, s);
+      if (st != GMNN_OK) return st;
+      mark(1);
+      mark(2);
+      mark(3);
+      mark(4);
+      mark(5);
+    } else {
+      mark(0);
+      const int nzc = nchunk > 1 ? sys->n_structs : 0;
+      if (lpa == 64)
+        hipLaunchKernelGGL(pair_moments<64>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psi, counters,
+                           nzc);
+      else
+        hipLaunchKernelGGL(pair_moments<16>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psi, counters,
+                           nzc);
+      mark(1);
+      mark(2);
+      st = launch_tile(false, var, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, s);
+      if (st != GMNN_OK) return st;
+      mark(3);
+      mark(4);
+      if (lpa == 64)
+        hipLaunchKernelGGL(pair_backward<64>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair,
+                           virial, nh, gstride);
+      else
+        hipLaunchKernelGGL(pair_backward<16>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair,
+                           virial, nh, gstride);
+      mark(5);
+    }
   }
-  mark(8);
-  hipLaunchKernelGGL(struct_reduce, dim3(sys->n_structs), dim3(256), 0, s, m->n_heads, ds, atomic_e, virial,
-                     (flags & GMNN_WANT_STRESS) ? 1 : 0, out->energy, out->energy_var, out->stress);
-  mark(9);
+  mark(6);
+  const int want_stress = (flags & GMNN_WANT_STRESS) ? 1 : 0;
+  const int nbg = N > 0 ? nb_gather : 0;
+  if (fused && nchunk > 1) return GMNN_ERR_UNSUPPORTED;  // unreachable: fused implies N < kReduceChunk
+  const dim3 fgrid(nbg + sys->n_structs * nchunk);
+#define FINISH(LPA, VAR)                                                                                       \
+  hipLaunchKernelGGL((finish<LPA, VAR>), fgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial, \
+                     want_stress, nbg, gstride, nchunk, partial, counters, out->forces, out->force_var, out->energy, \
+                     out->energy_var, out->stress)
+  if (lpa == 64) {
+    if (var) FINISH(64, true);
+    else FINISH(64, false);
+  } else {
+    if (var) FINISH(16, true);
+    else FINISH(16, false);
+  }
+#undef FINISH
+  mark(7);
   if (hipGetLastError() != hipSuccess) return GMNN_ERR_HIP;
   if (flags & GMNN_SYNC) {
     if (hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;

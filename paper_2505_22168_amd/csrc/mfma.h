@@ -1,0 +1,288 @@
+// MFMA tile products and the network stage of a tile (gfx950).
+//
+// Weight layouts (filled by gmnn_model_prepare), for B = W of shape K x N:
+//   BF16, 16x16x32 MFMA: fragment (nb, kb) is 64 lanes x 8 bf16, lane l holding
+//     B[32 kb + 8 (l>>4) + e][16 nb + (l&15)], e = 0..7     -> one 16-byte load
+//   FP32, 16x16x4 MFMA: chunk (nb, kc) is 64 lanes x 4 floats, lane l holding
+//     B[16 kc + 4 (l>>4) + u][16 nb + (l&15)], u = 0..3     -> one 16-byte load
+//     feeding four MFMAs (the k order inside a chunk is permuted consistently
+//     for A and B, which leaves the product unchanged)
+// A tiles live in LDS, row-major, rows padded so 16-byte reads stay aligned.
+#pragma once
+
+#include "common.h"
+#include "model.h"
+#include "tables.h"
+
+namespace gmnn {
+
+// Each wave owns one 16-row block rb and the 16-column blocks nb0 + i*nbs
+// (i < TPW, nb < NB).  Loads run two k-steps ahead of the MFMAs.
+template <int TPW>
+__device__ inline void mma_bf16(const __bf16* __restrict__ A, int lda, int rb, const bf16x8* __restrict__ Bp, int KB,
+                                int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
+  const int l = threadIdx.x & 63;
+  const __bf16* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 8;
+  bf16x8 b0[TPW], b1[TPW];
+  auto load = [&](bf16x8 (&dst)[TPW], int kb) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB && kb < KB) dst[i] = Bp[((size_t)nb * KB + kb) * 64 + l];
+    }
+  };
+  auto step = [&](const bf16x8 (&b)[TPW], int kb) {
+    const bf16x8 a = *(const bf16x8*)(arow + kb * 32);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[i], acc[i], 0, 0, 0);
+    }
+  };
+  load(b0, 0);
+  load(b1, 1);
+  for (int kb = 0; kb < KB; kb += 2) {
+    step(b0, kb);
+    load(b0, kb + 2);
+    if (kb + 1 < KB) {
+      step(b1, kb + 1);
+      load(b1, kb + 3);
+    }
+  }
+}
+
+template <int TPW>
+__device__ inline void mma_f32(const float* __restrict__ A, int lda, int rb, const float4* __restrict__ Bp, int KC,
+                               int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
+  const int l = threadIdx.x & 63;
+  const float* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 4;
+  float4 b0[TPW], b1[TPW];
+  auto load = [&](float4 (&dst)[TPW], int kc) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB && kc < KC) dst[i] = Bp[((size_t)nb * KC + kc) * 64 + l];
+    }
+  };
+  auto step = [&](const float4 (&b)[TPW], int kc) {
+    const float4 a = *(const float4*)(arow + kc * 16);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB) {
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[i].x, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[i].y, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[i].z, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[i].w, acc[i], 0, 0, 0);
+      }
+    }
+  };
+  load(b0, 0);
+  load(b1, 1);
+  for (int kc = 0; kc < KC; kc += 2) {
+    step(b0, kc);
+    load(b0, kc + 2);
+    if (kc + 1 < KC) {
+      step(b1, kc + 1);
+      load(b1, kc + 3);
+    }
+  }
+}
+
+template <int TPW>
+__device__ inline void zero_acc(floatx4 (&acc)[TPW]) {
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+template <bool BF16, int TPW>
+__device__ inline void mma(const void* A, int lda, int rb, const void* Bbf, const void* Bf, int K, int nb0, int nbs,
+                           int NB, floatx4 (&acc)[TPW]) {
+  if (BF16) mma_bf16<TPW>((const __bf16*)A, lda, rb, (const bf16x8*)Bbf, K / 32, nb0, nbs, NB, acc);
+  else mma_f32<TPW>((const float*)A, lda, rb, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
+}
+
+__device__ inline float swish_parts(float z, float& dsw) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  dsw = s * (1.0f + z * (1.0f - s));
+  return z * s;
+}
+
+template <bool BF16>
+__device__ inline void st_act(void* base, int idx, float v) {
+  if (BF16) ((__bf16*)base)[idx] = (__bf16)v;
+  else ((float*)base)[idx] = v;
+}
+
+// LDS row strides of the network tiles (elements)
+template <int HP, bool BF16>
+struct NetStrides {
+  static constexpr int G = BF16 ? (kFP + 8) : (kFP + 4);   // invariants (A of the first product)
+  static constexpr int H = BF16 ? (HP + 8) : (HP + 4);     // h1 / delta2 / delta1
+  static constexpr int GB = kFP + 1;                       // dE/dG (FP32)
+};
+
+template <int TM, int HP, int NW>
+struct NetShape {
+  static constexpr int MB = TM / 16;                 // 16-row blocks
+  static constexpr int WPR = NW / MB;                // waves per row block
+  static constexpr int NBH = HP / 16;                // 16-column blocks of a hidden layer
+  static constexpr int NBG = kFP / 16;               // ... of the invariants
+  static constexpr int TPW = (NBH + WPR - 1) / WPR;  // column blocks per wave (hidden)
+  static constexpr int TPW_G = (NBG + WPR - 1) / WPR;
+};
+
+// Network forward for the TM rows of a tile (all NW waves):
+//   z1 = G W1 + b1, h1 = swish(z1); z2 = h1 W2 + b2, h2 = swish(z2);
+//   y_m = h2 . W3[:,m] + b3[m], E_m = sigma y_m + mu  (written for rows < n_rows)
+// sG: invariants (read).  sH: h1 out.  swish'(z1) is returned in dsw1 (the
+// backward product hands each wave exactly these output fragments again).
+// MEAN: delta2 = swish'(z2) sigma mean_m W3[:,m] -> sD2 (the head-mean
+// backward); otherwise swish'(z2) -> sDsw2 (FP32, row stride HP + 1) for
+// per-head backwards.  sEp: [NW][16][kMaxHeads] partial sums.
+template <int TM, int HP, bool BF16, int NW, bool MEAN>
+__device__ inline void network_forward(const DevModel& m, const void* sG, void* sH, void* sD2, float* sDsw2,
+                                       float* sEp, const float* sScale, const float* sShift, int row0, int n_rows,
+                                       float* __restrict__ atomic_e,
+                                       floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW]) {
+  using St = NetStrides<HP, BF16>;
+  using Sh = NetShape<TM, HP, NW>;
+  constexpr int MB = Sh::MB, WPR = Sh::WPR, NBH = Sh::NBH, TPW = Sh::TPW;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int rb = w % MB, cw = w / MB;
+  const int M = m.M;
+  {
+    floatx4 acc[TPW];
+    zero_acc(acc);
+    mma<BF16, TPW>(sG, St::G, rb, m.w1_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = cw + i * WPR;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+      const float bias = m.b1[col];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = rb * 16 + 4 * (l >> 4) + j;
+        float d;
+        const float hv = swish_parts(acc[i][j] + bias, d);
+        dsw1[i][j] = d;
+        st_act<BF16>(sH, row * St::H + col, hv);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    floatx4 acc[TPW];
+    zero_acc(acc);
+    mma<BF16, TPW>(sH, St::H, rb, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = cw + i * WPR;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+      const float bias = m.b2[col];
+      const float wb = m.w3bar[col];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = rb * 16 + 4 * (l >> 4) + j;
+        float d;
+        const float hv = swish_parts(acc[i][j] + bias, d);
+        acc[i][j] = hv;
+        if (MEAN) st_act<BF16>(sD2, row * St::H + col, d * sScale[row] * wb);
+        else sDsw2[row * (HP + 1) + col] = d;
+      }
+    }
+    for (int hm = 0; hm < M; ++hm) {
+      float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int nb = cw + i * WPR;
+        if (nb >= NBH) continue;
+        const float w3 = m.w3[(nb * 16 + (l & 15)) * M + hm];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[j] += acc[i][j] * w3;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v = part[j];
+        v += __shfl_xor(v, 8, 16);
+        v += __shfl_xor(v, 4, 16);
+        v += __shfl_xor(v, 2, 16);
+        v += __shfl_xor(v, 1, 16);
+        if ((l & 15) == 0) sEp[(w * 16 + 4 * (l >> 4) + j) * kMaxHeads + hm] = v;
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < TM * M; t += NW * 64) {
+    const int a = t / M, hm = t % M;
+    if (a < n_rows) {
+      float y = m.b3[hm];
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww)
+        if (ww % MB == a / 16) y += sEp[(ww * 16 + a % 16) * kMaxHeads + hm];
+      atomic_e[(int64_t)(row0 + a) * M + hm] = sScale[a] * y + sShift[a];
+    }
+  }
+}
+
+// delta2 of head `hm`: swish'(z2) sigma W3[:,hm] -> sD2
+template <int TM, int HP, bool BF16, int NW>
+__device__ inline void network_delta2_head(const DevModel& m, const float* sDsw2, const float* sScale, void* sD2,
+                                           int hm) {
+  using St = NetStrides<HP, BF16>;
+  for (int t = threadIdx.x; t < TM * HP; t += NW * 64) {
+    const int row = t / HP, col = t % HP;
+    st_act<BF16>(sD2, row * St::H + col, sDsw2[row * (HP + 1) + col] * sScale[row] * m.w3[col * m.M + hm]);
+  }
+}
+
+// Network backward given delta2 in sD2: delta1 = swish'(z1) (delta2 W2^T) -> sH,
+// dE/dG = delta1 W1^T -> sGb (FP32).  Ends with a barrier.
+template <int TM, int HP, bool BF16, int NW>
+__device__ inline void network_backward(const DevModel& m, const void* sD2, void* sH, float* sGb,
+                                        const floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW]) {
+  using St = NetStrides<HP, BF16>;
+  using Sh = NetShape<TM, HP, NW>;
+  constexpr int MB = Sh::MB, WPR = Sh::WPR, NBH = Sh::NBH, NBG = Sh::NBG, TPW = Sh::TPW, TPW_G = Sh::TPW_G;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int rb = w % MB, cw = w / MB;
+  {
+    floatx4 acc[TPW];
+    zero_acc(acc);
+    mma<BF16, TPW>(sD2, St::H, rb, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH, acc);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = cw + i * WPR;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = rb * 16 + 4 * (l >> 4) + j;
+        st_act<BF16>(sH, row * St::H + col, acc[i][j] * dsw1[i][j]);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    floatx4 acc[TPW_G];
+    zero_acc(acc);
+    mma<BF16, TPW_G>(sH, St::H, rb, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG, acc);
+#pragma unroll
+    for (int i = 0; i < TPW_G; ++i) {
+      const int nb = cw + i * WPR;
+      if (nb >= NBG) continue;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = rb * 16 + 4 * (l >> 4) + j;
+        sGb[row * St::GB + col] = acc[i][j];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace gmnn

@@ -1,0 +1,281 @@
+// Per-pair device math shared by the pair kernels and the fused tile kernel:
+// lane exchanges, the radial basis, monomials of the unit vector, and the
+// per-atom moment accumulation / pair backward loops.
+#pragma once
+
+#include "common.h"
+#include "model.h"
+
+namespace gmnn {
+
+constexpr int kPairBlock = 256;  // threads per block of the pair kernels
+
+// --- DPP lane exchanges inside rows of 16 lanes ----------------------------
+__device__ inline float dpp_mirror(float v) {  // lane 15 - l
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xf, 0xf, false));
+}
+__device__ inline float dpp_half_mirror(float v) {  // lane 7 - l inside each half row
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xf, 0xf, false));
+}
+__device__ inline float dpp_xor2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xf, 0xf, false));
+}
+__device__ inline float dpp_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+// sum over the 16 lanes of a row (every lane gets the total)
+__device__ inline float row16_sum(float v) {
+  v += dpp_mirror(v);
+  v += dpp_half_mirror(v);
+  v += dpp_xor2(v);
+  v += dpp_xor1(v);
+  return v;
+}
+
+// one reduce-scatter step: keep half H of the live values, send the other
+template <int H, int STEP>
+__device__ inline void rs_step(float* v, int bit) {
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const float lo = v[k], hi = v[k + H];
+    const float send = bit ? lo : hi;
+    const float keep = bit ? hi : lo;
+    float got;
+    if (STEP == 0) got = dpp_mirror(send);
+    else if (STEP == 1) got = dpp_half_mirror(send);
+    else if (STEP == 2) got = dpp_xor2(send);
+    else got = dpp_xor1(send);
+    v[k] = keep + got;
+  }
+}
+
+// cross-row steps: v_permlane32_swap / v_permlane16_swap exchange the kept and
+// sent halves in one instruction; the sum of the two outputs is the
+// reduce-scatter result in every lane (lanes with the bit clear keep the low
+// half, lanes with it set the high half)
+template <int H, int ROWS>
+__device__ inline void rs_swap(float* v) {
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const unsigned a = __float_as_uint(v[k]), b = __float_as_uint(v[k + H]);
+    if (ROWS == 32) {
+      const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+      v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+      const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+      v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+  }
+}
+
+// 128 values (100 live + 28 zero) per lane, summed over the LPA lanes of an
+// atom.  LPA = 16: lane q of the row owns indices 8q..8q+7 (v[0..7]).
+// LPA = 64: lane q of the wave owns indices 2q, 2q+1 (v[0..1]).
+template <int LPA>
+__device__ inline void reduce_scatter_128(float* v, int q) {
+  if (LPA == 64) {
+    rs_swap<64, 32>(v);
+    rs_swap<32, 16>(v);
+    rs_step<16, 0>(v, (q >> 3) & 1);
+    rs_step<8, 1>(v, (q >> 2) & 1);
+    rs_step<4, 2>(v, (q >> 1) & 1);
+    rs_step<2, 3>(v, q & 1);
+  } else {
+    rs_step<64, 0>(v, (q >> 3) & 1);
+    rs_step<32, 1>(v, (q >> 2) & 1);
+    rs_step<16, 2>(v, (q >> 1) & 1);
+    rs_step<8, 3>(v, q & 1);
+  }
+}
+
+// sum over the LPA lanes of an atom (every lane gets the total)
+template <int LPA>
+__device__ inline float atom_sum(float v) {
+  v = row16_sum(v);
+  if (LPA == 64) {
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+  }
+  return v;
+}
+
+// --- radial basis ------------------------------------------------------------
+struct Radial {
+  float R[kS];    // c * f_c(r) * sum_k beta[s][k] g_k(r)
+  float dR[kS];   // d R_s / dr
+};
+
+// Gaussians g_k = exp(-gamma (r - mu_k)^2), mu_k = r_min + k delta, by the
+// recurrence g_k = g_0 a^k exp(-gamma delta^2 k^2) with a = exp(2 gamma delta tau)
+template <bool DERIV>
+__device__ inline void radial(const DevModel& m, const float* __restrict__ bz /*[S][8]*/, float r, Radial& out) {
+  const float tau = r - m.r_min;
+  const float g0 = __expf(-m.gamma * tau * tau);
+  const float a = __expf(2.0f * m.gamma * m.delta * tau);
+  float g[kMaxBasis];
+  float p = g0;
+#pragma unroll
+  for (int k = 0; k < kMaxBasis; ++k) {
+    g[k] = p * m.ck[k];  // ck[k] = exp(-gamma delta^2 k^2), zero for k >= K
+    p *= a;
+  }
+  float sn, cs;
+  sincosf(3.14159265358979f * r / m.r_cut, &sn, &cs);
+  const float fc = 0.5f * (cs + 1.0f) * m.psi_scale;
+  const float dfc = -0.5f * (3.14159265358979f / m.r_cut) * sn * m.psi_scale;
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    float B = 0.0f, dB = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxBasis; ++k) {
+      const float bk = bz[s * kMaxBasis + k];
+      B += bk * g[k];
+      if (DERIV) dB += bk * (-2.0f * m.gamma * (tau - (float)k * m.delta)) * g[k];
+    }
+    out.R[s] = fc * B;
+    if (DERIV) out.dR[s] = dfc * B + fc * dB;
+  }
+}
+
+// monomials of u in packed order: 1, x y z, xx xy xz yy yz zz, xxx ... zzz
+__device__ inline void monomials(float x, float y, float z, float* mo) {
+  mo[0] = 1.0f;
+  mo[1] = x; mo[2] = y; mo[3] = z;
+  mo[4] = x * x; mo[5] = x * y; mo[6] = x * z; mo[7] = y * y; mo[8] = y * z; mo[9] = z * z;
+  mo[10] = mo[4] * x; mo[11] = mo[4] * y; mo[12] = mo[4] * z; mo[13] = mo[7] * x; mo[14] = mo[5] * z;
+  mo[15] = mo[9] * x; mo[16] = mo[7] * y; mo[17] = mo[7] * z; mo[18] = mo[9] * y; mo[19] = mo[9] * z;
+}
+
+// stage beta[zi][zj][s][k] into LDS as [zi][zj][s][8] (K padded to 8)
+__device__ inline void stage_beta(const DevModel& m, float* s_beta) {
+  const int n = m.n_species * m.n_species * kS * kMaxBasis;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const int k = t % kMaxBasis;
+    const int rest = t / kMaxBasis;  // (zi*nsp + zj)*S + s
+    s_beta[t] = (k < m.K) ? m.beta[rest * m.K + k] : 0.0f;
+  }
+}
+
+struct AtomCtx {
+  float xi, yi, zi;
+  float h[9];
+  int zsp;
+  int64_t p0, p1;
+};
+
+__device__ inline void load_atom(const DevSystem& sys, int i, AtomCtx& c) {
+  c.xi = sys.pos[3 * (int64_t)i];
+  c.yi = sys.pos[3 * (int64_t)i + 1];
+  c.zi = sys.pos[3 * (int64_t)i + 2];
+  const int b = sys.atom_struct[i];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) c.h[k] = (float)sys.cell[9 * (int64_t)b + k];
+  c.zsp = sys.species[i];
+  c.p0 = sys.row_ptr[i];
+  c.p1 = sys.row_ptr[i + 1];
+}
+
+// d_p = x_j - x_i + S . h (FP32)
+__device__ inline void pair_vec(const DevSystem& sys, const AtomCtx& c, int64_t p, int& j, float& dx, float& dy,
+                                float& dz) {
+  j = sys.nj[p];
+  int sx, sy, sz;
+  unpack_shift(sys.nshift[p], sx, sy, sz);
+  const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
+  dx = (sys.pos[3 * (int64_t)j] - c.xi) + (fx * c.h[0] + fy * c.h[3] + fz * c.h[6]);
+  dy = (sys.pos[3 * (int64_t)j + 1] - c.yi) + (fx * c.h[1] + fy * c.h[4] + fz * c.h[7]);
+  dz = (sys.pos[3 * (int64_t)j + 2] - c.zi) + (fx * c.h[2] + fy * c.h[5] + fz * c.h[8]);
+}
+
+
+// ---------------------------------------------------------------------------
+// moment partial sums of lane q of an atom: pairs p0+q, p0+q+LPA, ...
+// v[s*20 + t] += R_s(r) mono_t(u)   (v must be zeroed by the caller)
+template <int LPA>
+__device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta, int i,
+                                    int q, float (&v)[128]) {
+  AtomCtx c;
+  load_atom(sys, i, c);
+  const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
+  for (int64_t p = c.p0 + q; p < c.p1; p += LPA) {
+    int j;
+    float dx, dy, dz;
+    pair_vec(sys, c, p, j, dx, dy, dz);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < m.rc2) || r2 == 0.0f) continue;
+    const float r = sqrtf(r2);
+    const float ir = 1.0f / r;
+    Radial rad;
+    radial<false>(m, bzi + sys.species[j] * kS * kMaxBasis, r, rad);
+    float mo[20];
+    monomials(dx * ir, dy * ir, dz * ir, mo);
+#pragma unroll
+    for (int s = 0; s < kS; ++s)
+#pragma unroll
+      for (int t = 0; t < kPacked; ++t) v[s * kPacked + t] += rad.R[s] * mo[t];
+  }
+}
+
+// dE/dd_p for every pair of lane q of atom i, given pb = dE_i/dPsi_i (packed
+// components, each an independent variable).  With P_s(u) = sum_t pb[s][t]
+// mono_t(u) and Q(u) = sum_s R_s P_s(u):
+//   g = (sum_s dR_s/dr P_s(u)) u + (grad Q - (grad Q . u) u) / r
+// Writes g_p and accumulates this lane's share of sum_p g_p (x) d_p into vir.
+template <int LPA>
+__device__ inline void atom_pair_backward(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta,
+                                          int i, int q, const float (&pb)[kS * kPacked], float* __restrict__ gpair,
+                                          float (&vir)[9]) {
+  AtomCtx c;
+  load_atom(sys, i, c);
+  const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
+  for (int64_t p = c.p0 + q; p < c.p1; p += LPA) {
+    int j;
+    float dx, dy, dz;
+    pair_vec(sys, c, p, j, dx, dy, dz);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    if (r2 < m.rc2 && r2 > 0.0f) {
+      const float r = sqrtf(r2);
+      const float ir = 1.0f / r;
+      const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+      Radial rad;
+      radial<true>(m, bzi + sys.species[j] * kS * kMaxBasis, r, rad);
+      float mo[20];
+      monomials(ux, uy, uz, mo);
+      float radial_part = 0.0f;
+      float qc[kPacked];
+#pragma unroll
+      for (int t = 0; t < kPacked; ++t) qc[t] = 0.0f;
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+        float A = 0.0f;
+#pragma unroll
+        for (int t = 0; t < kPacked; ++t) {
+          A += pb[s * kPacked + t] * mo[t];
+          qc[t] += rad.R[s] * pb[s * kPacked + t];
+        }
+        radial_part += A * rad.dR[s];
+      }
+      const float x = ux, y = uy, z = uz;
+      const float Gx = qc[1] + 2.0f * qc[4] * x + qc[5] * y + qc[6] * z + 3.0f * qc[10] * x * x +
+                       2.0f * qc[11] * x * y + 2.0f * qc[12] * x * z + qc[13] * y * y + qc[14] * y * z +
+                       qc[15] * z * z;
+      const float Gy = qc[2] + qc[5] * x + 2.0f * qc[7] * y + qc[8] * z + qc[11] * x * x + 2.0f * qc[13] * x * y +
+                       qc[14] * x * z + 3.0f * qc[16] * y * y + 2.0f * qc[17] * y * z + qc[18] * z * z;
+      const float Gz = qc[3] + qc[6] * x + qc[8] * y + 2.0f * qc[9] * z + qc[12] * x * x + qc[14] * x * y +
+                       2.0f * qc[15] * x * z + qc[17] * y * y + 2.0f * qc[18] * y * z + 3.0f * qc[19] * z * z;
+      const float gu = Gx * x + Gy * y + Gz * z;
+      gx = radial_part * x + (Gx - gu * x) * ir;
+      gy = radial_part * y + (Gy - gu * y) * ir;
+      gz = radial_part * z + (Gz - gu * z) * ir;
+      vir[0] += gx * dx; vir[1] += gx * dy; vir[2] += gx * dz;
+      vir[3] += gy * dx; vir[4] += gy * dy; vir[5] += gy * dz;
+      vir[6] += gz * dx; vir[7] += gz * dy; vir[8] += gz * dz;
+    }
+    gpair[3 * p] = gx;
+    gpair[3 * p + 1] = gy;
+    gpair[3 * p + 2] = gz;
+  }
+}
+
+}  // namespace gmnn

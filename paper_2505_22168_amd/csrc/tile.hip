@@ -1,0 +1,263 @@
+// Tile kernels of the GMNN energy/force path (gfx950, wave64, MFMA).
+//
+// One block of 512 threads (8 waves) owns a tile of TM = 16 atoms and keeps
+// everything of the tile in LDS:
+//   [FUSED only] pair moments of its atoms (Section 2.1, eq. basis_fn), one
+//                wave per atom
+//   invariants  (Section 2.1, eq. contraction): families 1-4 and the
+//               intermediates T7, V8, M5, v6 in one pass, families 5-8 in a
+//               second pass
+//   network     (Section 2.1, eq. scale_shift) forward and the backward of
+//               the head-mean energy (Section 2.2, eq. jacobian) on MFMA
+//   invariants backward: intermediates U8, Y, Qv, then every entry of
+//               dE/dPsi in one pass, folded onto the packed components
+//   [FUSED only] pair backward of its atoms (Section 3.3): per-pair
+//               gradients and the per-atom virial, one wave per atom
+// The fused kernel serves small systems, where the whole step is latency
+// bound and one launch per stage would dominate; the unfused readout serves
+// large systems between the high-occupancy pair kernels.
+#include "common.h"
+#include "contraction.h"
+#include "mfma.h"
+#include "model.h"
+#include "pair_math.h"
+
+namespace gmnn {
+
+constexpr int kTileThreads = 512;
+constexpr int kTileWaves = kTileThreads / 64;
+constexpr int kTM = 16;
+constexpr int kFusedMaxSpecies = 8;
+
+template <int HP, bool BF16, bool FUSED, bool PERHEAD>
+struct TileLds {
+  using St = NetStrides<HP, BF16>;
+  static constexpr int TM = kTM;
+  static constexpr int ESZ = BF16 ? 2 : 4;
+  static constexpr size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+  static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
+  static constexpr size_t tables = 0;
+  static constexpr size_t psi = al(sizeof(Tables));
+  static constexpr size_t inter = psi + al(4 * (size_t)TM * PS);
+  static constexpr size_t regb = inter + al(4 * (size_t)TM * IS);
+  static constexpr size_t regb_bytes =
+      mx(mx((size_t)ESZ * TM * St::G, (size_t)ESZ * TM * St::H), 4 * (size_t)TM * St::GB);
+  static constexpr size_t regc = regb + al(regb_bytes);
+  static constexpr size_t regc_bytes = mx((size_t)ESZ * TM * St::H, 4 * (size_t)TM * PS);
+  static constexpr size_t ep = regc + al(regc_bytes);
+  static constexpr size_t rowsc = ep + al(4 * (size_t)kTileWaves * 16 * kMaxHeads);
+  static constexpr size_t vir = rowsc + al(4 * 2 * (size_t)TM);
+  static constexpr size_t psibar = vir + al(4 * 9 * (size_t)TM);
+  static constexpr size_t dsw2 = psibar + (FUSED ? al(4 * (size_t)TM * kS * kPacked) : 0);
+  static constexpr size_t beta = dsw2 + (PERHEAD ? al(4 * (size_t)TM * (HP + 1)) : 0);
+  static constexpr size_t bytes =
+      beta + (FUSED ? al(4 * (size_t)kFusedMaxSpecies * kFusedMaxSpecies * kS * kMaxBasis) : 0);
+};
+
+// psibar_out: [nh][N][100] (unfused); gpair: [nh][gstride][3] (fused);
+// nh = n_heads with PERHEAD (one backward per head), else 1 (head mean)
+template <int HP, bool BF16, bool FUSED, bool PERHEAD>
+__global__ void __launch_bounds__(kTileThreads)
+    tile_kernel(DevModel m, DevSystem sys, const float* __restrict__ psi_in, float* __restrict__ atomic_e,
+                float* __restrict__ psibar_out, float* __restrict__ gpair, float* __restrict__ virial,
+                int64_t gstride) {
+  using L = TileLds<HP, BF16, FUSED, PERHEAD>;
+  using Sh = NetShape<kTM, HP, kTileWaves>;
+  constexpr int TM = kTM;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  Tables& tb = *(Tables*)(lds + L::tables);
+  float* sPsi = (float*)(lds + L::psi);
+  float* sI = (float*)(lds + L::inter);
+  void* sG = (void*)(lds + L::regb);
+  void* sD2 = (void*)(lds + L::regb);
+  float* sGb = (float*)(lds + L::regb);
+  void* sH = (void*)(lds + L::regc);
+  float* sPb = (float*)(lds + L::regc);
+  float* sEp = (float*)(lds + L::ep);
+  float* sScale = (float*)(lds + L::rowsc);
+  float* sShift = sScale + TM;
+  float* sVir = (float*)(lds + L::vir);
+  float* sPsibar = (float*)(lds + L::psibar);
+  float* sDsw2 = (float*)(lds + L::dsw2);
+  float* s_beta = (float*)(lds + L::beta);
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int row0 = blockIdx.x * TM;
+  const int n_rows = min(TM, sys.n_atoms - row0);
+  const int nh = PERHEAD ? m.M : 1;
+
+  load_tables(&tb);
+  for (int a = tid; a < TM; a += kTileThreads) {
+    float sc = 0.0f, sh = 0.0f;
+    if (a < n_rows) {
+      const int z = sys.species[row0 + a];
+      sc = m.scale[z];
+      sh = m.shift[z];
+    }
+    sScale[a] = sc;
+    sShift[a] = sh;
+  }
+  for (int t = tid; t < TM * 9; t += kTileThreads) sVir[t] = 0.0f;
+  if (FUSED) stage_beta(m, s_beta);
+  __syncthreads();
+
+  // ---- moments -> full tensors in LDS ------------------------------------
+  if (FUSED) {
+    for (int a = w; a < TM; a += kTileWaves) {
+      float v[128];
+#pragma unroll
+      for (int k = 0; k < 128; ++k) v[k] = 0.0f;
+      if (a < n_rows) atom_moments<64>(m, sys, s_beta, row0 + a, l, v);
+      reduce_scatter_128<64>(v, l);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int k = 2 * l + e;
+        if (k < kS * kPacked) {
+          const int s = k / kPacked, t = k % kPacked;
+          const int n = tb.packed_mult[t];
+          for (int q = 0; q < n; ++q) sPsi[a * PS + s * kFull + tb.packed_full[t][q]] = v[e];
+        }
+      }
+    }
+  } else {
+    for (int t = tid; t < TM * kS * kFull; t += kTileThreads) {
+      const int a = t % TM, e = t / TM;
+      const int s = e / kFull, r = e % kFull;
+      float v = 0.0f;
+      if (a < n_rows) v = psi_in[(int64_t)(row0 + a) * (kS * kPacked) + s * kPacked + tb.full_to_packed[r]];
+      sPsi[a * PS + e] = v;
+    }
+  }
+  __syncthreads();
+
+  // ---- invariants ------------------------------------------------------------
+  contract_forward_a<TM, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  __syncthreads();
+  contract_forward_b<TM, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  __syncthreads();
+
+  // ---- network forward ---------------------------------------------------------
+  floatx4 dsw1[Sh::TPW];
+  network_forward<TM, HP, BF16, kTileWaves, !PERHEAD>(m, sG, sH, sD2, sDsw2, sEp, sScale, sShift, row0, n_rows,
+                                                       atomic_e, dsw1);
+  constexpr int LDGB = NetStrides<HP, BF16>::GB;
+  for (int hm = 0; hm < nh; ++hm) {
+    // ---- network backward (head mean, or head hm) ------------------------------
+    if (PERHEAD) {
+      network_delta2_head<TM, HP, BF16, kTileWaves>(m, sDsw2, sScale, sD2, hm);
+      __syncthreads();
+    }
+    network_backward<TM, HP, BF16, kTileWaves>(m, sD2, sH, sGb, dsw1);
+    // ---- invariants backward ---------------------------------------------------
+    contract_backward_a<TM, kTileThreads>(sPsi, sGb, LDGB, sI, tb);
+    __syncthreads();
+    contract_backward_b<TM, kTileThreads>(sPsi, sGb, LDGB, sI, sPb, tb);
+    __syncthreads();
+    if (FUSED) {
+      fold_packed<TM, kTileThreads>(sPb, tb, [&](int a, int e, float v) { sPsibar[a * (kS * kPacked) + e] = v; });
+      __syncthreads();
+      // ---- pair backward -----------------------------------------------------
+      float* g_head = gpair + (int64_t)hm * gstride * 3;
+      for (int a = w; a < TM; a += kTileWaves) {
+        float vir[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) vir[k] = 0.0f;
+        if (a < n_rows) {
+          float pb[kS * kPacked];
+#pragma unroll
+          for (int k = 0; k < kS * kPacked; ++k) pb[k] = sPsibar[a * (kS * kPacked) + k];
+          atom_pair_backward<64>(m, sys, s_beta, row0 + a, l, pb, g_head, vir);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) vir[k] = atom_sum<64>(vir[k]);
+        if (l < 9) {
+          float vk = vir[0];
+#pragma unroll
+          for (int k = 1; k < 9; ++k)
+            if (l == k) vk = vir[k];
+          sVir[a * 9 + l] += vk;
+        }
+      }
+      __syncthreads();
+    } else {
+      float* pbo = psibar_out + (int64_t)hm * sys.n_atoms * (kS * kPacked);
+      fold_packed<TM, kTileThreads>(sPb, tb, [&](int a, int e, float v) {
+        if (a < n_rows) pbo[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+      });
+      __syncthreads();
+    }
+  }
+  if (FUSED) {
+    const float inv = 1.0f / (float)nh;
+    for (int t = tid; t < n_rows * 9; t += kTileThreads) virial[(int64_t)row0 * 9 + t] = sVir[t] * inv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int HP, bool BF16, bool FUSED, bool PERHEAD>
+static gmnn_status launch_tile_t(const DevModel& m, const DevSystem& sys, const float* psi, float* atomic_e,
+                                 float* psibar, float* gpair, float* virial, int64_t gstride, hipStream_t stream) {
+  using L = TileLds<HP, BF16, FUSED, PERHEAD>;
+  if (L::bytes > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
+  auto k = tile_kernel<HP, BF16, FUSED, PERHEAD>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes) != hipSuccess)
+      return GMNN_ERR_HIP;
+    attr_set = true;
+  }
+  const int grid = (sys.n_atoms + kTM - 1) / kTM;
+  if (grid == 0) return GMNN_OK;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kTileThreads), L::bytes, stream, m, sys, psi, atomic_e, psibar, gpair,
+                     virial, gstride);
+  return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
+}
+
+size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead) {
+#define SZ(HP) \
+  if (hp == HP) { \
+    if (fused && perhead) return ~size_t(0); \
+    if (bf16) return fused ? TileLds<HP, true, true, false>::bytes \
+                           : (perhead ? TileLds<HP, true, false, true>::bytes : TileLds<HP, true, false, false>::bytes); \
+    return fused ? TileLds<HP, false, true, false>::bytes \
+                 : (perhead ? TileLds<HP, false, false, true>::bytes : TileLds<HP, false, false, false>::bytes); \
+  }
+  SZ(64) SZ(128) SZ(256) SZ(512)
+#undef SZ
+  return ~size_t(0);
+}
+
+// the fused kernel serves the head-mean backward only: with one backward per
+// head the tile would have to keep swish'(z1) for every head's product live
+// across the pair stage, beyond the register file
+bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead) {
+  return !perhead && n_species <= kFusedMaxSpecies && tile_lds_bytes(hp, bf16, true, false) <= 160 * 1024;
+}
+
+// fused: moments + readout + pair backward in one launch (gpair, virial out);
+// otherwise the readout alone (psi in, psibar out)
+gmnn_status launch_tile(bool fused, bool perhead, const DevModel& m, const DevSystem& sys, bool bf16,
+                        const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
+                        int64_t gstride, hipStream_t stream) {
+  if (fused && !tile_fused_supported(m.n_species, m.HP1, bf16, perhead)) return GMNN_ERR_UNSUPPORTED;
+#define CASE4(HP, BF, FU)                                                                                          \
+  return perhead ? launch_tile_t<HP, BF, FU, true>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream)  \
+                 : launch_tile_t<HP, BF, FU, false>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream);
+#define CASE(HP)                                                                                        \
+  if (m.HP1 == HP) {                                                                                    \
+    if (fused) {                                                                                        \
+      if (perhead) return GMNN_ERR_UNSUPPORTED;                                                         \
+      return bf16 ? launch_tile_t<HP, true, true, false>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream) \
+                  : launch_tile_t<HP, false, true, false>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream); \
+    }                                                                                                   \
+    if (bf16) { CASE4(HP, true, false) }                                                                \
+    CASE4(HP, false, false)                                                                             \
+  }
+  CASE(64) CASE(128) CASE(256) CASE(512)
+#undef CASE
+#undef CASE4
+  return GMNN_ERR_UNSUPPORTED;
+}
+
+}  // namespace gmnn

@@ -126,3 +126,69 @@ def test_net_force_and_lattice_translation():
     out2 = _run(g, b2, params, 5.0, "fp32")
     assert abs(_np(out2.energy) - _np(out.energy)).max() / batch.n_atoms < 1e-5
     assert np.abs(_np(out2.forces) - _np(out.forces)).max() < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_force_variance_over_heads(precision):
+    """Shallow ensemble (Section 2.2): per-head forces in one launch per stage,
+    their mean (the force of the mean energy) and the per-atom variance."""
+    g = need_gpu()
+    batch, params, spec = make_workload("ensemble", n_structs=4)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, 5.0)
+    model = g.Model.from_params(params, "cuda")
+    out = g.energy_forces(model, system, nl, precision=precision, stress=True, force_var=True)
+    torch.cuda.synchronize()
+    onl = brute_force_neighbors(batch, 5.0)
+    ref = evaluate(batch, params, onl, bf16=(precision == "bf16"), want_force_var=True)
+    F = _np(out.forces)[: batch.n_atoms]
+    V = _np(out.force_var)[: batch.n_atoms]
+    if precision == "fp32":
+        assert np.abs(F - ref.forces).max() < 1e-4
+        assert np.allclose(V, ref.force_var, rtol=1e-3, atol=1e-5)
+        assert np.abs(_np(out.stress) - ref.stress).max() < 1e-6
+    else:
+        # scale of the per-head forces: E|F^m|^2 = |Fbar|^2 + var per atom
+        rms = np.sqrt(((ref.forces ** 2).sum(1) + ref.force_var).mean() / 3)
+        assert np.sqrt(((F - ref.forces) ** 2).mean()) < 2e-3 * rms
+        assert np.sqrt(((V - ref.force_var) ** 2).mean()) < 1e-2 * np.sqrt((ref.force_var ** 2).mean())
+    # the head-mean path gives the same mean force
+    mean_only = g.energy_forces(model, system, nl, precision=precision, stress=True)
+    torch.cuda.synchronize()
+    assert np.abs(_np(mean_only.forces)[: batch.n_atoms] - F).max() < (1e-5 if precision == "fp32" else 2e-2)
+
+
+def _oracle_force_on(batch, params, k, rc):
+    """-dE/dx_k from the rows that can see atom k (k and its neighbours): only
+    those atomic energies depend on x_k, so the oracle needs just their rows."""
+    from oracle.gmnn import atomic_energies
+    row_k = brute_force_neighbors(batch, rc, rows=[k])
+    rows = np.unique(np.concatenate([[k], row_k.j]))
+    sub = brute_force_neighbors(batch, rc, rows=rows)
+    pos = torch.as_tensor(batch.pos.astype(np.float64)).requires_grad_(True)
+    E = atomic_energies(batch, params, sub, pos=pos)
+    Esub = E[torch.as_tensor(rows)].mean(1).sum()
+    (gp,) = torch.autograd.grad(Esub, pos)
+    return -gp[k].numpy(), E.detach().numpy()[rows], rows
+
+
+def test_large_structure_chunked_reduction_and_sampled_parity():
+    """An 8712-atom lattice takes the unfused high-occupancy path and the
+    chunked per-structure reduction; atomic energies and forces of sampled
+    atoms are checked against the oracle one by one."""
+    g = need_gpu()
+    batch, params, spec = make_workload("solid", reps=(22, 22, 18))
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, 6.0, 1.0)
+    model = g.Model.from_params(params, "cuda")
+    out = g.energy_forces(model, system, nl, precision="fp32", stress=True)
+    torch.cuda.synchronize()
+    Ei = _np(out.atomic_energy)[: batch.n_atoms, 0].astype(np.float64)
+    assert abs(_np(out.energy)[0, 0] - Ei.sum()) < 1e-9 * abs(Ei.sum())
+    F = _np(out.forces)[: batch.n_atoms]
+    assert np.abs(F.astype(np.float64).sum(0)).max() < 2e-3
+    rng = np.random.default_rng(5)
+    for k in rng.choice(batch.n_atoms, 4, replace=False):
+        fk, e_rows, rows = _oracle_force_on(batch, params, int(k), 6.0)
+        assert np.abs(F[k] - fk).max() < 1e-4
+        assert np.abs(Ei[rows] - e_rows[:, 0]).max() < 1e-4
