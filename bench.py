@@ -160,6 +160,50 @@ def cpu_baseline(batch, params, nl_ref, budget_s):
                       f"{batch.n_atoms}-atom workload, {el:.1f} s"}
 
 
+def run_md(args):
+    """NVE velocity-Verlet MD of the workload (skin list, HIP graph of
+    --graph-steps steps replayed); reports atom-steps/s of whole MD steps
+    including list rebuilds, as MD step time is quoted per atom and step."""
+    import torch
+    import paper_2505_22168_amd as g
+    from workloads import make_workload
+    masses_by_species = {0: 6.94, 1: 30.974, 2: 15.999, 3: 12.011, 4: 1.008}
+    batch, params, spec = make_workload(args.workload)
+    masses = np.array([masses_by_species[int(z) % 5] for z in batch.species])
+    v0 = g.maxwell_boltzmann(masses, 600.0, seed=3)
+    system = g.System.from_batch(batch, "cuda")
+    model = g.Model.from_params(params, "cuda")
+    skin = spec.skin if spec.skin > 0 else 1.0
+    out = {}
+    for prec in ("bf16", "fp32"):
+        system.pos.copy_(torch.as_tensor(batch.pos, device="cuda"))
+        md = g.MD(model, system, masses, dt=0.5, skin=skin, velocities=v0, precision=prec)
+        e0 = float(md.energy.sum().item()) + md.kinetic_energy(masses)
+        gs = args.graph_steps
+        md.capture(gs)
+        md.run(1)  # warm-up replay
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // gs)
+        t0 = time.perf_counter()
+        md.run(reps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e1 = float(md.energy.sum().item()) + md.kinetic_energy(masses)
+        nsteps = reps * gs
+        out[prec] = {"value": batch.n_atoms * nsteps / wall, "ms_per_step": wall / nsteps * 1e3,
+                     "us_per_atom_step": wall / nsteps / batch.n_atoms * 1e6, "steps": nsteps + gs,
+                     "status": md.status(), "total_energy_drift_eV_per_atom": (e1 - e0) / batch.n_atoms,
+                     "finite": bool(torch.isfinite(system.pos).all().item())}
+        print(f"[bench-md] {prec}: {out[prec]}", file=sys.stderr, flush=True)
+        md.release()
+    line = {"metric": "MD atom-steps/s (NVE velocity Verlet, HIP graph, skin list)", "value": out["bf16"]["value"],
+            "unit": "atom-steps/s", "n_gpus": 1, "steps": out["bf16"]["steps"], "dtype": "bf16",
+            "config": {"workload": args.workload, "n_atoms": batch.n_atoms, "dt_fs": 0.5, "skin": skin,
+                       "graph_steps": args.graph_steps, "mlp": list(spec.model.hidden)},
+            "bf16": out["bf16"], "fp32": out["fp32"]}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,12 +212,16 @@ def main():
     ap.add_argument("--workload", default="liquid")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-oracle", action="store_true", help="skip oracle errors and the CPU baseline")
+    ap.add_argument("--md", action="store_true", help="time whole MD steps instead (not the headline metric)")
+    ap.add_argument("--graph-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
+    if args.md:
+        return run_md(args)
     import torch
     import paper_2505_22168_amd as g
     from paper_2505_22168_amd import _capi as A

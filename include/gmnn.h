@@ -244,6 +244,54 @@ gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmn
                           gmnn_param_grads* grads, float* dL_dpos,
                           void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Molecular dynamics on the device (Section 3.5: the whole simulation loop
+ * runs on the GPU; the neighbour list carries a skin).  NVE velocity Verlet:
+ *   v += dt/2 k_u F/m;  x += dt v;  rebuild the list if some atom moved more
+ *   than skin/2 since the last build (decided on the device);  F = forces(x);
+ *   v += dt/2 k_u F/m,     k_u = 9.648533e-3 A/fs^2 per eV/(A amu).
+ * The steps write the positions sys->pos in place.  All arrays device. */
+typedef struct gmnn_md {
+  float dt;               /* time step, fs */
+  float skin;             /* list skin, A (the list cutoff is r_cut + skin) */
+  const float* inv_mass;  /* [N] 1/mass, 1/amu */
+  float* vel;             /* [N,3] velocities, A/fs (updated) */
+  float* forces;          /* [N,3] forces at the current positions, eV/A (updated) */
+  double* energy;         /* [B, n_heads] potential energies at the current positions */
+  float* ref_pos;         /* [N,3] positions at the last list build */
+  uint32_t* disp;         /* [1] largest squared displacement of the step (scratch word) */
+} gmnn_md;
+
+/* Workspace of gmnn_md_init / _steps / _graph_create (list build and
+ * energy/forces); nl->cutoff must already hold r_cut + skin.  flags: the
+ * precision bit only.  Returns 0 on invalid arguments. */
+size_t gmnn_md_workspace_bytes(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                               uint32_t flags);
+
+/* Build the list (recording ref_pos), compute forces and energies at the
+ * current positions, clear md->disp.  Call before the first step and before
+ * capturing a graph. */
+gmnn_status gmnn_md_init(const gmnn_model* m, const gmnn_system* sys, gmnn_neighbors* nl, const gmnn_md* md,
+                         uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
+/* n_steps steps enqueued on `stream` (no host synchronisation).  A list that
+ * outgrows nl->capacity during a rebuild raises GMNN_FLAG_CAPACITY in
+ * nl->status and is left empty; the caller checks the status between calls,
+ * re-sizes and restarts from saved state. */
+gmnn_status gmnn_md_steps(const gmnn_model* m, const gmnn_system* sys, gmnn_neighbors* nl, const gmnn_md* md,
+                          uint32_t flags, int32_t n_steps, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
+/* Capture n_steps steps into a HIP graph (on an internal stream; every
+ * pointer of the arguments is baked in); replay with gmnn_md_graph_launch on
+ * any stream; release with gmnn_md_graph_destroy.  The graph handle is host
+ * memory owned by the caller. */
+gmnn_status gmnn_md_graph_create(const gmnn_model* m, const gmnn_system* sys, gmnn_neighbors* nl,
+                                 const gmnn_md* md, uint32_t flags, int32_t n_steps, void* workspace,
+                                 size_t workspace_bytes, void** graph_out);
+gmnn_status gmnn_md_graph_launch(void* graph, void* stream);
+void gmnn_md_graph_destroy(void* graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,11 @@ class gmnn_param_grads(C.Structure):
     _fields_ = [(k, vp) for k in ("beta", "W1", "b1", "W2", "b2", "W3", "b3", "scale", "shift")]
 
 
+class gmnn_md(C.Structure):
+    _fields_ = [("dt", C.c_float), ("skin", C.c_float), ("inv_mass", vp), ("vel", vp), ("forces", vp),
+                ("energy", vp), ("ref_pos", vp), ("disp", vp)]
+
+
 class gmnn_outputs(C.Structure):
     _fields_ = [("energy", vp), ("forces", vp), ("stress", vp), ("energy_var", vp),
                 ("force_var", vp), ("atomic_energy", vp)]
@@ -81,6 +86,17 @@ EXPORTS = {
                                              C.c_size_t, vp, vp]),
     "gmnn_backward": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
                                   vp, vp, C.c_uint32, C.POINTER(gmnn_param_grads), vp, vp, C.c_size_t, vp]),
+    "gmnn_md_workspace_bytes": (C.c_size_t, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
+                                             C.POINTER(gmnn_neighbors), C.c_uint32]),
+    "gmnn_md_init": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
+                                 C.POINTER(gmnn_md), C.c_uint32, vp, C.c_size_t, vp]),
+    "gmnn_md_steps": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
+                                  C.POINTER(gmnn_md), C.c_uint32, C.c_int32, vp, C.c_size_t, vp]),
+    "gmnn_md_graph_create": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
+                                         C.POINTER(gmnn_md), C.c_uint32, C.c_int32, vp, C.c_size_t,
+                                         C.POINTER(C.c_void_p)]),
+    "gmnn_md_graph_launch": (C.c_int32, [vp, vp]),
+    "gmnn_md_graph_destroy": (None, [vp]),
 }
 
 _lib = None

@@ -241,3 +241,93 @@ def energy_forces(model: Model, system: System, nl: NeighborList, precision: str
                   force_var: bool = False) -> Outputs:
     """One evaluation (allocates its outputs and workspace)."""
     return EnergyForces(model, system, nl, precision, stress, force_var)(sync=False)
+
+
+# ---------------------------------------------------------------------------
+KB_EV_PER_K = 8.617333262e-5
+ACCEL_UNIT = 9.648533e-3          # (eV/A)/amu -> A/fs^2
+
+
+class MD:
+    """NVE velocity-Verlet MD on the device (gmnn_md_*), with the steps
+    replayed from a HIP graph.  Positions in `system.pos` are updated in place."""
+
+    def __init__(self, model: Model, system: System, masses, dt: float, skin: float, velocities=None,
+                 precision: str = "fp32", capacity: int | None = None):
+        lib = A.load()
+        dev = system.device
+        N, B, M = system.n_atoms, system.n_structs, model.spec.n_heads
+        self.model, self.system, self.lib = model, system, lib
+        self.flags = A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32
+        cap = capacity if capacity is not None else int(estimate_capacity(system, model.spec.r_cut, skin) * 1.3)
+        self.nl = NeighborList(N, cap, dev)
+        self.nl.cutoff = float(np.float32(model.spec.r_cut) + np.float32(skin))
+        self.inv_mass = (1.0 / torch.as_tensor(np.asarray(masses, dtype=np.float64))).to(torch.float32).to(dev)
+        self.vel = torch.zeros((max(N, 1), 3), dtype=torch.float32, device=dev)
+        if velocities is not None:
+            self.vel[:N] = torch.as_tensor(np.asarray(velocities, dtype=np.float32)).to(dev)
+        self.forces = torch.zeros((max(N, 1), 3), dtype=torch.float32, device=dev)
+        self.energy = torch.zeros((B, M), dtype=torch.float64, device=dev)
+        self.ref_pos = torch.zeros((max(N, 1), 3), dtype=torch.float32, device=dev)
+        self.disp = torch.zeros(1, dtype=torch.int32, device=dev)
+        self._md = A.gmnn_md(dt, skin, _ptr(self.inv_mass), _ptr(self.vel), _ptr(self.forces), _ptr(self.energy),
+                             _ptr(self.ref_pos), _ptr(self.disp))
+        self._mc, self._sc, self._nc = model.c(), system.c(), self.nl.c()
+        nbytes = lib.gmnn_md_workspace_bytes(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), self.flags)
+        if nbytes == 0:
+            raise A.GMNNError(A.GMNN_ERR_INVALID_ARG, "gmnn_md_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.ws_bytes = nbytes
+        self.graph = None
+        self.graph_steps = 0
+        A.check(lib.gmnn_md_init(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), C.byref(self._md),
+                                 self.flags, _ptr(self.workspace), nbytes, _stream()), "gmnn_md_init")
+
+    def steps(self, n: int):
+        """n steps launched eagerly (one C call, no host synchronisation)."""
+        A.check(self.lib.gmnn_md_steps(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), C.byref(self._md),
+                                       self.flags, n, _ptr(self.workspace), self.ws_bytes, _stream()),
+                "gmnn_md_steps")
+
+    def capture(self, n: int):
+        """Capture n steps into a HIP graph (replayed by run())."""
+        self.release()
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        A.check(self.lib.gmnn_md_graph_create(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc),
+                                              C.byref(self._md), self.flags, n, _ptr(self.workspace), self.ws_bytes,
+                                              C.byref(h)), "gmnn_md_graph_create")
+        self.graph, self.graph_steps = h, n
+
+    def run(self, replays: int = 1):
+        for _ in range(replays):
+            A.check(self.lib.gmnn_md_graph_launch(self.graph, _stream()), "gmnn_md_graph_launch")
+
+    def release(self):
+        if self.graph is not None:
+            self.lib.gmnn_md_graph_destroy(self.graph)
+            self.graph = None
+
+    def status(self) -> int:
+        return self.nl.status
+
+    def kinetic_energy(self, masses) -> float:
+        """FP64 kinetic energy in eV (diagnostic, computed on the host)."""
+        v = self.vel[: self.system.n_atoms].double().cpu().numpy()
+        return float(0.5 * (np.asarray(masses)[:, None] * v * v).sum() / ACCEL_UNIT)
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def maxwell_boltzmann(masses, temperature: float, seed: int):
+    """Velocities (A/fs) at `temperature` (K) with zero total momentum."""
+    rng = np.random.default_rng(seed)
+    m = np.asarray(masses, dtype=np.float64)
+    sig = np.sqrt(KB_EV_PER_K * temperature * ACCEL_UNIT / m)
+    v = rng.normal(size=(len(m), 3)) * sig[:, None]
+    v -= (m[:, None] * v).sum(0) / m.sum()
+    return v.astype(np.float32)

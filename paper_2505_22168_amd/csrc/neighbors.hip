@@ -58,19 +58,28 @@ __device__ inline void grid_of_structure(const double* h, const uint8_t* pbc, do
   g.n_cells = (int)cells;
 }
 
+// disp_bits (optional): the largest squared displacement since the last
+// build (float bits); the build runs only if it exceeds thresh2 (the go flag
+// every later kernel of the build checks)
 __global__ void __launch_bounds__(1024) nl_setup(const double* __restrict__ cell, const uint8_t* __restrict__ pbc,
                                                  int n_structs, double rbin, StructGrid* __restrict__ grids,
                                                  int64_t cell_capacity, int32_t* __restrict__ cell_count,
                                                  int32_t* __restrict__ cell_fill, int64_t* __restrict__ n_cells_total,
-                                                 uint32_t* __restrict__ status) {
+                                                 uint32_t* __restrict__ status, const uint32_t* __restrict__ disp_bits,
+                                                 float thresh2, int* __restrict__ go) {
   __shared__ int64_t run;
   __shared__ int64_t part[1024];
+  __shared__ int s_go;
   const int t = threadIdx.x;
   if (t == 0) {
+    const int g = disp_bits ? (__uint_as_float(*disp_bits) > thresh2 ? 1 : 0) : 1;
+    *go = g;
+    s_go = g;
     run = 0;
-    *status = 0u;
+    if (g) *status = 0u;
   }
   __syncthreads();
+  if (!s_go) return;
   for (int b0 = 0; b0 < n_structs; b0 += 1024) {
     const int b = b0 + t;
     StructGrid g;
@@ -119,9 +128,16 @@ __device__ inline int find_struct(const int64_t* __restrict__ atom_ptr, int n_st
 __global__ void nl_bin(const float* __restrict__ pos, const int64_t* __restrict__ atom_ptr, int n_structs,
                        int n_atoms, const StructGrid* __restrict__ grids, const int64_t* __restrict__ n_cells_total,
                        int64_t cell_capacity, int32_t* __restrict__ atom_struct, int32_t* __restrict__ atom_cell,
-                       int4* __restrict__ atom_img, int32_t* __restrict__ cell_count, uint32_t* __restrict__ status) {
+                       int4* __restrict__ atom_img, int32_t* __restrict__ cell_count, uint32_t* __restrict__ status,
+                       const int* __restrict__ go, float* __restrict__ ref_pos) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_atoms) return;
+  if (!*go) return;
+  if (ref_pos) {
+    ref_pos[3 * (int64_t)i] = pos[3 * (int64_t)i];
+    ref_pos[3 * (int64_t)i + 1] = pos[3 * (int64_t)i + 1];
+    ref_pos[3 * (int64_t)i + 2] = pos[3 * (int64_t)i + 2];
+  }
   if (*n_cells_total > cell_capacity) return;
   const int b = find_struct(atom_ptr, n_structs, i);
   atom_struct[i] = b;
@@ -158,18 +174,29 @@ __global__ void nl_bin(const float* __restrict__ pos, const int64_t* __restrict_
 
 __global__ void __launch_bounds__(1024) scan_i32(const int32_t* __restrict__ in, int64_t* __restrict__ out,
                                                  const int64_t* __restrict__ n_dev, int64_t n_host,
-                                                 int64_t* __restrict__ total) {
+                                                 int64_t* __restrict__ total, const int* __restrict__ go,
+                                                 int64_t cap) {
+  if (!*go) return;
   // n_dev (if given) is clamped to n_host, the length of `in`
   int64_t n = n_host;
   if (n_dev && *n_dev < n_host) n = *n_dev;
   block_exclusive_scan<1024>(in, out, n, total);
+  // cap >= 0: offsets beyond the pair capacity would send the pair kernels
+  // past the list arrays, so an overflowing list is left empty (the total
+  // still reports the size needed, and the capacity flag is raised later)
+  if (cap >= 0) {
+    __syncthreads();
+    if (out[n] > cap)
+      for (int64_t k = threadIdx.x; k <= n; k += 1024) out[k] = 0;
+  }
 }
 
 __global__ void nl_cellfill(int n_atoms, const int32_t* __restrict__ atom_cell, const int64_t* __restrict__ cell_start,
                             const int64_t* __restrict__ n_cells_total, int64_t cell_capacity,
-                            int32_t* __restrict__ cell_fill, int32_t* __restrict__ cell_atoms) {
+                            int32_t* __restrict__ cell_fill, int32_t* __restrict__ cell_atoms, const int* __restrict__ go) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_atoms) return;
+  if (!*go) return;
   if (*n_cells_total > cell_capacity) return;
   const int c = atom_cell[i];
   const int slot = atomicAdd(&cell_fill[c], 1);
@@ -203,7 +230,8 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_rows(
     const int64_t* __restrict__ cell_start, const int32_t* __restrict__ cell_atoms,
     const int64_t* __restrict__ n_cells_total, int64_t cell_capacity, double rc2,
     int32_t* __restrict__ row_count, const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ n_pairs,
-    int64_t capacity, int32_t* __restrict__ out_j, int32_t* __restrict__ out_shift, uint32_t* __restrict__ status) {
+    int64_t capacity, int32_t* __restrict__ out_j, int32_t* __restrict__ out_shift, uint32_t* __restrict__ status,
+    const int* __restrict__ go) {
   __shared__ int s_excl[kRowsWaves][64];
   __shared__ int s_start[kRowsWaves][64];
   __shared__ int s_sw[kRowsWaves][64];
@@ -212,6 +240,7 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_rows(
   const int l = threadIdx.x & 63;
   const int i = blockIdx.x * kRowsWaves + w;
   if (i >= n_atoms) return;
+  if (!*go) return;
   if (*n_cells_total > cell_capacity) return;
   if (MODE == 1 && *n_pairs > capacity) {
     if (i == 0 && l == 0) raise_flag(status, GMNN_FLAG_CAPACITY);
@@ -347,11 +376,13 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_reverse(int n_atoms, const
                                                              const int32_t* __restrict__ nj,
                                                              const int32_t* __restrict__ nshift,
                                                              const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                             int32_t* __restrict__ rev, uint32_t* __restrict__ status) {
+                                                             int32_t* __restrict__ rev, uint32_t* __restrict__ status,
+                                                             const int* __restrict__ go) {
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int i = blockIdx.x * kRowsWaves + w;
   if (i >= n_atoms) return;
+  if (!*go) return;
   if (*n_pairs > capacity) return;
   const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
   for (int64_t p = p0 + l; p < p1; p += 64) {
@@ -426,12 +457,13 @@ NlLayout nl_layout(const gmnn_system* sys, double rbin) {
   L.off_atom_img = take(16 * (size_t)N);
   L.off_cell_atoms = take(4 * (size_t)N);
   L.off_row_count = take(4 * (size_t)N + 4);
+  L.off_go = take(4);
   L.bytes = off;
   return L;
 }
 
 gmnn_status nl_build(const gmnn_system* sys, float cutoff, float skin, gmnn_neighbors* nl, void* ws,
-                     size_t ws_bytes, hipStream_t stream) {
+                     size_t ws_bytes, hipStream_t stream, const uint32_t* disp_bits, float thresh2, float* ref_pos) {
   const double rl = (double)(cutoff + skin);
   const double rbin = rl + 1.0e-4;
   NlLayout L = nl_layout(sys, rbin);
@@ -446,6 +478,7 @@ gmnn_status nl_build(const gmnn_system* sys, float cutoff, float skin, gmnn_neig
   int4* atom_img = (int4*)(w + L.off_atom_img);
   int32_t* cell_atoms = (int32_t*)(w + L.off_cell_atoms);
   int32_t* row_count = (int32_t*)(w + L.off_row_count);
+  int* go = (int*)(w + L.off_go);
   const int N = sys->n_atoms;
   const int B = sys->n_structs;
   const float rlf = cutoff + skin;
@@ -453,33 +486,34 @@ gmnn_status nl_build(const gmnn_system* sys, float cutoff, float skin, gmnn_neig
   nl->cutoff = rlf;
 
   hipLaunchKernelGGL(nl_setup, dim3(1), dim3(1024), 0, stream, sys->cell, sys->pbc, B, rbin, grids,
-                     L.cell_capacity, cell_count, cell_fill, cells_total, nl->status);
+                     L.cell_capacity, cell_count, cell_fill, cells_total, nl->status, disp_bits, thresh2, go);
   const int tb = 256;
   const int nb_atoms = (N + tb - 1) / tb;
   if (N > 0) {
     hipLaunchKernelGGL(nl_bin, dim3(nb_atoms), dim3(tb), 0, stream, sys->pos, sys->atom_ptr, B, N, grids,
-                       cells_total, L.cell_capacity, nl->atom_struct, atom_cell, atom_img, cell_count, nl->status);
+                       cells_total, L.cell_capacity, nl->atom_struct, atom_cell, atom_img, cell_count, nl->status, go,
+                       ref_pos);
   }
   hipLaunchKernelGGL(scan_i32, dim3(1), dim3(1024), 0, stream, cell_count, cell_start, cells_total,
-                     (int64_t)L.cell_capacity, (int64_t*)nullptr);
+                     (int64_t)L.cell_capacity, (int64_t*)nullptr, (const int*)go, (int64_t)-1);
   if (N > 0) {
     hipLaunchKernelGGL(nl_cellfill, dim3(nb_atoms), dim3(tb), 0, stream, N, atom_cell, cell_start, cells_total,
-                       L.cell_capacity, cell_fill, cell_atoms);
+                       L.cell_capacity, cell_fill, cell_atoms, (const int*)go);
     const int nb_rows = (N + kRowsWaves - 1) / kRowsWaves;
     hipLaunchKernelGGL(nl_rows<0>, dim3(nb_rows), dim3(64 * kRowsWaves), 0, stream, sys->pos, N, grids,
                        nl->atom_struct, atom_img, cell_start, cell_atoms, cells_total, L.cell_capacity, rc2, row_count,
                        (const int64_t*)nullptr, (const int64_t*)nullptr, nl->capacity, (int32_t*)nullptr,
-                       (int32_t*)nullptr, nl->status);
+                       (int32_t*)nullptr, nl->status, (const int*)go);
     hipLaunchKernelGGL(scan_i32, dim3(1), dim3(1024), 0, stream, row_count, nl->row_ptr, (const int64_t*)nullptr,
-                       (int64_t)N, nl->n_pairs);
+                       (int64_t)N, nl->n_pairs, (const int*)go, (int64_t)nl->capacity);
     hipLaunchKernelGGL(nl_rows<1>, dim3(nb_rows), dim3(64 * kRowsWaves), 0, stream, sys->pos, N, grids,
                        nl->atom_struct, atom_img, cell_start, cell_atoms, cells_total, L.cell_capacity, rc2, row_count,
-                       nl->row_ptr, nl->n_pairs, nl->capacity, nl->j, nl->shift, nl->status);
+                       nl->row_ptr, nl->n_pairs, nl->capacity, nl->j, nl->shift, nl->status, (const int*)go);
     hipLaunchKernelGGL(nl_reverse, dim3(nb_rows), dim3(64 * kRowsWaves), 0, stream, N, nl->row_ptr, nl->j, nl->shift,
-                       nl->n_pairs, nl->capacity, nl->rev, nl->status);
+                       nl->n_pairs, nl->capacity, nl->rev, nl->status, (const int*)go);
   } else {
     hipLaunchKernelGGL(scan_i32, dim3(1), dim3(1024), 0, stream, row_count, nl->row_ptr, (const int64_t*)nullptr,
-                       (int64_t)0, nl->n_pairs);
+                       (int64_t)0, nl->n_pairs, (const int*)go, (int64_t)nl->capacity);
   }
   return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
 }
