@@ -5,9 +5,9 @@ Importing the package does not touch the GPU; the library is loaded on first
 use and a missing build raises ImportError (there is no CPU fallback)."""
 from ._capi import GMNNError, load as load_library, LIB_PATH
 from .api import (System, NeighborList, Model, Outputs, EnergyForces, build_neighbors, energy_forces, MD,
-                  maxwell_boltzmann,
+                  maxwell_boltzmann, param_grads, EnergyForcesFunction, PARAM_NAMES,
                   estimate_capacity)
 
 __all__ = ["GMNNError", "load_library", "LIB_PATH", "System", "NeighborList", "Model", "Outputs", "MD",
-           "maxwell_boltzmann",
+           "maxwell_boltzmann", "param_grads", "EnergyForcesFunction", "PARAM_NAMES",
            "EnergyForces", "build_neighbors", "energy_forces", "estimate_capacity"]

@@ -178,6 +178,10 @@ class Model:
     def c(self):
         return self._c(self.packed)
 
+    def params(self):
+        """The FP32 parameter tensors in C-ABI order (beta, W1, b1, W2, b2, W3, b3, scale, shift)."""
+        return [self.tensors[k] for k in PARAM_NAMES]
+
     def prepare(self):
         """Refresh the packed weights after the FP32 parameters changed."""
         c = self.c()
@@ -331,3 +335,46 @@ def maxwell_boltzmann(masses, temperature: float, seed: int):
     v = rng.normal(size=(len(m), 3)) * sig[:, None]
     v -= (m[:, None] * v).sum(0) / m.sum()
     return v.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, workspace=None):
+    """Gradients of a loss w.r.t. every model parameter (gmnn_backward), given
+    dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3]."""
+    lib = A.load()
+    dev = system.device
+    dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=dev).contiguous()
+    dF = torch.as_tensor(dL_dF, dtype=torch.float32, device=dev).reshape(-1, 3).contiguous()
+    grads = {k: torch.zeros_like(v) for k, v in model.tensors.items()}
+    gc = A.gmnn_param_grads(*[_ptr(grads[k]) for k in PARAM_NAMES])
+    mc, sc, nc = model.c(), system.c(), nl.c()
+    nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), 0)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    st = lib.gmnn_backward(C.byref(mc), C.byref(sc), C.byref(nc), _ptr(dE), _ptr(dF), 0, C.byref(gc), None,
+                           _ptr(workspace), nbytes, _stream())
+    A.check(st, "gmnn_backward")
+    return grads
+
+
+class EnergyForcesFunction(torch.autograd.Function):
+    """(E, F) = GMNN(theta) as a differentiable torch op: forward runs
+    gmnn_energy_forces (FP32 network), backward runs gmnn_backward, giving
+    the gradients of any loss of E and F w.r.t. the parameter tensors.
+
+        E, F = EnergyForcesFunction.apply(model, system, nl, *model.params())
+    """
+
+    @staticmethod
+    def forward(ctx, model, system, nl, *params):
+        out = energy_forces(model, system, nl, precision="fp32", stress=False)
+        ctx.model, ctx.system, ctx.nl = model, system, nl
+        return out.energy.mean(1), out.forces[: system.n_atoms].clone()
+
+    @staticmethod
+    def backward(ctx, gE, gF):
+        B, N = ctx.system.n_structs, ctx.system.n_atoms
+        gE = torch.zeros(B, dtype=torch.float64, device=ctx.system.device) if gE is None else gE.double()
+        gF = torch.zeros((N, 3), dtype=torch.float32, device=ctx.system.device) if gF is None else gF.float()
+        grads = param_grads(ctx.model, ctx.system, ctx.nl, gE, gF)
+        return (None, None, None, *[grads[k] for k in PARAM_NAMES])

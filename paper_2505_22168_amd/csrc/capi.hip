@@ -24,6 +24,10 @@ gmnn_status launch_tile(bool fused, bool perhead, const DevModel& m, const DevSy
                         int64_t gstride, hipStream_t stream);
 bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead);
 size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead);
+bool train_supported(const DevModel& m);
+size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
+gmnn_status train_backward(const DevModel& m, const DevSystem& sys, int H1, int H2, const double* ebar,
+                           const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s);
 
 constexpr int kPairThreads = 256;
 // systems below this many atoms take the fused (latency) path
@@ -275,7 +279,11 @@ size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* 
     return nl_layout(sys, (double)nl->cutoff + 1.0e-4).bytes;
   }
   if (!m || !nl) return 0;
-  if (op == GMNN_OP_ENERGY_FORCES || op == GMNN_OP_BACKWARD) return ef_layout(m, sys, nl, flags).bytes;
+  if (op == GMNN_OP_ENERGY_FORCES) return ef_layout(m, sys, nl, flags).bytes;
+  if (op == GMNN_OP_BACKWARD) {
+    const PackedLayout P = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+    return train_workspace_bytes(sys->n_atoms, P.HP1, m->n_species);
+  }
   return 0;
 }
 
@@ -423,9 +431,25 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, cons
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, const double* dL_dE,
                           const float* dL_dF, uint32_t flags, gmnn_param_grads* grads, float* dL_dpos, void* workspace,
                           size_t workspace_bytes, void* stream) {
-  (void)m; (void)sys; (void)nl; (void)dL_dE; (void)dL_dF; (void)flags; (void)grads; (void)dL_dpos;
-  (void)workspace; (void)workspace_bytes; (void)stream;
-  return GMNN_ERR_UNSUPPORTED;
+  gmnn_status st = check_model(m);
+  if (st != GMNN_OK) return st;
+  st = check_system(sys);
+  if (st != GMNN_OK) return st;
+  if (!nl || !nl->row_ptr || !nl->atom_struct || (nl->capacity > 0 && (!nl->j || !nl->shift || !nl->rev)) || !dL_dE ||
+      (sys->n_atoms > 0 && !dL_dF) || !grads || !grads->beta || !grads->W1 || !grads->b1 || !grads->W2 ||
+      !grads->b2 || !grads->W3 || !grads->b3 || !grads->scale || !grads->shift || !workspace)
+    return GMNN_ERR_INVALID_ARG;
+  if (nl->cutoff + 1e-6f < m->r_cut) return GMNN_ERR_INVALID_ARG;
+  // the FP32 network path only; positions gradients are not produced
+  if ((flags & (GMNN_PREC_BF16 | GMNN_WANT_FORCE_VAR)) || dL_dpos) return GMNN_ERR_UNSUPPORTED;
+  const DevModel dm = dev_model(m);
+  if (!train_supported(dm)) return GMNN_ERR_UNSUPPORTED;
+  const DevSystem ds = dev_system(sys, nl);
+  hipStream_t s = (hipStream_t)stream;
+  st = train_backward(dm, ds, m->hidden1, m->hidden2, dL_dE, dL_dF, grads, workspace, workspace_bytes, s);
+  if (st != GMNN_OK) return st;
+  if ((flags & GMNN_SYNC) && hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
+  return GMNN_OK;
 }
 
 }  // extern "C"

@@ -74,11 +74,12 @@ __device__ inline void store_feature(void* G, int idx, float v) {
 
 // Phase A of the forward: families 1-4 directly, and the intermediates
 // T7, V8, M5, v6 (all read only P).  Also zeroes the padding features.
-template <int TM, int NT, bool BF16>
+// FEATURES = false computes the intermediates only.
+template <int TM, int NT, bool BF16, bool FEATURES = true>
 __device__ inline void contract_forward_a(const float* __restrict__ P, float* __restrict__ I, void* G, int ldg,
                                           const Tables& tb) {
   const int tid = threadIdx.x;
-  for (int t = tid; t < TM * 50; t += NT) {
+  for (int t = tid; t < (FEATURES ? TM * 50 : 0); t += NT) {
     const int a = t % TM, f = t / TM;
     float v = 0.0f;
     if (f < kFam2) {
@@ -98,7 +99,8 @@ __device__ inline void contract_forward_a(const float* __restrict__ P, float* __
     }
     store_feature<BF16>(G, a * ldg + f, v);
   }
-  for (int t = tid; t < TM * (kFP - kF); t += NT) store_feature<BF16>(G, (t % TM) * ldg + kF + t / TM, 0.0f);
+  for (int t = tid; t < (FEATURES ? TM * (kFP - kF) : 0); t += NT)
+    store_feature<BF16>(G, (t % TM) * ldg + kF + t / TM, 0.0f);
   // T7
   for (int t = tid; t < TM * 135; t += NT) {
     const int a = t % TM, e = t / TM;

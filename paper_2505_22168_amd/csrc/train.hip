@@ -1,0 +1,767 @@
+// Training gradients of an energy + force loss (Section 3.4: weighted loss
+// terms on energies and forces; Section 3.3: forces are -dE/dx, so the force
+// term needs the mixed second derivative of E).
+//
+// With upstream gradients ebar_b = dL/dEbar_b and lambda = dL/dF, every
+// parameter gradient is the gradient of
+//     Phi(theta) = sum_i a_i Ebar_i(theta) - D(theta),   a_i = ebar_{b(i)},
+//     D = sum_p delta_p . dEbar/dd_p,   delta_p = lambda_j(p) - lambda_i(p),
+// i.e. of the energy plus the directional derivative of the energy along
+// the position perturbation lambda.  D is evaluated in forward (tangent)
+// mode and Phi differentiated in reverse mode:
+//   pair_tangent    Psidot_i = sum_p dPsi/dd_p . delta_p
+//   train_tile      per 8 atoms: invariants G and their tangent Gdot (the
+//                   invariants are cubic in Psi, so Gdot is the exact 4-point
+//                   difference of G along Psidot); the network forward in
+//                   dual numbers with primal and tangent rows stacked into one
+//                   16-row MFMA tile; its reverse pass; the invariant
+//                   backward Psibar = J^T Gbar + (d/dPsi J Psidot)^T Gdotbar
+//                   (the backward map is quadratic in Psi, so the second
+//                   term is an exact central difference) and Psidotbar =
+//                   J^T Gdotbar.  Writes the rows the weight products need.
+//   pair_beta_grad  dPhi/dbeta per pair, reduced per (Z_i, Z_j) without
+//                   atomics on the result
+//   weight_grad     W1bar = [G;Gdot]^T [z1bar;z1dotbar],
+//                   W2bar = [h1;h1dot]^T [z2bar;z2dotbar] as split-K MFMA
+//                   products over all atoms, partials summed in a fixed order
+//   reductions      bias, W3, scale and shift gradients (fixed order)
+#include "common.h"
+#include "contraction.h"
+#include "mfma.h"
+#include "model.h"
+#include "pair_math.h"
+
+namespace gmnn {
+
+constexpr int kTrainThreads = 512;
+constexpr int kTrainWaves = kTrainThreads / 64;
+constexpr int kTA = 8;  // atoms per training tile (16 MFMA rows: primal + tangent)
+
+// directional derivative of every monomial at u along v
+__device__ inline void dmonomials(float x, float y, float z, float vx, float vy, float vz, float* d) {
+  d[0] = 0.0f;
+  d[1] = vx; d[2] = vy; d[3] = vz;
+  d[4] = 2.0f * x * vx; d[5] = x * vy + y * vx; d[6] = x * vz + z * vx;
+  d[7] = 2.0f * y * vy; d[8] = y * vz + z * vy; d[9] = 2.0f * z * vz;
+  d[10] = 3.0f * x * x * vx;
+  d[11] = 2.0f * x * y * vx + x * x * vy;
+  d[12] = 2.0f * x * z * vx + x * x * vz;
+  d[13] = y * y * vx + 2.0f * x * y * vy;
+  d[14] = y * z * vx + x * z * vy + x * y * vz;
+  d[15] = z * z * vx + 2.0f * x * z * vz;
+  d[16] = 3.0f * y * y * vy;
+  d[17] = 2.0f * y * z * vy + y * y * vz;
+  d[18] = z * z * vy + 2.0f * y * z * vz;
+  d[19] = 3.0f * z * z * vz;
+}
+
+// ---------------------------------------------------------------------------
+// Psidot_i = sum_p [ dR_s (u.delta) mono(u) + R_s Dmono(u)[delta_perp / r] ]
+template <int LPA>
+__global__ void __launch_bounds__(kPairBlock) pair_tangent(DevModel m, DevSystem sys, const float* __restrict__ lambda,
+                                                           float* __restrict__ psidot) {
+  extern __shared__ float s_beta[];
+  stage_beta(m, s_beta);
+  __syncthreads();
+  const int q = threadIdx.x & (LPA - 1);
+  const int i = blockIdx.x * (kPairBlock / LPA) + threadIdx.x / LPA;
+  const bool live = i < sys.n_atoms;
+  float v[128];
+#pragma unroll
+  for (int k = 0; k < 128; ++k) v[k] = 0.0f;
+  if (live) {
+    AtomCtx c;
+    load_atom(sys, i, c);
+    const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
+    const float lix = lambda[3 * (int64_t)i], liy = lambda[3 * (int64_t)i + 1], liz = lambda[3 * (int64_t)i + 2];
+    for (int64_t p = c.p0 + q; p < c.p1; p += LPA) {
+      int j;
+      float dx, dy, dz;
+      pair_vec(sys, c, p, j, dx, dy, dz);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      if (!(r2 < m.rc2) || r2 == 0.0f) continue;
+      const float r = sqrtf(r2), ir = 1.0f / r;
+      const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+      const float ex = lambda[3 * (int64_t)j] - lix, ey = lambda[3 * (int64_t)j + 1] - liy,
+                  ez = lambda[3 * (int64_t)j + 2] - liz;
+      const float ud = ux * ex + uy * ey + uz * ez;
+      Radial rad;
+      radial<true>(m, bzi + sys.species[j] * kS * kMaxBasis, r, rad);
+      float mo[20], dm[20];
+      monomials(ux, uy, uz, mo);
+      dmonomials(ux, uy, uz, (ex - ud * ux) * ir, (ey - ud * uy) * ir, (ez - ud * uz) * ir, dm);
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+        const float a = rad.dR[s] * ud;
+#pragma unroll
+        for (int t = 0; t < kPacked; ++t) v[s * kPacked + t] += a * mo[t] + rad.R[s] * dm[t];
+      }
+    }
+  }
+  reduce_scatter_128<LPA>(v, q);
+  constexpr int OWN = 128 / LPA;
+  if (live) {
+#pragma unroll
+    for (int e = 0; e < OWN; ++e) {
+      const int idx = OWN * q + e;
+      if (idx < kS * kPacked) psidot[(int64_t)i * (kS * kPacked) + idx] = v[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__device__ inline void swish_d2(float z, float& s, float& d1, float& d2) {
+  const float sg = 1.0f / (1.0f + __expf(-z));
+  s = z * sg;
+  d1 = sg * (1.0f + z * (1.0f - sg));
+  d2 = sg * (1.0f - sg) * (2.0f + z * (1.0f - 2.0f * sg));
+}
+
+template <int HP>
+struct TrainLds {
+  static constexpr int TA = kTA;
+  static constexpr int LDG = kFP + 4;   // FP32 A tiles
+  static constexpr int LDH = HP + 4;
+  static constexpr int LDGB = kFP + 1;
+  static constexpr size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+  static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
+  static constexpr size_t tables = 0;
+  static constexpr size_t psi = al(sizeof(Tables));
+  static constexpr size_t psid = psi + al(4 * (size_t)TA * PS);
+  static constexpr size_t ptmp = psid + al(4 * (size_t)TA * PS);
+  static constexpr size_t inter = ptmp + al(4 * (size_t)TA * PS);
+  static constexpr size_t gt = inter + al(4 * (size_t)TA * IS);           // [16][LDG]: G rows 0-7, Gdot rows 8-15
+  static constexpr size_t gtmp = gt + al(4 * (size_t)16 * LDG);           // [8][LDG] scratch invariants; later Gbar [16][LDGB]
+  static constexpr size_t gtmp_bytes = mx(4 * (size_t)TA * LDG, 4 * (size_t)16 * LDGB);
+  static constexpr size_t ht = gtmp + al(gtmp_bytes);                      // [16][LDH]: h1 / delta tiles
+  static constexpr size_t pba = ht + al(4 * (size_t)16 * LDH);            // Psibar accumulator [8][PS]
+  static constexpr size_t pbs = pba + al(4 * (size_t)TA * PS);            // scratch full gradient [8][PS]
+  static constexpr size_t ep = pbs + al(4 * (size_t)TA * PS);             // [waves][16 rows] partial sums (2 values)
+  static constexpr size_t rows = ep + al(4 * (size_t)kTrainWaves * 16 * 2);
+  static constexpr size_t bytes = rows + al(4 * 4 * (size_t)TA);          // scale, a, t, y-mean sums
+};
+
+// weight-product rows: row k = 16 * tile + r, r < 8 primal atom rows, r >= 8 tangent rows
+template <int HP>
+__global__ void __launch_bounds__(kTrainThreads)
+    train_tile(DevModel m, DevSystem sys, const float* __restrict__ psi, const float* __restrict__ psidot,
+               const double* __restrict__ ebar, float* __restrict__ psibar, float* __restrict__ psidotbar,
+               float* __restrict__ X1, float* __restrict__ Y1, float* __restrict__ X2, float* __restrict__ Y2,
+               float* __restrict__ w3g, float* __restrict__ qsig) {
+  using L = TrainLds<HP>;
+  using Sh = NetShape<16, HP, kTrainWaves>;
+  constexpr int TA = kTA;
+  constexpr int TPW = Sh::TPW, TPW_G = Sh::TPW_G, NBH = Sh::NBH, NBG = Sh::NBG, WPR = Sh::WPR;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  Tables& tb = *(Tables*)(lds + L::tables);
+  float* sPsi = (float*)(lds + L::psi);
+  float* sPd = (float*)(lds + L::psid);
+  float* sPt = (float*)(lds + L::ptmp);
+  float* sI = (float*)(lds + L::inter);
+  float* sGT = (float*)(lds + L::gt);
+  float* sGtmp = (float*)(lds + L::gtmp);
+  float* sGb = (float*)(lds + L::gtmp);
+  float* sH = (float*)(lds + L::ht);
+  float* sPbA = (float*)(lds + L::pba);
+  float* sPbS = (float*)(lds + L::pbs);
+  float* sEp = (float*)(lds + L::ep);
+  float* sScale = (float*)(lds + L::rows);
+  float* sA = sScale + TA;
+  float* sT = sA + TA;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int row0 = blockIdx.x * TA;
+  const int n_rows = min(TA, sys.n_atoms - row0);
+  const int64_t k0 = (int64_t)blockIdx.x * 16;  // first weight-product row of this tile
+
+  load_tables(&tb);
+  for (int a = tid; a < TA; a += kTrainThreads) {
+    float sc = 0.0f, aa = 0.0f;
+    if (a < n_rows) {
+      sc = m.scale[sys.species[row0 + a]];
+      aa = (float)ebar[sys.atom_struct[row0 + a]];
+    }
+    sScale[a] = sc;
+    sA[a] = aa;
+  }
+  for (int t = tid; t < TA * kS * kFull; t += kTrainThreads) {
+    const int a = t % TA, e = t / TA;
+    const int s = e / kFull, r = e % kFull;
+    float v = 0.0f, vd = 0.0f;
+    if (a < n_rows) {
+      const int64_t o = (int64_t)(row0 + a) * (kS * kPacked) + s * kPacked + c_full_to_packed[r];
+      v = psi[o];
+      vd = psidot[o];
+    }
+    sPsi[a * PS + e] = v;
+    sPd[a * PS + e] = vd;
+  }
+  __syncthreads();
+  // per-atom step t = |Psi| / |Psidot| for the exact polynomial differences
+  if (w < TA) {
+    float n0 = 0.0f, n1 = 0.0f;
+    for (int e = l; e < kS * kFull; e += 64) {
+      n0 += sPsi[w * PS + e] * sPsi[w * PS + e];
+      n1 += sPd[w * PS + e] * sPd[w * PS + e];
+    }
+    n0 = wave_sum(n0);
+    n1 = wave_sum(n1);
+    if (l == 0) sT[w] = (n1 > 0.0f && n0 > 0.0f) ? sqrtf(n0 / n1) : 1.0f;
+  }
+  __syncthreads();
+
+  // ---- invariants G (rows 0-7) and Gdot (rows 8-15) ---------------------------
+  contract_forward_a<TA, kTrainThreads, false>(sPsi, sI, sGT, L::LDG, tb);
+  __syncthreads();
+  contract_forward_b<TA, kTrainThreads, false>(sPsi, sI, sGT, L::LDG, tb);
+  __syncthreads();
+  // Gdot = [8 (G(+t) - G(-t)) - (G(+2t) - G(-2t))] / (12 t)
+  const float cf[4] = {1.0f, -1.0f, 2.0f, -2.0f};
+  const float wf[4] = {8.0f, -8.0f, -1.0f, 1.0f};
+  for (int ev = 0; ev < 4; ++ev) {
+    for (int t = tid; t < TA * kS * kFull; t += kTrainThreads) {
+      const int a = t % TA, e = t / TA;
+      sPt[a * PS + e] = sPsi[a * PS + e] + cf[ev] * sT[a] * sPd[a * PS + e];
+    }
+    __syncthreads();
+    contract_forward_a<TA, kTrainThreads, false>(sPt, sI, sGtmp, L::LDG, tb);
+    __syncthreads();
+    contract_forward_b<TA, kTrainThreads, false>(sPt, sI, sGtmp, L::LDG, tb);
+    __syncthreads();
+    for (int t = tid; t < TA * kFP; t += kTrainThreads) {
+      const int a = t / kFP, f = t % kFP;
+      const float v = wf[ev] * sGtmp[a * L::LDG + f] / (12.0f * sT[a]);
+      sGT[(8 + a) * L::LDG + f] = (ev == 0 ? 0.0f : sGT[(8 + a) * L::LDG + f]) + v;
+    }
+    __syncthreads();
+  }
+  // weight-product rows X1 = [G; Gdot]
+  for (int t = tid; t < 16 * kFP; t += kTrainThreads) {
+    const int r = t / kFP, f = t % kFP;
+    X1[(k0 + r) * kFP + f] = ((r & 7) < n_rows) ? sGT[r * L::LDG + f] : 0.0f;
+  }
+
+  // ---- network forward in dual numbers ---------------------------------------------
+  // the wave's output fragments: rows 4 (l>>4) + j; lanes l and l^32 hold the
+  // primal (row < 8) and tangent (row + 8) value of the same column
+  const bool prim = l < 32;
+  const int cw = w;  // one 16-row block: waves split the columns
+  floatx4 s1d[TPW], s1dd[TPW], z1dot[TPW];
+  {
+    floatx4 acc[TPW];
+    zero_acc(acc);
+    mma_f32<TPW>(sGT, L::LDG, 0, (const float4*)m.w1_f32, kFP / 16, cw, WPR, NBH, acc);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = cw + i * WPR;
+      const int col = nb * 16 + (l & 15);
+      const float bias = nb < NBH ? m.b1[col] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float zv = acc[i][j] + (prim ? bias : 0.0f);
+        const float other = __shfl_xor(zv, 32, 64);
+        const float z1 = prim ? zv : other, zd = prim ? other : zv;
+        float s, d1, d2;
+        swish_d2(z1, s, d1, d2);
+        s1d[i][j] = d1;
+        s1dd[i][j] = d2;
+        z1dot[i][j] = zd;
+        const int row = 4 * (l >> 4) + j;
+        if (nb < NBH) sH[row * L::LDH + col] = prim ? s : d1 * zd;
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < 16 * HP; t += kTrainThreads) {
+    const int r = t / HP, c = t % HP;
+    X2[(k0 + r) * HP + c] = ((r & 7) < n_rows) ? sH[r * L::LDH + c] : 0.0f;
+  }
+  {
+    floatx4 acc[TPW];
+    zero_acc(acc);
+    mma_f32<TPW>(sH, L::LDH, 0, (const float4*)m.w2_f32, HP / 16, cw, WPR, NBH, acc);
+    float ypart[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // primal lanes: h2 . w3bar, tangent lanes: h2dot . w3bar
+    floatx4 d2out[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = cw + i * WPR;
+      const int col = nb * 16 + (l & 15);
+      const bool ok = nb < NBH;
+      const float bias = ok ? m.b2[col] : 0.0f;
+      const float wb = ok ? m.w3bar[col] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 4 * (l >> 4) + j;
+        const int a = row & 7;
+        const float zv = acc[i][j] + (prim ? bias : 0.0f);
+        const float other = __shfl_xor(zv, 32, 64);
+        const float z2 = prim ? zv : other, zd = prim ? other : zv;
+        float h2, d1, dd;
+        swish_d2(z2, h2, d1, dd);
+        const float h2d = d1 * zd;
+        const float sg = sScale[a];
+        const float hbar = sA[a] * sg * wb;       // dPhi/dh2
+        const float hdbar = -sg * wb;             // dPhi/dh2dot
+        // primal row: z2bar = hbar s' + hdbar s'' z2dot; tangent row: z2dotbar = hdbar s'
+        d2out[i][j] = prim ? (hbar * d1 + hdbar * dd * zd) : (hdbar * d1);
+        ypart[j] += (prim ? h2 : h2d) * wb;
+        if (ok && prim && a < n_rows) w3g[(int64_t)(row0 + a) * HP + col] = (sA[a] * h2 - h2d) * sg / (float)m.M;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v = ypart[j];
+      v += __shfl_xor(v, 8, 16);
+      v += __shfl_xor(v, 4, 16);
+      v += __shfl_xor(v, 2, 16);
+      v += __shfl_xor(v, 1, 16);
+      if ((l & 15) == 0) sEp[w * 16 + 4 * (l >> 4) + j] = v;
+    }
+    __syncthreads();  // everyone has read h1 (sH) for the product above
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = cw + i * WPR;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sH[(4 * (l >> 4) + j) * L::LDH + col] = d2out[i][j];
+    }
+  }
+  __syncthreads();
+  // scale gradient per atom: a ybar_mean - ydot_mean, with y_mean = h2 . w3bar + mean b3
+  if (tid < TA) {
+    float yp = 0.0f, yt = 0.0f, b3m = 0.0f;
+    for (int hm = 0; hm < m.M; ++hm) b3m += m.b3[hm];
+    b3m /= (float)m.M;
+    for (int ww = 0; ww < kTrainWaves; ++ww) {
+      yp += sEp[ww * 16 + tid];
+      yt += sEp[ww * 16 + 8 + tid];
+    }
+    if (tid < n_rows) qsig[row0 + tid] = sA[tid] * (yp + b3m) - yt;
+  }
+  for (int t = tid; t < 16 * HP; t += kTrainThreads) {
+    const int r = t / HP, c = t % HP;
+    Y2[(k0 + r) * HP + c] = ((r & 7) < n_rows) ? sH[r * L::LDH + c] : 0.0f;
+  }
+  // ---- network reverse ------------------------------------------------------------
+  {
+    floatx4 acc[TPW];
+    zero_acc(acc);
+    mma_f32<TPW>(sH, L::LDH, 0, (const float4*)m.w2t_f32, HP / 16, cw, WPR, NBH, acc);
+    __syncthreads();  // all reads of [z2bar; z2dotbar] done before the tile is overwritten
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = cw + i * WPR;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float hv = acc[i][j];                // primal lanes: h1bar, tangent lanes: h1dotbar
+        const float other = __shfl_xor(hv, 32, 64);
+        const float hbar = prim ? hv : other, hdbar = prim ? other : hv;
+        const float out = prim ? (hbar * s1d[i][j] + hdbar * s1dd[i][j] * z1dot[i][j]) : (hdbar * s1d[i][j]);
+        if (nb < NBH) sH[(4 * (l >> 4) + j) * L::LDH + col] = out;
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < 16 * HP; t += kTrainThreads) {
+    const int r = t / HP, c = t % HP;
+    Y1[(k0 + r) * HP + c] = ((r & 7) < n_rows) ? sH[r * L::LDH + c] : 0.0f;
+  }
+  {
+    floatx4 acc[TPW_G];
+    zero_acc(acc);
+    mma_f32<TPW_G>(sH, L::LDH, 0, (const float4*)m.w1t_f32, HP / 16, cw, WPR, NBG, acc);
+#pragma unroll
+    for (int i = 0; i < TPW_G; ++i) {
+      const int nb = cw + i * WPR;
+      if (nb >= NBG) continue;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sGb[(4 * (l >> 4) + j) * L::LDGB + col] = acc[i][j];  // rows 0-7 Gbar, 8-15 Gdotbar
+    }
+  }
+  __syncthreads();
+
+  // ---- invariant backward ---------------------------------------------------------
+  const float* Gbar = sGb;
+  const float* Gdbar = sGb + 8 * L::LDGB;
+  // Psidotbar = B(Psi; Gdotbar)
+  contract_forward_a<TA, kTrainThreads, false, false>(sPsi, sI, nullptr, 0, tb);  // intermediates of Psi
+  __syncthreads();
+  contract_backward_a<TA, kTrainThreads>(sPsi, Gdbar, L::LDGB, sI, tb);
+  __syncthreads();
+  contract_backward_b<TA, kTrainThreads>(sPsi, Gdbar, L::LDGB, sI, sPbS, tb);
+  __syncthreads();
+  fold_packed<TA, kTrainThreads>(sPbS, tb, [&](int a, int e, float v) {
+    if (a < n_rows) psidotbar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+  });
+  // Psibar = B(Psi; Gbar) + [B(Psi + t Psidot; Gdotbar) - B(Psi - t Psidot; Gdotbar)] / (2t)
+  contract_backward_a<TA, kTrainThreads>(sPsi, Gbar, L::LDGB, sI, tb);
+  __syncthreads();
+  contract_backward_b<TA, kTrainThreads>(sPsi, Gbar, L::LDGB, sI, sPbA, tb);
+  __syncthreads();
+  for (int ev = 0; ev < 2; ++ev) {
+    const float sgn = ev == 0 ? 1.0f : -1.0f;
+    for (int t = tid; t < TA * kS * kFull; t += kTrainThreads) {
+      const int a = t % TA, e = t / TA;
+      sPt[a * PS + e] = sPsi[a * PS + e] + sgn * sT[a] * sPd[a * PS + e];
+    }
+    __syncthreads();
+    contract_forward_a<TA, kTrainThreads, false, false>(sPt, sI, nullptr, 0, tb);  // intermediates of Psi +- t Psidot
+    __syncthreads();
+    contract_backward_a<TA, kTrainThreads>(sPt, Gdbar, L::LDGB, sI, tb);
+    __syncthreads();
+    contract_backward_b<TA, kTrainThreads>(sPt, Gdbar, L::LDGB, sI, sPbS, tb);
+    __syncthreads();
+    for (int t = tid; t < TA * kS * kFull; t += kTrainThreads) {
+      const int a = t % TA, e = t / TA;
+      sPbA[a * PS + e] += sgn * sPbS[a * PS + e] / (2.0f * sT[a]);
+    }
+    __syncthreads();
+  }
+  fold_packed<TA, kTrainThreads>(sPbA, tb, [&](int a, int e, float v) {
+    if (a < n_rows) psibar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// dPhi/dbeta per pair:
+//   c [ f_c g_k (A_s + B_s) + (f_c g_k)' (u.delta) Adot_s ]
+// with A_s = Psibar_s . mono(u), Adot_s = Psidotbar_s . mono(u),
+// B_s = Psidotbar_s . Dmono(u)[delta_perp / r].  The 35 values of a pair go to
+// its (Z_i, Z_j) slot: for each Z_j the wave reduce-scatters the masked
+// values, lane k owning slot k, and adds them to the wave's LDS copy of the
+// gradient (one writer per slot); per-block copies are summed in wave order
+// and written as block partials.
+__global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSystem sys, const float* __restrict__ lambda,
+                                                             const float* __restrict__ psibar,
+                                                             const float* __restrict__ psidotbar,
+                                                             float* __restrict__ beta_partial) {
+  extern __shared__ float sm[];
+  const int nsp = m.n_species;
+  const int nslots = nsp * nsp * kS * kMaxBasis;
+  float* s_beta = sm;
+  float* s_acc = sm + nslots;  // [waves][nslots]
+  constexpr int NW = kPairBlock / 64;
+  stage_beta(m, s_beta);
+  for (int t = threadIdx.x; t < NW * nslots; t += kPairBlock) s_acc[t] = 0.0f;
+  __syncthreads();
+  const int w = threadIdx.x >> 6, q = threadIdx.x & 63;
+  for (int i = blockIdx.x * NW + w; i < sys.n_atoms; i += gridDim.x * NW) {
+    AtomCtx c;
+    load_atom(sys, i, c);
+    const float* bzi = s_beta + c.zsp * nsp * kS * kMaxBasis;
+    const float lix = lambda[3 * (int64_t)i], liy = lambda[3 * (int64_t)i + 1], liz = lambda[3 * (int64_t)i + 2];
+    for (int64_t p0 = c.p0; p0 < c.p1; p0 += 64) {
+      const int64_t p = p0 + q;
+      float val[kS * kMaxBasis];
+#pragma unroll
+      for (int k = 0; k < kS * kMaxBasis; ++k) val[k] = 0.0f;
+      int zj = -1;
+      if (p < c.p1) {
+        int j;
+        float dx, dy, dz;
+        pair_vec(sys, c, p, j, dx, dy, dz);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < m.rc2 && r2 > 0.0f) {
+          zj = sys.species[j];
+          const float r = sqrtf(r2), ir = 1.0f / r;
+          const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+          const float ex = lambda[3 * (int64_t)j] - lix, ey = lambda[3 * (int64_t)j + 1] - liy,
+                      ez = lambda[3 * (int64_t)j + 2] - liz;
+          const float ud = ux * ex + uy * ey + uz * ez;
+          float mo[20], dm[20];
+          monomials(ux, uy, uz, mo);
+          dmonomials(ux, uy, uz, (ex - ud * ux) * ir, (ey - ud * uy) * ir, (ez - ud * uz) * ir, dm);
+          // basis: g_k and (f_c g_k)'
+          const float tau = r - m.r_min;
+          const float g0 = __expf(-m.gamma * tau * tau);
+          const float aa = __expf(2.0f * m.gamma * m.delta * tau);
+          float sn, cs;
+          sincosf(3.14159265358979f * r / m.r_cut, &sn, &cs);
+          const float fc = 0.5f * (cs + 1.0f) * m.psi_scale;
+          const float dfc = -0.5f * (3.14159265358979f / m.r_cut) * sn * m.psi_scale;
+          const float* pb = psibar + (int64_t)i * (kS * kPacked);
+          const float* pd = psidotbar + (int64_t)i * (kS * kPacked);
+#pragma unroll
+          for (int s = 0; s < kS; ++s) {
+            float A = 0.0f, Ad = 0.0f, Bs = 0.0f;
+#pragma unroll
+            for (int t = 0; t < kPacked; ++t) {
+              A += pb[s * kPacked + t] * mo[t];
+              Ad += pd[s * kPacked + t] * mo[t];
+              Bs += pd[s * kPacked + t] * dm[t];
+            }
+            float gk = g0;
+#pragma unroll
+            for (int k = 0; k < kMaxBasis; ++k) {
+              const float g = gk * m.ck[k];
+              const float dg = -2.0f * m.gamma * (tau - (float)k * m.delta) * g;
+              val[s * kMaxBasis + k] = fc * g * (A + Bs) + (dfc * g + fc * dg) * ud * Ad;
+              gk *= aa;
+            }
+          }
+        }
+      }
+      for (int z = 0; z < nsp; ++z) {
+        float vz[64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) vz[k] = (k < kS * kMaxBasis && zj == z) ? val[k < kS * kMaxBasis ? k : 0] : 0.0f;
+        // 64 values over 64 lanes: lane q ends with slot q
+        rs_swap<32, 32>(vz);
+        rs_swap<16, 16>(vz);
+        rs_step<8, 0>(vz, (q >> 3) & 1);
+        rs_step<4, 1>(vz, (q >> 2) & 1);
+        rs_step<2, 2>(vz, (q >> 1) & 1);
+        rs_step<1, 3>(vz, q & 1);
+        if (q < kS * kMaxBasis) s_acc[w * nslots + (c.zsp * nsp + z) * kS * kMaxBasis + q] += vz[0];
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nslots; t += kPairBlock) {
+    float v = 0.0f;
+    for (int ww = 0; ww < NW; ++ww) v += s_acc[ww * nslots + t];
+    beta_partial[(int64_t)blockIdx.x * nslots + t] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C[M][N] = sum_k A[k][M]^T B[k][N] over k in a chunk (split-K), FP32 MFMA.
+// One wave per 16 x 16 output tile; partial[chunk][M][N].
+__global__ void __launch_bounds__(256) weight_grad(const float* __restrict__ A, int ldA, const float* __restrict__ B,
+                                                   int ldB, int Mdim, int Ndim, int64_t K, int64_t kchunk,
+                                                   float* __restrict__ partial) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tiles_n = Ndim / 16;
+  const int tile = blockIdx.x * 4 + w;
+  if (tile >= (Mdim / 16) * tiles_n) return;
+  const int mt = tile / tiles_n, nt = tile % tiles_n;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  // 16x16x4: lane l supplies A^T[m = l&15][k = l>>4] = A[k][m], B[k = l>>4][n = l&15]
+  for (int64_t k = kb; k < ke; k += 4) {
+    const int64_t kk = k + (l >> 4);
+    const float a = kk < ke ? A[kk * ldA + mt * 16 + (l & 15)] : 0.0f;
+    const float b = kk < ke ? B[kk * ldB + nt * 16 + (l & 15)] : 0.0f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = mt * 16 + 4 * (l >> 4) + j, col = nt * 16 + (l & 15);
+    partial[((int64_t)blockIdx.y * Mdim + row) * Ndim + col] = acc[j];
+  }
+}
+
+// out[i] = scale * sum_c partial[c][i] (chunks in order); optionally strided copies
+__global__ void sum_partials(const float* __restrict__ partial, int nchunks, int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float v = 0.0f;
+  for (int c = 0; c < nchunks; ++c) v += partial[(int64_t)c * n + i];
+  out[i] = v;
+}
+
+// column sums over weight-product rows: out[c] = sum over rows k with (k & 15) < 8 (primal rows)
+// of Y[k][c], for c < ncols < HP; padded columns are dropped
+__global__ void column_sums(const float* __restrict__ Y, int ld, int64_t nrows, int ncols, bool primal_only,
+                            float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  float v = 0.0f;
+  for (int64_t k = 0; k < nrows; ++k)
+    if (!primal_only || (k & 15) < 8) v += Y[k * ld + c];
+  out[c] = v;
+}
+
+// scale / shift / b3 gradients (one thread per species, fixed order over atoms)
+__global__ void species_sums(DevModel m, DevSystem sys, const double* __restrict__ ebar, const float* __restrict__ qsig,
+                             float* __restrict__ gscale, float* __restrict__ gshift, float* __restrict__ gb3) {
+  const int z = threadIdx.x;
+  if (z < m.n_species) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < sys.n_atoms; ++i)
+      if (sys.species[i] == z) {
+        s1 += qsig[i];
+        s2 += ebar[sys.atom_struct[i]];
+      }
+    gscale[z] = (float)s1;
+    gshift[z] = (float)s2;
+  }
+  if (z == 0) {
+    // dPhi/db3_m = sum_i a_i sigma_i / M (the same for every head)
+    double s = 0.0;
+    for (int i = 0; i < sys.n_atoms; ++i) s += ebar[sys.atom_struct[i]] * m.scale[sys.species[i]];
+    for (int hm = 0; hm < m.M; ++hm) gb3[hm] = (float)(s / m.M);
+  }
+}
+
+// W3 gradient: every head column equals sum_i w3g[i][h]
+__global__ void w3_grad(const float* __restrict__ w3g, int HP, int64_t n_atoms, int H2, int M, float* __restrict__ gw3) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H2) return;
+  float v = 0.0f;
+  for (int64_t i = 0; i < n_atoms; ++i) v += w3g[i * HP + h];
+  for (int hm = 0; hm < M; ++hm) gw3[(int64_t)h * M + hm] = v;
+}
+
+// unpad a [HP or kFP rows][HP cols] gradient into the caller's [F][H1] / [H1][H2] array
+__global__ void unpad_copy(const float* __restrict__ src, int ld, int rows, int cols, float* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * cols) return;
+  const int r = (int)(t / cols), c = (int)(t % cols);
+  dst[t] = src[(int64_t)r * ld + c];
+}
+
+// beta gradient: sum of block partials in block order
+__global__ void beta_unpack(const float* __restrict__ summed, int nsp, int K, float* __restrict__ gbeta) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = nsp * nsp * kS * K;
+  if (t >= n) return;
+  const int k = t % K, rest = t / K;
+  gbeta[t] = summed[rest * kMaxBasis + k];
+}
+
+// ---------------------------------------------------------------------------
+template <int HP>
+static gmnn_status launch_train_tile_t(const DevModel& m, const DevSystem& sys, const float* psi, const float* psidot,
+                                       const double* ebar, float* psibar, float* psidotbar, float* X1, float* Y1,
+                                       float* X2, float* Y2, float* w3g, float* qsig, hipStream_t s) {
+  using L = TrainLds<HP>;
+  if (L::bytes > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
+  auto k = train_tile<HP>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes) != hipSuccess)
+      return GMNN_ERR_HIP;
+    attr_set = true;
+  }
+  const int grid = (sys.n_atoms + kTA - 1) / kTA;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kTrainThreads), L::bytes, s, m, sys, psi, psidot, ebar, psibar, psidotbar,
+                     X1, Y1, X2, Y2, w3g, qsig);
+  return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
+}
+
+struct TrainLayout {
+  size_t psi, psidot, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, part1, part2, sum1, sum2, bpart, bsum, bytes;
+  int64_t K;           // weight-product rows
+  int kchunks;
+  int beta_blocks;
+};
+
+TrainLayout train_layout(int n_atoms, int HP, int nsp) {
+  TrainLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t N = (size_t)n_atoms;
+  const int64_t tiles = (n_atoms + kTA - 1) / kTA;
+  L.K = tiles * 16;
+  L.kchunks = (int)((L.K + 4095) / 4096);
+  L.beta_blocks = 256;
+  L.psi = take(4 * N * 100);
+  L.psidot = take(4 * N * 100);
+  L.psibar = take(4 * N * 100);
+  L.psidotbar = take(4 * N * 100);
+  L.X1 = take(4 * (size_t)L.K * kFP);
+  L.Y1 = take(4 * (size_t)L.K * HP);
+  L.X2 = take(4 * (size_t)L.K * HP);
+  L.Y2 = take(4 * (size_t)L.K * HP);
+  L.w3g = take(4 * N * HP);
+  L.qsig = take(4 * N);
+  L.part1 = take(4 * (size_t)L.kchunks * kFP * HP);
+  L.part2 = take(4 * (size_t)L.kchunks * HP * HP);
+  L.sum1 = take(4 * (size_t)kFP * HP);
+  L.sum2 = take(4 * (size_t)HP * HP);
+  const size_t nslots = (size_t)nsp * nsp * kS * kMaxBasis;
+  L.bpart = take(4 * (size_t)L.beta_blocks * nslots);
+  L.bsum = take(4 * nslots);
+  L.bytes = off;
+  return L;
+}
+
+template <int LPA>
+__global__ void pair_moments(DevModel m, DevSystem sys, float* psi, int* counters, int n_counters);
+
+bool train_supported(const DevModel& m) {
+  return m.n_species <= 8 && TrainLds<512>::bytes <= 160 * 1024 &&
+         (m.HP1 == 64 || m.HP1 == 128 || m.HP1 == 256 || m.HP1 == 512);
+}
+
+size_t train_workspace_bytes(int n_atoms, int HP, int nsp) { return train_layout(n_atoms, HP, nsp).bytes; }
+
+gmnn_status train_backward(const DevModel& m, const DevSystem& sys, int H1, int H2, const double* ebar,
+                           const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int HP = m.HP1;
+  const int nsp = m.n_species;
+  const TrainLayout L = train_layout(sys.n_atoms, HP, nsp);
+  if (ws_bytes < L.bytes) return GMNN_ERR_WORKSPACE;
+  char* W = (char*)ws;
+  float* psi = (float*)(W + L.psi);
+  float* psidot = (float*)(W + L.psidot);
+  float* psibar = (float*)(W + L.psibar);
+  float* psidotbar = (float*)(W + L.psidotbar);
+  float *X1 = (float*)(W + L.X1), *Y1 = (float*)(W + L.Y1), *X2 = (float*)(W + L.X2), *Y2 = (float*)(W + L.Y2);
+  float* w3g = (float*)(W + L.w3g);
+  float* qsig = (float*)(W + L.qsig);
+  float* part1 = (float*)(W + L.part1);
+  float* part2 = (float*)(W + L.part2);
+  float* sum1 = (float*)(W + L.sum1);
+  float* sum2 = (float*)(W + L.sum2);
+  float* bpart = (float*)(W + L.bpart);
+  float* bsum = (float*)(W + L.bsum);
+  const int N = sys.n_atoms;
+  const int nslots = nsp * nsp * kS * kMaxBasis;
+  const size_t beta_lds = sizeof(float) * (size_t)nslots;
+  const int lpa = N < 8192 ? 64 : 16;
+  const int nb = (N + kPairBlock / lpa - 1) / (kPairBlock / lpa);
+  gmnn_status st = GMNN_OK;
+  if (N > 0) {
+    if (lpa == 64) {
+      hipLaunchKernelGGL(pair_moments<64>, dim3(nb), dim3(kPairBlock), beta_lds, s, m, sys, psi, (int*)nullptr, 0);
+      hipLaunchKernelGGL(pair_tangent<64>, dim3(nb), dim3(kPairBlock), beta_lds, s, m, sys, lambda, psidot);
+    } else {
+      hipLaunchKernelGGL(pair_moments<16>, dim3(nb), dim3(kPairBlock), beta_lds, s, m, sys, psi, (int*)nullptr, 0);
+      hipLaunchKernelGGL(pair_tangent<16>, dim3(nb), dim3(kPairBlock), beta_lds, s, m, sys, lambda, psidot);
+    }
+    switch (HP) {
+      case 64: st = launch_train_tile_t<64>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
+      case 128: st = launch_train_tile_t<128>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
+      case 256: st = launch_train_tile_t<256>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
+      case 512: st = launch_train_tile_t<512>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
+      default: return GMNN_ERR_UNSUPPORTED;
+    }
+    if (st != GMNN_OK) return st;
+  }
+  hipLaunchKernelGGL(pair_beta_grad, dim3(L.beta_blocks), dim3(kPairBlock), beta_lds * (1 + kPairBlock / 64), s, m, sys,
+                     lambda, psibar, psidotbar, bpart);
+  // weight products, split over chunks of 4096 rows, partials summed in chunk order
+  {
+    const int t1 = (kFP / 16) * (HP / 16);
+    hipLaunchKernelGGL(weight_grad, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
+                       (int64_t)4096, part1);
+    const int t2 = (HP / 16) * (HP / 16);
+    hipLaunchKernelGGL(weight_grad, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
+                       (int64_t)4096, part2);
+    const int64_t n1 = (int64_t)kFP * HP, n2 = (int64_t)HP * HP;
+    hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part1, L.kchunks, n1, sum1);
+    hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part2, L.kchunks, n2, sum2);
+    hipLaunchKernelGGL(unpad_copy, dim3((kF * H1 + 255) / 256), dim3(256), 0, s, sum1, HP, kF, H1, g->W1);
+    hipLaunchKernelGGL(unpad_copy, dim3((H1 * H2 + 255) / 256), dim3(256), 0, s, sum2, HP, H1, H2, g->W2);
+  }
+  hipLaunchKernelGGL(column_sums, dim3((H1 + 255) / 256), dim3(256), 0, s, Y1, HP, L.K, H1, true, g->b1);
+  hipLaunchKernelGGL(column_sums, dim3((H2 + 255) / 256), dim3(256), 0, s, Y2, HP, L.K, H2, true, g->b2);
+  hipLaunchKernelGGL(w3_grad, dim3((H2 + 255) / 256), dim3(256), 0, s, w3g, HP, (int64_t)N, H2, m.M, g->W3);
+  hipLaunchKernelGGL(species_sums, dim3(1), dim3(64), 0, s, m, sys, ebar, qsig, g->scale, g->shift, g->b3);
+  hipLaunchKernelGGL(sum_partials, dim3((nslots + 255) / 256), dim3(256), 0, s, bpart, L.beta_blocks,
+                     (int64_t)nslots, bsum);
+  hipLaunchKernelGGL(beta_unpack, dim3((nsp * nsp * kS * m.K + 255) / 256), dim3(256), 0, s, bsum, nsp, m.K, g->beta);
+  return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
+}
+
+}  // namespace gmnn

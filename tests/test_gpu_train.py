@@ -1,0 +1,66 @@
+"""Training gradients (energy + force loss, double backward) through the C
+ABI vs the FP64 oracle's autograd gradients, and the torch.autograd.Function."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import brute_force_neighbors, evaluate, loss_and_param_grads
+from oracle.gmnn import PARAM_NAMES
+from workloads import make_workload
+from workloads.configs import ModelSpec, make_params
+from gpu_helpers import gpu, need_gpu
+
+pytestmark = gpu
+
+
+def _case(name="train", hidden=None, **kw):
+    batch, params, spec = make_workload(name, **kw)
+    if hidden is not None:
+        import dataclasses
+        s2 = dataclasses.replace(spec.model, hidden=hidden)
+        params = make_params(s2, 7)
+        spec = dataclasses.replace(spec, model=s2)
+    teacher = make_params(params.spec, 107)
+    onl = brute_force_neighbors(batch, params.spec.r_cut)
+    rt = evaluate(batch, teacher, onl)
+    return batch, params, onl, rt.energy_mean, rt.forces
+
+
+@pytest.mark.parametrize("hidden", [(32, 32), (512, 512)])
+def test_param_gradients_match_oracle(hidden):
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(hidden=hidden, n_structs=3, n_lo=30, n_hi=70)
+    L, gref, dLdE, dLdF = loss_and_param_grads(batch, params, onl, Er, Fr)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, params.spec.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    grads = g.param_grads(model, system, nl, dLdE, dLdF)
+    torch.cuda.synchronize()
+    for k in PARAM_NAMES:
+        got = grads[k].cpu().numpy().astype(np.float64).reshape(np.shape(gref[k]))
+        ref = gref[k]
+        err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+        print(k, err)
+        assert err < 1e-4, (k, err)
+
+
+def test_autograd_function_matches_oracle_loss_gradient():
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(hidden=(64, 64), n_structs=2, n_lo=40, n_hi=60)
+    L, gref, _, _ = loss_and_param_grads(batch, params, onl, Er, Fr)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, params.spec.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    ps = [p.requires_grad_(True) for p in model.params()]
+    E, F = g.EnergyForcesFunction.apply(model, system, nl, *ps)
+    nb = torch.as_tensor(np.diff(batch.atom_ptr), dtype=torch.float64, device="cuda")
+    Er_t = torch.as_tensor(Er, device="cuda")
+    Fr_t = torch.as_tensor(Fr, dtype=torch.float32, device="cuda")
+    loss = (((E - Er_t) / nb) ** 2).sum() / batch.n_structs + ((F - Fr_t) ** 2).sum().double() / (3 * batch.n_atoms)
+    assert abs(loss.item() - L) < 1e-5 * max(1.0, abs(L))
+    loss.backward()
+    for k, p in zip(PARAM_NAMES, ps):
+        ref = gref[k]
+        got = p.grad.cpu().numpy().astype(np.float64).reshape(np.shape(ref))
+        err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+        assert err < 1e-4, (k, err)
