@@ -37,6 +37,8 @@ struct Tables {
   unsigned char pair_index[25];
   unsigned char tri_s1[35], tri_s2[35], tri_s3[35];
   unsigned char tri_index[125];
+  unsigned char tri_xp[kS * 15];  // sorted-triple index of (x, s1, s2), p = (s1 <= s2)
+  float c5[kS * 15];              // 3 (2 if s1 != s2) / (distinct orderings of {x, s1, s2})
 };
 
 __device__ inline void load_tables(Tables* t) {
@@ -57,6 +59,13 @@ __device__ inline void load_tables(Tables* t) {
       t->tri_s3[k] = c_tri_s3[k];
     }
     t->tri_index[k] = c_tri_index[k / 25][(k / 5) % 5][k % 5];
+    if (k < kS * 15) {
+      const int x = k / 15, p = k % 15;
+      const int s1 = c_pair_s1[p], s2 = c_pair_s2[p];
+      const int mult = (x == s1 && s1 == s2) ? 1 : ((x == s1 || x == s2 || s1 == s2) ? 3 : 6);
+      t->tri_xp[k] = c_tri_index[x][s1][s2];
+      t->c5[k] = 3.0f * (s1 != s2 ? 2.0f : 1.0f) / (float)mult;
+    }
   }
 }
 
@@ -235,6 +244,7 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
       v = GM_GB(a, x);
     } else {
       const int i = r - 1;
+#pragma unroll
       for (int sp = 0; sp < kS; ++sp) {
         const int p = tb.pair_index[x * 5 + sp];
         const float f2 = (x == sp) ? 2.0f : 1.0f;
@@ -244,7 +254,10 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
         for (int s3 = 0; s3 < kS; ++s3) w6 += GM_GB(a, kFam6 + p * 5 + s3) * GM_I(a, kV6 + (s3 * 5 + sp) * 3 + i);
         v += f2 * w6;
       }
-      for (int s23 = 0; s23 < 25; ++s23) v += GM_GB(a, kFam8 + x * 25 + s23) * GM_I(a, kV8 + s23 * 3 + i);
+      float v8 = 0.0f;
+#pragma unroll
+      for (int s23 = 0; s23 < 25; ++s23) v8 += GM_GB(a, kFam8 + x * 25 + s23) * GM_I(a, kV8 + s23 * 3 + i);
+      v += v8;
     }
     Pb[a * PS + x * kFull + r] = v;
   }
@@ -254,17 +267,20 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
     const int x = e / 9, ij = e % 9;
     const int i = ij / 3, j = ij % 3;
     float v = 0.0f;
+#pragma unroll
     for (int sp = 0; sp < kS; ++sp)
       v += (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam3 + tb.pair_index[x * 5 + sp]) * GM_P2(a, sp, ij);
+    float v5 = 0.0f, v6 = 0.0f, v7 = 0.0f, v8 = 0.0f;
+#pragma unroll
     for (int p = 0; p < 15; ++p) {
       const int s1 = tb.pair_s1[p], s2 = tb.pair_s2[p];
-      const int mult = (x == s1 && s1 == s2) ? 1 : ((x == s1 || x == s2 || s1 == s2) ? 3 : 6);
-      const float c5 = 3.0f * (s1 != s2 ? 2.0f : 1.0f) / (float)mult;
-      v += c5 * GM_GB(a, kFam5 + tb.tri_index[x * 25 + s1 * 5 + s2]) * GM_I(a, kM5 + p * 9 + ij);
-      v += GM_GB(a, kFam6 + p * 5 + x) * GM_P1(a, s1, i) * GM_P1(a, s2, j);
-      v += GM_GB(a, kFam7 + x * 15 + p) * GM_I(a, kT7 + p * 9 + ij);
+      v5 += tb.c5[x * 15 + p] * GM_GB(a, kFam5 + tb.tri_xp[x * 15 + p]) * GM_I(a, kM5 + p * 9 + ij);
+      v6 += GM_GB(a, kFam6 + p * 5 + x) * GM_P1(a, s1, i) * GM_P1(a, s2, j);
+      v7 += GM_GB(a, kFam7 + x * 15 + p) * GM_I(a, kT7 + p * 9 + ij);
     }
-    for (int s12 = 0; s12 < 25; ++s12) v += GM_GB(a, kFam8 + s12 * 5 + x) * GM_I(a, kU8 + s12 * 9 + ij);
+#pragma unroll
+    for (int s12 = 0; s12 < 25; ++s12) v8 += GM_GB(a, kFam8 + s12 * 5 + x) * GM_I(a, kU8 + s12 * 9 + ij);
+    v += (v5 + v6) + (v7 + v8);
     Pb[a * PS + x * kFull + 4 + ij] = v;
   }
   // Psi3 entries: (x, i bc)
@@ -273,6 +289,7 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
     const int x = e / 27, ibc = e % 27;
     const int i = ibc / 9, bc = ibc % 9;
     float v = 0.0f;
+#pragma unroll
     for (int sp = 0; sp < kS; ++sp) {
       v += (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam4 + tb.pair_index[x * 5 + sp]) * GM_P3(a, sp, ibc);
 #pragma unroll

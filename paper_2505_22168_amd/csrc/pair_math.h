@@ -71,8 +71,17 @@ __device__ inline void rs_swap(float* v) {
 // 128 values (100 live + 28 zero) per lane, summed over the LPA lanes of an
 // atom.  LPA = 16: lane q of the row owns indices 8q..8q+7 (v[0..7]).
 // LPA = 64: lane q of the wave owns indices 2q, 2q+1 (v[0..1]).
+// LPA = 32: lane q of the half wave owns indices 4q .. 4q+3 (v[0..3]).
 template <int LPA>
 __device__ inline void reduce_scatter_128(float* v, int q) {
+  if (LPA == 32) {
+    rs_swap<64, 16>(v);
+    rs_step<32, 0>(v, (q >> 3) & 1);
+    rs_step<16, 1>(v, (q >> 2) & 1);
+    rs_step<8, 2>(v, (q >> 1) & 1);
+    rs_step<4, 3>(v, q & 1);
+    return;
+  }
   if (LPA == 64) {
     rs_swap<64, 32>(v);
     rs_swap<32, 16>(v);
@@ -92,10 +101,8 @@ __device__ inline void reduce_scatter_128(float* v, int q) {
 template <int LPA>
 __device__ inline float atom_sum(float v) {
   v = row16_sum(v);
-  if (LPA == 64) {
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-  }
+  if (LPA >= 32) v += __shfl_xor(v, 16, 64);
+  if (LPA == 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 

@@ -2,8 +2,8 @@
 //
 // One block of 512 threads (8 waves) owns a tile of TM = 16 atoms and keeps
 // everything of the tile in LDS:
-//   [FUSED only] pair moments of its atoms (Section 2.1, eq. basis_fn), one
-//                wave per atom
+//   [FUSED only] pair moments of its atoms (Section 2.1, eq. basis_fn), two
+//                atoms per wave, 32 lanes each
 //   invariants  (Section 2.1, eq. contraction): families 1-4 and the
 //               intermediates T7, V8, M5, v6 in one pass, families 5-8 in a
 //               second pass
@@ -12,7 +12,7 @@
 //   invariants backward: intermediates U8, Y, Qv, then every entry of
 //               dE/dPsi in one pass, folded onto the packed components
 //   [FUSED only] pair backward of its atoms (Section 3.3): per-pair
-//               gradients and the per-atom virial, one wave per atom
+//               gradients and the per-atom virial, two atoms per wave
 // The fused kernel serves small systems, where the whole step is latency
 // bound and one launch per stage would dominate; the unfused readout serves
 // large systems between the high-occupancy pair kernels.
@@ -103,21 +103,23 @@ __global__ void __launch_bounds__(kTileThreads)
   __syncthreads();
 
   // ---- moments -> full tensors in LDS ------------------------------------
+  // fused pair stages: each wave runs two atoms at once, 32 lanes each
+  static_assert(TM == 2 * kTileWaves, "two atoms per wave");
+  const int fa = w + kTileWaves * (l >> 5);  // this half wave's atom
+  const int fq = l & 31;
   if (FUSED) {
-    for (int a = w; a < TM; a += kTileWaves) {
-      float v[128];
+    float v[128];
 #pragma unroll
-      for (int k = 0; k < 128; ++k) v[k] = 0.0f;
-      if (a < n_rows) atom_moments<64>(m, sys, s_beta, row0 + a, l, v);
-      reduce_scatter_128<64>(v, l);
+    for (int k = 0; k < 128; ++k) v[k] = 0.0f;
+    if (fa < n_rows) atom_moments<32>(m, sys, s_beta, row0 + fa, fq, v);
+    reduce_scatter_128<32>(v, fq);
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int k = 2 * l + e;
-        if (k < kS * kPacked) {
-          const int s = k / kPacked, t = k % kPacked;
-          const int n = tb.packed_mult[t];
-          for (int q = 0; q < n; ++q) sPsi[a * PS + s * kFull + tb.packed_full[t][q]] = v[e];
-        }
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * fq + e;
+      if (k < kS * kPacked) {
+        const int s = k / kPacked, t = k % kPacked;
+        const int n = tb.packed_mult[t];
+        for (int q = 0; q < n; ++q) sPsi[fa * PS + s * kFull + tb.packed_full[t][q]] = v[e];
       }
     }
   } else {
@@ -159,24 +161,24 @@ __global__ void __launch_bounds__(kTileThreads)
       __syncthreads();
       // ---- pair backward -----------------------------------------------------
       float* g_head = gpair + (int64_t)hm * gstride * 3;
-      for (int a = w; a < TM; a += kTileWaves) {
+      {
         float vir[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) vir[k] = 0.0f;
-        if (a < n_rows) {
+        if (fa < n_rows) {
           float pb[kS * kPacked];
 #pragma unroll
-          for (int k = 0; k < kS * kPacked; ++k) pb[k] = sPsibar[a * (kS * kPacked) + k];
-          atom_pair_backward<64>(m, sys, s_beta, row0 + a, l, pb, g_head, vir);
+          for (int k = 0; k < kS * kPacked; ++k) pb[k] = sPsibar[fa * (kS * kPacked) + k];
+          atom_pair_backward<32>(m, sys, s_beta, row0 + fa, fq, pb, g_head, vir);
         }
 #pragma unroll
-        for (int k = 0; k < 9; ++k) vir[k] = atom_sum<64>(vir[k]);
-        if (l < 9) {
+        for (int k = 0; k < 9; ++k) vir[k] = atom_sum<32>(vir[k]);
+        if (fq < 9) {
           float vk = vir[0];
 #pragma unroll
           for (int k = 1; k < 9; ++k)
-            if (l == k) vk = vir[k];
-          sVir[a * 9 + l] += vk;
+            if (fq == k) vk = vir[k];
+          sVir[fa * 9 + fq] += vk;
         }
       }
       __syncthreads();
