@@ -83,9 +83,9 @@ def algorithmic_work(spec, n_atoms, n_pairs):
     }
 
 
-def run_path(g, A, model, system, nl, precision, steps, warmup, events):
+def run_path(g, A, model, system, nl, precision, steps, warmup, events, plan="auto", force_var=False):
     import torch
-    ev = g.EnergyForces(model, system, nl, precision=precision, stress=True)
+    ev = g.EnergyForces(model, system, nl, precision=precision, stress=True, force_var=force_var, plan=plan)
     for _ in range(warmup):
         ev()
     torch.cuda.synchronize()
@@ -101,8 +101,8 @@ def run_path(g, A, model, system, nl, precision, steps, warmup, events):
     torch.cuda.synchronize()
     for k in range(steps):
         st = lib.gmnn_energy_forces_timed(C.byref(ev._mc), C.byref(ev._sc), C.byref(ev._nc), ev.flags,
-                                          C.byref(ev._oc), C.c_void_p(ev.workspace.data_ptr()), ev.ws_bytes,
-                                          stream, evs[k])
+                                          None if ev._plan is None else C.byref(ev._plan), C.byref(ev._oc),
+                                          C.c_void_p(ev.workspace.data_ptr()), ev.ws_bytes, stream, evs[k])
         A.check(st, "gmnn_energy_forces_timed")
     torch.cuda.synchronize()
     stage_ms = {name: float(np.mean([events.elapsed_ms(e[2 * s], e[2 * s + 1]) for e in evs]))
@@ -118,7 +118,7 @@ def run_path(g, A, model, system, nl, precision, steps, warmup, events):
     overhead = float(np.median([events.elapsed_ms(e[0], e[1]) for e in empty]))
     for e in empty:
         events.destroy(e)
-    if lib.gmnn_uses_fused_path(C.byref(ev._mc), C.byref(ev._sc), ev.flags) == 1:
+    if ev.plan["schedule"] == A.GMNN_SCHEDULE_FUSED:
         # small systems run moments, readout and pair backward in one launch
         stage_ms = {"fused_tile": stage_ms["pair_moments"], "finish": stage_ms["finish"]}
     stage_ms = {k: max(v - overhead, 0.0) for k, v in stage_ms.items()}
@@ -126,6 +126,7 @@ def run_path(g, A, model, system, nl, precision, steps, warmup, events):
     for e in evs:
         events.destroy(e)
     out = ev(sync=True)
+    stage_ms["_plan"] = ev.plan
     return wall, stage_ms, out
 
 
@@ -204,6 +205,106 @@ def run_md(args):
     print(json.dumps(line))
 
 
+def _wall(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_ensemble(args):
+    """Shallow-ensemble batched inference: all structures of the workload in
+    one launch sequence (head-mean energy and forces, energy variance, per-atom
+    force variance from one backward per head) vs the same evaluation issued
+    structure by structure."""
+    import torch
+    import paper_2505_22168_amd as g
+    from workloads import make_workload
+    name = args.workload if args.workload != "liquid" else "ensemble"
+    batch, params, spec = make_workload(name)
+    dev = torch.device("cuda:0")
+    model = g.Model.from_params(params, dev)
+    system = g.System.from_batch(batch, dev)
+    nl = g.build_neighbors(system, spec.model.r_cut, spec.skin)
+    plan = None if args.plan == "builtin" else "auto"
+    out = {}
+    for prec in ("bf16", "fp32"):
+        ev = g.EnergyForces(model, system, nl, precision=prec, stress=True, force_var=True, plan=plan)
+        t_batched = _wall(ev, args.steps, args.warmup)
+        per = []
+        for b in range(batch.n_structs):
+            sb = batch.structure(b)
+            s_sys = g.System.from_batch(sb, dev)
+            s_nl = g.build_neighbors(s_sys, spec.model.r_cut, spec.skin)
+            per.append(g.EnergyForces(model, s_sys, s_nl, precision=prec, stress=True, force_var=True, plan=plan))
+
+        def all_structs():
+            for e in per:
+                e()
+        t_per = _wall(all_structs, max(1, args.steps // 5), 2)
+        # the two must agree (same kernels, same order within a structure)
+        o = ev(sync=True)
+        e_b = o.energy.cpu().numpy()
+        e_s = np.concatenate([e(sync=True).energy.cpu().numpy() for e in per])
+        out[prec] = {"batched_ms": t_batched * 1e3, "per_structure_ms": t_per * 1e3,
+                     "batched_atom_evals_per_s": batch.n_atoms / t_batched,
+                     "per_structure_atom_evals_per_s": batch.n_atoms / t_per, "speedup": t_per / t_batched,
+                     "plan": ev.plan, "energy_max_abs_diff_batched_vs_single": float(np.abs(e_b - e_s).max())}
+        print(f"[bench-ensemble] {prec}: {out[prec]}", file=sys.stderr, flush=True)
+    line = {"metric": "shallow-ensemble energy+force(+variance) atom-evals/s, batched vs per-structure",
+            "value": out["bf16"]["batched_atom_evals_per_s"], "unit": "atom-evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": name, "n_atoms": batch.n_atoms, "n_structs": batch.n_structs,
+                       "n_pairs": nl.n_pairs, "heads": spec.model.n_heads, "mlp": list(spec.model.hidden)},
+            "bf16": out["bf16"], "fp32": out["fp32"]}
+    print(json.dumps(line))
+
+
+def run_train(args):
+    """Training-gradient step of the energy+force loss: energies and forces
+    (FP32), then the loss gradients w.r.t. every parameter (double backward)."""
+    import torch
+    import paper_2505_22168_amd as g
+    from workloads import make_workload
+    name = args.workload if args.workload != "liquid" else "train"
+    batch, params, spec = make_workload(name)
+    dev = torch.device("cuda:0")
+    model = g.Model.from_params(params, dev)
+    system = g.System.from_batch(batch, dev)
+    nl = g.build_neighbors(system, spec.model.r_cut, spec.skin)
+    ev = g.EnergyForces(model, system, nl, precision="fp32", stress=False)
+    rng = np.random.default_rng(7)
+    dE = torch.as_tensor(rng.normal(size=batch.n_structs), device=dev)
+    dF = torch.as_tensor(rng.normal(size=(batch.n_atoms, 3)).astype(np.float32), device=dev)
+    ws = None
+
+    def step():
+        nonlocal ws
+        ev()
+        grads = g.param_grads(model, system, nl, dE, dF, workspace=ws)
+        return grads
+
+    lib = g.load_library()
+    from paper_2505_22168_amd import _capi as A
+    nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(model.c()), C.byref(system.c()),
+                                      C.byref(nl.c()), 0)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    t = _wall(step, args.steps, args.warmup)
+    t_fwd = _wall(ev, args.steps, args.warmup)
+    line = {"metric": "training-gradient atom-evals/s (energy+forces, then parameter gradients of an "
+                      "energy+force loss)", "value": batch.n_atoms / t, "unit": "atom-evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "dtype": "fp32",
+            "data": "synthetic", "forward_ms": t_fwd * 1e3, "backward_ms": (t - t_fwd) * 1e3,
+            "config": {"workload": name, "n_atoms": batch.n_atoms, "n_structs": batch.n_structs,
+                       "n_pairs": nl.n_pairs, "mlp": list(spec.model.hidden)}}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +315,12 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip oracle errors and the CPU baseline")
     ap.add_argument("--md", action="store_true", help="time whole MD steps instead (not the headline metric)")
     ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--plan", default="auto", choices=["auto", "builtin"],
+                    help="execution plan: autotuned (cached per shape class) or the library's built-in choice")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="C5 mode: one batched launch (heads, energy/force variance) vs per-structure launches")
+    ap.add_argument("--train", action="store_true",
+                    help="training-gradient mode: energy+forces then gmnn_backward per step (FP32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -222,6 +329,13 @@ def main():
 
     if args.md:
         return run_md(args)
+    if args.plan == "auto" and "GMNN_TUNE_CACHE" not in os.environ:
+        import tempfile
+        os.environ["GMNN_TUNE_CACHE"] = os.path.join(tempfile.gettempdir(), f"gmnn_tune_{os.getpid()}.json")
+    if args.ensemble:
+        return run_ensemble(args)
+    if args.train:
+        return run_train(args)
     import torch
     import paper_2505_22168_amd as g
     from paper_2505_22168_amd import _capi as A
@@ -240,12 +354,14 @@ def main():
 
     res = {}
     for prec in ("bf16", "fp32"):
-        wall, stage_ms, out = run_path(g, A, model, system, nl, prec, args.steps, args.warmup, events)
-        res[prec] = (wall, stage_ms, out)
-        print(f"[bench] {prec}: {wall / args.steps * 1e3:.4f} ms/step, stages(us) "
+        wall, stage_ms, out = run_path(g, A, model, system, nl, prec, args.steps, args.warmup, events,
+                                       plan=None if args.plan == "builtin" else "auto")
+        plan = stage_ms.pop("_plan")
+        res[prec] = (wall, stage_ms, out, plan)
+        print(f"[bench] {prec}: {wall / args.steps * 1e3:.4f} ms/step, plan {plan}, stages(us) "
               + ", ".join(f"{k}={v * 1e3:.1f}" for k, v in stage_ms.items()), file=sys.stderr, flush=True)
 
-    wall, stage_ms, out16 = res["bf16"]
+    wall, stage_ms, out16, plan16 = res["bf16"]
     ms_per_step = wall / args.steps * 1e3
     value = N * args.steps / wall
     work = algorithmic_work(spec.model, N, P)
@@ -264,9 +380,9 @@ def main():
                                "avg_duration_us": stage_ms[dom] * 1e3,
                                "event_bracket_overhead_us_subtracted": overhead_ms * 1e3}}
 
-    wall32, stage32, out32 = res["fp32"]
+    wall32, stage32, out32, plan32 = res["fp32"]
     fp32 = {"value": N * args.steps / wall32, "ms_per_step": wall32 / args.steps * 1e3,
-            "stages_us": {k: v * 1e3 for k, v in stage32.items()}}
+            "stages_us": {k: v * 1e3 for k, v in stage32.items()}, "plan": plan32}
 
     accuracy = None
     cpu = None
@@ -286,7 +402,7 @@ def main():
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": args.workload, "n_atoms": N, "n_pairs": P, "n_structs": batch.n_structs,
                    "r_cut": spec.model.r_cut, "mlp": list(spec.model.hidden), "heads": spec.model.n_heads,
-                   "features": spec.model.n_features, "parallelism": "single GPU"},
+                   "features": spec.model.n_features, "parallelism": "single GPU", "plan": plan16},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_us": {k: v * 1e3 for k, v in stage_ms.items()},

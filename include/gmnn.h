@@ -215,22 +215,70 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
                                const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
                                void* workspace, size_t workspace_bytes, void* stream);
 
-/* gmnn_energy_forces with a hipEvent_t recorded on `stream` right before and
- * right after each kernel stage, for profiling: stage_events[2k] / [2k+1]
- * bracket stage k = 0 pair moments (on small systems: the fused tile kernel,
- * which also covers stages 1 and 2), 1 readout (invariants + network +
- * invariant backward), 2 pair backward, 3 force gather + per-structure
- * reductions (8 events, created by the caller with hipEventCreate). */
-/* 1 if gmnn_energy_forces runs the fused small-system schedule for these
- * shapes and flags (moments, readout and pair backward in one launch, then
- * the gather/reduction launch), 0 for the four-launch schedule, -1 on
- * invalid arguments.  Host only. */
+/* ---------------------------------------------------------------------- */
+/* Execution plans.  Every plan computes the same quantities (up to FP32
+ * summation order); they differ in how the work is cut into kernels:
+ *   FUSED  one tile kernel computes the moments, the readout and the pair
+ *          backward of 16 atoms, then one kernel gathers the forces and sums
+ *          per structure (latency-bound small systems; needs <= 8 species,
+ *          no force variance, every structure <= 8192 atoms);
+ *   SPLIT  pair moments -> readout tiles -> pair backward -> gather/sums.
+ * lanes_per_atom (16, 32 or 64) is the number of lanes that share one atom's
+ * neighbour row in the pair and gather kernels.  Zero fields mean "built-in
+ * choice": FUSED with 64 lanes below 8192 atoms, SPLIT with 16 beyond. */
+#define GMNN_SCHEDULE_AUTO 0
+#define GMNN_SCHEDULE_FUSED 1
+#define GMNN_SCHEDULE_SPLIT 2
+typedef struct gmnn_plan {
+  int32_t schedule;        /* GMNN_SCHEDULE_* */
+  int32_t lanes_per_atom;  /* 0, 16, 32 or 64 */
+} gmnn_plan;
+
+/* Resolve the zero fields of `plan` (NULL: all zero) for these shapes and
+ * flags into `resolved` (may be NULL).  GMNN_ERR_UNSUPPORTED if the plan
+ * cannot run them, GMNN_ERR_INVALID_ARG for an unknown field value.  Host only. */
+gmnn_status gmnn_resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint32_t flags,
+                              const gmnn_plan* plan, gmnn_plan* resolved);
+
+/* 1 if the built-in plan for these shapes and flags is FUSED, 0 if SPLIT,
+ * -1 on invalid arguments.  Host only. */
 int32_t gmnn_uses_fused_path(const gmnn_model* m, const gmnn_system* sys, uint32_t flags);
 
+/* gmnn_energy_forces under an explicit plan (NULL: the built-in one). */
+gmnn_status gmnn_energy_forces_plan(const gmnn_model* m, const gmnn_system* sys,
+                                    const gmnn_neighbors* nl, uint32_t flags, const gmnn_plan* plan,
+                                    gmnn_outputs* out, void* workspace, size_t workspace_bytes,
+                                    void* stream);
+
+/* gmnn_energy_forces_plan with a hipEvent_t recorded on `stream` right before
+ * and right after each kernel stage, for profiling: stage_events[2k] /
+ * [2k+1] bracket stage k = 0 pair moments (FUSED: the tile kernel, which also
+ * covers stages 1 and 2), 1 readout (invariants + network + invariant
+ * backward), 2 pair backward, 3 force gather + per-structure reductions
+ * (8 events, created by the caller with hipEventCreate; NULL: none). */
 gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys,
-                                     const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
-                                     void* workspace, size_t workspace_bytes, void* stream,
-                                     void* const* stage_events);
+                                     const gmnn_neighbors* nl, uint32_t flags, const gmnn_plan* plan,
+                                     gmnn_outputs* out, void* workspace, size_t workspace_bytes,
+                                     void* stream, void* const* stage_events);
+
+/* Autotuner: runs gmnn_energy_forces under every plan these shapes support
+ * (2 warm-up calls, then `reps` calls each bracketed by hipEvents on
+ * `stream`), and returns in *best the plan of least median time.  The
+ * candidates and their median / minimum times in microseconds go to
+ * entries[0 .. min(max_entries, *n_entries)) (entries may be NULL when
+ * max_entries is 0).  Synchronises `stream`; `out` ends holding the results
+ * of the chosen plan.  Same workspace as gmnn_energy_forces.  The choice
+ * depends on the shapes (atom count, structure sizes, neighbours per atom,
+ * model widths, flags), not on positions: callers may cache it per shape. */
+typedef struct gmnn_tune_entry {
+  gmnn_plan plan;
+  float median_us;
+  float min_us;
+} gmnn_tune_entry;
+gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                          uint32_t flags, gmnn_outputs* out, void* workspace, size_t workspace_bytes,
+                          void* stream, int32_t reps, gmnn_plan* best, gmnn_tune_entry* entries,
+                          int32_t max_entries, int32_t* n_entries);
 
 /* Gradients of a scalar loss L(E, F) w.r.t. the model parameters and the
  * positions, given the upstream gradients dL/dE (per structure, w.r.t. the

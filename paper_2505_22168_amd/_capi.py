@@ -28,6 +28,10 @@ GMNN_WANT_STRESS = 2
 GMNN_WANT_FORCE_VAR = 4
 GMNN_SYNC = 8
 
+GMNN_SCHEDULE_AUTO = 0
+GMNN_SCHEDULE_FUSED = 1
+GMNN_SCHEDULE_SPLIT = 2
+
 GMNN_OP_NEIGHBORS = 0
 GMNN_OP_ENERGY_FORCES = 1
 GMNN_OP_BACKWARD = 2
@@ -63,6 +67,14 @@ class gmnn_md(C.Structure):
                 ("energy", vp), ("ref_pos", vp), ("disp", vp)]
 
 
+class gmnn_plan(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("lanes_per_atom", C.c_int32)]
+
+
+class gmnn_tune_entry(C.Structure):
+    _fields_ = [("plan", gmnn_plan), ("median_us", C.c_float), ("min_us", C.c_float)]
+
+
 class gmnn_outputs(C.Structure):
     _fields_ = [("energy", vp), ("forces", vp), ("stress", vp), ("energy_var", vp),
                 ("force_var", vp), ("atomic_energy", vp)]
@@ -80,10 +92,19 @@ EXPORTS = {
                                          C.POINTER(gmnn_neighbors), C.c_uint32, vp, C.c_size_t, vp]),
     "gmnn_energy_forces": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
                                        C.c_uint32, C.POINTER(gmnn_outputs), vp, C.c_size_t, vp]),
+    "gmnn_resolve_plan": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.c_uint32,
+                                      C.POINTER(gmnn_plan), C.POINTER(gmnn_plan)]),
     "gmnn_uses_fused_path": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.c_uint32]),
+    "gmnn_energy_forces_plan": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
+                                            C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_plan),
+                                            C.POINTER(gmnn_outputs), vp, C.c_size_t, vp]),
     "gmnn_energy_forces_timed": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
-                                             C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_outputs), vp,
-                                             C.c_size_t, vp, vp]),
+                                             C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_plan),
+                                             C.POINTER(gmnn_outputs), vp, C.c_size_t, vp, vp]),
+    "gmnn_autotune": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
+                                  C.c_uint32, C.POINTER(gmnn_outputs), vp, C.c_size_t, vp, C.c_int32,
+                                  C.POINTER(gmnn_plan), C.POINTER(gmnn_tune_entry), C.c_int32,
+                                  C.POINTER(C.c_int32)]),
     "gmnn_backward": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
                                   vp, vp, C.c_uint32, C.POINTER(gmnn_param_grads), vp, vp, C.c_size_t, vp]),
     "gmnn_md_workspace_bytes": (C.c_size_t, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),

@@ -203,7 +203,10 @@ class EnergyForces:
     list / model shape, so repeated calls allocate nothing."""
 
     def __init__(self, model: Model, system: System, nl: NeighborList, precision: str = "bf16",
-                 stress: bool = True, force_var: bool = False):
+                 stress: bool = True, force_var: bool = False, plan=None):
+        """plan: None (the library's built-in choice), "auto" (the autotuned
+        plan of this shape class, cached; tunes on first use), or a dict /
+        (schedule, lanes_per_atom) pair with GMNN_SCHEDULE_* and 16/32/64."""
         self.model, self.system, self.nl = model, system, nl
         self.flags = (A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32)
         if precision not in ("bf16", "fp32"):
@@ -232,19 +235,46 @@ class EnergyForces:
         o = self.out
         self._oc = A.gmnn_outputs(_ptr(o.energy), _ptr(o.forces), _ptr(o.stress), _ptr(o.energy_var),
                                   _ptr(o.force_var), _ptr(o.atomic_energy))
+        self._plan = None
+        self.set_plan(plan)
+
+    def set_plan(self, plan):
+        if isinstance(plan, str):
+            if plan != "auto":
+                raise ValueError(plan)
+            from .autotune import tuned_plan
+            plan = tuned_plan(self)
+        if plan is None:
+            self._plan = None
+            return
+        if isinstance(plan, dict):
+            plan = (plan["schedule"], plan["lanes_per_atom"])
+        self._plan = A.gmnn_plan(int(plan[0]), int(plan[1]))
+        A.check(A.load().gmnn_resolve_plan(C.byref(self._mc), C.byref(self._sc), self.flags,
+                                           C.byref(self._plan), None), "gmnn_resolve_plan")
+
+    @property
+    def plan(self) -> dict:
+        """The plan the library runs (zero fields resolved)."""
+        r = A.gmnn_plan()
+        A.check(A.load().gmnn_resolve_plan(C.byref(self._mc), C.byref(self._sc), self.flags,
+                                           None if self._plan is None else C.byref(self._plan), C.byref(r)),
+                "gmnn_resolve_plan")
+        return {"schedule": r.schedule, "lanes_per_atom": r.lanes_per_atom}
 
     def __call__(self, sync: bool = False) -> Outputs:
         flags = self.flags | (A.GMNN_SYNC if sync else 0)
-        st = A.load().gmnn_energy_forces(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), flags,
-                                         C.byref(self._oc), _ptr(self.workspace), self.ws_bytes, _stream())
+        st = A.load().gmnn_energy_forces_plan(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), flags,
+                                              None if self._plan is None else C.byref(self._plan),
+                                              C.byref(self._oc), _ptr(self.workspace), self.ws_bytes, _stream())
         A.check(st, "gmnn_energy_forces")
         return self.out
 
 
 def energy_forces(model: Model, system: System, nl: NeighborList, precision: str = "bf16", stress: bool = True,
-                  force_var: bool = False) -> Outputs:
+                  force_var: bool = False, plan=None) -> Outputs:
     """One evaluation (allocates its outputs and workspace)."""
-    return EnergyForces(model, system, nl, precision, stress, force_var)(sync=False)
+    return EnergyForces(model, system, nl, precision, stress, force_var, plan)(sync=False)
 
 
 # ---------------------------------------------------------------------------

@@ -1,7 +1,9 @@
 // C ABI entry points of the GMNN library (declared in include/gmnn.h).
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 #include "model.h"
@@ -30,11 +32,9 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, int H1, int 
                            const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s);
 
 constexpr int kPairThreads = 256;
-// systems below this many atoms take the fused (latency) path
+// below this many atoms the built-in plan takes the fused (latency) schedule
 constexpr int kFusedMaxAtoms = 8192;
 // per-structure reductions split into chunks of at most this many atoms
-// (never below kFusedMaxAtoms: chunked sums need counters zeroed by the
-// unfused path's first kernel)
 constexpr int kReduceChunk = 8192;
 
 static int reduce_chunks(const gmnn_system* sys) {
@@ -45,6 +45,44 @@ static int reduce_chunks(const gmnn_system* sys) {
   }
   const int64_t c = (mx + kReduceChunk - 1) / kReduceChunk;
   return c < 1 ? 1 : (int)c;
+}
+
+// ---------------------------------------------------------------------------
+// execution plans
+// ---------------------------------------------------------------------------
+struct Plan {
+  bool fused;  // one tile kernel for moments + readout + pair backward
+  int lpa;     // lanes per atom row in the pair and gather kernels
+};
+
+// the fused tile needs few species (beta staged in its LDS), the head-mean
+// backward only, and one reduction chunk per structure (its chunk counters
+// are zeroed by the split schedule's first kernel)
+static bool fused_allowed(const gmnn_model* m, const gmnn_system* sys, uint32_t flags, int HP1) {
+  return tile_fused_supported(m->n_species, HP1, (flags & GMNN_PREC_BF16) != 0, (flags & GMNN_WANT_FORCE_VAR) != 0) &&
+         reduce_chunks(sys) == 1;
+}
+
+// fills the AUTO fields of `in` (built-in heuristic: the fused schedule for
+// systems of fewer than kFusedMaxAtoms atoms, 64 lanes per atom there and 16
+// beyond); UNSUPPORTED for a plan these shapes cannot run
+static gmnn_status resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint32_t flags, const gmnn_plan* in,
+                                Plan& out) {
+  const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+  const int sched = in ? in->schedule : GMNN_SCHEDULE_AUTO;
+  const int lpa = in ? in->lanes_per_atom : 0;
+  if (sched != GMNN_SCHEDULE_AUTO && sched != GMNN_SCHEDULE_FUSED && sched != GMNN_SCHEDULE_SPLIT)
+    return GMNN_ERR_INVALID_ARG;
+  if (lpa != 0 && lpa != 16 && lpa != 32 && lpa != 64) return GMNN_ERR_INVALID_ARG;
+  const bool small = sys->n_atoms < kFusedMaxAtoms;
+  const bool can_fuse = fused_allowed(m, sys, flags, L.HP1);
+  if (sched == GMNN_SCHEDULE_FUSED && !can_fuse) return GMNN_ERR_UNSUPPORTED;
+  out.fused = sched == GMNN_SCHEDULE_FUSED || (sched == GMNN_SCHEDULE_AUTO && small && can_fuse);
+  if (!out.fused && tile_lds_bytes(L.HP1, (flags & GMNN_PREC_BF16) != 0, false, (flags & GMNN_WANT_FORCE_VAR) != 0) >
+                        160 * 1024)
+    return GMNN_ERR_UNSUPPORTED;
+  out.lpa = lpa ? lpa : (small ? 64 : 16);
+  return GMNN_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -317,16 +355,30 @@ gmnn_status gmnn_build_neighbors(const gmnn_system* sys, float cutoff, float ski
 
 int32_t gmnn_uses_fused_path(const gmnn_model* m, const gmnn_system* sys, uint32_t flags) {
   if (check_model(m) != GMNN_OK || check_system(sys) != GMNN_OK) return -1;
-  const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
-  return (sys->n_atoms < kFusedMaxAtoms &&
-          tile_fused_supported(m->n_species, L.HP1, (flags & GMNN_PREC_BF16) != 0, (flags & GMNN_WANT_FORCE_VAR) != 0))
-             ? 1
-             : 0;
+  Plan p;
+  if (resolve_plan(m, sys, flags, nullptr, p) != GMNN_OK) return -1;
+  return p.fused ? 1 : 0;
+}
+
+gmnn_status gmnn_resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint32_t flags, const gmnn_plan* plan,
+                              gmnn_plan* resolved) {
+  gmnn_status st = check_model(m);
+  if (st != GMNN_OK) return st;
+  st = check_system(sys);
+  if (st != GMNN_OK) return st;
+  Plan p;
+  st = resolve_plan(m, sys, flags, plan, p);
+  if (st != GMNN_OK) return st;
+  if (resolved) {
+    resolved->schedule = p.fused ? GMNN_SCHEDULE_FUSED : GMNN_SCHEDULE_SPLIT;
+    resolved->lanes_per_atom = p.lpa;
+  }
+  return GMNN_OK;
 }
 
 gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
-                                     uint32_t flags, gmnn_outputs* out, void* workspace, size_t workspace_bytes,
-                                     void* stream, void* const* stage_events) {
+                                     uint32_t flags, const gmnn_plan* plan, gmnn_outputs* out, void* workspace,
+                                     size_t workspace_bytes, void* stream, void* const* stage_events) {
   gmnn_status st = check_model(m);
   if (st != GMNN_OK) return st;
   st = check_system(sys);
@@ -358,9 +410,11 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
     if (ev) hipEventRecord(ev[k], s);
   };
   const bool var = (flags & GMNN_WANT_FORCE_VAR) != 0;
-  const bool fused = N < kFusedMaxAtoms && tile_fused_supported(m->n_species, dm.HP1, bf16, var);
-  if (!fused && tile_lds_bytes(dm.HP1, bf16, false, var) > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
-  const int lpa = (N < kFusedMaxAtoms) ? 64 : 16;
+  Plan P;
+  st = resolve_plan(m, sys, flags, plan, P);
+  if (st != GMNN_OK) return st;
+  const bool fused = P.fused;
+  const int lpa = P.lpa;
   const int nb_gather = (N + kPairThreads / lpa - 1) / (kPairThreads / lpa);
   const int64_t gstride = nl->capacity;
   const int nh = var ? m->n_heads : 1;
@@ -377,31 +431,31 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
     } else {
       mark(0);
       const int nzc = nchunk > 1 ? sys->n_structs : 0;
-      if (lpa == 64)
-        hipLaunchKernelGGL(pair_moments<64>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psi, counters,
-                           nzc);
-      else
-        hipLaunchKernelGGL(pair_moments<16>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psi, counters,
-                           nzc);
+#define MOMENTS(LPA) \
+  hipLaunchKernelGGL(pair_moments<LPA>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psi, counters, nzc)
+      if (lpa == 64) MOMENTS(64);
+      else if (lpa == 32) MOMENTS(32);
+      else MOMENTS(16);
+#undef MOMENTS
       mark(1);
       mark(2);
       st = launch_tile(false, var, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, s);
       if (st != GMNN_OK) return st;
       mark(3);
       mark(4);
-      if (lpa == 64)
-        hipLaunchKernelGGL(pair_backward<64>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair,
-                           virial, nh, gstride);
-      else
-        hipLaunchKernelGGL(pair_backward<16>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair,
-                           virial, nh, gstride);
+#define PAIR_BACKWARD(LPA)                                                                                 \
+  hipLaunchKernelGGL(pair_backward<LPA>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair, \
+                     virial, nh, gstride)
+      if (lpa == 64) PAIR_BACKWARD(64);
+      else if (lpa == 32) PAIR_BACKWARD(32);
+      else PAIR_BACKWARD(16);
+#undef PAIR_BACKWARD
       mark(5);
     }
   }
   mark(6);
   const int want_stress = (flags & GMNN_WANT_STRESS) ? 1 : 0;
   const int nbg = N > 0 ? nb_gather : 0;
-  if (fused && nchunk > 1) return GMNN_ERR_UNSUPPORTED;  // unreachable: fused implies N < kReduceChunk
   const dim3 fgrid(nbg + sys->n_structs * nchunk);
 #define FINISH(LPA, VAR)                                                                                       \
   hipLaunchKernelGGL((finish<LPA, VAR>), fgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial, \
@@ -410,6 +464,9 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   if (lpa == 64) {
     if (var) FINISH(64, true);
     else FINISH(64, false);
+  } else if (lpa == 32) {
+    if (var) FINISH(32, true);
+    else FINISH(32, false);
   } else {
     if (var) FINISH(16, true);
     else FINISH(16, false);
@@ -425,7 +482,79 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
 
 gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
                                gmnn_outputs* out, void* workspace, size_t workspace_bytes, void* stream) {
-  return gmnn_energy_forces_timed(m, sys, nl, flags, out, workspace, workspace_bytes, stream, nullptr);
+  return gmnn_energy_forces_timed(m, sys, nl, flags, nullptr, out, workspace, workspace_bytes, stream, nullptr);
+}
+
+gmnn_status gmnn_energy_forces_plan(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                    uint32_t flags, const gmnn_plan* plan, gmnn_outputs* out, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
+  return gmnn_energy_forces_timed(m, sys, nl, flags, plan, out, workspace, workspace_bytes, stream, nullptr);
+}
+
+gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
+                          gmnn_outputs* out, void* workspace, size_t workspace_bytes, void* stream, int32_t reps,
+                          gmnn_plan* best, gmnn_tune_entry* entries, int32_t max_entries, int32_t* n_entries) {
+  gmnn_status st = check_model(m);
+  if (st != GMNN_OK) return st;
+  st = check_system(sys);
+  if (st != GMNN_OK) return st;
+  if (!best || reps < 1 || reps > 1000 || max_entries < 0 || (max_entries > 0 && !entries))
+    return GMNN_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  static const int kSched[2] = {GMNN_SCHEDULE_FUSED, GMNN_SCHEDULE_SPLIT};
+  static const int kLanes[3] = {16, 32, 64};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return GMNN_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return GMNN_ERR_HIP;
+  }
+  int n = 0;
+  float best_us = 0.0f;
+  bool have = false;
+  std::vector<float> t(reps);
+  for (int si = 0; si < 2 && st == GMNN_OK; ++si) {
+    for (int li = 0; li < 3 && st == GMNN_OK; ++li) {
+      const gmnn_plan cand = {kSched[si], kLanes[li]};
+      Plan P;
+      if (resolve_plan(m, sys, flags, &cand, P) != GMNN_OK) continue;
+      // warm-up (also surfaces argument errors before anything is timed)
+      for (int w = 0; w < 2 && st == GMNN_OK; ++w)
+        st = gmnn_energy_forces_plan(m, sys, nl, flags, &cand, out, workspace, workspace_bytes, stream);
+      for (int r = 0; r < reps && st == GMNN_OK; ++r) {
+        if (hipEventRecord(e0, s) != hipSuccess) st = GMNN_ERR_HIP;
+        if (st == GMNN_OK) st = gmnn_energy_forces_plan(m, sys, nl, flags, &cand, out, workspace, workspace_bytes, stream);
+        if (st == GMNN_OK && hipEventRecord(e1, s) != hipSuccess) st = GMNN_ERR_HIP;
+        if (st == GMNN_OK && hipEventSynchronize(e1) != hipSuccess) st = GMNN_ERR_HIP;
+        float ms = 0.0f;
+        if (st == GMNN_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = GMNN_ERR_HIP;
+        t[r] = 1000.0f * ms;
+      }
+      if (st != GMNN_OK) break;
+      std::sort(t.begin(), t.end());
+      const float med = t[reps / 2];
+      if (n < max_entries) {
+        entries[n].plan = cand;
+        entries[n].median_us = med;
+        entries[n].min_us = t[0];
+      }
+      ++n;
+      if (!have || med < best_us) {
+        have = true;
+        best_us = med;
+        *best = cand;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != GMNN_OK) return st;
+  if (!have) return GMNN_ERR_UNSUPPORTED;
+  if (n_entries) *n_entries = n;
+  // leave the outputs of the chosen plan in `out`
+  st = gmnn_energy_forces_plan(m, sys, nl, flags, best, out, workspace, workspace_bytes, stream);
+  if (st == GMNN_OK && hipStreamSynchronize(s) != hipSuccess) st = GMNN_ERR_HIP;
+  return st;
 }
 
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, const double* dL_dE,

@@ -1,0 +1,91 @@
+"""Every execution plan (fused / split schedule, 16 / 32 / 64 lanes per atom)
+against the FP64 oracle, and the autotuner's choice.
+
+The plans only re-cut the same arithmetic into kernels, so each is held to
+the FP32 bound (|dE|/N <= 1e-5 eV/atom, max|dF| <= 1e-4 eV/A, stress 1e-6)
+and, with force variance, to the oracle's per-head forces."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import brute_force_neighbors, evaluate
+from workloads import make_workload
+from gpu_helpers import gpu, need_gpu
+
+pytestmark = gpu
+
+PLANS = [(1, 16), (1, 32), (1, 64), (2, 16), (2, 32), (2, 64)]
+
+
+def _setup(g, name, kw):
+    batch, params, spec = make_workload(name, **kw)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, spec.model.r_cut, 0.0)
+    model = g.Model.from_params(params, "cuda")
+    return batch, params, spec, system, nl, model
+
+
+def _check(out, ref, batch, var=False):
+    nb = np.diff(batch.atom_ptr)
+    E = out.energy.cpu().numpy()
+    assert (np.abs(E - ref.energy) / nb[:, None]).max() < 1e-5
+    F = out.forces.cpu().numpy()[: batch.n_atoms]
+    assert np.abs(F - ref.forces).max() < 1e-4
+    assert np.abs(out.stress.cpu().numpy() - ref.stress).max() < 1e-6
+    if var:
+        fv = out.force_var.cpu().numpy()[: batch.n_atoms]
+        assert np.allclose(fv, ref.force_var, rtol=1e-3, atol=1e-5)
+        assert np.allclose(out.energy_var.cpu().numpy(), ref.energy_var, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("sched,lanes", PLANS)
+def test_every_plan_matches_oracle(sched, lanes):
+    g = need_gpu()
+    batch, params, spec, system, nl, model = _setup(g, "ensemble", dict(n_structs=6))
+    ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
+    print(f"plan schedule={sched} lanes={lanes} ensemble n_structs=6", flush=True)
+    ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(sched, lanes))
+    assert ev.plan == {"schedule": sched, "lanes_per_atom": lanes}
+    _check(ev(sync=True), ref, batch)
+
+
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+def test_split_plans_with_force_variance(lanes):
+    g = need_gpu()
+    batch, params, spec, system, nl, model = _setup(g, "ensemble", dict(n_structs=4))
+    ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut), want_force_var=True)
+    print(f"force-variance plan lanes={lanes}", flush=True)
+    ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True, force_var=True, plan=(2, lanes))
+    _check(ev(sync=True), ref, batch, var=True)
+
+
+def test_fused_plan_refused_with_force_variance():
+    g = need_gpu()
+    batch, params, spec, system, nl, model = _setup(g, "ensemble", dict(n_structs=2))
+    with pytest.raises(g.GMNNError):
+        g.EnergyForces(model, system, nl, precision="fp32", force_var=True, plan=(1, 16))
+
+
+def test_autotune_choice_and_cache(tmp_path, monkeypatch):
+    g = need_gpu()
+    from paper_2505_22168_amd import autotune
+    monkeypatch.setenv("GMNN_TUNE_CACHE", str(tmp_path / "tune.json"))
+    batch, params, spec, system, nl, model = _setup(g, "liquid", dict(n=400))
+    ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
+    ev = g.EnergyForces(model, system, nl, precision="bf16", stress=True)
+    plan, table = autotune.run_autotune(ev, reps=5)
+    assert len(table) == 6  # both schedules x three lane counts are supported here
+    assert plan in [p for p, _, _ in table]
+    best = min(table, key=lambda t: t[1])
+    assert best[0] == plan
+    assert all(t[1] > 0 and t[2] <= t[1] for t in table)
+    # cached: a second evaluator of the same shape class reuses the choice
+    ev32 = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan="auto")
+    cache = autotune.TuneCache()
+    key = autotune.shape_key(model, system, nl, ev32.flags)
+    assert cache.get(key) is not None
+    ev32b = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan="auto")
+    assert ev32b.plan == ev32.plan
+    _check(ev32b(sync=True), ref, batch)

@@ -1,0 +1,86 @@
+"""Execution-plan resolution (host-only C code) and the autotune cache file.
+
+gmnn_resolve_plan reads only host-side fields (shapes, the host copies of
+atom_ptr / cell), so it runs here without a device: the device pointers are
+placeholders that the call never dereferences."""
+import ctypes as C
+import json
+
+import numpy as np
+import pytest
+
+from paper_2505_22168_amd import _capi as A
+
+FAKE = C.c_void_p(0x1000)  # stands in for device pointers; never read
+
+
+def _model(n_species=5, hidden=256, heads=1):
+    return A.gmnn_model(n_species, 5, 7, hidden, hidden, heads, 0.5, 5.0, 1.0, 0.1,
+                        FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE)
+
+
+class _Sys:
+    def __init__(self, sizes):
+        self.ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        B = len(sizes)
+        self.cell = np.tile(np.eye(3) * 20.0, (B, 1, 1)).astype(np.float64)
+        self.pbc = np.ones((B, 3), np.uint8)
+        self.c = A.gmnn_system(B, int(self.ptr[-1]), FAKE, self.ptr.ctypes.data_as(C.c_void_p), FAKE, FAKE,
+                               FAKE, self.cell.ctypes.data_as(C.c_void_p), FAKE, self.pbc.ctypes.data_as(C.c_void_p))
+
+
+def _resolve(model, sysobj, flags, sched=None, lanes=0):
+    lib = A.load()
+    out = A.gmnn_plan()
+    plan = None if sched is None else C.byref(A.gmnn_plan(sched, lanes))
+    st = lib.gmnn_resolve_plan(C.byref(model), C.byref(sysobj.c), flags, plan, C.byref(out))
+    return st, (out.schedule, out.lanes_per_atom)
+
+
+def test_builtin_plan_small_and_large():
+    m = _model()
+    assert _resolve(m, _Sys([1536]), 0) == (A.GMNN_OK, (A.GMNN_SCHEDULE_FUSED, 64))
+    assert _resolve(m, _Sys([100000]), 0) == (A.GMNN_OK, (A.GMNN_SCHEDULE_SPLIT, 16))
+    # force variance needs one backward per head: the fused tile does not serve it
+    assert _resolve(m, _Sys([1536]), A.GMNN_WANT_FORCE_VAR) == (A.GMNN_OK, (A.GMNN_SCHEDULE_SPLIT, 64))
+    assert A.load().gmnn_uses_fused_path(C.byref(m), C.byref(_Sys([1536]).c), 0) == 1
+
+
+def test_explicit_plans():
+    m = _model()
+    small = _Sys([120] * 30)
+    for lanes in (16, 32, 64):
+        assert _resolve(m, small, 0, A.GMNN_SCHEDULE_SPLIT, lanes) == (A.GMNN_OK, (A.GMNN_SCHEDULE_SPLIT, lanes))
+        assert _resolve(m, small, A.GMNN_PREC_BF16, A.GMNN_SCHEDULE_FUSED, lanes)[0] == A.GMNN_OK
+    # the fused tile on a large batch of small structures is allowed (one
+    # reduction chunk per structure) ...
+    assert _resolve(m, _Sys([200] * 100), 0, A.GMNN_SCHEDULE_FUSED, 16)[0] == A.GMNN_OK
+    # ... but not for a structure that needs chunked reductions
+    assert _resolve(m, _Sys([9000]), 0, A.GMNN_SCHEDULE_FUSED, 16)[0] == A.GMNN_ERR_UNSUPPORTED
+    assert _resolve(m, small, A.GMNN_WANT_FORCE_VAR, A.GMNN_SCHEDULE_FUSED, 0)[0] == A.GMNN_ERR_UNSUPPORTED
+    assert _resolve(_model(n_species=9), small, 0, A.GMNN_SCHEDULE_FUSED, 0)[0] == A.GMNN_ERR_UNSUPPORTED
+    assert _resolve(_model(n_species=9), small, 0)[1][0] == A.GMNN_SCHEDULE_SPLIT
+
+
+def test_invalid_plans():
+    m = _model()
+    s = _Sys([100])
+    assert _resolve(m, s, 0, A.GMNN_SCHEDULE_SPLIT, 8)[0] == A.GMNN_ERR_INVALID_ARG
+    assert _resolve(m, s, 0, 7, 16)[0] == A.GMNN_ERR_INVALID_ARG
+    lib = A.load()
+    assert lib.gmnn_resolve_plan(None, C.byref(s.c), 0, None, None) == A.GMNN_ERR_INVALID_ARG
+    best = A.gmnn_plan()
+    assert lib.gmnn_autotune(C.byref(m), C.byref(s.c), None, 0, None, None, 0, None, 0, C.byref(best), None, 0,
+                             None) == A.GMNN_ERR_INVALID_ARG
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    from paper_2505_22168_amd.autotune import TuneCache, _pow2
+    path = str(tmp_path / "sub" / "tune.json")
+    c = TuneCache(path)
+    assert c.get("k") is None
+    c.put("k", {"schedule": 2, "lanes_per_atom": 32, "table": [[2, 32, 10.0, 9.0]]})
+    c2 = TuneCache(path)
+    assert c2.get("k")["lanes_per_atom"] == 32
+    assert json.load(open(path))["k"]["schedule"] == 2
+    assert [_pow2(x) for x in (0, 1, 3, 5, 1536, 100000)] == [0, 1, 4, 4, 2048, 131072]
