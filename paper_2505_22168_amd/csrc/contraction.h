@@ -81,222 +81,363 @@ __device__ inline void store_feature(void* G, int idx, float v) {
   else ((float*)G)[idx] = v;
 }
 
-// Phase A of the forward: families 1-4 directly, and the intermediates
-// T7, V8, M5, v6 (all read only P).  Also zeroes the padding features.
-// FEATURES = false computes the intermediates only.
+// pair index of (s1 <= s2) in the lexicographic pair order, as arithmetic
+// (folds to a constant when both channels are compile-time constants)
+__host__ __device__ constexpr int pair_idx(int s1, int s2) {
+  return (s1 <= s2) ? s1 * kS - s1 * (s1 - 1) / 2 + (s2 - s1) : s2 * kS - s2 * (s2 - 1) / 2 + (s1 - s2);
+}
+__host__ __device__ constexpr int pair_first(int p) { return p < 5 ? 0 : p < 9 ? 1 : p < 12 ? 2 : p < 14 ? 3 : 4; }
+__host__ __device__ constexpr int pair_second(int p) {
+  return pair_first(p) + p - (pair_first(p) * kS - pair_first(p) * (pair_first(p) - 1) / 2);
+}
+
+// Phase A of the forward: families 1-4 and the intermediates T7, V8, M5, v6
+// (all read only P).  Also zeroes the padding features.  FEATURES = false
+// computes the intermediates only.  Register-blocked tasks (atom fastest):
+//   pair task (a, p = (s1 <= s2)):  T7[p], M5[p]; fam4[p] = tr T7[p] and
+//                                   fam3[p] = tr M5[p] (Psi2 is symmetric)
+//   channel task (a, s):            V8[s, .], v6[s, .]; fam1[s]; fam2[(s, s2 >= s)]
 template <int TM, int NT, bool BF16, bool FEATURES = true>
 __device__ inline void contract_forward_a(const float* __restrict__ P, float* __restrict__ I, void* G, int ldg,
                                           const Tables& tb) {
   const int tid = threadIdx.x;
-  for (int t = tid; t < (FEATURES ? TM * 50 : 0); t += NT) {
-    const int a = t % TM, f = t / TM;
-    float v = 0.0f;
-    if (f < kFam2) {
-      v = GM_P0(a, f);
-    } else if (f < kFam3) {
-      const int p = f - kFam2, s1 = tb.pair_s1[p], s2 = tb.pair_s2[p];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) v += GM_P1(a, s1, i) * GM_P1(a, s2, i);
-    } else if (f < kFam4) {
-      const int p = f - kFam3, s1 = tb.pair_s1[p], s2 = tb.pair_s2[p];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) v += GM_P2(a, s1, i) * GM_P2(a, s2, i);
-    } else {
-      const int p = f - kFam4, s1 = tb.pair_s1[p], s2 = tb.pair_s2[p];
-#pragma unroll
-      for (int i = 0; i < 27; ++i) v += GM_P3(a, s1, i) * GM_P3(a, s2, i);
-    }
-    store_feature<BF16>(G, a * ldg + f, v);
-  }
   for (int t = tid; t < (FEATURES ? TM * (kFP - kF) : 0); t += NT)
     store_feature<BF16>(G, (t % TM) * ldg + kF + t / TM, 0.0f);
-  // T7
-  for (int t = tid; t < TM * 135; t += NT) {
-    const int a = t % TM, e = t / TM;
-    const int p = e / 9, ia = (e % 9) / 3, ib = e % 3;
-    const int s2 = tb.pair_s1[p], s3 = tb.pair_s2[p];
-    float v = 0.0f;
+  constexpr int np = TM * 15, ns = TM * kS;
+  for (int t = tid; t < np + ns; t += NT) {
+    if (t < np) {
+      const int a = t % TM, p = t / TM;
+      const int s1 = pair_first(p), s2 = pair_second(p);
+      float A3[27], B3[27];
 #pragma unroll
-    for (int cd = 0; cd < 9; ++cd) v += GM_P3(a, s2, ia * 9 + cd) * GM_P3(a, s3, ib * 9 + cd);
-    GM_I(a, kT7 + e) = v;
-  }
-  // V8
-  for (int t = tid; t < TM * 75; t += NT) {
-    const int a = t % TM, e = t / TM;
-    const int s23 = e / 3, i = e % 3;
-    const int s2 = s23 / 5, s3 = s23 % 5;
-    float v = 0.0f;
+      for (int k = 0; k < 27; ++k) {
+        A3[k] = GM_P3(a, s1, k);
+        B3[k] = GM_P3(a, s2, k);
+      }
+      float tr4 = 0.0f;
 #pragma unroll
-    for (int bc = 0; bc < 9; ++bc) v += GM_P3(a, s2, i * 9 + bc) * GM_P2(a, s3, bc);
-    GM_I(a, kV8 + e) = v;
-  }
-  // M5
-  for (int t = tid; t < TM * 135; t += NT) {
-    const int a = t % TM, e = t / TM;
-    const int p = e / 9, i = (e % 9) / 3, j = e % 3;
-    const int s1 = tb.pair_s1[p], s2 = tb.pair_s2[p];
-    float v = 0.0f;
+      for (int ia = 0; ia < 3; ++ia)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v += GM_P2(a, s1, i * 3 + c) * GM_P2(a, s2, c * 3 + j);
-    GM_I(a, kM5 + e) = v;
-  }
-  // v6
-  for (int t = tid; t < TM * 75; t += NT) {
-    const int a = t % TM, e = t / TM;
-    const int s31 = e / 3, i = e % 3;
-    const int s3 = s31 / 5, s1 = s31 % 5;
-    float v = 0.0f;
+        for (int ib = 0; ib < 3; ++ib) {
+          float v = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) v += GM_P2(a, s3, i * 3 + j) * GM_P1(a, s1, j);
-    GM_I(a, kV6 + e) = v;
+          for (int cd = 0; cd < 9; ++cd) v += A3[ia * 9 + cd] * B3[ib * 9 + cd];
+          GM_I(a, kT7 + p * 9 + ia * 3 + ib) = v;
+          if (ia == ib) tr4 += v;
+        }
+      float A2[9], B2[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        A2[k] = GM_P2(a, s1, k);
+        B2[k] = GM_P2(a, s2, k);
+      }
+      float tr3 = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          float v = 0.0f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v += A2[i * 3 + c] * B2[c * 3 + j];
+          GM_I(a, kM5 + p * 9 + i * 3 + j) = v;
+          if (i == j) tr3 += v;
+        }
+      if (FEATURES) {
+        store_feature<BF16>(G, a * ldg + kFam3 + p, tr3);
+        store_feature<BF16>(G, a * ldg + kFam4 + p, tr4);
+      }
+    } else {
+      const int u = t - np;
+      const int a = u % TM, sc = u / TM;
+      float A3[27], C2[9];
+#pragma unroll
+      for (int k = 0; k < 27; ++k) A3[k] = GM_P3(a, sc, k);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) C2[k] = GM_P2(a, sc, k);
+#pragma unroll
+      for (int s3 = 0; s3 < kS; ++s3) {
+        float B2[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) B2[k] = GM_P2(a, s3, k);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          float v = 0.0f;
+#pragma unroll
+          for (int bc = 0; bc < 9; ++bc) v += A3[i * 9 + bc] * B2[bc];
+          GM_I(a, kV8 + (sc * 5 + s3) * 3 + i) = v;
+        }
+      }
+      float p1[kS][3];
+#pragma unroll
+      for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) p1[s1][j] = GM_P1(a, s1, j);
+#pragma unroll
+      for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          float v = 0.0f;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) v += C2[i * 3 + j] * p1[s1][j];
+          GM_I(a, kV6 + (sc * 5 + s1) * 3 + i) = v;
+        }
+      if (FEATURES) {
+        store_feature<BF16>(G, a * ldg + sc, GM_P0(a, sc));
+#pragma unroll
+        for (int s2 = 0; s2 < kS; ++s2) {
+          if (s2 < sc) continue;
+          float v = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            // p1[sc][i] with sc a runtime index: read it again from LDS
+            v += GM_P1(a, sc, i) * p1[s2][i];
+          }
+          store_feature<BF16>(G, a * ldg + kFam2 + pair_idx(sc, s2), v);
+        }
+      }
+    }
   }
 }
 
 // Phase B of the forward: families 5-8 from the intermediates.
+//   pair task (a, p = (s1 <= s2)):  fam7[(s', p)] for every s'; fam5[(s1, s2, s3)]
+//                                   for s3 >= s2; fam6[(p, s3)] for every s3
+//   channel task (a, s2):           fam8[(s1, s2, s3)] for every s1, s3
 template <int TM, int NT, bool BF16>
 __device__ inline void contract_forward_b(const float* __restrict__ P, const float* __restrict__ I, void* G, int ldg,
                                           const Tables& tb) {
-  const int tid = threadIdx.x;
-  for (int t = tid; t < TM * 35; t += NT) {  // fam5: M5[(s1,s2)] : Psi2[s3]
-    const int a = t % TM, e = t / TM;
-    const int p = tb.pair_index[tb.tri_s1[e] * 5 + tb.tri_s2[e]], s3 = tb.tri_s3[e];
-    float v = 0.0f;
+  constexpr int np = TM * 15, ns = TM * kS;
+  for (int t = threadIdx.x; t < np + ns; t += NT) {
+    if (t < np) {
+      const int a = t % TM, p = t / TM;
+      const int s1 = pair_first(p), s2 = pair_second(p);
+      float t7[9], m5[9];
 #pragma unroll
-    for (int ij = 0; ij < 9; ++ij) v += GM_I(a, kM5 + p * 9 + ij) * GM_P2(a, s3, ij);
-    store_feature<BF16>(G, a * ldg + kFam5 + e, v);
-  }
-  for (int t = tid; t < TM * 75; t += NT) {  // fam6: v6[s3][s1] . Psi1[s2]
-    const int a = t % TM, e = t / TM;
-    const int p = e / 5, s3 = e % 5;
-    const int s1 = tb.pair_s1[p], s2 = tb.pair_s2[p];
-    float v = 0.0f;
+      for (int k = 0; k < 9; ++k) {
+        t7[k] = GM_I(a, kT7 + p * 9 + k);
+        m5[k] = GM_I(a, kM5 + p * 9 + k);
+      }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) v += GM_I(a, kV6 + (s3 * 5 + s1) * 3 + i) * GM_P1(a, s2, i);
-    store_feature<BF16>(G, a * ldg + kFam6 + e, v);
-  }
-  for (int t = tid; t < TM * 75; t += NT) {  // fam7: Psi2[s1] : T7[p]
-    const int a = t % TM, e = t / TM;
-    const int s1 = e / 15, p = e % 15;
-    float v = 0.0f;
+      for (int sq = 0; sq < kS; ++sq) {
+        float q[9];
 #pragma unroll
-    for (int ij = 0; ij < 9; ++ij) v += GM_P2(a, s1, ij) * GM_I(a, kT7 + p * 9 + ij);
-    store_feature<BF16>(G, a * ldg + kFam7 + e, v);
-  }
-  for (int t = tid; t < TM * 125; t += NT) {  // fam8: Psi1[s1] . V8[s2 s3]
-    const int a = t % TM, e = t / TM;
-    const int s1 = e / 25, s23 = e % 25;
-    float v = 0.0f;
+        for (int k = 0; k < 9; ++k) q[k] = GM_P2(a, sq, k);
+        float f7 = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) v += GM_P1(a, s1, i) * GM_I(a, kV8 + s23 * 3 + i);
-    store_feature<BF16>(G, a * ldg + kFam8 + e, v);
+        for (int k = 0; k < 9; ++k) f7 += q[k] * t7[k];
+        store_feature<BF16>(G, a * ldg + kFam7 + sq * 15 + p, f7);
+        if (sq >= s2) {
+          float f5 = 0.0f;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) f5 += m5[k] * q[k];
+          store_feature<BF16>(G, a * ldg + kFam5 + tb.tri_index[s1 * 25 + s2 * 5 + sq], f5);
+        }
+      }
+      float r[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) r[i] = GM_P1(a, s2, i);
+#pragma unroll
+      for (int s3 = 0; s3 < kS; ++s3) {
+        float f6 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) f6 += GM_I(a, kV6 + (s3 * 5 + s1) * 3 + i) * r[i];
+        store_feature<BF16>(G, a * ldg + kFam6 + p * 5 + s3, f6);
+      }
+    } else {
+      const int u = t - np;
+      const int a = u % TM, s2 = u / TM;
+      float p1[kS][3];
+#pragma unroll
+      for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) p1[s1][i] = GM_P1(a, s1, i);
+#pragma unroll
+      for (int s3 = 0; s3 < kS; ++s3) {
+        float w[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) w[i] = GM_I(a, kV8 + (s2 * 5 + s3) * 3 + i);
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1) {
+          float f8 = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) f8 += p1[s1][i] * w[i];
+          store_feature<BF16>(G, a * ldg + kFam8 + s1 * 25 + s2 * 5 + s3, f8);
+        }
+      }
+    }
   }
 }
 
 #define GM_GB(a, f) Gb[(a) * ldgb + (f)]
 
 // Phase A of the backward: intermediates U8, Y, Qv (read P and dE/dG).
+//   task (a, s2, b):  U8[(s1, s2)][b, c] for every s1, c, and the five Qv
+//                     entries [x = s2][s3][i] with 3 s3 + i in [5b, 5b + 5)
+//   task (a, p = (x <= s')):  Y[(x, s')] and its mirror Y[(s', x)]
 template <int TM, int NT>
 __device__ inline void contract_backward_a(const float* __restrict__ P, const float* __restrict__ Gb, int ldgb,
                                            float* __restrict__ I, const Tables& tb) {
-  const int tid = threadIdx.x;
-  for (int t = tid; t < TM * 225; t += NT) {  // U8
-    const int a = t % TM, e = t / TM;
-    const int s12 = e / 9, bc = e % 9;
-    const int s1 = s12 / 5, s2 = s12 % 5;
-    float v = 0.0f;
+  constexpr int nu = TM * 15, ny = TM * 15;
+  for (int t = threadIdx.x; t < nu + ny; t += NT) {
+    if (t < nu) {
+      const int a = t % TM, e = t / TM;
+      const int s2 = e / 3, b = e % 3;
+      float p1[kS][3], p3[3][3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) v += GM_P1(a, s1, i) * GM_P3(a, s2, i * 9 + bc);
-    GM_I(a, kU8 + e) = v;
-  }
-  for (int t = tid; t < TM * 225; t += NT) {  // Y
-    const int a = t % TM, e = t / TM;
-    const int xs = e / 9, ab = e % 9;
-    const int x = xs / 5, sp = xs % 5;
-    const int p = tb.pair_index[x * 5 + sp];
-    float v = 0.0f;
+      for (int s1 = 0; s1 < kS; ++s1)
 #pragma unroll
-    for (int s1 = 0; s1 < kS; ++s1) v += GM_GB(a, kFam7 + s1 * 15 + p) * GM_P2(a, s1, ab);
-    GM_I(a, kY + e) = (x == sp ? 2.0f : 1.0f) * v;
-  }
-  for (int t = tid; t < TM * 75; t += NT) {  // Qv
-    const int a = t % TM, e = t / TM;
-    const int xs = e / 3, i = e % 3;
-    const int x = xs / 5, s3 = xs % 5;
-    float v = 0.0f;
+        for (int i = 0; i < 3; ++i) p1[s1][i] = GM_P1(a, s1, i);
 #pragma unroll
-    for (int s1 = 0; s1 < kS; ++s1) v += GM_GB(a, kFam8 + s1 * 25 + x * 5 + s3) * GM_P1(a, s1, i);
-    GM_I(a, kQv + e) = v;
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p3[i][c] = GM_P3(a, s2, i * 9 + b * 3 + c);
+#pragma unroll
+      for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float v = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) v += p1[s1][i] * p3[i][c];
+          GM_I(a, kU8 + (s1 * 5 + s2) * 9 + b * 3 + c) = v;
+        }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const int lin = 5 * b + q;
+        const int s3 = lin / 3, i = lin % 3;
+        float v = 0.0f;
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1) v += GM_GB(a, kFam8 + s1 * 25 + s2 * 5 + s3) * GM_P1(a, s1, i);
+        GM_I(a, kQv + (s2 * 5 + s3) * 3 + i) = v;
+      }
+    } else {
+      const int u = t - nu;
+      const int a = u % TM, p = u / TM;
+      const int x = pair_first(p), sp = pair_second(p);
+      float g[kS];
+#pragma unroll
+      for (int s1 = 0; s1 < kS; ++s1) g[s1] = GM_GB(a, kFam7 + s1 * 15 + p);
+      const float f = (x == sp) ? 2.0f : 1.0f;
+#pragma unroll
+      for (int ab = 0; ab < 9; ++ab) {
+        float v = 0.0f;
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1) v += g[s1] * GM_P2(a, s1, ab);
+        GM_I(a, kY + (x * 5 + sp) * 9 + ab) = f * v;
+        if (x != sp) GM_I(a, kY + (sp * 5 + x) * 9 + ab) = f * v;
+      }
+    }
   }
 }
 
 // Phase B of the backward: every entry of the full-tensor gradient, each
-// summing all of its contributions (one writer per entry).
+// summing all of its contributions (one writer per entry).  Register-blocked
+// tasks, all kinds in one pass over the threads (atom fastest):
+//   Psi2 task (a, x, i):  the 3 entries (x, i, j); the Psi1 entries and the
+//                         contraction intermediates are read once per task
+//   Psi3 task (a, i, b):  the 15 entries (x, i, b, c), sharing the Psi2/Psi3
+//                         entries of every channel across x
+//   Psi01 task (a, x):    Psi0 and the 3 Psi1 entries of channel x
 template <int TM, int NT>
 __device__ inline void contract_backward_b(const float* __restrict__ P, const float* __restrict__ Gb, int ldgb,
                                            const float* __restrict__ I, float* __restrict__ Pb, const Tables& tb) {
-  const int tid = threadIdx.x;
-  // Psi0 and Psi1 entries: (x, r), r in 0..3
-  for (int t = tid; t < TM * 20; t += NT) {
-    const int a = t % TM, e = t / TM;
-    const int x = e / 4, r = e % 4;
-    float v = 0.0f;
-    if (r == 0) {
-      v = GM_GB(a, x);
-    } else {
-      const int i = r - 1;
+  constexpr int n2 = TM * 15, n3 = TM * 9, n1 = TM * 5;
+  for (int t = threadIdx.x; t < n2 + n3 + n1; t += NT) {
+    if (t < n2) {
+      const int a = t % TM, e = t / TM;
+      const int x = e / 3, i = e % 3;
+      float p1i[kS], p1[kS][3];
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+        p1i[s] = GM_P1(a, s, i);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) p1[s][j] = GM_P1(a, s, j);
+      }
+      float v[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int sp = 0; sp < kS; ++sp) {
-        const int p = tb.pair_index[x * 5 + sp];
-        const float f2 = (x == sp) ? 2.0f : 1.0f;
-        v += f2 * GM_GB(a, kFam2 + p) * GM_P1(a, sp, i);
-        float w6 = 0.0f;
+        const float g = (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam3 + pair_idx(x, sp));
 #pragma unroll
-        for (int s3 = 0; s3 < kS; ++s3) w6 += GM_GB(a, kFam6 + p * 5 + s3) * GM_I(a, kV6 + (s3 * 5 + sp) * 3 + i);
-        v += f2 * w6;
+        for (int j = 0; j < 3; ++j) v[j] += g * GM_P2(a, sp, 3 * i + j);
       }
-      float v8 = 0.0f;
 #pragma unroll
-      for (int s23 = 0; s23 < 25; ++s23) v8 += GM_GB(a, kFam8 + x * 25 + s23) * GM_I(a, kV8 + s23 * 3 + i);
-      v += v8;
+      for (int p = 0; p < 15; ++p) {
+        const int s1 = pair_first(p), s2 = pair_second(p);
+        const float g5 = tb.c5[x * 15 + p] * GM_GB(a, kFam5 + tb.tri_xp[x * 15 + p]);
+        const float g6 = GM_GB(a, kFam6 + p * 5 + x) * p1i[s1];
+        const float g7 = GM_GB(a, kFam7 + x * 15 + p);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          v[j] += g5 * GM_I(a, kM5 + p * 9 + 3 * i + j) + g7 * GM_I(a, kT7 + p * 9 + 3 * i + j) + g6 * p1[s2][j];
+      }
+#pragma unroll
+      for (int s12 = 0; s12 < 25; ++s12) {
+        const float g8 = GM_GB(a, kFam8 + s12 * 5 + x);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j] += g8 * GM_I(a, kU8 + s12 * 9 + 3 * i + j);
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Pb[a * PS + x * kFull + 4 + 3 * i + j] = v[j];
+    } else if (t < n2 + n3) {
+      const int u = t - n2;
+      const int a = u % TM, e = u / TM;
+      const int i = e / 3, b = e % 3;
+      float v[kS][3];
+#pragma unroll
+      for (int x = 0; x < kS; ++x) v[x][0] = v[x][1] = v[x][2] = 0.0f;
+#pragma unroll
+      for (int sp = 0; sp < kS; ++sp) {
+        float p3i[3], p3d[3][3], p2b[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          p3i[c] = GM_P3(a, sp, i * 9 + b * 3 + c);
+          p2b[c] = GM_P2(a, sp, b * 3 + c);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) p3d[d][c] = GM_P3(a, sp, d * 9 + b * 3 + c);
+        }
+#pragma unroll
+        for (int x = 0; x < kS; ++x) {
+          const float g4 = (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam4 + pair_idx(x, sp));
+          const float y0 = GM_I(a, kY + (x * 5 + sp) * 9 + i * 3);
+          const float y1 = GM_I(a, kY + (x * 5 + sp) * 9 + i * 3 + 1);
+          const float y2 = GM_I(a, kY + (x * 5 + sp) * 9 + i * 3 + 2);
+          const float q = GM_I(a, kQv + (x * 5 + sp) * 3 + i);
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            v[x][c] += g4 * p3i[c] + y0 * p3d[0][c] + y1 * p3d[1][c] + y2 * p3d[2][c] + q * p2b[c];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < kS; ++x)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Pb[a * PS + x * kFull + 13 + i * 9 + b * 3 + c] = v[x][c];
+    } else {
+      const int u = t - n2 - n3;
+      const int a = u % TM, x = u / TM;
+      float v[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int sp = 0; sp < kS; ++sp) {
+        const int p = pair_idx(x, sp);
+        const float f2 = (x == sp) ? 2.0f : 1.0f;
+        const float g2 = f2 * GM_GB(a, kFam2 + p);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] += g2 * GM_P1(a, sp, k);
+#pragma unroll
+        for (int s3 = 0; s3 < kS; ++s3) {
+          const float g6 = f2 * GM_GB(a, kFam6 + p * 5 + s3);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) v[k] += g6 * GM_I(a, kV6 + (s3 * 5 + sp) * 3 + k);
+        }
+      }
+#pragma unroll
+      for (int s23 = 0; s23 < 25; ++s23) {
+        const float g8 = GM_GB(a, kFam8 + x * 25 + s23);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] += g8 * GM_I(a, kV8 + s23 * 3 + k);
+      }
+      Pb[a * PS + x * kFull] = GM_GB(a, x);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Pb[a * PS + x * kFull + 1 + k] = v[k];
     }
-    Pb[a * PS + x * kFull + r] = v;
-  }
-  // Psi2 entries: (x, ij)
-  for (int t = tid; t < TM * 45; t += NT) {
-    const int a = t % TM, e = t / TM;
-    const int x = e / 9, ij = e % 9;
-    const int i = ij / 3, j = ij % 3;
-    float v = 0.0f;
-#pragma unroll
-    for (int sp = 0; sp < kS; ++sp)
-      v += (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam3 + tb.pair_index[x * 5 + sp]) * GM_P2(a, sp, ij);
-    float v5 = 0.0f, v6 = 0.0f, v7 = 0.0f, v8 = 0.0f;
-#pragma unroll
-    for (int p = 0; p < 15; ++p) {
-      const int s1 = tb.pair_s1[p], s2 = tb.pair_s2[p];
-      v5 += tb.c5[x * 15 + p] * GM_GB(a, kFam5 + tb.tri_xp[x * 15 + p]) * GM_I(a, kM5 + p * 9 + ij);
-      v6 += GM_GB(a, kFam6 + p * 5 + x) * GM_P1(a, s1, i) * GM_P1(a, s2, j);
-      v7 += GM_GB(a, kFam7 + x * 15 + p) * GM_I(a, kT7 + p * 9 + ij);
-    }
-#pragma unroll
-    for (int s12 = 0; s12 < 25; ++s12) v8 += GM_GB(a, kFam8 + s12 * 5 + x) * GM_I(a, kU8 + s12 * 9 + ij);
-    v += (v5 + v6) + (v7 + v8);
-    Pb[a * PS + x * kFull + 4 + ij] = v;
-  }
-  // Psi3 entries: (x, i bc)
-  for (int t = tid; t < TM * 135; t += NT) {
-    const int a = t % TM, e = t / TM;
-    const int x = e / 27, ibc = e % 27;
-    const int i = ibc / 9, bc = ibc % 9;
-    float v = 0.0f;
-#pragma unroll
-    for (int sp = 0; sp < kS; ++sp) {
-      v += (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam4 + tb.pair_index[x * 5 + sp]) * GM_P3(a, sp, ibc);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) v += GM_I(a, kY + (x * 5 + sp) * 9 + i * 3 + d) * GM_P3(a, sp, d * 9 + bc);
-      v += GM_I(a, kQv + (x * 5 + sp) * 3 + i) * GM_P2(a, sp, bc);
-    }
-    Pb[a * PS + x * kFull + 13 + ibc] = v;
   }
 }
 

@@ -123,12 +123,25 @@ __global__ void __launch_bounds__(kTileThreads)
       }
     }
   } else {
-    for (int t = tid; t < TM * kS * kFull; t += kTileThreads) {
-      const int a = t % TM, e = t / TM;
-      const int s = e / kFull, r = e % kFull;
-      float v = 0.0f;
-      if (a < n_rows) v = psi_in[(int64_t)(row0 + a) * (kS * kPacked) + s * kPacked + tb.full_to_packed[r]];
-      sPsi[a * PS + e] = v;
+    // the tile's packed moments are one contiguous run: all loads issued at
+    // once, coalesced, then expanded into the full tensors
+    constexpr int NP = kS * kPacked;
+    constexpr int NU = (TM * NP + kTileThreads - 1) / kTileThreads;
+    float v[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int t = tid + u * kTileThreads;
+      v[u] = t < n_rows * NP ? psi_in[(int64_t)row0 * NP + t] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int t = tid + u * kTileThreads;
+      if (t < TM * NP) {
+        const int a = t / NP, e = t % NP;
+        const int s = e / kPacked, c = e % kPacked;
+        const int n = tb.packed_mult[c];
+        for (int q = 0; q < n; ++q) sPsi[a * PS + s * kFull + tb.packed_full[c][q]] = v[u];
+      }
     }
   }
   __syncthreads();

@@ -564,47 +564,85 @@ __global__ void sum_partials(const float* __restrict__ partial, int nchunks, int
   out[i] = v;
 }
 
-// column sums over weight-product rows: out[c] = sum over rows k with (k & 15) < 8 (primal rows)
-// of Y[k][c], for c < ncols < HP; padded columns are dropped
-__global__ void column_sums(const float* __restrict__ Y, int ld, int64_t nrows, int ncols, bool primal_only,
-                            float* __restrict__ out) {
+// column sums, stage 1: partial[chunk][c] = sum of Y[k][c] over the rows k
+// of the chunk (with primal_only, the rows with (k & 15) < 8: the primal
+// halves of the dual-number tiles); grid (ceil(ncols / 256), chunks)
+constexpr int kColChunk = 256;
+__global__ void column_partials(const float* __restrict__ Y, int ld, int64_t nrows, int ncols, bool primal_only,
+                                float* __restrict__ partial) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols) return;
+  const int64_t k0 = (int64_t)blockIdx.y * kColChunk;
+  const int64_t k1 = min(nrows, k0 + kColChunk);
   float v = 0.0f;
-  for (int64_t k = 0; k < nrows; ++k)
+  for (int64_t k = k0; k < k1; ++k)
     if (!primal_only || (k & 15) < 8) v += Y[k * ld + c];
-  out[c] = v;
+  partial[(int64_t)blockIdx.y * ncols + c] = v;
 }
 
-// scale / shift / b3 gradients (one thread per species, fixed order over atoms)
-__global__ void species_sums(DevModel m, DevSystem sys, const double* __restrict__ ebar, const float* __restrict__ qsig,
-                             float* __restrict__ gscale, float* __restrict__ gshift, float* __restrict__ gb3) {
-  const int z = threadIdx.x;
-  if (z < m.n_species) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = 0; i < sys.n_atoms; ++i)
-      if (sys.species[i] == z) {
-        s1 += qsig[i];
-        s2 += ebar[sys.atom_struct[i]];
-      }
-    gscale[z] = (float)s1;
-    gshift[z] = (float)s2;
+// per-species sums, stage 1: block b takes atoms [b*256, b*256+256) and
+// writes, in FP64, sp[b][z][0] = sum qsig_i and sp[b][z][1] = sum ebar_b(i)
+// over its atoms of species z, and sp[b][nsp][0] = sum ebar_b(i) sigma_z(i)
+// (fixed-shape tree sums: the result does not depend on scheduling)
+constexpr int kSpeciesChunk = 256;
+__global__ void __launch_bounds__(kSpeciesChunk)
+    species_partials(DevModel m, DevSystem sys, const double* __restrict__ ebar, const float* __restrict__ qsig,
+                     double* __restrict__ sp) {
+  __shared__ double red[kSpeciesChunk / 64][kMaxSpecies + 1][2];
+  const int i = blockIdx.x * kSpeciesChunk + threadIdx.x;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  int z = -1;
+  double q = 0.0, e = 0.0;
+  if (i < sys.n_atoms) {
+    z = sys.species[i];
+    q = (double)qsig[i];
+    e = ebar[sys.atom_struct[i]];
   }
-  if (z == 0) {
+  const int nsp = m.n_species;
+  for (int t = 0; t < nsp; ++t) {
+    const double a = wave_sum(z == t ? q : 0.0);
+    const double b = wave_sum(z == t ? e : 0.0);
+    if (l == 0) {
+      red[w][t][0] = a;
+      red[w][t][1] = b;
+    }
+  }
+  const double c = wave_sum(z >= 0 ? e * (double)m.scale[z] : 0.0);
+  if (l == 0) red[w][nsp][0] = c;
+  __syncthreads();
+  if (threadIdx.x < 2 * (nsp + 1)) {
+    const int t = threadIdx.x >> 1, k = threadIdx.x & 1;
+    double v = 0.0;
+    for (int ww = 0; ww < kSpeciesChunk / 64; ++ww) v += (t < nsp || k == 0) ? red[ww][t][k] : 0.0;
+    sp[((int64_t)blockIdx.x * (kMaxSpecies + 1) + t) * 2 + k] = v;
+  }
+}
+
+// stage 2: scale / shift / b3 gradients from the block partials, in block order
+__global__ void species_finish(DevModel m, const double* __restrict__ sp, int nblocks, float* __restrict__ gscale,
+                               float* __restrict__ gshift, float* __restrict__ gb3) {
+  const int t = threadIdx.x;
+  const int nsp = m.n_species;
+  if (t > nsp) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    s1 += sp[((int64_t)b * (kMaxSpecies + 1) + t) * 2];
+    s2 += sp[((int64_t)b * (kMaxSpecies + 1) + t) * 2 + 1];
+  }
+  if (t < nsp) {
+    gscale[t] = (float)s1;
+    gshift[t] = (float)s2;
+  } else {
     // dPhi/db3_m = sum_i a_i sigma_i / M (the same for every head)
-    double s = 0.0;
-    for (int i = 0; i < sys.n_atoms; ++i) s += ebar[sys.atom_struct[i]] * m.scale[sys.species[i]];
-    for (int hm = 0; hm < m.M; ++hm) gb3[hm] = (float)(s / m.M);
+    for (int hm = 0; hm < m.M; ++hm) gb3[hm] = (float)(s1 / m.M);
   }
 }
 
-// W3 gradient: every head column equals sum_i w3g[i][h]
-__global__ void w3_grad(const float* __restrict__ w3g, int HP, int64_t n_atoms, int H2, int M, float* __restrict__ gw3) {
+// W3 gradient: every head column equals the column sum of w3g
+__global__ void w3_broadcast(const float* __restrict__ w3sum, int H2, int M, float* __restrict__ gw3) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= H2) return;
-  float v = 0.0f;
-  for (int64_t i = 0; i < n_atoms; ++i) v += w3g[i * HP + h];
-  for (int hm = 0; hm < M; ++hm) gw3[(int64_t)h * M + hm] = v;
+  for (int hm = 0; hm < M; ++hm) gw3[(int64_t)h * M + hm] = w3sum[h];
 }
 
 // unpad a [HP or kFP rows][HP cols] gradient into the caller's [F][H1] / [H1][H2] array
@@ -645,7 +683,10 @@ static gmnn_status launch_train_tile_t(const DevModel& m, const DevSystem& sys, 
 }
 
 struct TrainLayout {
-  size_t psi, psidot, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, part1, part2, sum1, sum2, bpart, bsum, bytes;
+  size_t psi, psidot, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, part1, part2, sum1, sum2, bpart, bsum;
+  size_t cpart, w3sum, spart, bytes;
+  int ccK, ccN;        // row chunks of the column sums over K rows / over N atoms
+  int sp_blocks;       // blocks of the per-species sums
   int64_t K;           // weight-product rows
   int kchunks;
   int beta_blocks;
@@ -681,6 +722,12 @@ TrainLayout train_layout(int n_atoms, int HP, int nsp) {
   const size_t nslots = (size_t)nsp * nsp * kS * kMaxBasis;
   L.bpart = take(4 * (size_t)L.beta_blocks * nslots);
   L.bsum = take(4 * nslots);
+  L.ccK = (int)((L.K + kColChunk - 1) / kColChunk);
+  L.ccN = (int)((N + kColChunk - 1) / kColChunk);
+  L.cpart = take(4 * (size_t)HP * (size_t)(L.ccK > L.ccN ? L.ccK : L.ccN));
+  L.w3sum = take(4 * (size_t)HP);
+  L.sp_blocks = (int)((N + kSpeciesChunk - 1) / kSpeciesChunk);
+  L.spart = take(8 * 2 * (size_t)(kMaxSpecies + 1) * (L.sp_blocks > 0 ? L.sp_blocks : 1));
   L.bytes = off;
   return L;
 }
@@ -743,21 +790,38 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, int H1, int 
   // weight products, split over chunks of 4096 rows, partials summed in chunk order
   {
     const int t1 = (kFP / 16) * (HP / 16);
-    hipLaunchKernelGGL(weight_grad, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
-                       (int64_t)4096, part1);
     const int t2 = (HP / 16) * (HP / 16);
-    hipLaunchKernelGGL(weight_grad, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
-                       (int64_t)4096, part2);
+    if (L.kchunks > 0) {
+      hipLaunchKernelGGL(weight_grad, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
+                         (int64_t)4096, part1);
+      hipLaunchKernelGGL(weight_grad, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
+                         (int64_t)4096, part2);
+    }
     const int64_t n1 = (int64_t)kFP * HP, n2 = (int64_t)HP * HP;
     hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part1, L.kchunks, n1, sum1);
     hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part2, L.kchunks, n2, sum2);
     hipLaunchKernelGGL(unpad_copy, dim3((kF * H1 + 255) / 256), dim3(256), 0, s, sum1, HP, kF, H1, g->W1);
     hipLaunchKernelGGL(unpad_copy, dim3((H1 * H2 + 255) / 256), dim3(256), 0, s, sum2, HP, H1, H2, g->W2);
   }
-  hipLaunchKernelGGL(column_sums, dim3((H1 + 255) / 256), dim3(256), 0, s, Y1, HP, L.K, H1, true, g->b1);
-  hipLaunchKernelGGL(column_sums, dim3((H2 + 255) / 256), dim3(256), 0, s, Y2, HP, L.K, H2, true, g->b2);
-  hipLaunchKernelGGL(w3_grad, dim3((H2 + 255) / 256), dim3(256), 0, s, w3g, HP, (int64_t)N, H2, m.M, g->W3);
-  hipLaunchKernelGGL(species_sums, dim3(1), dim3(64), 0, s, m, sys, ebar, qsig, g->scale, g->shift, g->b3);
+  // bias, W3, scale/shift gradients: two-stage sums with chunk partials added in order
+  float* cpart = (float*)(W + L.cpart);
+  float* w3sum = (float*)(W + L.w3sum);
+  double* spart = (double*)(W + L.spart);
+  // (with no atoms there are no chunks: the sums of zero partials are zero)
+  if (N > 0)
+    hipLaunchKernelGGL(column_partials, dim3((H1 + 255) / 256, L.ccK), dim3(256), 0, s, Y1, HP, L.K, H1, true, cpart);
+  hipLaunchKernelGGL(sum_partials, dim3((H1 + 255) / 256), dim3(256), 0, s, cpart, L.ccK, (int64_t)H1, g->b1);
+  if (N > 0)
+    hipLaunchKernelGGL(column_partials, dim3((H2 + 255) / 256, L.ccK), dim3(256), 0, s, Y2, HP, L.K, H2, true, cpart);
+  hipLaunchKernelGGL(sum_partials, dim3((H2 + 255) / 256), dim3(256), 0, s, cpart, L.ccK, (int64_t)H2, g->b2);
+  if (N > 0) {
+    hipLaunchKernelGGL(column_partials, dim3((H2 + 255) / 256, L.ccN), dim3(256), 0, s, w3g, HP, (int64_t)N, H2, false,
+                       cpart);
+    hipLaunchKernelGGL(species_partials, dim3(L.sp_blocks), dim3(kSpeciesChunk), 0, s, m, sys, ebar, qsig, spart);
+  }
+  hipLaunchKernelGGL(sum_partials, dim3((H2 + 255) / 256), dim3(256), 0, s, cpart, L.ccN, (int64_t)H2, w3sum);
+  hipLaunchKernelGGL(w3_broadcast, dim3((H2 + 255) / 256), dim3(256), 0, s, w3sum, H2, m.M, g->W3);
+  hipLaunchKernelGGL(species_finish, dim3(1), dim3(64), 0, s, m, spart, L.sp_blocks, g->scale, g->shift, g->b3);
   hipLaunchKernelGGL(sum_partials, dim3((nslots + 255) / 256), dim3(256), 0, s, bpart, L.beta_blocks,
                      (int64_t)nslots, bsum);
   hipLaunchKernelGGL(beta_unpack, dim3((nsp * nsp * kS * m.K + 255) / 256), dim3(256), 0, s, bsum, nsp, m.K, g->beta);
