@@ -444,15 +444,26 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
 // Fold the full-tensor gradient onto the packed components: out(a, k) for
 // k = s*20 + t receives the sum of the full entries packed component t
 // stands for.
+// One task per (atom, channel), compile-time component indices: the 40 full
+// entries of the channel are read once each.
 template <int TM, int NT, typename Out>
 __device__ inline void fold_packed(const float* __restrict__ Pb, const Tables& tb, Out out) {
-  for (int t = threadIdx.x; t < TM * kS * kPacked; t += NT) {
-    const int a = t / (kS * kPacked), e = t % (kS * kPacked);
-    const int s = e / kPacked, mp = e % kPacked;
-    float v = 0.0f;
-    const int n = tb.packed_mult[mp];
-    for (int k = 0; k < n; ++k) v += Pb[a * PS + s * kFull + tb.packed_full[mp][k]];
-    out(a, e, v);
+  constexpr unsigned char mult[kPacked] = {1, 1, 1, 1, 1, 2, 2, 1, 2, 1, 1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
+  constexpr unsigned char full[kPacked][6] = {
+      {0}, {1}, {2}, {3}, {4}, {5, 7}, {6, 10}, {8}, {9, 11}, {12},
+      {13}, {14, 16, 22}, {15, 19, 31}, {17, 23, 25}, {18, 20, 24, 28, 32, 34}, {21, 33, 37},
+      {26}, {27, 29, 35}, {30, 36, 38}, {39}};
+  for (int t = threadIdx.x; t < TM * kS; t += NT) {
+    const int a = t % TM, s = t / TM;
+    const float* f = Pb + a * PS + s * kFull;
+#pragma unroll
+    for (int c = 0; c < kPacked; ++c) {
+      float v = f[full[c][0]];
+#pragma unroll
+      for (int k = 1; k < 6; ++k)
+        if (k < mult[c]) v += f[full[c][k]];
+      out(a, s * kPacked + c, v);
+    }
   }
 }
 

@@ -182,18 +182,57 @@ __device__ inline void load_atom(const DevSystem& sys, int i, AtomCtx& c) {
   c.p1 = sys.row_ptr[i + 1];
 }
 
-// d_p = x_j - x_i + S . h (FP32)
+// d_p = x_j - x_i + S . h (FP32) of the pair with neighbour j, image code sh
+__device__ inline void pair_vec_of(const AtomCtx& c, float xj, float yj, float zj, int32_t sh, float& dx, float& dy,
+                                   float& dz) {
+  int sx, sy, sz;
+  unpack_shift(sh, sx, sy, sz);
+  const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
+  dx = (xj - c.xi) + (fx * c.h[0] + fy * c.h[3] + fz * c.h[6]);
+  dy = (yj - c.yi) + (fx * c.h[1] + fy * c.h[4] + fz * c.h[7]);
+  dz = (zj - c.zi) + (fx * c.h[2] + fy * c.h[5] + fz * c.h[8]);
+}
+
+// d_p of pair p of the row
 __device__ inline void pair_vec(const DevSystem& sys, const AtomCtx& c, int64_t p, int& j, float& dx, float& dy,
                                 float& dz) {
   j = sys.nj[p];
-  int sx, sy, sz;
-  unpack_shift(sys.nshift[p], sx, sy, sz);
-  const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
-  dx = (sys.pos[3 * (int64_t)j] - c.xi) + (fx * c.h[0] + fy * c.h[3] + fz * c.h[6]);
-  dy = (sys.pos[3 * (int64_t)j + 1] - c.yi) + (fx * c.h[1] + fy * c.h[4] + fz * c.h[7]);
-  dz = (sys.pos[3 * (int64_t)j + 2] - c.zi) + (fx * c.h[2] + fy * c.h[5] + fz * c.h[8]);
+  pair_vec_of(c, sys.pos[3 * (int64_t)j], sys.pos[3 * (int64_t)j + 1], sys.pos[3 * (int64_t)j + 2], sys.nshift[p], dx,
+              dy, dz);
 }
 
+// The lane's pairs are taken U at a time with every load of the group issued
+// before any arithmetic (neighbour index and image code, then the neighbour's
+// position and species): one memory round trip per group, not per pair.
+constexpr int kPairUnroll = 2;
+struct PairGroup {
+  float dx[kPairUnroll], dy[kPairUnroll], dz[kPairUnroll];
+  int zj[kPairUnroll];
+  bool ok[kPairUnroll];
+};
+
+template <int LPA>
+__device__ inline void fetch_pairs(const DevSystem& sys, const AtomCtx& c, int64_t p, PairGroup& g) {
+  int j[kPairUnroll];
+  int32_t sh[kPairUnroll];
+#pragma unroll
+  for (int u = 0; u < kPairUnroll; ++u) {
+    const int64_t pu = p + (int64_t)u * LPA;
+    g.ok[u] = pu < c.p1;
+    j[u] = g.ok[u] ? sys.nj[pu] : 0;
+    sh[u] = g.ok[u] ? sys.nshift[pu] : 0;
+  }
+  float x[kPairUnroll], y[kPairUnroll], z[kPairUnroll];
+#pragma unroll
+  for (int u = 0; u < kPairUnroll; ++u) {
+    x[u] = g.ok[u] ? sys.pos[3 * (int64_t)j[u]] : 0.0f;
+    y[u] = g.ok[u] ? sys.pos[3 * (int64_t)j[u] + 1] : 0.0f;
+    z[u] = g.ok[u] ? sys.pos[3 * (int64_t)j[u] + 2] : 0.0f;
+    g.zj[u] = g.ok[u] ? sys.species[j[u]] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < kPairUnroll; ++u) pair_vec_of(c, x[u], y[u], z[u], sh[u], g.dx[u], g.dy[u], g.dz[u]);
+}
 
 // ---------------------------------------------------------------------------
 // moment partial sums of lane q of an atom: pairs p0+q, p0+q+LPA, ...
@@ -204,22 +243,25 @@ __device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, con
   AtomCtx c;
   load_atom(sys, i, c);
   const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
-  for (int64_t p = c.p0 + q; p < c.p1; p += LPA) {
-    int j;
-    float dx, dy, dz;
-    pair_vec(sys, c, p, j, dx, dy, dz);
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < m.rc2) || r2 == 0.0f) continue;
-    const float r = sqrtf(r2);
-    const float ir = 1.0f / r;
-    Radial rad;
-    radial<false>(m, bzi + sys.species[j] * kS * kMaxBasis, r, rad);
-    float mo[20];
-    monomials(dx * ir, dy * ir, dz * ir, mo);
+  for (int64_t p = c.p0 + q; p < c.p1; p += kPairUnroll * LPA) {
+    PairGroup g;
+    fetch_pairs<LPA>(sys, c, p, g);
 #pragma unroll
-    for (int s = 0; s < kS; ++s)
+    for (int u = 0; u < kPairUnroll; ++u) {
+      const float dx = g.dx[u], dy = g.dy[u], dz = g.dz[u];
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      if (!g.ok[u] || !(r2 < m.rc2) || r2 == 0.0f) continue;
+      const float r = sqrtf(r2);
+      const float ir = 1.0f / r;
+      Radial rad;
+      radial<false>(m, bzi + g.zj[u] * kS * kMaxBasis, r, rad);
+      float mo[20];
+      monomials(dx * ir, dy * ir, dz * ir, mo);
 #pragma unroll
-      for (int t = 0; t < kPacked; ++t) v[s * kPacked + t] += rad.R[s] * mo[t];
+      for (int s = 0; s < kS; ++s)
+#pragma unroll
+        for (int t = 0; t < kPacked; ++t) v[s * kPacked + t] += rad.R[s] * mo[t];
+    }
   }
 }
 
@@ -235,53 +277,59 @@ __device__ inline void atom_pair_backward(const DevModel& m, const DevSystem& sy
   AtomCtx c;
   load_atom(sys, i, c);
   const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
-  for (int64_t p = c.p0 + q; p < c.p1; p += LPA) {
-    int j;
-    float dx, dy, dz;
-    pair_vec(sys, c, p, j, dx, dy, dz);
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-    if (r2 < m.rc2 && r2 > 0.0f) {
-      const float r = sqrtf(r2);
-      const float ir = 1.0f / r;
-      const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
-      Radial rad;
-      radial<true>(m, bzi + sys.species[j] * kS * kMaxBasis, r, rad);
-      float mo[20];
-      monomials(ux, uy, uz, mo);
-      float radial_part = 0.0f;
-      float qc[kPacked];
+  for (int64_t p = c.p0 + q; p < c.p1; p += kPairUnroll * LPA) {
+    PairGroup g;
+    fetch_pairs<LPA>(sys, c, p, g);
 #pragma unroll
-      for (int t = 0; t < kPacked; ++t) qc[t] = 0.0f;
+    for (int u = 0; u < kPairUnroll; ++u) {
+      if (!g.ok[u]) continue;
+      const float dx = g.dx[u], dy = g.dy[u], dz = g.dz[u];
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+      if (r2 < m.rc2 && r2 > 0.0f) {
+        const float r = sqrtf(r2);
+        const float ir = 1.0f / r;
+        const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+        Radial rad;
+        radial<true>(m, bzi + g.zj[u] * kS * kMaxBasis, r, rad);
+        float mo[20];
+        monomials(ux, uy, uz, mo);
+        float radial_part = 0.0f;
+        float qc[kPacked];
 #pragma unroll
-      for (int s = 0; s < kS; ++s) {
-        float A = 0.0f;
+        for (int t = 0; t < kPacked; ++t) qc[t] = 0.0f;
 #pragma unroll
-        for (int t = 0; t < kPacked; ++t) {
-          A += pb[s * kPacked + t] * mo[t];
-          qc[t] += rad.R[s] * pb[s * kPacked + t];
+        for (int s = 0; s < kS; ++s) {
+          float A = 0.0f;
+#pragma unroll
+          for (int t = 0; t < kPacked; ++t) {
+            A += pb[s * kPacked + t] * mo[t];
+            qc[t] += rad.R[s] * pb[s * kPacked + t];
+          }
+          radial_part += A * rad.dR[s];
         }
-        radial_part += A * rad.dR[s];
+        const float x = ux, y = uy, z = uz;
+        const float Gx = qc[1] + 2.0f * qc[4] * x + qc[5] * y + qc[6] * z + 3.0f * qc[10] * x * x +
+                         2.0f * qc[11] * x * y + 2.0f * qc[12] * x * z + qc[13] * y * y + qc[14] * y * z +
+                         qc[15] * z * z;
+        const float Gy = qc[2] + qc[5] * x + 2.0f * qc[7] * y + qc[8] * z + qc[11] * x * x +
+                         2.0f * qc[13] * x * y + qc[14] * x * z + 3.0f * qc[16] * y * y + 2.0f * qc[17] * y * z +
+                         qc[18] * z * z;
+        const float Gz = qc[3] + qc[6] * x + qc[8] * y + 2.0f * qc[9] * z + qc[12] * x * x + qc[14] * x * y +
+                         2.0f * qc[15] * x * z + qc[17] * y * y + 2.0f * qc[18] * y * z + 3.0f * qc[19] * z * z;
+        const float gu = Gx * x + Gy * y + Gz * z;
+        gx = radial_part * x + (Gx - gu * x) * ir;
+        gy = radial_part * y + (Gy - gu * y) * ir;
+        gz = radial_part * z + (Gz - gu * z) * ir;
+        vir[0] += gx * dx; vir[1] += gx * dy; vir[2] += gx * dz;
+        vir[3] += gy * dx; vir[4] += gy * dy; vir[5] += gy * dz;
+        vir[6] += gz * dx; vir[7] += gz * dy; vir[8] += gz * dz;
       }
-      const float x = ux, y = uy, z = uz;
-      const float Gx = qc[1] + 2.0f * qc[4] * x + qc[5] * y + qc[6] * z + 3.0f * qc[10] * x * x +
-                       2.0f * qc[11] * x * y + 2.0f * qc[12] * x * z + qc[13] * y * y + qc[14] * y * z +
-                       qc[15] * z * z;
-      const float Gy = qc[2] + qc[5] * x + 2.0f * qc[7] * y + qc[8] * z + qc[11] * x * x + 2.0f * qc[13] * x * y +
-                       qc[14] * x * z + 3.0f * qc[16] * y * y + 2.0f * qc[17] * y * z + qc[18] * z * z;
-      const float Gz = qc[3] + qc[6] * x + qc[8] * y + 2.0f * qc[9] * z + qc[12] * x * x + qc[14] * x * y +
-                       2.0f * qc[15] * x * z + qc[17] * y * y + 2.0f * qc[18] * y * z + 3.0f * qc[19] * z * z;
-      const float gu = Gx * x + Gy * y + Gz * z;
-      gx = radial_part * x + (Gx - gu * x) * ir;
-      gy = radial_part * y + (Gy - gu * y) * ir;
-      gz = radial_part * z + (Gz - gu * z) * ir;
-      vir[0] += gx * dx; vir[1] += gx * dy; vir[2] += gx * dz;
-      vir[3] += gy * dx; vir[4] += gy * dy; vir[5] += gy * dz;
-      vir[6] += gz * dx; vir[7] += gz * dy; vir[8] += gz * dz;
+      const int64_t pu = p + (int64_t)u * LPA;
+      gpair[3 * pu] = gx;
+      gpair[3 * pu + 1] = gy;
+      gpair[3 * pu + 2] = gz;
     }
-    gpair[3 * p] = gx;
-    gpair[3 * p + 1] = gy;
-    gpair[3 * p + 2] = gz;
   }
 }
 

@@ -90,10 +90,11 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
 }
 
 // ---------------------------------------------------------------------------
-// blocks [0, nb_gather): force gather, LPA lanes per atom; with VAR, gpair
+// blocks [0, B*nchunk): FP64 sums per structure, fixed order (first in the
+// grid, so they start at once and overlap the gather);
+// the last nb_gather blocks: force gather, LPA lanes per atom; with VAR, gpair
 // holds one gradient set per head ([M][gstride][3]) and the kernel writes the
-// mean force and the per-atom force variance (1/M) sum_m |F^m - Fbar|^2;
-// blocks [nb_gather, nb_gather + B*nchunk): FP64 sums per structure, fixed order
+// mean force and the per-atom force variance (1/M) sum_m |F^m - Fbar|^2
 template <int LPA, bool VAR>
 __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const float* __restrict__ gpair,
                                                      const float* __restrict__ atomic_e,
@@ -102,9 +103,10 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
                                                      int* __restrict__ counters, float* __restrict__ forces,
                                                      float* __restrict__ force_var, double* __restrict__ energy,
                                                      double* __restrict__ energy_var, double* __restrict__ stress) {
-  if ((int)blockIdx.x < nb_gather) {
+  const int n_red = (int)gridDim.x - nb_gather;
+  if ((int)blockIdx.x >= n_red) {
     const int q = threadIdx.x & (LPA - 1);
-    const int i = blockIdx.x * (kPairBlock / LPA) + threadIdx.x / LPA;
+    const int i = ((int)blockIdx.x - n_red) * (kPairBlock / LPA) + threadIdx.x / LPA;
     const bool live = i < sys.n_atoms;
     if (!VAR) {
       float f[3] = {0.0f, 0.0f, 0.0f};
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   __shared__ double part[NW][NV];
   __shared__ double vals[NV];
   __shared__ int last;
-  const int rb = blockIdx.x - nb_gather;
+  const int rb = blockIdx.x;
   const int b = rb / nchunk, chunk = rb % nchunk;
   const int64_t s0 = sys.atom_ptr[b], s1 = sys.atom_ptr[b + 1];
   const int64_t csz = (s1 - s0 + nchunk - 1) / nchunk;
@@ -202,6 +204,7 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
+    if (v < kMaxHeads ? v >= M : !want_stress) continue;  // uniform: unused heads / no stress
     double x = v < kMaxHeads ? accE[v] : accV[v - kMaxHeads];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -210,9 +213,11 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   __syncthreads();
   if (threadIdx.x < NV) {
     double x = 0.0;
+    const int v = threadIdx.x;
+    if (v < kMaxHeads ? v < M : want_stress != 0)
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) x += part[ww][threadIdx.x];
-    vals[threadIdx.x] = x;
+      for (int ww = 0; ww < NW; ++ww) x += part[ww][v];
+    vals[v] = x;
   }
   if (nchunk > 1) {
     __syncthreads();

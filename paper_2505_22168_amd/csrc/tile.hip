@@ -88,16 +88,6 @@ __global__ void __launch_bounds__(kTileThreads)
   const int nh = PERHEAD ? m.M : 1;
 
   load_tables(&tb);
-  for (int a = tid; a < TM; a += kTileThreads) {
-    float sc = 0.0f, sh = 0.0f;
-    if (a < n_rows) {
-      const int z = sys.species[row0 + a];
-      sc = m.scale[z];
-      sh = m.shift[z];
-    }
-    sScale[a] = sc;
-    sShift[a] = sh;
-  }
   for (int t = tid; t < TM * 9; t += kTileThreads) sVir[t] = 0.0f;
   if (FUSED) stage_beta(m, s_beta);
   __syncthreads();
@@ -148,6 +138,19 @@ __global__ void __launch_bounds__(kTileThreads)
 
   // ---- invariants ------------------------------------------------------------
   contract_forward_a<TM, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  // per-atom scale / shift, by the last wave (idle in the phase above), for
+  // the network epilogue
+  if (tid >= kTileThreads - 64 && tid - (kTileThreads - 64) < TM) {
+    const int a = tid - (kTileThreads - 64);
+    float sc = 0.0f, sh = 0.0f;
+    if (a < n_rows) {
+      const int z = sys.species[row0 + a];
+      sc = m.scale[z];
+      sh = m.shift[z];
+    }
+    sScale[a] = sc;
+    sShift[a] = sh;
+  }
   __syncthreads();
   contract_forward_b<TM, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
   __syncthreads();
