@@ -168,8 +168,13 @@ def run_md(args):
     import torch
     import paper_2505_22168_amd as g
     from workloads import make_workload
+    import dataclasses
+    from workloads.configs import make_params
     masses_by_species = {0: 6.94, 1: 30.974, 2: 15.999, 3: 12.011, 4: 1.008}
     batch, params, spec = make_workload(args.workload)
+    # random weights make an unphysical potential: the species scale sigma0
+    # sets the force magnitude (the arithmetic per step does not depend on it)
+    params = make_params(dataclasses.replace(spec.model, sigma0=args.md_sigma0), spec.seed + 1000)
     masses = np.array([masses_by_species[int(z) % 5] for z in batch.species])
     v0 = g.maxwell_boltzmann(masses, 600.0, seed=3)
     system = g.System.from_batch(batch, "cuda")
@@ -189,18 +194,21 @@ def run_md(args):
         md.run(reps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        e1 = float(md.energy.sum().item()) + md.kinetic_energy(masses)
+        ke1 = md.kinetic_energy(masses)
+        e1 = float(md.energy.sum().item()) + ke1
+        t1 = 2.0 * ke1 / (3.0 * batch.n_atoms * g.api.KB_EV_PER_K)
         nsteps = reps * gs
         out[prec] = {"value": batch.n_atoms * nsteps / wall, "ms_per_step": wall / nsteps * 1e3,
                      "us_per_atom_step": wall / nsteps / batch.n_atoms * 1e6, "steps": nsteps + gs,
                      "status": md.status(), "total_energy_drift_eV_per_atom": (e1 - e0) / batch.n_atoms,
-                     "finite": bool(torch.isfinite(system.pos).all().item())}
+                     "finite": bool(torch.isfinite(system.pos).all().item()), "T_final_K": t1}
         print(f"[bench-md] {prec}: {out[prec]}", file=sys.stderr, flush=True)
         md.release()
     line = {"metric": "MD atom-steps/s (NVE velocity Verlet, HIP graph, skin list)", "value": out["bf16"]["value"],
             "unit": "atom-steps/s", "n_gpus": 1, "steps": out["bf16"]["steps"], "dtype": "bf16",
             "config": {"workload": args.workload, "n_atoms": batch.n_atoms, "dt_fs": 0.5, "skin": skin,
-                       "graph_steps": args.graph_steps, "mlp": list(spec.model.hidden)},
+                       "graph_steps": args.graph_steps, "mlp": list(spec.model.hidden), "sigma0": args.md_sigma0,
+                       "T0_K": 600.0},
             "bf16": out["bf16"], "fp32": out["fp32"]}
     print(json.dumps(line))
 
@@ -315,6 +323,9 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip oracle errors and the CPU baseline")
     ap.add_argument("--md", action="store_true", help="time whole MD steps instead (not the headline metric)")
     ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--md-sigma0", type=float, default=0.01, help="species energy scale of the MD model")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (reference for HBM byte counters)")
     ap.add_argument("--plan", default="auto", choices=["auto", "builtin"],
                     help="execution plan: autotuned (cached per shape class) or the library's built-in choice")
     ap.add_argument("--ensemble", action="store_true",
@@ -327,6 +338,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe:
+        import torch
+        x = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": args.steps}))
+        return
     if args.md:
         return run_md(args)
     if args.plan == "auto" and "GMNN_TUNE_CACHE" not in os.environ:

@@ -28,6 +28,20 @@ __host__ __device__ inline uint64_t pair_key(int j, int sx, int sy, int sz) {
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware block order.  The 8 XCDs of the chip (each with its own L2) take
+// workgroups round-robin by block index; xcd_block maps the launch so that
+// XCD x processes one contiguous run of logical blocks (nb split as evenly
+// as possible), keeping the neighbour rows that nearby atoms share in one
+// L2.  A bijection of [0, nb).
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// ---------------------------------------------------------------------------
 // wave-level helpers
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return __lane_id(); }

@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_rows(
   __shared__ uint64_t s_keys[MODE ? kRowsWaves : 1][MODE ? GMNN_MAX_ROW : 1];
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
-  const int i = blockIdx.x * kRowsWaves + w;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kRowsWaves + w;
   if (i >= n_atoms) return;
   if (!*go) return;
   if (*n_cells_total > cell_capacity) return;
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_reverse(int n_atoms, const
                                                              const int* __restrict__ go) {
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
-  const int i = blockIdx.x * kRowsWaves + w;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kRowsWaves + w;
   if (i >= n_atoms) return;
   if (!*go) return;
   if (*n_pairs > capacity) return;

@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(kPairBlock) pair_moments(DevModel m, DevSystem
   stage_beta(m, s_beta);
   __syncthreads();
   const int q = threadIdx.x & (LPA - 1);
-  const int i = blockIdx.x * (kPairBlock / LPA) + threadIdx.x / LPA;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * (kPairBlock / LPA) + threadIdx.x / LPA;
   const bool live = i < sys.n_atoms;
   float v[128];
 #pragma unroll
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
   stage_beta(m, s_beta);
   __syncthreads();
   const int q = threadIdx.x & (LPA - 1);
-  const int i = blockIdx.x * (kPairBlock / LPA) + threadIdx.x / LPA;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * (kPairBlock / LPA) + threadIdx.x / LPA;
   const bool live = i < sys.n_atoms;
   float vir[9];
 #pragma unroll
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   const int n_red = (int)gridDim.x - nb_gather;
   if ((int)blockIdx.x >= n_red) {
     const int q = threadIdx.x & (LPA - 1);
-    const int i = ((int)blockIdx.x - n_red) * (kPairBlock / LPA) + threadIdx.x / LPA;
+    const int i = xcd_block((int)blockIdx.x - n_red, nb_gather) * (kPairBlock / LPA) + threadIdx.x / LPA;
     const bool live = i < sys.n_atoms;
     if (!VAR) {
       float f[3] = {0.0f, 0.0f, 0.0f};

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kTileThreads)
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
-  const int row0 = blockIdx.x * TM;
+  const int row0 = xcd_block(blockIdx.x, gridDim.x) * TM;
   const int n_rows = min(TM, sys.n_atoms - row0);
   const int nh = PERHEAD ? m.M : 1;
 

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kPairBlock) pair_tangent(DevModel m, DevSystem
   stage_beta(m, s_beta);
   __syncthreads();
   const int q = threadIdx.x & (LPA - 1);
-  const int i = blockIdx.x * (kPairBlock / LPA) + threadIdx.x / LPA;
+  const int i = xcd_block(blockIdx.x, gridDim.x) * (kPairBlock / LPA) + threadIdx.x / LPA;
   const bool live = i < sys.n_atoms;
   float v[128];
 #pragma unroll
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   float* sT = sA + TA;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
-  const int row0 = blockIdx.x * TA;
+  const int row0 = xcd_block(blockIdx.x, gridDim.x) * TA;
   const int n_rows = min(TA, sys.n_atoms - row0);
   const int64_t k0 = (int64_t)blockIdx.x * 16;  // first weight-product row of this tile
 
