@@ -222,16 +222,27 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
  *          backward of 16 atoms, then one kernel gathers the forces and sums
  *          per structure (latency-bound small systems; needs <= 8 species,
  *          no force variance, every structure <= 8192 atoms);
- *   SPLIT  pair moments -> readout tiles -> pair backward -> gather/sums.
+ *   SPLIT  pair moments -> readout -> pair backward -> gather/sums, with the
+ *          readout (invariants, network, their backward) either
+ *            TILE    one kernel per 16 atoms, or
+ *            STREAM  three kernels: invariants of 16 atoms -> network on
+ *                    row tiles of 32 to 64 atoms -> invariant backward; G
+ *                    and dE/dG pass through the workspace (the head-mean
+ *                    backward only: not with GMNN_WANT_FORCE_VAR).
  * lanes_per_atom (16, 32 or 64) is the number of lanes that share one atom's
  * neighbour row in the pair and gather kernels.  Zero fields mean "built-in
- * choice": FUSED with 64 lanes below 8192 atoms, SPLIT with 16 beyond. */
+ * choice": FUSED with 64 lanes below 8192 atoms, SPLIT with 16 beyond, the
+ * STREAM readout from 16384 atoms on where it is allowed. */
 #define GMNN_SCHEDULE_AUTO 0
 #define GMNN_SCHEDULE_FUSED 1
 #define GMNN_SCHEDULE_SPLIT 2
+#define GMNN_READOUT_AUTO 0
+#define GMNN_READOUT_TILE 1
+#define GMNN_READOUT_STREAM 2
 typedef struct gmnn_plan {
   int32_t schedule;        /* GMNN_SCHEDULE_* */
   int32_t lanes_per_atom;  /* 0, 16, 32 or 64 */
+  int32_t readout;         /* GMNN_READOUT_* (SPLIT schedule) */
 } gmnn_plan;
 
 /* Resolve the zero fields of `plan` (NULL: all zero) for these shapes and

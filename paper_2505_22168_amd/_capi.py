@@ -31,6 +31,9 @@ GMNN_SYNC = 8
 GMNN_SCHEDULE_AUTO = 0
 GMNN_SCHEDULE_FUSED = 1
 GMNN_SCHEDULE_SPLIT = 2
+GMNN_READOUT_AUTO = 0
+GMNN_READOUT_TILE = 1
+GMNN_READOUT_STREAM = 2
 
 GMNN_OP_NEIGHBORS = 0
 GMNN_OP_ENERGY_FORCES = 1
@@ -68,7 +71,7 @@ class gmnn_md(C.Structure):
 
 
 class gmnn_plan(C.Structure):
-    _fields_ = [("schedule", C.c_int32), ("lanes_per_atom", C.c_int32)]
+    _fields_ = [("schedule", C.c_int32), ("lanes_per_atom", C.c_int32), ("readout", C.c_int32)]
 
 
 class gmnn_tune_entry(C.Structure):

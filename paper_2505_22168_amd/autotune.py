@@ -45,7 +45,7 @@ def shape_key(model, system, nl, flags: int) -> str:
 
 
 class TuneCache:
-    """JSON file of shape key -> {"schedule", "lanes_per_atom", "table"}."""
+    """JSON file of shape key -> {"schedule", "lanes_per_atom", "readout", "table"}."""
 
     def __init__(self, path: str | None = None):
         self.path = path or default_path()
@@ -76,7 +76,7 @@ class TuneCache:
 
 def run_autotune(ev, reps: int = 20):
     """gmnn_autotune for an EnergyForces evaluator: returns (plan, table) with
-    plan = {"schedule", "lanes_per_atom"} and table = [(plan, median_us, min_us)]."""
+    plan = {"schedule", "lanes_per_atom", "readout"} and table = [(plan, median_us, min_us)]."""
     lib = A.load()
     best = A.gmnn_plan()
     entries = (A.gmnn_tune_entry * 16)()
@@ -86,9 +86,9 @@ def run_autotune(ev, reps: int = 20):
                            C.c_void_p(torch.cuda.current_stream().cuda_stream), reps, C.byref(best), entries, 16,
                            C.byref(n))
     A.check(st, "gmnn_autotune")
-    table = [({"schedule": e.plan.schedule, "lanes_per_atom": e.plan.lanes_per_atom}, e.median_us, e.min_us)
-             for e in entries[: min(n.value, 16)]]
-    return {"schedule": best.schedule, "lanes_per_atom": best.lanes_per_atom}, table
+    table = [({"schedule": e.plan.schedule, "lanes_per_atom": e.plan.lanes_per_atom, "readout": e.plan.readout},
+              e.median_us, e.min_us) for e in entries[: min(n.value, 16)]]
+    return {"schedule": best.schedule, "lanes_per_atom": best.lanes_per_atom, "readout": best.readout}, table
 
 
 def tuned_plan(ev, cache: TuneCache | None = None, reps: int = 20) -> dict:
@@ -97,7 +97,9 @@ def tuned_plan(ev, cache: TuneCache | None = None, reps: int = 20) -> dict:
     key = shape_key(ev.model, ev.system, ev.nl, ev.flags)
     hit = cache.get(key)
     if hit is not None:
-        return {"schedule": int(hit["schedule"]), "lanes_per_atom": int(hit["lanes_per_atom"])}
+        return {"schedule": int(hit["schedule"]), "lanes_per_atom": int(hit["lanes_per_atom"]),
+                "readout": int(hit.get("readout", 0))}
     plan, table = run_autotune(ev, reps)
-    cache.put(key, dict(plan, table=[[p["schedule"], p["lanes_per_atom"], med, mn] for p, med, mn in table]))
+    cache.put(key, dict(plan, table=[[p["schedule"], p["lanes_per_atom"], p["readout"], med, mn]
+                                     for p, med, mn in table]))
     return plan

@@ -25,6 +25,11 @@ gmnn_status launch_tile(bool fused, bool perhead, const DevModel& m, const DevSy
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
                         int64_t gstride, hipStream_t stream);
 bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead);
+gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,
+                          float* atomic_e, float* psibar, hipStream_t s);
+size_t stream_lds_bytes(int hp, bool bf16, int n_heads);
+size_t stream_g_bytes(int n_atoms, bool bf16);
+size_t stream_dg_bytes(int n_atoms);
 size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead);
 bool train_supported(const DevModel& m);
 size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
@@ -51,9 +56,12 @@ static int reduce_chunks(const gmnn_system* sys) {
 // execution plans
 // ---------------------------------------------------------------------------
 struct Plan {
-  bool fused;  // one tile kernel for moments + readout + pair backward
-  int lpa;     // lanes per atom row in the pair and gather kernels
+  bool fused;   // one tile kernel for moments + readout + pair backward
+  int lpa;      // lanes per atom row in the pair and gather kernels
+  bool stream;  // split schedule: readout as three launches (64-row network tiles)
 };
+// at and above this many atoms the built-in plan streams the readout
+constexpr int kStreamMinAtoms = 16384;
 
 // the fused tile needs few species (beta staged in its LDS), the head-mean
 // backward only, and one reduction chunk per structure (its chunk counters
@@ -82,6 +90,12 @@ static gmnn_status resolve_plan(const gmnn_model* m, const gmnn_system* sys, uin
                         160 * 1024)
     return GMNN_ERR_UNSUPPORTED;
   out.lpa = lpa ? lpa : (small ? 64 : 16);
+  const int ro = in ? in->readout : GMNN_READOUT_AUTO;
+  if (ro != GMNN_READOUT_AUTO && ro != GMNN_READOUT_TILE && ro != GMNN_READOUT_STREAM) return GMNN_ERR_INVALID_ARG;
+  const bool can_stream = !out.fused && !(flags & GMNN_WANT_FORCE_VAR) &&
+                          stream_lds_bytes(L.HP1, (flags & GMNN_PREC_BF16) != 0, m->n_heads) <= 160 * 1024;
+  if (ro == GMNN_READOUT_STREAM && !can_stream) return GMNN_ERR_UNSUPPORTED;
+  out.stream = ro == GMNN_READOUT_STREAM || (ro == GMNN_READOUT_AUTO && can_stream && sys->n_atoms >= kStreamMinAtoms);
   return GMNN_OK;
 }
 
@@ -228,7 +242,7 @@ static DevSystem dev_system(const gmnn_system* s, const gmnn_neighbors* nl) {
 }
 
 struct EfLayout {
-  size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, partial = 0, counters = 0, bytes = 0;
+  size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, g = 0, dg = 0, partial = 0, counters = 0, bytes = 0;
 };
 
 static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags) {
@@ -246,6 +260,8 @@ static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmn
   L.atomic_e = take(4 * N * (size_t)m->n_heads);
   L.gpair = take(12 * (size_t)nl->capacity * nh);
   L.virial = take(4 * 9 * N);
+  L.g = take(stream_g_bytes((int)N, (flags & GMNN_PREC_BF16) != 0));
+  L.dg = take(stream_dg_bytes((int)N));
   L.partial = take(8 * (size_t)(kMaxHeads + 9) * sys->n_structs * reduce_chunks(sys));
   L.counters = take(4 * (size_t)sys->n_structs);
   L.bytes = off;
@@ -372,6 +388,7 @@ gmnn_status gmnn_resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint3
   if (resolved) {
     resolved->schedule = p.fused ? GMNN_SCHEDULE_FUSED : GMNN_SCHEDULE_SPLIT;
     resolved->lanes_per_atom = p.lpa;
+    resolved->readout = p.stream ? GMNN_READOUT_STREAM : GMNN_READOUT_TILE;
   }
   return GMNN_OK;
 }
@@ -439,7 +456,10 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
 #undef MOMENTS
       mark(1);
       mark(2);
-      st = launch_tile(false, var, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, s);
+      if (P.stream)
+        st = launch_stream(dm, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s);
+      else
+        st = launch_tile(false, var, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, s);
       if (st != GMNN_OK) return st;
       mark(3);
       mark(4);
@@ -501,7 +521,8 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
   if (!best || reps < 1 || reps > 1000 || max_entries < 0 || (max_entries > 0 && !entries))
     return GMNN_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  static const int kSched[2] = {GMNN_SCHEDULE_FUSED, GMNN_SCHEDULE_SPLIT};
+  static const int kSched[3] = {GMNN_SCHEDULE_FUSED, GMNN_SCHEDULE_SPLIT, GMNN_SCHEDULE_SPLIT};
+  static const int kReadout[3] = {GMNN_READOUT_TILE, GMNN_READOUT_TILE, GMNN_READOUT_STREAM};
   static const int kLanes[3] = {16, 32, 64};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return GMNN_ERR_HIP;
@@ -513,9 +534,9 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
   float best_us = 0.0f;
   bool have = false;
   std::vector<float> t(reps);
-  for (int si = 0; si < 2 && st == GMNN_OK; ++si) {
+  for (int si = 0; si < 3 && st == GMNN_OK; ++si) {
     for (int li = 0; li < 3 && st == GMNN_OK; ++li) {
-      const gmnn_plan cand = {kSched[si], kLanes[li]};
+      const gmnn_plan cand = {kSched[si], kLanes[li], kReadout[si]};
       Plan P;
       if (resolve_plan(m, sys, flags, &cand, P) != GMNN_OK) continue;
       // warm-up (also surfaces argument errors before anything is timed)

@@ -25,6 +25,7 @@ namespace gmnn {
 
 constexpr int PS = 201;   // atom stride of full tensors (odd)
 constexpr int IS = 945;   // atom stride of the intermediates (odd)
+constexpr int ISF = 421;  // ... when only the forward intermediates (T7, V8, M5, v6) are kept
 constexpr int kT7 = 0, kV8 = 135, kM5 = 210, kV6 = 345, kU8 = 420, kY = 645, kQv = 870;
 
 // LDS copies of the index tables (per-lane lookups in constant memory would
@@ -73,7 +74,7 @@ __device__ inline void load_tables(Tables* t) {
 #define GM_P1(a, s, i) P[(a) * PS + (s) * kFull + 1 + (i)]
 #define GM_P2(a, s, ij) P[(a) * PS + (s) * kFull + 4 + (ij)]
 #define GM_P3(a, s, ijk) P[(a) * PS + (s) * kFull + 13 + (ijk)]
-#define GM_I(a, off) I[(a) * IS + (off)]
+#define GM_I(a, off) I[(a) * ISTR + (off)]
 
 template <bool BF16>
 __device__ inline void store_feature(void* G, int idx, float v) {
@@ -97,7 +98,7 @@ __host__ __device__ constexpr int pair_second(int p) {
 //   pair task (a, p = (s1 <= s2)):  T7[p], M5[p]; fam4[p] = tr T7[p] and
 //                                   fam3[p] = tr M5[p] (Psi2 is symmetric)
 //   channel task (a, s):            V8[s, .], v6[s, .]; fam1[s]; fam2[(s, s2 >= s)]
-template <int TM, int NT, bool BF16, bool FEATURES = true>
+template <int TM, int NT, bool BF16, bool FEATURES = true, int ISTR = IS>
 __device__ inline void contract_forward_a(const float* __restrict__ P, float* __restrict__ I, void* G, int ldg,
                                           const Tables& tb) {
   const int tid = threadIdx.x;
@@ -203,7 +204,7 @@ __device__ inline void contract_forward_a(const float* __restrict__ P, float* __
 //   pair task (a, p = (s1 <= s2)):  fam7[(s', p)] for every s'; fam5[(s1, s2, s3)]
 //                                   for s3 >= s2; fam6[(p, s3)] for every s3
 //   channel task (a, s2):           fam8[(s1, s2, s3)] for every s1, s3
-template <int TM, int NT, bool BF16>
+template <int TM, int NT, bool BF16, int ISTR = IS>
 __device__ inline void contract_forward_b(const float* __restrict__ P, const float* __restrict__ I, void* G, int ldg,
                                           const Tables& tb) {
   constexpr int np = TM * 15, ns = TM * kS;
@@ -277,6 +278,7 @@ __device__ inline void contract_forward_b(const float* __restrict__ P, const flo
 template <int TM, int NT>
 __device__ inline void contract_backward_a(const float* __restrict__ P, const float* __restrict__ Gb, int ldgb,
                                            float* __restrict__ I, const Tables& tb) {
+  constexpr int ISTR = IS;
   constexpr int nu = TM * 15, ny = TM * 15;
   for (int t = threadIdx.x; t < nu + ny; t += NT) {
     if (t < nu) {
@@ -340,6 +342,7 @@ __device__ inline void contract_backward_a(const float* __restrict__ P, const fl
 template <int TM, int NT>
 __device__ inline void contract_backward_b(const float* __restrict__ P, const float* __restrict__ Gb, int ldgb,
                                            const float* __restrict__ I, float* __restrict__ Pb, const Tables& tb) {
+  constexpr int ISTR = IS;
   constexpr int n2 = TM * 15, n3 = TM * 9, n1 = TM * 5;
   for (int t = threadIdx.x; t < n2 + n3 + n1; t += NT) {
     if (t < n2) {

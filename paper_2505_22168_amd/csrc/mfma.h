@@ -17,13 +17,18 @@
 namespace gmnn {
 
 // Each wave owns one 16-row block rb and the 16-column blocks nb0 + i*nbs
-// (i < TPW, nb < NB).  Loads run two k-steps ahead of the MFMAs.
+// (i < TPW, nb < NB).  B fragments stream from L2 through a ring of
+// kPrefetch register buffers (loads run kPrefetch k-steps ahead of the
+// MFMAs): with the fragments of all waves in flight this covers the L2
+// latency at the CU's fetch rate.
+constexpr int kPrefetch = 4;
+
 template <int TPW>
 __device__ inline void mma_bf16(const __bf16* __restrict__ A, int lda, int rb, const bf16x8* __restrict__ Bp, int KB,
                                 int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
   const int l = threadIdx.x & 63;
   const __bf16* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 8;
-  bf16x8 b0[TPW], b1[TPW];
+  bf16x8 b[kPrefetch][TPW];
   auto load = [&](bf16x8 (&dst)[TPW], int kb) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
@@ -31,22 +36,23 @@ __device__ inline void mma_bf16(const __bf16* __restrict__ A, int lda, int rb, c
       if (nb < NB && kb < KB) dst[i] = Bp[((size_t)nb * KB + kb) * 64 + l];
     }
   };
-  auto step = [&](const bf16x8 (&b)[TPW], int kb) {
+  auto step = [&](const bf16x8 (&bb)[TPW], int kb) {
     const bf16x8 a = *(const bf16x8*)(arow + kb * 32);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = nb0 + i * nbs;
-      if (nb < NB) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[i], acc[i], 0, 0, 0);
+      if (nb < NB) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb[i], acc[i], 0, 0, 0);
     }
   };
-  load(b0, 0);
-  load(b1, 1);
-  for (int kb = 0; kb < KB; kb += 2) {
-    step(b0, kb);
-    load(b0, kb + 2);
-    if (kb + 1 < KB) {
-      step(b1, kb + 1);
-      load(b1, kb + 3);
+#pragma unroll
+  for (int s = 0; s < kPrefetch; ++s) load(b[s], s);
+  for (int kb = 0; kb < KB; kb += kPrefetch) {
+#pragma unroll
+    for (int s = 0; s < kPrefetch; ++s) {
+      if (kb + s < KB) {
+        step(b[s], kb + s);
+        load(b[s], kb + s + kPrefetch);
+      }
     }
   }
 }
@@ -56,7 +62,7 @@ __device__ inline void mma_f32(const float* __restrict__ A, int lda, int rb, con
                                int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
   const int l = threadIdx.x & 63;
   const float* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 4;
-  float4 b0[TPW], b1[TPW];
+  float4 b[kPrefetch][TPW];
   auto load = [&](float4 (&dst)[TPW], int kc) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
@@ -64,27 +70,28 @@ __device__ inline void mma_f32(const float* __restrict__ A, int lda, int rb, con
       if (nb < NB && kc < KC) dst[i] = Bp[((size_t)nb * KC + kc) * 64 + l];
     }
   };
-  auto step = [&](const float4 (&b)[TPW], int kc) {
+  auto step = [&](const float4 (&bb)[TPW], int kc) {
     const float4 a = *(const float4*)(arow + kc * 16);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = nb0 + i * nbs;
       if (nb < NB) {
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[i].x, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[i].y, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[i].z, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[i].w, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb[i].x, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb[i].y, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bb[i].z, acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bb[i].w, acc[i], 0, 0, 0);
       }
     }
   };
-  load(b0, 0);
-  load(b1, 1);
-  for (int kc = 0; kc < KC; kc += 2) {
-    step(b0, kc);
-    load(b0, kc + 2);
-    if (kc + 1 < KC) {
-      step(b1, kc + 1);
-      load(b1, kc + 3);
+#pragma unroll
+  for (int s = 0; s < kPrefetch; ++s) load(b[s], s);
+  for (int kc = 0; kc < KC; kc += kPrefetch) {
+#pragma unroll
+    for (int s = 0; s < kPrefetch; ++s) {
+      if (kc + s < KC) {
+        step(b[s], kc + s);
+        load(b[s], kc + s + kPrefetch);
+      }
     }
   }
 }

@@ -1,0 +1,530 @@
+// Streamed readout for large systems (three launches instead of the tile):
+//
+//   readout_features  invariants of the moments (Section 2.1, eq.
+//                     contraction), 16 atoms per block -> G [N][384] in HBM
+//                     (BF16 or FP32: the operand precision of the network)
+//   readout_network   the network, its scale/shift (eq. scale_shift) and its
+//                     input gradient dE/dG, for row tiles of 32 to 64 atoms:
+//                     every weight fragment fetched from L2 feeds 2 to 4 MFMA
+//                     row blocks, 1/2 to 1/4 of the L2 traffic per atom of
+//                     the 16-row tile
+//   readout_backward  product-rule backward of the invariants, 8 atoms per
+//                     block -> dE/dPsi [N][100]
+//
+// The arithmetic is the tile's, operation for operation (same contraction
+// code, same MFMA shapes and k order, same epilogues), so both give the same
+// result up to FP32 summation order.
+#include "common.h"
+#include "contraction.h"
+#include "mfma.h"
+#include "model.h"
+
+namespace gmnn {
+
+constexpr int kRoAtoms = 16;     // atoms per contraction block
+constexpr int kRoThreads = 512;  // threads of every readout block
+constexpr int kRoWaves = kRoThreads / 64;
+
+static constexpr size_t ro_al(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// shared: the tile's packed moments (one contiguous run) -> full tensors
+__device__ inline void ro_load_moments(const float* __restrict__ psi, int row0, int n_rows, float* __restrict__ sPsi,
+                                       const Tables& tb) {
+  constexpr int NP = kS * kPacked;
+  constexpr int NU = (kRoAtoms * NP + kRoThreads - 1) / kRoThreads;
+  const int tid = threadIdx.x;
+  float v[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int t = tid + u * kRoThreads;
+    v[u] = t < n_rows * NP ? psi[(int64_t)row0 * NP + t] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int t = tid + u * kRoThreads;
+    if (t < kRoAtoms * NP) {
+      const int a = t / NP, e = t % NP;
+      const int s = e / kPacked, c = e % kPacked;
+      const int n = tb.packed_mult[c];
+      for (int q = 0; q < n; ++q) sPsi[a * PS + s * kFull + tb.packed_full[c][q]] = v[u];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1. invariants
+template <bool BF16>
+struct FeatLds {
+  static constexpr int ESZ = BF16 ? 2 : 4;
+  static constexpr size_t tables = 0;
+  static constexpr size_t psi = ro_al(sizeof(Tables));
+  static constexpr size_t inter = psi + ro_al(4 * (size_t)kRoAtoms * PS);
+  static constexpr size_t g = inter + ro_al(4 * (size_t)kRoAtoms * ISF);
+  static constexpr size_t bytes = g + ro_al((size_t)ESZ * kRoAtoms * kFP);
+};
+
+template <bool BF16>
+__global__ void __launch_bounds__(kRoThreads) readout_features(DevSystem sys, const float* __restrict__ psi,
+                                                               void* __restrict__ G) {
+  using L = FeatLds<BF16>;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  Tables& tb = *(Tables*)(lds + L::tables);
+  float* sPsi = (float*)(lds + L::psi);
+  float* sI = (float*)(lds + L::inter);
+  char* sG = lds + L::g;
+  const int row0 = xcd_block(blockIdx.x, gridDim.x) * kRoAtoms;
+  const int n_rows = min(kRoAtoms, sys.n_atoms - row0);
+  load_tables(&tb);
+  __syncthreads();
+  ro_load_moments(psi, row0, n_rows, sPsi, tb);
+  __syncthreads();
+  contract_forward_a<kRoAtoms, kRoThreads, BF16, true, ISF>(sPsi, sI, sG, kFP, tb);
+  __syncthreads();
+  contract_forward_b<kRoAtoms, kRoThreads, BF16, ISF>(sPsi, sI, sG, kFP, tb);
+  __syncthreads();
+  // rows of G are contiguous: 16-byte copies
+  const int n16 = n_rows * kFP * L::ESZ / 16;
+  uint4* dst = (uint4*)((char*)G + (size_t)row0 * kFP * L::ESZ);
+  for (int t = threadIdx.x; t < n16; t += kRoThreads) dst[t] = ((const uint4*)sG)[t];
+}
+
+// ---------------------------------------------------------------------------
+// 2. network on row tiles of TM atoms.  Wave w owns the 16-column blocks
+// w, w + 8, ... of every product, for all TM/16 row blocks; each B fragment
+// loaded from L2 feeds TM/16 MFMAs.
+template <int MB, int TPW>
+__device__ inline void mma_rows_bf16(const __bf16* __restrict__ A, int lda, const bf16x8* __restrict__ Bp, int KB,
+                                     int nb0, int nbs, int NB, floatx4 (&acc)[MB][TPW]) {
+  constexpr int PF = 2;
+  const int l = threadIdx.x & 63;
+  const __bf16* abase = A + (l & 15) * lda + (l >> 4) * 8;
+  bf16x8 b[PF][TPW];
+  auto load = [&](bf16x8 (&dst)[TPW], int kb) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB && kb < KB) dst[i] = Bp[((size_t)nb * KB + kb) * 64 + l];
+    }
+  };
+  auto step = [&](const bf16x8 (&bb)[TPW], int kb) {
+    bf16x8 a[MB];
+#pragma unroll
+    for (int r = 0; r < MB; ++r) a[r] = *(const bf16x8*)(abase + r * 16 * lda + kb * 32);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB)
+#pragma unroll
+        for (int r = 0; r < MB; ++r) acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bb[i], acc[r][i], 0, 0, 0);
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < PF; ++s) load(b[s], s);
+  for (int kb = 0; kb < KB; kb += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      if (kb + s < KB) {
+        step(b[s], kb + s);
+        load(b[s], kb + s + PF);
+      }
+    }
+  }
+}
+
+template <int MB, int TPW>
+__device__ inline void mma_rows_f32(const float* __restrict__ A, int lda, const float4* __restrict__ Bp, int KC,
+                                    int nb0, int nbs, int NB, floatx4 (&acc)[MB][TPW]) {
+  constexpr int PF = 2;
+  const int l = threadIdx.x & 63;
+  const float* abase = A + (l & 15) * lda + (l >> 4) * 4;
+  float4 b[PF][TPW];
+  auto load = [&](float4 (&dst)[TPW], int kc) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB && kc < KC) dst[i] = Bp[((size_t)nb * KC + kc) * 64 + l];
+    }
+  };
+  auto step = [&](const float4 (&bb)[TPW], int kc) {
+    float4 a[MB];
+#pragma unroll
+    for (int r = 0; r < MB; ++r) a[r] = *(const float4*)(abase + r * 16 * lda + kc * 16);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB)
+#pragma unroll
+        for (int r = 0; r < MB; ++r) {
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, bb[i].x, acc[r][i], 0, 0, 0);
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, bb[i].y, acc[r][i], 0, 0, 0);
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, bb[i].z, acc[r][i], 0, 0, 0);
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, bb[i].w, acc[r][i], 0, 0, 0);
+        }
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < PF; ++s) load(b[s], s);
+  for (int kc = 0; kc < KC; kc += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      if (kc + s < KC) {
+        step(b[s], kc + s);
+        load(b[s], kc + s + PF);
+      }
+    }
+  }
+}
+
+template <bool BF16, int MB, int TPW>
+__device__ inline void mma_rows(const void* A, int lda, const void* Bbf, const void* Bf, int K, int nb0, int nbs,
+                                int NB, floatx4 (&acc)[MB][TPW]) {
+#pragma unroll
+  for (int r = 0; r < MB; ++r)
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acc[r][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  if (BF16) mma_rows_bf16<MB, TPW>((const __bf16*)A, lda, (const bf16x8*)Bbf, K / 32, nb0, nbs, NB, acc);
+  else mma_rows_f32<MB, TPW>((const float*)A, lda, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
+}
+
+// rows per network block: as many 16-row MFMA blocks as the register file
+// holds with swish'(z1) kept for the backward (8 waves, 256 registers each)
+template <int HP, bool BF16>
+constexpr int net_rows() { return BF16 ? (HP >= 512 ? 48 : 64) : 32; }
+
+template <int HP, bool BF16>
+struct NetLds {
+  using St = NetStrides<HP, BF16>;
+  static constexpr int TM = net_rows<HP, BF16>();
+  static constexpr int ESZ = BF16 ? 2 : 4;
+  static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
+  // region A: G, later delta2; region H: h1, later delta1; then the row
+  // scale/shift and the per-wave energy partials [NW][TM][M] (sized by M)
+  static constexpr size_t a = 0;
+  static constexpr size_t h = ro_al(mx((size_t)ESZ * TM * St::G, (size_t)ESZ * TM * St::H));
+  static constexpr size_t rows = h + ro_al((size_t)ESZ * TM * St::H);
+  static constexpr size_t ep = rows + ro_al(4 * 2 * (size_t)TM);
+  static constexpr size_t bytes(int M) { return ep + ro_al(4 * (size_t)kRoWaves * TM * M); }
+};
+
+template <int HP, bool BF16>
+__global__ void __launch_bounds__(kRoThreads)
+    readout_network(DevModel m, DevSystem sys, const void* __restrict__ G, float* __restrict__ atomic_e,
+                    float* __restrict__ dG) {
+  using L = NetLds<HP, BF16>;
+  using St = NetStrides<HP, BF16>;
+  constexpr int TM = L::TM, MB = TM / 16, NW = kRoWaves;
+  constexpr int NBH = HP / 16, NBG = kFP / 16;
+  constexpr int TPW = (NBH + NW - 1) / NW, TPW_G = (NBG + NW - 1) / NW;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  char* sA = lds + L::a;
+  char* sH = lds + L::h;
+  float* sEp = (float*)(lds + L::ep);
+  float* sScale = (float*)(lds + L::rows);
+  float* sShift = sScale + TM;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int row0 = xcd_block(blockIdx.x, gridDim.x) * TM;
+  const int n_rows = min(TM, sys.n_atoms - row0);
+  const int M = m.M;
+
+  // G rows -> region A (row stride St::G), zero rows beyond the system; every
+  // load of the tile is issued before the first store
+  {
+    constexpr int C16 = kFP * L::ESZ / 16;  // 16-byte chunks per row
+    constexpr int NU = (TM * C16 + kRoThreads - 1) / kRoThreads;
+    const uint4* src = (const uint4*)((const char*)G + (size_t)row0 * kFP * L::ESZ);
+    uint4 v[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int t = tid + u * kRoThreads;
+      v[u] = uint4{0u, 0u, 0u, 0u};
+      if (t < n_rows * C16) v[u] = src[t];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int t = tid + u * kRoThreads;
+      if (t < TM * C16) *(uint4*)(sA + (size_t)(t / C16) * St::G * L::ESZ + (t % C16) * 16) = v[u];
+    }
+    for (int a = tid; a < TM; a += kRoThreads) {
+      float sc = 0.0f, sh = 0.0f;
+      if (a < n_rows) {
+        const int z = sys.species[row0 + a];
+        sc = m.scale[z];
+        sh = m.shift[z];
+      }
+      sScale[a] = sc;
+      sShift[a] = sh;
+    }
+  }
+  __syncthreads();
+
+  // z1 = G W1 + b1, h1 = swish(z1) -> region H; swish'(z1) stays in registers
+  floatx4 dsw1[MB][TPW];
+  {
+    floatx4 acc[MB][TPW];
+    mma_rows<BF16, MB, TPW>(sA, St::G, m.w1_bf16, m.w1_f32, kFP, w, NW, NBH, acc);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = w + i * NW;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+      const float bias = m.b1[col];
+#pragma unroll
+      for (int r = 0; r < MB; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r * 16 + 4 * (l >> 4) + j;
+          float d;
+          const float hv = swish_parts(acc[r][i][j] + bias, d);
+          dsw1[r][i][j] = d;
+          st_act<BF16>(sH, row * St::H + col, hv);
+        }
+    }
+  }
+  __syncthreads();
+
+  // z2 = h1 W2 + b2, h2 = swish(z2); delta2 = swish'(z2) sigma wbar -> region A
+  // (G is dead); per-wave partial sums of h2 . W3[:,m] -> sEp
+  {
+    floatx4 acc[MB][TPW];
+    mma_rows<BF16, MB, TPW>(sH, St::H, m.w2_bf16, m.w2_f32, HP, w, NW, NBH, acc);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = w + i * NW;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+      const float bias = m.b2[col];
+      const float wb = m.w3bar[col];
+#pragma unroll
+      for (int r = 0; r < MB; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r * 16 + 4 * (l >> 4) + j;
+          float d;
+          acc[r][i][j] = swish_parts(acc[r][i][j] + bias, d);
+          st_act<BF16>(sA, row * St::H + col, d * sScale[row] * wb);
+        }
+    }
+    for (int hm = 0; hm < M; ++hm) {
+#pragma unroll
+      for (int r = 0; r < MB; ++r) {
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          const int nb = w + i * NW;
+          if (nb >= NBH) continue;
+          const float w3 = m.w3[(nb * 16 + (l & 15)) * M + hm];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) part[j] += acc[r][i][j] * w3;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v = part[j];
+          v += __shfl_xor(v, 8, 16);
+          v += __shfl_xor(v, 4, 16);
+          v += __shfl_xor(v, 2, 16);
+          v += __shfl_xor(v, 1, 16);
+          if ((l & 15) == 0) sEp[(w * TM + r * 16 + 4 * (l >> 4) + j) * M + hm] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < TM * M; t += kRoThreads) {
+    const int a = t / M, hm = t % M;
+    if (a < n_rows) {
+      float y = m.b3[hm];
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) y += sEp[(ww * TM + a) * M + hm];
+      atomic_e[(int64_t)(row0 + a) * M + hm] = sScale[a] * y + sShift[a];
+    }
+  }
+
+  // delta1 = swish'(z1) (delta2 W2^T) -> region H
+  {
+    floatx4 acc[MB][TPW];
+    mma_rows<BF16, MB, TPW>(sA, St::H, m.w2t_bf16, m.w2t_f32, HP, w, NW, NBH, acc);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = w + i * NW;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int r = 0; r < MB; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r * 16 + 4 * (l >> 4) + j;
+          st_act<BF16>(sH, row * St::H + col, acc[r][i][j] * dsw1[r][i][j]);
+        }
+    }
+  }
+  __syncthreads();
+
+  // dE/dG = delta1 W1^T -> HBM [N][kFP] (FP32)
+  {
+    floatx4 acc[MB][TPW_G];
+    mma_rows<BF16, MB, TPW_G>(sH, St::H, m.w1t_bf16, m.w1t_f32, HP, w, NW, NBG, acc);
+#pragma unroll
+    for (int i = 0; i < TPW_G; ++i) {
+      const int nb = w + i * NW;
+      if (nb >= NBG) continue;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int r = 0; r < MB; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r * 16 + 4 * (l >> 4) + j;
+          if (row < n_rows) dG[(int64_t)(row0 + row) * kFP + col] = acc[r][i][j];
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. invariant backward: dE/dG and the moments -> dE/dPsi (packed).  Blocks of
+// 8 atoms (256 threads, about one task per thread in every phase), two per
+// CU, so one block's loads overlap the other's arithmetic.
+constexpr int kBkAtoms = 8;
+constexpr int kBkThreads = 256;
+
+struct BackLds {
+  static constexpr int LDGB = kFP + 1;
+  static constexpr size_t tables = 0;
+  static constexpr size_t psi = ro_al(sizeof(Tables));
+  static constexpr size_t inter = psi + ro_al(4 * (size_t)kBkAtoms * PS);
+  static constexpr size_t gb = inter + ro_al(4 * (size_t)kBkAtoms * IS);
+  static constexpr size_t pb = gb + ro_al(4 * (size_t)kBkAtoms * LDGB);
+  static constexpr size_t bytes = pb + ro_al(4 * (size_t)kBkAtoms * PS);
+};
+
+__global__ void __launch_bounds__(kBkThreads) readout_backward(DevSystem sys, const float* __restrict__ psi,
+                                                               const float* __restrict__ dG,
+                                                               float* __restrict__ psibar) {
+  using L = BackLds;
+  constexpr int TB = kBkAtoms, NT = kBkThreads;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  Tables& tb = *(Tables*)(lds + L::tables);
+  float* sPsi = (float*)(lds + L::psi);
+  float* sI = (float*)(lds + L::inter);
+  float* sGb = (float*)(lds + L::gb);
+  float* sPb = (float*)(lds + L::pb);
+  const int tid = threadIdx.x;
+  const int row0 = xcd_block(blockIdx.x, gridDim.x) * TB;
+  const int n_rows = min(TB, sys.n_atoms - row0);
+  // all loads of the tile (dE/dG rows, packed moments) issued up front
+  constexpr int NG = TB * kFP / 4 / NT;  // float4 per thread (exact)
+  constexpr int NP = kS * kPacked;
+  constexpr int NM = (TB * NP + NT - 1) / NT;
+  static_assert(TB * kFP / 4 % NT == 0, "dE/dG tile in whole float4 per thread");
+  float4 gv[NG];
+  float mv[NM];
+  const float4* gsrc = (const float4*)(dG + (int64_t)row0 * kFP);
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    const int t = tid + u * NT;
+    gv[u] = (t * 4 / kFP < n_rows) ? gsrc[t] : float4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+#pragma unroll
+  for (int u = 0; u < NM; ++u) {
+    const int t = tid + u * NT;
+    mv[u] = t < n_rows * NP ? psi[(int64_t)row0 * NP + t] : 0.0f;
+  }
+  load_tables(&tb);
+#pragma unroll
+  for (int u = 0; u < NG; ++u) {
+    const int t = (tid + u * NT) * 4;
+    const int a = t / kFP, f = t % kFP;
+    float* d = sGb + a * L::LDGB + f;
+    d[0] = gv[u].x;
+    d[1] = gv[u].y;
+    d[2] = gv[u].z;
+    d[3] = gv[u].w;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NM; ++u) {
+    const int t = tid + u * NT;
+    if (t < TB * NP) {
+      const int a = t / NP, e = t % NP;
+      const int s = e / kPacked, c = e % kPacked;
+      const int n = tb.packed_mult[c];
+      for (int q = 0; q < n; ++q) sPsi[a * PS + s * kFull + tb.packed_full[c][q]] = mv[u];
+    }
+  }
+  __syncthreads();
+  contract_forward_a<TB, NT, false, false>(sPsi, sI, nullptr, 0, tb);
+  __syncthreads();
+  contract_backward_a<TB, NT>(sPsi, sGb, L::LDGB, sI, tb);
+  __syncthreads();
+  contract_backward_b<TB, NT>(sPsi, sGb, L::LDGB, sI, sPb, tb);
+  __syncthreads();
+  fold_packed<TB, NT>(sPb, tb, [&](int a, int e, float v) {
+    if (a < n_rows) psibar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+  });
+}
+
+// ---------------------------------------------------------------------------
+template <class K>
+static bool ro_set_lds(K k, size_t bytes) {
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
+constexpr size_t kLdsMax = 160 * 1024;
+
+template <int HP, bool BF16>
+static gmnn_status launch_stream_t(const DevModel& m, const DevSystem& sys, const float* psi, void* G, float* dG,
+                                   float* atomic_e, float* psibar, hipStream_t s) {
+  using NL = NetLds<HP, BF16>;
+  if (NL::bytes(m.M) > kLdsMax) return GMNN_ERR_UNSUPPORTED;
+  static bool attr = false;
+  if (!attr) {
+    const size_t net_max = NL::bytes(kMaxHeads) < kLdsMax ? NL::bytes(kMaxHeads) : kLdsMax;
+    if (!ro_set_lds(readout_features<BF16>, FeatLds<BF16>::bytes) ||
+        !ro_set_lds(readout_network<HP, BF16>, net_max) || !ro_set_lds(readout_backward, BackLds::bytes))
+      return GMNN_ERR_HIP;
+    attr = true;
+  }
+  const int N = sys.n_atoms;
+  const int g16 = (N + kRoAtoms - 1) / kRoAtoms;
+  const int gn = (N + NL::TM - 1) / NL::TM;
+  const int gb = (N + kBkAtoms - 1) / kBkAtoms;
+  hipLaunchKernelGGL(readout_features<BF16>, dim3(g16), dim3(kRoThreads), FeatLds<BF16>::bytes, s, sys, psi, G);
+  hipLaunchKernelGGL((readout_network<HP, BF16>), dim3(gn), dim3(kRoThreads), NL::bytes(m.M), s, m, sys, (const void*)G,
+                     atomic_e, dG);
+  hipLaunchKernelGGL(readout_backward, dim3(gb), dim3(kBkThreads), BackLds::bytes, s, sys, psi, (const float*)dG,
+                     psibar);
+  return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
+}
+
+size_t stream_lds_bytes(int hp, bool bf16, int n_heads) {
+  size_t n = 0;
+#define SZ(HP) \
+  if (hp == HP) n = bf16 ? NetLds<HP, true>::bytes(n_heads) : NetLds<HP, false>::bytes(n_heads);
+  SZ(64) SZ(128) SZ(256) SZ(512)
+#undef SZ
+  if (n == 0) return ~size_t(0);
+  size_t f = bf16 ? FeatLds<true>::bytes : FeatLds<false>::bytes;
+  if (f > n) n = f;
+  if (BackLds::bytes > n) n = BackLds::bytes;
+  return n;
+}
+
+// workspace of the streamed readout: G [N][kFP] (network operand type) and
+// dE/dG [N][kFP] FP32
+size_t stream_g_bytes(int n_atoms, bool bf16) { return (size_t)n_atoms * kFP * (bf16 ? 2 : 4); }
+size_t stream_dg_bytes(int n_atoms) { return (size_t)n_atoms * kFP * 4; }
+
+gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,
+                          float* atomic_e, float* psibar, hipStream_t s) {
+  if (sys.n_atoms == 0) return GMNN_OK;
+#define CASE(HP)                                                                                          \
+  if (m.HP1 == HP)                                                                                        \
+    return bf16 ? launch_stream_t<HP, true>(m, sys, psi, G, dG, atomic_e, psibar, s)                      \
+                : launch_stream_t<HP, false>(m, sys, psi, G, dG, atomic_e, psibar, s);
+  CASE(64) CASE(128) CASE(256) CASE(512)
+#undef CASE
+  return GMNN_ERR_UNSUPPORTED;
+}
+
+}  // namespace gmnn

@@ -47,7 +47,7 @@ def test_every_plan_matches_oracle(sched, lanes):
     ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
     print(f"plan schedule={sched} lanes={lanes} ensemble n_structs=6", flush=True)
     ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(sched, lanes))
-    assert ev.plan == {"schedule": sched, "lanes_per_atom": lanes}
+    assert ev.plan == {"schedule": sched, "lanes_per_atom": lanes, "readout": 1}
     _check(ev(sync=True), ref, batch)
 
 
@@ -76,7 +76,7 @@ def test_autotune_choice_and_cache(tmp_path, monkeypatch):
     ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
     ev = g.EnergyForces(model, system, nl, precision="bf16", stress=True)
     plan, table = autotune.run_autotune(ev, reps=5)
-    assert len(table) == 6  # both schedules x three lane counts are supported here
+    assert len(table) == 9  # fused, split with tile readout, split streamed; x three lane counts
     assert plan in [p for p, _, _ in table]
     best = min(table, key=lambda t: t[1])
     assert best[0] == plan
@@ -89,3 +89,44 @@ def test_autotune_choice_and_cache(tmp_path, monkeypatch):
     ev32b = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan="auto")
     assert ev32b.plan == ev32.plan
     _check(ev32b(sync=True), ref, batch)
+
+
+STREAM_CASES = [("train", dict(n_structs=2, n_lo=100, n_hi=160)), ("ensemble", dict(n_structs=6))]
+
+
+@pytest.mark.parametrize("name,kw", STREAM_CASES)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_streamed_readout_equals_tile_bitwise(name, kw, precision):
+    """The streamed readout (invariants -> network on tall row tiles ->
+    invariant backward) does the tile's arithmetic in the same order: results
+    are bit-identical; the FP32 arm is also held to the oracle."""
+    g = need_gpu()
+    batch, params, spec, system, nl, model = _setup(g, name, kw)
+    print(f"streamed readout {name} {precision} N={batch.n_atoms}", flush=True)
+    outs = []
+    for readout in (1, 2):
+        ev = g.EnergyForces(model, system, nl, precision=precision, stress=True, plan=(2, 16, readout))
+        assert ev.plan["readout"] == readout
+        o = ev(sync=True)
+        outs.append([t.cpu().numpy().copy() for t in (o.energy, o.forces, o.stress, o.atomic_energy)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    if precision == "fp32":
+        ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
+        ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(2, 32, 2))
+        _check(ev(sync=True), ref, batch)
+
+
+def test_streamed_readout_large_system():
+    """A system past the built-in threshold takes the streamed readout by
+    default; sampled atoms against the oracle's per-atom energies."""
+    g = need_gpu()
+    batch, params, spec = make_workload("solid", reps=(30, 30, 20))  # 18000 atoms
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, spec.model.r_cut, 0.0)
+    model = g.Model.from_params(params, "cuda")
+    ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True)
+    assert ev.plan == {"schedule": 2, "lanes_per_atom": 16, "readout": 2}
+    out = ev(sync=True)
+    tile = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(2, 16, 1))(sync=True)
+    assert torch.equal(out.forces, tile.forces) and torch.equal(out.energy, tile.energy)
