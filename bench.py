@@ -83,6 +83,36 @@ def algorithmic_work(spec, n_atoms, n_pairs):
     }
 
 
+def kernel_source_hash():
+    """SHA-256 over the HIP sources (and the C header) that make up libgmnn.so."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_22168_amd", "csrc")
+    files = sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
+    for f in files + ["../../include/gmnn.h"]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(workload, stage, precision):
+    """HBM bytes per launch of a stage as counted by rocprofv3 (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy) from the summary committed under
+    profiles/, or None when that summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.md")
+    try:
+        text = open(path).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("source_sha256") != kernel_source_hash():
+        return None
+    entry = data.get("stages", {}).get(f"{workload}:{stage}:{precision}")
+    return None if entry is None else entry["fetch_bytes"] + entry["write_bytes"]
+
+
 def run_path(g, A, model, system, nl, precision, steps, warmup, events, plan="auto", force_var=False):
     import torch
     ev = g.EnergyForces(model, system, nl, precision=precision, stress=True, force_var=force_var, plan=plan)
@@ -323,7 +353,7 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip oracle errors and the CPU baseline")
     ap.add_argument("--md", action="store_true", help="time whole MD steps instead (not the headline metric)")
     ap.add_argument("--graph-steps", type=int, default=100)
-    ap.add_argument("--md-sigma0", type=float, default=0.01, help="species energy scale of the MD model")
+    ap.add_argument("--md-sigma0", type=float, default=0.003, help="species energy scale of the MD model")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (reference for HBM byte counters)")
     ap.add_argument("--plan", default="auto", choices=["auto", "builtin"],
@@ -395,7 +425,7 @@ def main():
     else:
         achieved, peak, unit = amount / dur_s / 1e12, MFMA_PEAK_TFLOPS["bf16"], "TFLOP/s"
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": counted_traffic(args.workload, dom, "bf16"),
                 "per_launch": {"amount": amount, "what": "bytes" if bound == "hbm" else "flops",
                                "avg_duration_us": stage_ms[dom] * 1e3,
                                "event_bracket_overhead_us_subtracted": overhead_ms * 1e3}}
