@@ -17,96 +17,100 @@
 namespace gmnn {
 
 // Each wave owns one 16-row block rb and the 16-column blocks nb0 + i*nbs
-// (i < TPW, nb < NB).  B fragments stream from L2 through a ring of
-// kPrefetch register buffers (loads run kPrefetch k-steps ahead of the
-// MFMAs): with the fragments of all waves in flight this covers the L2
-// latency at the CU's fetch rate.
-constexpr int kPrefetch = 4;
-
+// (i < TPW, nb < NB).  B fragments stream from L2 through a ring of register
+// buffers, prefetch_depth<TPW> k-steps ahead of the MFMAs: 16 fragments
+// (64 registers) in flight per wave whatever the width.  The ring of a
+// product can be filled ahead of it (ring_fill), e.g. before the epilogue and
+// barrier of the previous product, so its first fragments arrive during them.
 template <int TPW>
-__device__ inline void mma_bf16(const __bf16* __restrict__ A, int lda, int rb, const bf16x8* __restrict__ Bp, int KB,
-                                int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
+constexpr int prefetch_depth() { return TPW >= 4 ? 4 : 16 / TPW > 8 ? 8 : 16 / TPW; }
+
+template <bool BF16>
+struct FragT { using type = bf16x8; };
+template <>
+struct FragT<false> { using type = floatx4; };  // native vector: kept in registers inside the ring
+
+template <bool BF16, int TPW, int DEPTH = prefetch_depth<TPW>()>
+struct BRing {
+  static constexpr int PF = DEPTH;
+  typename FragT<BF16>::type b[PF][TPW];
+};
+
+// k-steps of K: 32 per BF16 fragment, 16 per FP32 chunk (four 16x16x4 MFMAs)
+template <bool BF16>
+constexpr int ksteps(int K) { return BF16 ? K / 32 : K / 16; }
+
+template <bool BF16, int TPW, int DEPTH>
+__device__ __forceinline__ void ring_load(BRing<BF16, TPW, DEPTH>& r, int slot, const void* Bp, int KB, int kb, int nb0, int nbs,
+                                 int NB) {
+  using F = typename FragT<BF16>::type;
   const int l = threadIdx.x & 63;
-  const __bf16* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 8;
-  bf16x8 b[kPrefetch][TPW];
-  auto load = [&](bf16x8 (&dst)[TPW], int kb) {
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int nb = nb0 + i * nbs;
+    if (nb < NB && kb < KB) r.b[slot][i] = ((const F*)Bp)[((size_t)nb * KB + kb) * 64 + l];
+  }
+}
+
+// issue the first PF k-steps of the product with B = (Bbf or Bf) of K rows
+template <bool BF16, int TPW, int DEPTH>
+__device__ __forceinline__ void ring_fill(BRing<BF16, TPW, DEPTH>& r, const void* Bbf, const void* Bf, int K, int nb0, int nbs,
+                                 int NB) {
+  const void* Bp = BF16 ? Bbf : Bf;
+#pragma unroll
+  for (int s = 0; s < DEPTH; ++s) ring_load(r, s, Bp, ksteps<BF16>(K), s, nb0, nbs, NB);
+}
+
+// acc += A[rb rows] B over K, with the ring already holding k-steps 0..PF-1
+template <bool BF16, int TPW, int DEPTH>
+__device__ __forceinline__ void mma_ring(BRing<BF16, TPW, DEPTH>& r, const void* A, int lda, int rb, const void* Bbf,
+                                         const void* Bf, int K, int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
+  constexpr int PF = DEPTH;
+  const int l = threadIdx.x & 63;
+  const void* Bp = BF16 ? Bbf : Bf;
+  const int KB = ksteps<BF16>(K);
+  auto step = [&](int slot, int kb) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = nb0 + i * nbs;
-      if (nb < NB && kb < KB) dst[i] = Bp[((size_t)nb * KB + kb) * 64 + l];
+      if (nb >= NB) continue;
+      if constexpr (BF16) {
+        const bf16x8 a = *(const bf16x8*)((const __bf16*)A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 8 + kb * 32);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, r.b[slot][i], acc[i], 0, 0, 0);
+      } else {
+        const floatx4 a = *(const floatx4*)((const float*)A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 4 + kb * 16);
+        const floatx4 bb = r.b[slot][i];
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], bb[0], acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], bb[1], acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], bb[2], acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], bb[3], acc[i], 0, 0, 0);
+      }
     }
   };
-  auto step = [&](const bf16x8 (&bb)[TPW], int kb) {
-    const bf16x8 a = *(const bf16x8*)(arow + kb * 32);
+  for (int kb = 0; kb < KB; kb += PF) {
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-      const int nb = nb0 + i * nbs;
-      if (nb < NB) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb[i], acc[i], 0, 0, 0);
-    }
-  };
-#pragma unroll
-  for (int s = 0; s < kPrefetch; ++s) load(b[s], s);
-  for (int kb = 0; kb < KB; kb += kPrefetch) {
-#pragma unroll
-    for (int s = 0; s < kPrefetch; ++s) {
+    for (int s = 0; s < PF; ++s) {
       if (kb + s < KB) {
-        step(b[s], kb + s);
-        load(b[s], kb + s + kPrefetch);
+        step(s, kb + s);
+        ring_load(r, s, Bp, KB, kb + s + PF, nb0, nbs, NB);
       }
     }
   }
 }
 
+// the same product with the ring filled on the spot (FP32 only: the training tile)
 template <int TPW>
 __device__ inline void mma_f32(const float* __restrict__ A, int lda, int rb, const float4* __restrict__ Bp, int KC,
                                int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
-  const int l = threadIdx.x & 63;
-  const float* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 4;
-  float4 b[kPrefetch][TPW];
-  auto load = [&](float4 (&dst)[TPW], int kc) {
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-      const int nb = nb0 + i * nbs;
-      if (nb < NB && kc < KC) dst[i] = Bp[((size_t)nb * KC + kc) * 64 + l];
-    }
-  };
-  auto step = [&](const float4 (&bb)[TPW], int kc) {
-    const float4 a = *(const float4*)(arow + kc * 16);
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-      const int nb = nb0 + i * nbs;
-      if (nb < NB) {
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb[i].x, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb[i].y, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bb[i].z, acc[i], 0, 0, 0);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bb[i].w, acc[i], 0, 0, 0);
-      }
-    }
-  };
-#pragma unroll
-  for (int s = 0; s < kPrefetch; ++s) load(b[s], s);
-  for (int kc = 0; kc < KC; kc += kPrefetch) {
-#pragma unroll
-    for (int s = 0; s < kPrefetch; ++s) {
-      if (kc + s < KC) {
-        step(b[s], kc + s);
-        load(b[s], kc + s + kPrefetch);
-      }
-    }
-  }
+  BRing<false, TPW> r;
+  ring_fill(r, nullptr, Bp, KC * 16, nb0, nbs, NB);
+  mma_ring(r, A, lda, rb, nullptr, Bp, KC * 16, nb0, nbs, NB, acc);
 }
 
 template <int TPW>
 __device__ inline void zero_acc(floatx4 (&acc)[TPW]) {
 #pragma unroll
   for (int i = 0; i < TPW; ++i) acc[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-}
-
-template <bool BF16, int TPW>
-__device__ inline void mma(const void* A, int lda, int rb, const void* Bbf, const void* Bf, int K, int nb0, int nbs,
-                           int NB, floatx4 (&acc)[TPW]) {
-  if (BF16) mma_bf16<TPW>((const __bf16*)A, lda, rb, (const bf16x8*)Bbf, K / 32, nb0, nbs, NB, acc);
-  else mma_f32<TPW>((const float*)A, lda, rb, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
 }
 
 __device__ inline float swish_parts(float z, float& dsw) {
@@ -147,11 +151,12 @@ struct NetShape {
 // MEAN: delta2 = swish'(z2) sigma mean_m W3[:,m] -> sD2 (the head-mean
 // backward); otherwise swish'(z2) -> sDsw2 (FP32, row stride HP + 1) for
 // per-head backwards.  sEp: [NW][16][kMaxHeads] partial sums.
-template <int TM, int HP, bool BF16, int NW, bool MEAN>
-__device__ inline void network_forward(const DevModel& m, const void* sG, void* sH, void* sD2, float* sDsw2,
+template <int TM, int HP, bool BF16, int NW, bool MEAN, int DEPTH>
+__device__ __forceinline__ void network_forward(const DevModel& m, const void* sG, void* sH, void* sD2, float* sDsw2,
                                        float* sEp, const float* sScale, const float* sShift, int row0, int n_rows,
                                        float* __restrict__ atomic_e,
-                                       floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW]) {
+                                       floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW],
+                                       BRing<BF16, NetShape<TM, HP, NW>::TPW, DEPTH>& ring) {
   using St = NetStrides<HP, BF16>;
   using Sh = NetShape<TM, HP, NW>;
   constexpr int MB = Sh::MB, WPR = Sh::WPR, NBH = Sh::NBH, TPW = Sh::TPW;
@@ -159,21 +164,32 @@ __device__ inline void network_forward(const DevModel& m, const void* sG, void* 
   const int w = tid >> 6, l = tid & 63;
   const int rb = w % MB, cw = w / MB;
   const int M = m.M;
+  // per-column epilogue constants of this wave, loaded ahead of the products
+  float b1v[TPW], b2v[TPW], wbv[TPW], w30[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int nb = cw + i * WPR;
+    const int col = (nb < NBH ? nb : 0) * 16 + (l & 15);
+    b1v[i] = m.b1[col];
+    b2v[i] = m.b2[col];
+    wbv[i] = m.w3bar[col];
+    w30[i] = m.w3[col * M];
+  }
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma<BF16, TPW>(sG, St::G, rb, m.w1_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
+    mma_ring(ring, sG, St::G, rb, m.w1_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
+    ring_fill(ring, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = cw + i * WPR;
       if (nb >= NBH) continue;
       const int col = nb * 16 + (l & 15);
-      const float bias = m.b1[col];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = rb * 16 + 4 * (l >> 4) + j;
         float d;
-        const float hv = swish_parts(acc[i][j] + bias, d);
+        const float hv = swish_parts(acc[i][j] + b1v[i], d);
         dsw1[i][j] = d;
         st_act<BF16>(sH, row * St::H + col, hv);
       }
@@ -183,21 +199,21 @@ __device__ inline void network_forward(const DevModel& m, const void* sG, void* 
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma<BF16, TPW>(sH, St::H, rb, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
+    mma_ring(ring, sH, St::H, rb, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
+    // the backward's first product (W2^T) starts loading now
+    ring_fill(ring, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = cw + i * WPR;
       if (nb >= NBH) continue;
       const int col = nb * 16 + (l & 15);
-      const float bias = m.b2[col];
-      const float wb = m.w3bar[col];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = rb * 16 + 4 * (l >> 4) + j;
         float d;
-        const float hv = swish_parts(acc[i][j] + bias, d);
+        const float hv = swish_parts(acc[i][j] + b2v[i], d);
         acc[i][j] = hv;
-        if (MEAN) st_act<BF16>(sD2, row * St::H + col, d * sScale[row] * wb);
+        if (MEAN) st_act<BF16>(sD2, row * St::H + col, d * sScale[row] * wbv[i]);
         else sDsw2[row * (HP + 1) + col] = d;
       }
     }
@@ -207,7 +223,7 @@ __device__ inline void network_forward(const DevModel& m, const void* sG, void* 
       for (int i = 0; i < TPW; ++i) {
         const int nb = cw + i * WPR;
         if (nb >= NBH) continue;
-        const float w3 = m.w3[(nb * 16 + (l & 15)) * M + hm];
+        const float w3 = hm == 0 ? w30[i] : m.w3[(nb * 16 + (l & 15)) * M + hm];
 #pragma unroll
         for (int j = 0; j < 4; ++j) part[j] += acc[i][j] * w3;
       }
@@ -237,7 +253,7 @@ __device__ inline void network_forward(const DevModel& m, const void* sG, void* 
 
 // delta2 of head `hm`: swish'(z2) sigma W3[:,hm] -> sD2
 template <int TM, int HP, bool BF16, int NW>
-__device__ inline void network_delta2_head(const DevModel& m, const float* sDsw2, const float* sScale, void* sD2,
+__device__ __forceinline__ void network_delta2_head(const DevModel& m, const float* sDsw2, const float* sScale, void* sD2,
                                            int hm) {
   using St = NetStrides<HP, BF16>;
   for (int t = threadIdx.x; t < TM * HP; t += NW * 64) {
@@ -246,20 +262,24 @@ __device__ inline void network_delta2_head(const DevModel& m, const float* sDsw2
   }
 }
 
-// Network backward given delta2 in sD2: delta1 = swish'(z1) (delta2 W2^T) -> sH,
-// dE/dG = delta1 W1^T -> sGb (FP32).  Ends with a barrier.
-template <int TM, int HP, bool BF16, int NW>
-__device__ inline void network_backward(const DevModel& m, const void* sD2, void* sH, float* sGb,
-                                        const floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW]) {
+// Network backward given delta2 in sD2 and the ring holding the first k-steps
+// of W2^T: delta1 = swish'(z1) (delta2 W2^T) -> sH, dE/dG = delta1 W1^T ->
+// sGb (FP32).  Ends with a barrier.
+template <int TM, int HP, bool BF16, int NW, int DEPTH>
+__device__ __forceinline__ void network_backward(const DevModel& m, const void* sD2, void* sH, float* sGb,
+                                        const floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW],
+                                        BRing<BF16, NetShape<TM, HP, NW>::TPW, DEPTH>& ring) {
   using St = NetStrides<HP, BF16>;
   using Sh = NetShape<TM, HP, NW>;
   constexpr int MB = Sh::MB, WPR = Sh::WPR, NBH = Sh::NBH, NBG = Sh::NBG, TPW = Sh::TPW, TPW_G = Sh::TPW_G;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rb = w % MB, cw = w / MB;
+  BRing<BF16, TPW_G, (DEPTH < prefetch_depth<TPW_G>() ? DEPTH : prefetch_depth<TPW_G>())> ring_g;
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma<BF16, TPW>(sD2, St::H, rb, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH, acc);
+    mma_ring(ring, sD2, St::H, rb, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH, acc);
+    ring_fill(ring_g, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = cw + i * WPR;
@@ -276,7 +296,7 @@ __device__ inline void network_backward(const DevModel& m, const void* sD2, void
   {
     floatx4 acc[TPW_G];
     zero_acc(acc);
-    mma<BF16, TPW_G>(sH, St::H, rb, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG, acc);
+    mma_ring(ring_g, sH, St::H, rb, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG, acc);
 #pragma unroll
     for (int i = 0; i < TPW_G; ++i) {
       const int nb = cw + i * WPR;

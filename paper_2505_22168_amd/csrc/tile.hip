@@ -137,6 +137,11 @@ __global__ void __launch_bounds__(kTileThreads)
   __syncthreads();
 
   // ---- invariants ------------------------------------------------------------
+  // the first weight fragments of the network start loading now
+  // (one backward per head keeps more live state: a shallower ring there)
+  constexpr int kDepth = PERHEAD ? 2 : prefetch_depth<Sh::TPW>();
+  BRing<BF16, Sh::TPW, kDepth> ring;
+  ring_fill(ring, m.w1_bf16, m.w1_f32, kFP, (tid >> 6) / Sh::MB, Sh::WPR, Sh::NBH);
   contract_forward_a<TM, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
   // per-atom scale / shift, by the last wave (idle in the phase above), for
   // the network epilogue
@@ -157,16 +162,17 @@ __global__ void __launch_bounds__(kTileThreads)
 
   // ---- network forward ---------------------------------------------------------
   floatx4 dsw1[Sh::TPW];
-  network_forward<TM, HP, BF16, kTileWaves, !PERHEAD>(m, sG, sH, sD2, sDsw2, sEp, sScale, sShift, row0, n_rows,
-                                                       atomic_e, dsw1);
+  network_forward<TM, HP, BF16, kTileWaves, !PERHEAD, kDepth>(m, sG, sH, sD2, sDsw2, sEp, sScale, sShift, row0, n_rows,
+                                                       atomic_e, dsw1, ring);
   constexpr int LDGB = NetStrides<HP, BF16>::GB;
   for (int hm = 0; hm < nh; ++hm) {
     // ---- network backward (head mean, or head hm) ------------------------------
     if (PERHEAD) {
+      if (hm > 0) ring_fill(ring, m.w2t_bf16, m.w2t_f32, HP, (tid >> 6) / Sh::MB, Sh::WPR, Sh::NBH);
       network_delta2_head<TM, HP, BF16, kTileWaves>(m, sDsw2, sScale, sD2, hm);
       __syncthreads();
     }
-    network_backward<TM, HP, BF16, kTileWaves>(m, sD2, sH, sGb, dsw1);
+    network_backward<TM, HP, BF16, kTileWaves, kDepth>(m, sD2, sH, sGb, dsw1, ring);
     // ---- invariants backward ---------------------------------------------------
     contract_backward_a<TM, kTileThreads>(sPsi, sGb, LDGB, sI, tb);
     __syncthreads();
