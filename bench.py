@@ -304,8 +304,9 @@ def run_ensemble(args):
 
 
 def run_train(args):
-    """Training-gradient step of the energy+force loss: energies and forces
-    (FP32), then the loss gradients w.r.t. every parameter (double backward)."""
+    """Training-gradient step of the energy+force loss: energies and forces,
+    then the loss gradients w.r.t. every parameter (double backward), with the
+    network products in BF16 (headline) and in FP32."""
     import torch
     import paper_2505_22168_amd as g
     from workloads import make_workload
@@ -315,29 +316,36 @@ def run_train(args):
     model = g.Model.from_params(params, dev)
     system = g.System.from_batch(batch, dev)
     nl = g.build_neighbors(system, spec.model.r_cut, spec.skin)
-    ev = g.EnergyForces(model, system, nl, precision="fp32", stress=False)
     rng = np.random.default_rng(7)
     dE = torch.as_tensor(rng.normal(size=batch.n_structs), device=dev)
     dF = torch.as_tensor(rng.normal(size=(batch.n_atoms, 3)).astype(np.float32), device=dev)
-    ws = None
-
-    def step():
-        nonlocal ws
-        ev()
-        grads = g.param_grads(model, system, nl, dE, dF, workspace=ws)
-        return grads
-
     lib = g.load_library()
     from paper_2505_22168_amd import _capi as A
     nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(model.c()), C.byref(system.c()),
                                       C.byref(nl.c()), 0)
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    t = _wall(step, args.steps, args.warmup)
-    t_fwd = _wall(ev, args.steps, args.warmup)
+    res = {}
+    grads = {}
+    for prec in ("bf16", "fp32"):
+        ev = g.EnergyForces(model, system, nl, precision=prec, stress=False)
+
+        def step():
+            ev()
+            return g.param_grads(model, system, nl, dE, dF, workspace=ws, precision=prec)
+        t = _wall(step, args.steps, args.warmup)
+        t_fwd = _wall(ev, args.steps, args.warmup)
+        grads[prec] = step()
+        res[prec] = {"value": batch.n_atoms / t, "ms_per_step": t * 1e3, "forward_ms": t_fwd * 1e3,
+                     "backward_ms": (t - t_fwd) * 1e3}
+        print(f"[bench-train] {prec}: {res[prec]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    # BF16 gradients against the FP32 path's (relative l2 per parameter)
+    diff = {k: float(torch.linalg.norm((grads["bf16"][k] - grads["fp32"][k]).double())
+                     / max(float(torch.linalg.norm(grads["fp32"][k].double())), 1e-30)) for k in grads["fp32"]}
     line = {"metric": "training-gradient atom-evals/s (energy+forces, then parameter gradients of an "
-                      "energy+force loss)", "value": batch.n_atoms / t, "unit": "atom-evals/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3, "dtype": "fp32",
-            "data": "synthetic", "forward_ms": t_fwd * 1e3, "backward_ms": (t - t_fwd) * 1e3,
+                      "energy+force loss)", "value": res["bf16"]["value"], "unit": "atom-evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["bf16"]["ms_per_step"], "dtype": "bf16",
+            "data": "synthetic", "bf16": res["bf16"], "fp32": res["fp32"], "bf16_grad_rel_diff_vs_fp32": diff,
             "config": {"workload": name, "n_atoms": batch.n_atoms, "n_structs": batch.n_structs,
                        "n_pairs": nl.n_pairs, "mlp": list(spec.model.hidden)}}
     print(json.dumps(line))

@@ -296,8 +296,12 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
  * head-mean energy) and dL/dF [N,3] (Section 3.4: energy + force losses;
  * Section 3.3: forces are -dE/dx, so the force term needs the mixed second
  * derivative).  Every array of `grads` is overwritten; dL_dpos may be
- * NULL.  Requires the workspace of gmnn_energy_forces for the same inputs;
- * recomputes the forward pass itself. */
+ * NULL.  With GMNN_PREC_BF16 the network products of the forward and
+ * reverse passes (primal and tangent rows) run in BF16 on MFMA with FP32
+ * accumulation, the operands rounded as in gmnn_energy_forces; the products
+ * that form the parameter gradients stay FP32.  Requires the workspace of
+ * gmnn_energy_forces for the same inputs; recomputes the forward pass
+ * itself. */
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
                           const double* dL_dE, const float* dL_dF, uint32_t flags,
                           gmnn_param_grads* grads, float* dL_dpos,

@@ -154,6 +154,7 @@ class Model:
 
     def __init__(self, spec, params: dict, device="cuda"):
         device = _require_device(device)
+        self.train_precision = "fp32"  # network precision of EnergyForcesFunction ("fp32" or "bf16")
         self.spec = spec
         self.device = device
         self.tensors = {k: torch.as_tensor(np.asarray(params[k], dtype=np.float32)).contiguous().to(device)
@@ -370,9 +371,14 @@ def maxwell_boltzmann(masses, temperature: float, seed: int):
 
 
 # ---------------------------------------------------------------------------
-def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, workspace=None):
+def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, workspace=None,
+                precision: str = "fp32"):
     """Gradients of a loss w.r.t. every model parameter (gmnn_backward), given
-    dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3]."""
+    dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3];
+    precision "bf16" runs the network products of the double backward in BF16."""
+    if precision not in ("fp32", "bf16"):
+        raise ValueError(precision)
+    flags = A.GMNN_PREC_BF16 if precision == "bf16" else 0
     lib = A.load()
     dev = system.device
     dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=dev).contiguous()
@@ -383,7 +389,7 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
     nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), 0)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    st = lib.gmnn_backward(C.byref(mc), C.byref(sc), C.byref(nc), _ptr(dE), _ptr(dF), 0, C.byref(gc), None,
+    st = lib.gmnn_backward(C.byref(mc), C.byref(sc), C.byref(nc), _ptr(dE), _ptr(dF), flags, C.byref(gc), None,
                            _ptr(workspace), nbytes, _stream())
     A.check(st, "gmnn_backward")
     return grads
@@ -391,15 +397,16 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
 
 class EnergyForcesFunction(torch.autograd.Function):
     """(E, F) = GMNN(theta) as a differentiable torch op: forward runs
-    gmnn_energy_forces (FP32 network), backward runs gmnn_backward, giving
-    the gradients of any loss of E and F w.r.t. the parameter tensors.
+    gmnn_energy_forces, backward runs gmnn_backward (network products in
+    model.train_precision, "fp32" or "bf16"), giving the gradients of any
+    loss of E and F w.r.t. the parameter tensors.
 
         E, F = EnergyForcesFunction.apply(model, system, nl, *model.params())
     """
 
     @staticmethod
     def forward(ctx, model, system, nl, *params):
-        out = energy_forces(model, system, nl, precision="fp32", stress=False)
+        out = energy_forces(model, system, nl, precision=model.train_precision, stress=False)
         ctx.model, ctx.system, ctx.nl = model, system, nl
         return out.energy.mean(1), out.forces[: system.n_atoms].clone()
 
@@ -408,5 +415,5 @@ class EnergyForcesFunction(torch.autograd.Function):
         B, N = ctx.system.n_structs, ctx.system.n_atoms
         gE = torch.zeros(B, dtype=torch.float64, device=ctx.system.device) if gE is None else gE.double()
         gF = torch.zeros((N, 3), dtype=torch.float32, device=ctx.system.device) if gF is None else gF.float()
-        grads = param_grads(ctx.model, ctx.system, ctx.nl, gE, gF)
+        grads = param_grads(ctx.model, ctx.system, ctx.nl, gE, gF, precision=ctx.model.train_precision)
         return (None, None, None, *[grads[k] for k in PARAM_NAMES])

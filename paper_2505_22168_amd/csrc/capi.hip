@@ -33,7 +33,7 @@ size_t stream_dg_bytes(int n_atoms);
 size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead);
 bool train_supported(const DevModel& m);
 size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
-gmnn_status train_backward(const DevModel& m, const DevSystem& sys, int H1, int H2, const double* ebar,
+gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, int H1, int H2, const double* ebar,
                            const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s);
 
 constexpr int kPairThreads = 256;
@@ -590,13 +590,14 @@ gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmn
       !grads->b2 || !grads->W3 || !grads->b3 || !grads->scale || !grads->shift || !workspace)
     return GMNN_ERR_INVALID_ARG;
   if (nl->cutoff + 1e-6f < m->r_cut) return GMNN_ERR_INVALID_ARG;
-  // the FP32 network path only; positions gradients are not produced
-  if ((flags & (GMNN_PREC_BF16 | GMNN_WANT_FORCE_VAR)) || dL_dpos) return GMNN_ERR_UNSUPPORTED;
+  // the head-mean loss only; positions gradients are not produced
+  if ((flags & GMNN_WANT_FORCE_VAR) || dL_dpos) return GMNN_ERR_UNSUPPORTED;
   const DevModel dm = dev_model(m);
   if (!train_supported(dm)) return GMNN_ERR_UNSUPPORTED;
   const DevSystem ds = dev_system(sys, nl);
   hipStream_t s = (hipStream_t)stream;
-  st = train_backward(dm, ds, m->hidden1, m->hidden2, dL_dE, dL_dF, grads, workspace, workspace_bytes, s);
+  st = train_backward(dm, ds, (flags & GMNN_PREC_BF16) != 0, m->hidden1, m->hidden2, dL_dE, dL_dF, grads, workspace,
+                      workspace_bytes, s);
   if (st != GMNN_OK) return st;
   if ((flags & GMNN_SYNC) && hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
   return GMNN_OK;

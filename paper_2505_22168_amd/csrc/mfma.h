@@ -107,6 +107,42 @@ __device__ inline void mma_f32(const float* __restrict__ A, int lda, int rb, con
   mma_ring(r, A, lda, rb, nullptr, Bp, KC * 16, nb0, nbs, NB, acc);
 }
 
+// BF16 product with the A tile kept in FP32 in LDS: the 8 values of each A
+// fragment are rounded to BF16 (nearest even) as they are loaded (the
+// training tile keeps its activations in FP32 for the parameter products)
+template <int TPW>
+__device__ __forceinline__ void mma_bf16_a32(const float* __restrict__ A, int lda, int rb,
+                                             const bf16x8* __restrict__ Bp, int K, int nb0, int nbs, int NB,
+                                             floatx4 (&acc)[TPW]) {
+  BRing<true, TPW> r;
+  ring_fill(r, Bp, nullptr, K, nb0, nbs, NB);
+  constexpr int PF = BRing<true, TPW>::PF;
+  const int l = threadIdx.x & 63;
+  const int KB = K / 32;
+  const float* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 8;
+  auto step = [&](int slot, int kb) {
+    const float4 lo = *(const float4*)(arow + kb * 32);
+    const float4 hi = *(const float4*)(arow + kb * 32 + 4);
+    bf16x8 a;
+    a[0] = (__bf16)lo.x; a[1] = (__bf16)lo.y; a[2] = (__bf16)lo.z; a[3] = (__bf16)lo.w;
+    a[4] = (__bf16)hi.x; a[5] = (__bf16)hi.y; a[6] = (__bf16)hi.z; a[7] = (__bf16)hi.w;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, r.b[slot][i], acc[i], 0, 0, 0);
+    }
+  };
+  for (int kb = 0; kb < KB; kb += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      if (kb + s < KB) {
+        step(s, kb + s);
+        ring_load(r, s, Bp, KB, kb + s + PF, nb0, nbs, NB);
+      }
+    }
+  }
+}
+
 template <int TPW>
 __device__ inline void zero_acc(floatx4 (&acc)[TPW]) {
 #pragma unroll

@@ -117,6 +117,15 @@ __device__ inline void swish_d2(float z, float& s, float& d1, float& d2) {
   d2 = sg * (1.0f - sg) * (2.0f + z * (1.0f - 2.0f * sg));
 }
 
+// network products of the training tile: FP32 MFMA, or BF16 MFMA on the
+// BF16 weight copies with the FP32 activation tile rounded on load
+template <bool BF16, int TPW>
+__device__ __forceinline__ void train_mma(const DevModel& m, const float* A, int lda, const bf16x8* Bbf,
+                                          const float* Bf, int K, int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
+  if constexpr (BF16) mma_bf16_a32<TPW>(A, lda, 0, Bbf, K, nb0, nbs, NB, acc);
+  else mma_f32<TPW>(A, lda, 0, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
+}
+
 template <int HP>
 struct TrainLds {
   static constexpr int TA = kTA;
@@ -142,7 +151,7 @@ struct TrainLds {
 };
 
 // weight-product rows: row k = 16 * tile + r, r < 8 primal atom rows, r >= 8 tangent rows
-template <int HP>
+template <int HP, bool BF16>
 __global__ void __launch_bounds__(kTrainThreads)
     train_tile(DevModel m, DevSystem sys, const float* __restrict__ psi, const float* __restrict__ psidot,
                const double* __restrict__ ebar, float* __restrict__ psibar, float* __restrict__ psidotbar,
@@ -250,7 +259,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma_f32<TPW>(sGT, L::LDG, 0, (const float4*)m.w1_f32, kFP / 16, cw, WPR, NBH, acc);
+    train_mma<BF16, TPW>(m, sGT, L::LDG, m.w1_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = cw + i * WPR;
@@ -279,7 +288,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma_f32<TPW>(sH, L::LDH, 0, (const float4*)m.w2_f32, HP / 16, cw, WPR, NBH, acc);
+    train_mma<BF16, TPW>(m, sH, L::LDH, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
     float ypart[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // primal lanes: h2 . w3bar, tangent lanes: h2dot . w3bar
     floatx4 d2out[TPW];
 #pragma unroll
@@ -347,7 +356,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma_f32<TPW>(sH, L::LDH, 0, (const float4*)m.w2t_f32, HP / 16, cw, WPR, NBH, acc);
+    train_mma<BF16, TPW>(m, sH, L::LDH, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH, acc);
     __syncthreads();  // all reads of [z2bar; z2dotbar] done before the tile is overwritten
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
@@ -371,7 +380,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   {
     floatx4 acc[TPW_G];
     zero_acc(acc);
-    mma_f32<TPW_G>(sH, L::LDH, 0, (const float4*)m.w1t_f32, HP / 16, cw, WPR, NBG, acc);
+    train_mma<BF16, TPW_G>(m, sH, L::LDH, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG, acc);
 #pragma unroll
     for (int i = 0; i < TPW_G; ++i) {
       const int nb = cw + i * WPR;
@@ -663,13 +672,13 @@ __global__ void beta_unpack(const float* __restrict__ summed, int nsp, int K, fl
 }
 
 // ---------------------------------------------------------------------------
-template <int HP>
+template <int HP, bool BF16>
 static gmnn_status launch_train_tile_t(const DevModel& m, const DevSystem& sys, const float* psi, const float* psidot,
                                        const double* ebar, float* psibar, float* psidotbar, float* X1, float* Y1,
                                        float* X2, float* Y2, float* w3g, float* qsig, hipStream_t s) {
   using L = TrainLds<HP>;
   if (L::bytes > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
-  auto k = train_tile<HP>;
+  auto k = train_tile<HP, BF16>;
   static bool attr_set = false;
   if (!attr_set) {
     if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes) != hipSuccess)
@@ -742,7 +751,7 @@ bool train_supported(const DevModel& m) {
 
 size_t train_workspace_bytes(int n_atoms, int HP, int nsp) { return train_layout(n_atoms, HP, nsp).bytes; }
 
-gmnn_status train_backward(const DevModel& m, const DevSystem& sys, int H1, int H2, const double* ebar,
+gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, int H1, int H2, const double* ebar,
                            const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s) {
   const int HP = m.HP1;
   const int nsp = m.n_species;
@@ -777,10 +786,22 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, int H1, int 
       hipLaunchKernelGGL(pair_tangent<16>, dim3(nb), dim3(kPairBlock), beta_lds, s, m, sys, lambda, psidot);
     }
     switch (HP) {
-      case 64: st = launch_train_tile_t<64>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
-      case 128: st = launch_train_tile_t<128>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
-      case 256: st = launch_train_tile_t<256>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
-      case 512: st = launch_train_tile_t<512>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s); break;
+      case 64:
+        st = bf16 ? launch_train_tile_t<64, true>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s)
+                  : launch_train_tile_t<64, false>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s);
+        break;
+      case 128:
+        st = bf16 ? launch_train_tile_t<128, true>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s)
+                  : launch_train_tile_t<128, false>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s);
+        break;
+      case 256:
+        st = bf16 ? launch_train_tile_t<256, true>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s)
+                  : launch_train_tile_t<256, false>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s);
+        break;
+      case 512:
+        st = bf16 ? launch_train_tile_t<512, true>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s)
+                  : launch_train_tile_t<512, false>(m, sys, psi, psidot, ebar, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, s);
+        break;
       default: return GMNN_ERR_UNSUPPORTED;
     }
     if (st != GMNN_OK) return st;
