@@ -537,31 +537,58 @@ __global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSyst
 }
 
 // ---------------------------------------------------------------------------
-// C[M][N] = sum_k A[k][M]^T B[k][N] over k in a chunk (split-K), FP32 MFMA.
-// One wave per 16 x 16 output tile; partial[chunk][M][N].
+// C[M][N] = sum_k A[k][M]^T B[k][N] over the rows k of chunk blockIdx.y
+// (split-K; partial[chunk][M][N]), FP32 MFMA 16x16x4.  Each wave owns a
+// 64 x 64 block of C as 4 x 4 MFMA tiles, so every value loaded feeds four
+// MFMAs; four k-steps of loads are issued before their MFMAs.  M and N are
+// multiples of 64.
+constexpr int kWgRows = 1024;  // rows per split-K chunk
 __global__ void __launch_bounds__(256) weight_grad(const float* __restrict__ A, int ldA, const float* __restrict__ B,
                                                    int ldB, int Mdim, int Ndim, int64_t K, int64_t kchunk,
                                                    float* __restrict__ partial) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int tiles_n = Ndim / 16;
+  const int tiles_n = Ndim / 64;
   const int tile = blockIdx.x * 4 + w;
-  if (tile >= (Mdim / 16) * tiles_n) return;
-  const int mt = tile / tiles_n, nt = tile % tiles_n;
+  if (tile >= (Mdim / 64) * tiles_n) return;
+  const int m0 = (tile / tiles_n) * 64, n0 = (tile % tiles_n) * 64;
   const int64_t kb = (int64_t)blockIdx.y * kchunk;
   const int64_t ke = min(K, kb + kchunk);
-  floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  // 16x16x4: lane l supplies A^T[m = l&15][k = l>>4] = A[k][m], B[k = l>>4][n = l&15]
-  for (int64_t k = kb; k < ke; k += 4) {
-    const int64_t kk = k + (l >> 4);
-    const float a = kk < ke ? A[kk * ldA + mt * 16 + (l & 15)] : 0.0f;
-    const float b = kk < ke ? B[kk * ldB + nt * 16 + (l & 15)] : 0.0f;
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  // lane l supplies A^T[m = l&15][k = l>>4] = A[k][m] and B[k = l>>4][n = l&15]
+  const float* ap = A + m0 + (l & 15);
+  const float* bp = B + n0 + (l & 15);
+  for (int64_t k = kb; k < ke; k += 16) {
+    float a[4][4], b[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t kk = k + 4 * u + (l >> 4);
+      const bool ok = kk < ke;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[u][r] = ok ? ap[kk * ldA + r * 16] : 0.0f;
+        b[u][r] = ok ? bp[kk * ldB + r * 16] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][r], b[u][c], acc[r][c], 0, 0, 0);
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int row = mt * 16 + 4 * (l >> 4) + j, col = nt * 16 + (l & 15);
-    partial[((int64_t)blockIdx.y * Mdim + row) * Ndim + col] = acc[j];
-  }
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = m0 + r * 16 + 4 * (l >> 4) + j, col = n0 + c * 16 + (l & 15);
+        partial[((int64_t)blockIdx.y * Mdim + row) * Ndim + col] = acc[r][c][j];
+      }
 }
 
 // out[i] = scale * sum_c partial[c][i] (chunks in order); optionally strided copies
@@ -712,7 +739,7 @@ TrainLayout train_layout(int n_atoms, int HP, int nsp) {
   const size_t N = (size_t)n_atoms;
   const int64_t tiles = (n_atoms + kTA - 1) / kTA;
   L.K = tiles * 16;
-  L.kchunks = (int)((L.K + 4095) / 4096);
+  L.kchunks = (int)((L.K + kWgRows - 1) / kWgRows);
   L.beta_blocks = 256;
   L.psi = take(4 * N * 100);
   L.psidot = take(4 * N * 100);
@@ -808,15 +835,15 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
   }
   hipLaunchKernelGGL(pair_beta_grad, dim3(L.beta_blocks), dim3(kPairBlock), beta_lds * (1 + kPairBlock / 64), s, m, sys,
                      lambda, psibar, psidotbar, bpart);
-  // weight products, split over chunks of 4096 rows, partials summed in chunk order
+  // weight products, split over chunks of kWgRows rows, partials summed in chunk order
   {
-    const int t1 = (kFP / 16) * (HP / 16);
-    const int t2 = (HP / 16) * (HP / 16);
+    const int t1 = (kFP / 64) * (HP / 64);
+    const int t2 = (HP / 64) * (HP / 64);
     if (L.kchunks > 0) {
       hipLaunchKernelGGL(weight_grad, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
-                         (int64_t)4096, part1);
+                         (int64_t)kWgRows, part1);
       hipLaunchKernelGGL(weight_grad, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
-                         (int64_t)4096, part2);
+                         (int64_t)kWgRows, part2);
     }
     const int64_t n1 = (int64_t)kFP * HP, n2 = (int64_t)HP * HP;
     hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part1, L.kchunks, n1, sum1);
