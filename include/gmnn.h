@@ -355,6 +355,24 @@ gmnn_status gmnn_md_graph_create(const gmnn_model* m, const gmnn_system* sys, gm
 gmnn_status gmnn_md_graph_launch(void* graph, void* stream);
 void gmnn_md_graph_destroy(void* graph);
 
+/* HIP graph of n_evals back-to-back evaluations (gmnn_energy_forces_plan
+ * with these arguments), for callers that evaluate the same buffers over
+ * and over (serving loops over fixed-size batches whose positions are
+ * rewritten in place): one graph launch replaces n_evals x (2 to 6) kernel
+ * launches.  The graph reads every buffer when it runs (new contents of
+ * sys->pos or the parameters are used; their addresses are baked in).  Runs
+ * one eager evaluation on an internal stream first (argument checks; it does
+ * not wait for other streams: the inputs must be ready), then captures;
+ * GMNN_SYNC is not allowed.  Replay with gmnn_graph_launch on
+ * any stream; release with gmnn_graph_destroy (host memory of the handle and
+ * the graph).  The MD graphs of gmnn_md_graph_create take the same two calls. */
+gmnn_status gmnn_energy_forces_graph_create(const gmnn_model* m, const gmnn_system* sys,
+                                            const gmnn_neighbors* nl, uint32_t flags, const gmnn_plan* plan,
+                                            gmnn_outputs* out, void* workspace, size_t workspace_bytes,
+                                            int32_t n_evals, void** graph);
+gmnn_status gmnn_graph_launch(void* graph, void* stream);
+void gmnn_graph_destroy(void* graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,6 +121,12 @@ EXPORTS = {
                                          C.POINTER(C.c_void_p)]),
     "gmnn_md_graph_launch": (C.c_int32, [vp, vp]),
     "gmnn_md_graph_destroy": (None, [vp]),
+    "gmnn_energy_forces_graph_create": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
+                                                    C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_plan),
+                                                    C.POINTER(gmnn_outputs), vp, C.c_size_t, C.c_int32,
+                                                    C.POINTER(C.c_void_p)]),
+    "gmnn_graph_launch": (C.c_int32, [vp, vp]),
+    "gmnn_graph_destroy": (None, [vp]),
 }
 
 _lib = None

@@ -265,6 +265,37 @@ class EnergyForces:
                 "gmnn_resolve_plan")
         return {"schedule": r.schedule, "lanes_per_atom": r.lanes_per_atom, "readout": r.readout}
 
+    def capture(self, n_evals: int = 1):
+        """Capture n_evals evaluations into a HIP graph (replayed by replay())."""
+        self.release()
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        A.check(A.load().gmnn_energy_forces_graph_create(
+            C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), self.flags,
+            None if self._plan is None else C.byref(self._plan), C.byref(self._oc), _ptr(self.workspace),
+            self.ws_bytes, n_evals, C.byref(h)), "gmnn_energy_forces_graph_create")
+        self._graph, self.graph_evals = h, n_evals
+        return self
+
+    def replay(self, times: int = 1) -> Outputs:
+        """Launch the captured graph `times` times on the current stream."""
+        if getattr(self, "_graph", None) is None:
+            raise RuntimeError("capture() first")
+        for _ in range(times):
+            A.check(A.load().gmnn_graph_launch(self._graph, _stream()), "gmnn_graph_launch")
+        return self.out
+
+    def release(self):
+        if getattr(self, "_graph", None) is not None:
+            A.load().gmnn_graph_destroy(self._graph)
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
     def __call__(self, sync: bool = False) -> Outputs:
         flags = self.flags | (A.GMNN_SYNC if sync else 0)
         st = A.load().gmnn_energy_forces_plan(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), flags,

@@ -173,6 +173,48 @@ gmnn_status gmnn_md_graph_create(const gmnn_model* m, const gmnn_system* sys, gm
   return GMNN_OK;
 }
 
+gmnn_status gmnn_energy_forces_graph_create(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                            uint32_t flags, const gmnn_plan* plan, gmnn_outputs* out,
+                                            void* workspace, size_t workspace_bytes, int32_t n_evals,
+                                            void** graph_out) {
+  if (n_evals < 1 || n_evals > 4096 || !graph_out || (flags & GMNN_SYNC)) return GMNN_ERR_INVALID_ARG;
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return GMNN_ERR_HIP;
+  // one eager evaluation first: checks the arguments and leaves every kernel
+  // attribute set before the capture
+  gmnn_status st = gmnn_energy_forces_plan(m, sys, nl, flags, plan, out, workspace, workspace_bytes, (void*)cs);
+  if (st == GMNN_OK && hipStreamSynchronize(cs) != hipSuccess) st = GMNN_ERR_HIP;
+  if (st != GMNN_OK) {
+    hipStreamDestroy(cs);
+    return st;
+  }
+  MdGraph* g = new (std::nothrow) MdGraph();
+  if (!g) {
+    hipStreamDestroy(cs);
+    return GMNN_ERR_HIP;
+  }
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = GMNN_ERR_HIP;
+  for (int k = 0; k < n_evals && st == GMNN_OK; ++k)
+    st = gmnn_energy_forces_plan(m, sys, nl, flags, plan, out, workspace, workspace_bytes, (void*)cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &graph);
+  if (st == GMNN_OK && (ec != hipSuccess || !graph)) st = GMNN_ERR_HIP;
+  if (st == GMNN_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) st = GMNN_ERR_HIP;
+  hipStreamDestroy(cs);
+  if (st != GMNN_OK) {
+    if (graph) hipGraphDestroy(graph);
+    delete g;
+    return st;
+  }
+  g->graph = graph;
+  *graph_out = g;
+  return GMNN_OK;
+}
+
+gmnn_status gmnn_graph_launch(void* graph, void* stream) { return gmnn_md_graph_launch(graph, stream); }
+
+void gmnn_graph_destroy(void* graph) { gmnn_md_graph_destroy(graph); }
+
 gmnn_status gmnn_md_graph_launch(void* graph, void* stream) {
   if (!graph) return GMNN_ERR_INVALID_ARG;
   MdGraph* g = (MdGraph*)graph;
