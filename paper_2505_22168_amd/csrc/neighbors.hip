@@ -258,7 +258,16 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_rows(
   bool overflow = false;
   bool coincident = false;
   bool shift_range = false;
-  if (MODE == 1 && row_count[i] > GMNN_MAX_ROW) return;  // flagged by the count pass
+  if (MODE == 1 && row_count[i] > GMNN_MAX_ROW) {
+    // flagged by the count pass; the row's slots take self pairs (zero
+    // separation: every kernel skips them) so the list stays well formed
+    const int64_t r0 = row_ptr[i];
+    for (int e = l; e < row_count[i]; e += 64) {
+      out_j[r0 + e] = i;
+      out_shift[r0 + e] = 0;
+    }
+    return;
+  }
   for (int t0 = 0; t0 < T; t0 += 64) {
     const int t = t0 + l;
     int cnt = 0, start = 0, swp = 0;
