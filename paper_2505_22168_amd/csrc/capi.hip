@@ -169,6 +169,7 @@ static DevModel dev_model(const gmnn_model* m) {
   d.r_min = m->r_min;
   d.r_cut = m->r_cut;
   d.rc2 = m->r_cut * m->r_cut;
+  d.half_inv_rc = (float)(0.5 / (double)m->r_cut);
   d.gamma = m->gamma;
   d.delta = (m->r_cut - m->r_min) / (float)(m->n_basis - 1);
   d.psi_scale = m->psi_scale;

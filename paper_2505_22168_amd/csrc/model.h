@@ -60,6 +60,7 @@ inline PackedLayout packed_layout(int H1, int H2, int M) {
 struct DevModel {
   int n_species, K, HP1, HP2, M;
   float r_min, r_cut, rc2, gamma, delta, psi_scale;
+  float half_inv_rc;    // 0.5 / r_cut: the cutoff's cosine argument in revolutions
   float ck[8];          // exp(-gamma delta^2 k^2) for k < K, 0 beyond
   const float* beta;    // [nsp][nsp][S][K]
   const float* scale;   // [nsp]

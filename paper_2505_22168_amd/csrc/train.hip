@@ -80,7 +80,8 @@ __global__ void __launch_bounds__(kPairBlock) pair_tangent(DevModel m, DevSystem
       pair_vec(sys, c, p, j, dx, dy, dz);
       const float r2 = dx * dx + dy * dy + dz * dz;
       if (!(r2 < m.rc2) || r2 == 0.0f) continue;
-      const float r = sqrtf(r2), ir = 1.0f / r;
+      float r, ir;
+      length_of(r2, r, ir);
       const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
       const float ex = lambda[3 * (int64_t)j] - lix, ey = lambda[3 * (int64_t)j + 1] - liy,
                   ez = lambda[3 * (int64_t)j + 2] - liz;
@@ -475,7 +476,8 @@ __global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSyst
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < m.rc2 && r2 > 0.0f) {
           zj = sys.species[j];
-          const float r = sqrtf(r2), ir = 1.0f / r;
+          float r, ir;
+          length_of(r2, r, ir);
           const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
           const float ex = lambda[3 * (int64_t)j] - lix, ey = lambda[3 * (int64_t)j + 1] - liy,
                       ez = lambda[3 * (int64_t)j + 2] - liz;
@@ -488,7 +490,7 @@ __global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSyst
           const float g0 = __expf(-m.gamma * tau * tau);
           const float aa = __expf(2.0f * m.gamma * m.delta * tau);
           float sn, cs;
-          sincosf(3.14159265358979f * r / m.r_cut, &sn, &cs);
+          cutoff_cos_sin(m, r, cs, sn);
           const float fc = 0.5f * (cs + 1.0f) * m.psi_scale;
           const float dfc = -0.5f * (3.14159265358979f / m.r_cut) * sn * m.psi_scale;
           const float* pb = psibar + (int64_t)i * (kS * kPacked);
