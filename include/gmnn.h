@@ -229,7 +229,7 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
  *                    row tiles of 32 to 64 atoms -> invariant backward; G
  *                    and dE/dG pass through the workspace (the head-mean
  *                    backward only: not with GMNN_WANT_FORCE_VAR).
- * lanes_per_atom (16, 32 or 64) is the number of lanes that share one atom's
+ * lanes_per_atom (8, 16, 32 or 64) is the number of lanes that share one atom's
  * neighbour row in the pair and gather kernels.  Zero fields mean "built-in
  * choice": FUSED with 64 lanes below 8192 atoms, SPLIT with 16 beyond, the
  * STREAM readout from 16384 atoms on where it is allowed. */
@@ -241,7 +241,7 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
 #define GMNN_READOUT_STREAM 2
 typedef struct gmnn_plan {
   int32_t schedule;        /* GMNN_SCHEDULE_* */
-  int32_t lanes_per_atom;  /* 0, 16, 32 or 64 */
+  int32_t lanes_per_atom;  /* 0, 8, 16, 32 or 64 */
   int32_t readout;         /* GMNN_READOUT_* (SPLIT schedule) */
 } gmnn_plan;
 

@@ -208,7 +208,7 @@ class EnergyForces:
         """plan: None (the library's built-in choice), "auto" (the autotuned
         plan of this shape class, cached; tunes on first use), or a dict /
         tuple (schedule, lanes_per_atom[, readout]) with GMNN_SCHEDULE_*,
-        16/32/64 and GMNN_READOUT_* (0 = built-in choice)."""
+        8/16/32/64 and GMNN_READOUT_* (0 = built-in choice)."""
         self.model, self.system, self.nl = model, system, nl
         self.flags = (A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32)
         if precision not in ("bf16", "fp32"):

@@ -81,7 +81,7 @@ static gmnn_status resolve_plan(const gmnn_model* m, const gmnn_system* sys, uin
   const int lpa = in ? in->lanes_per_atom : 0;
   if (sched != GMNN_SCHEDULE_AUTO && sched != GMNN_SCHEDULE_FUSED && sched != GMNN_SCHEDULE_SPLIT)
     return GMNN_ERR_INVALID_ARG;
-  if (lpa != 0 && lpa != 16 && lpa != 32 && lpa != 64) return GMNN_ERR_INVALID_ARG;
+  if (lpa != 0 && lpa != 8 && lpa != 16 && lpa != 32 && lpa != 64) return GMNN_ERR_INVALID_ARG;
   const bool small = sys->n_atoms < kFusedMaxAtoms;
   const bool can_fuse = fused_allowed(m, sys, flags, L.HP1);
   if (sched == GMNN_SCHEDULE_FUSED && !can_fuse) return GMNN_ERR_UNSUPPORTED;
@@ -453,7 +453,8 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   hipLaunchKernelGGL(pair_moments<LPA>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psi, counters, nzc)
       if (lpa == 64) MOMENTS(64);
       else if (lpa == 32) MOMENTS(32);
-      else MOMENTS(16);
+      else if (lpa == 16) MOMENTS(16);
+      else MOMENTS(8);
 #undef MOMENTS
       mark(1);
       mark(2);
@@ -469,7 +470,8 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
                      virial, nh, gstride)
       if (lpa == 64) PAIR_BACKWARD(64);
       else if (lpa == 32) PAIR_BACKWARD(32);
-      else PAIR_BACKWARD(16);
+      else if (lpa == 16) PAIR_BACKWARD(16);
+      else PAIR_BACKWARD(8);
 #undef PAIR_BACKWARD
       mark(5);
     }
@@ -488,9 +490,12 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   } else if (lpa == 32) {
     if (var) FINISH(32, true);
     else FINISH(32, false);
-  } else {
+  } else if (lpa == 16) {
     if (var) FINISH(16, true);
     else FINISH(16, false);
+  } else {
+    if (var) FINISH(8, true);
+    else FINISH(8, false);
   }
 #undef FINISH
   mark(7);
@@ -524,7 +529,7 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
   hipStream_t s = (hipStream_t)stream;
   static const int kSched[3] = {GMNN_SCHEDULE_FUSED, GMNN_SCHEDULE_SPLIT, GMNN_SCHEDULE_SPLIT};
   static const int kReadout[3] = {GMNN_READOUT_TILE, GMNN_READOUT_TILE, GMNN_READOUT_STREAM};
-  static const int kLanes[3] = {16, 32, 64};
+  static const int kLanes[4] = {8, 16, 32, 64};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return GMNN_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -536,7 +541,7 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
   bool have = false;
   std::vector<float> t(reps);
   for (int si = 0; si < 3 && st == GMNN_OK; ++si) {
-    for (int li = 0; li < 3 && st == GMNN_OK; ++li) {
+    for (int li = 0; li < 4 && st == GMNN_OK; ++li) {
       const gmnn_plan cand = {kSched[si], kLanes[li], kReadout[si]};
       Plan P;
       if (resolve_plan(m, sys, flags, &cand, P) != GMNN_OK) continue;

@@ -72,8 +72,15 @@ __device__ inline void rs_swap(float* v) {
 // atom.  LPA = 16: lane q of the row owns indices 8q..8q+7 (v[0..7]).
 // LPA = 64: lane q of the wave owns indices 2q, 2q+1 (v[0..1]).
 // LPA = 32: lane q of the half wave owns indices 4q .. 4q+3 (v[0..3]).
+// LPA = 8: lane q of the half row owns indices 16q .. 16q+15 (v[0..15]).
 template <int LPA>
 __device__ inline void reduce_scatter_128(float* v, int q) {
+  if (LPA == 8) {
+    rs_step<64, 1>(v, (q >> 2) & 1);
+    rs_step<32, 2>(v, (q >> 1) & 1);
+    rs_step<16, 3>(v, q & 1);
+    return;
+  }
   if (LPA == 32) {
     rs_swap<64, 16>(v);
     rs_step<32, 0>(v, (q >> 3) & 1);
@@ -100,6 +107,12 @@ __device__ inline void reduce_scatter_128(float* v, int q) {
 // sum over the LPA lanes of an atom (every lane gets the total)
 template <int LPA>
 __device__ inline float atom_sum(float v) {
+  if (LPA == 8) {
+    v += dpp_half_mirror(v);
+    v += dpp_xor2(v);
+    v += dpp_xor1(v);
+    return v;
+  }
   v = row16_sum(v);
   if (LPA >= 32) v += __shfl_xor(v, 16, 64);
   if (LPA == 64) v += __shfl_xor(v, 32, 64);

@@ -14,8 +14,8 @@
 //                  and virials (Section 2.1, eq. energy_sum) summed in FP64
 //                  in a fixed order.
 //
-// Each atom row is processed by LPA lanes (16, 32 or 64: four, two or one atom
-// per wave, chosen by the execution plan); the 100 moment accumulators of a lane are
+// Each atom row is processed by LPA lanes (8, 16, 32 or 64: eight, four, two or
+// one atom per wave, chosen by the execution plan); the 100 moment accumulators of a lane are
 // combined by a reduce-scatter (permlane swaps and DPP, no LDS, no atomics).
 #include "common.h"
 #include "model.h"
@@ -253,16 +253,18 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   }
 }
 
+template __global__ void pair_moments<8>(DevModel, DevSystem, float*, int*, int);
 template __global__ void pair_moments<16>(DevModel, DevSystem, float*, int*, int);
 template __global__ void pair_moments<32>(DevModel, DevSystem, float*, int*, int);
 template __global__ void pair_moments<64>(DevModel, DevSystem, float*, int*, int);
+template __global__ void pair_backward<8>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
 template __global__ void pair_backward<16>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
 template __global__ void pair_backward<32>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
 template __global__ void pair_backward<64>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
 #define FIN(LPA, VAR)                                                                                         \
   template __global__ void finish<LPA, VAR>(int, DevSystem, const float*, const float*, const float*, int, int, \
                                             int64_t, int, double*, int*, float*, float*, double*, double*, double*);
-FIN(16, false) FIN(32, false) FIN(64, false) FIN(16, true) FIN(32, true) FIN(64, true)
+FIN(8, false) FIN(16, false) FIN(32, false) FIN(64, false) FIN(8, true) FIN(16, true) FIN(32, true) FIN(64, true)
 #undef FIN
 
 }  // namespace gmnn

@@ -1,4 +1,4 @@
-"""Every execution plan (fused / split schedule, 16 / 32 / 64 lanes per atom)
+"""Every execution plan (fused / split schedule, 8 / 16 / 32 / 64 lanes per atom)
 against the FP64 oracle, and the autotuner's choice.
 
 The plans only re-cut the same arithmetic into kernels, so each is held to
@@ -16,7 +16,7 @@ from gpu_helpers import gpu, need_gpu
 
 pytestmark = gpu
 
-PLANS = [(1, 16), (1, 32), (1, 64), (2, 16), (2, 32), (2, 64)]
+PLANS = [(1, 8), (1, 16), (1, 32), (1, 64), (2, 8), (2, 16), (2, 32), (2, 64)]
 
 
 def _setup(g, name, kw):
@@ -51,7 +51,7 @@ def test_every_plan_matches_oracle(sched, lanes):
     _check(ev(sync=True), ref, batch)
 
 
-@pytest.mark.parametrize("lanes", [16, 32, 64])
+@pytest.mark.parametrize("lanes", [8, 16, 32, 64])
 def test_split_plans_with_force_variance(lanes):
     g = need_gpu()
     batch, params, spec, system, nl, model = _setup(g, "ensemble", dict(n_structs=4))
@@ -76,7 +76,7 @@ def test_autotune_choice_and_cache(tmp_path, monkeypatch):
     ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
     ev = g.EnergyForces(model, system, nl, precision="bf16", stress=True)
     plan, table = autotune.run_autotune(ev, reps=5)
-    assert len(table) == 9  # fused, split with tile readout, split streamed; x three lane counts
+    assert len(table) == 12  # fused, split with tile readout, split streamed; x four lane counts
     assert plan in [p for p, _, _ in table]
     best = min(table, key=lambda t: t[1])
     assert best[0] == plan

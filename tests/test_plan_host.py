@@ -51,7 +51,7 @@ def test_builtin_plan_small_and_large():
 def test_explicit_plans():
     m = _model()
     small = _Sys([120] * 30)
-    for lanes in (16, 32, 64):
+    for lanes in (8, 16, 32, 64):
         assert _resolve(m, small, 0, A.GMNN_SCHEDULE_SPLIT, lanes) == (A.GMNN_OK, (A.GMNN_SCHEDULE_SPLIT, lanes))
         assert _resolve(m, small, A.GMNN_PREC_BF16, A.GMNN_SCHEDULE_FUSED, lanes)[0] == A.GMNN_OK
     # the fused tile on a large batch of small structures is allowed (one
@@ -89,7 +89,7 @@ def test_readout_choice():
 def test_invalid_plans():
     m = _model()
     s = _Sys([100])
-    assert _resolve(m, s, 0, A.GMNN_SCHEDULE_SPLIT, 8)[0] == A.GMNN_ERR_INVALID_ARG
+    assert _resolve(m, s, 0, A.GMNN_SCHEDULE_SPLIT, 12)[0] == A.GMNN_ERR_INVALID_ARG
     assert _resolve(m, s, 0, 7, 16)[0] == A.GMNN_ERR_INVALID_ARG
     lib = A.load()
     assert lib.gmnn_resolve_plan(None, C.byref(s.c), 0, None, None) == A.GMNN_ERR_INVALID_ARG
