@@ -262,18 +262,34 @@ __device__ inline void fetch_pairs(const DevSystem& sys, const AtomCtx& c, int64
   for (int u = 0; u < kPairUnroll; ++u) pair_vec_of(c, x[u], y[u], z[u], sh[u], g.dx[u], g.dy[u], g.dz[u]);
 }
 
+// Optional LDS cache of an atom's context and of the first pair group of each
+// of its lanes, written by atom_moments and read back by atom_pair_backward
+// (the fused tile runs both on the same lanes): the backward then starts
+// without a global-memory round trip.  pv[q * kPairUnroll + u] = (d, zj) with
+// zj = -1 for a slot past the end of the row.
+struct PairCache {
+  AtomCtx* ctx;  // one per atom
+  float4* pv;    // [LPA][kPairUnroll] per atom
+};
+
 // ---------------------------------------------------------------------------
 // moment partial sums of lane q of an atom: pairs p0+q, p0+q+LPA, ...
 // v[s*20 + t] += R_s(r) mono_t(u)   (v must be zeroed by the caller)
 template <int LPA>
 __device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta, int i,
-                                    int q, float (&v)[128]) {
+                                    int q, float (&v)[128], PairCache cache = PairCache{nullptr, nullptr}) {
   AtomCtx c;
   load_atom(sys, i, c);
+  if (cache.ctx && q == 0) *cache.ctx = c;
   const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
   for (int64_t p = c.p0 + q; p < c.p1; p += kPairUnroll * LPA) {
     PairGroup g;
     fetch_pairs<LPA>(sys, c, p, g);
+    if (cache.pv && p == c.p0 + q) {
+#pragma unroll
+      for (int u = 0; u < kPairUnroll; ++u)
+        cache.pv[q * kPairUnroll + u] = make_float4(g.dx[u], g.dy[u], g.dz[u], __int_as_float(g.ok[u] ? g.zj[u] : -1));
+    }
 #pragma unroll
     for (int u = 0; u < kPairUnroll; ++u) {
       const float dx = g.dx[u], dy = g.dy[u], dz = g.dz[u];
@@ -301,13 +317,26 @@ __device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, con
 template <int LPA>
 __device__ inline void atom_pair_backward(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta,
                                           int i, int q, const float (&pb)[kS * kPacked], float* __restrict__ gpair,
-                                          float (&vir)[9]) {
+                                          float (&vir)[9], PairCache cache = PairCache{nullptr, nullptr}) {
   AtomCtx c;
-  load_atom(sys, i, c);
+  if (cache.ctx) c = *cache.ctx;
+  else load_atom(sys, i, c);
   const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
   for (int64_t p = c.p0 + q; p < c.p1; p += kPairUnroll * LPA) {
     PairGroup g;
-    fetch_pairs<LPA>(sys, c, p, g);
+    if (cache.pv && p == c.p0 + q) {
+#pragma unroll
+      for (int u = 0; u < kPairUnroll; ++u) {
+        const float4 e = cache.pv[q * kPairUnroll + u];
+        g.dx[u] = e.x;
+        g.dy[u] = e.y;
+        g.dz[u] = e.z;
+        g.zj[u] = __float_as_int(e.w);
+        g.ok[u] = g.zj[u] >= 0;
+      }
+    } else {
+      fetch_pairs<LPA>(sys, c, p, g);
+    }
 #pragma unroll
     for (int u = 0; u < kPairUnroll; ++u) {
       if (!g.ok[u]) continue;

@@ -186,6 +186,13 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   const int64_t csz = (s1 - s0 + nchunk - 1) / nchunk;
   const int64_t a0 = s0 + chunk * csz;
   const int64_t a1 = min(s1, a0 + csz);
+  // the cell (for the stress) is read now, its latency hidden by the sums
+  double cell_det = 1.0;
+  if (want_stress && threadIdx.x < 9) {
+    const double* h = sys.cell + 9 * (int64_t)b;
+    cell_det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
+               h[2] * (h[3] * h[7] - h[4] * h[6]);
+  }
   double accE[kMaxHeads], accV[9];
 #pragma unroll
   for (int v = 0; v < kMaxHeads; ++v) accE[v] = 0.0;
@@ -237,12 +244,7 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   }
   __syncthreads();
   if (threadIdx.x < M) energy[(int64_t)b * M + threadIdx.x] = vals[threadIdx.x];
-  if (want_stress && threadIdx.x < 9) {
-    const double* h = sys.cell + 9 * (int64_t)b;
-    const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
-                       h[2] * (h[3] * h[7] - h[4] * h[6]);
-    stress[(int64_t)b * 9 + threadIdx.x] = vals[kMaxHeads + threadIdx.x] / fabs(det);
-  }
+  if (want_stress && threadIdx.x < 9) stress[(int64_t)b * 9 + threadIdx.x] = vals[kMaxHeads + threadIdx.x] / fabs(cell_det);
   if (energy_var && threadIdx.x == 0) {
     double mean = 0.0;
     for (int v = 0; v < M; ++v) mean += vals[v];

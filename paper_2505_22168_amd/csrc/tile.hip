@@ -50,8 +50,10 @@ struct TileLds {
   static constexpr size_t psibar = vir + al(4 * 9 * (size_t)TM);
   static constexpr size_t dsw2 = psibar + (FUSED ? al(4 * (size_t)TM * kS * kPacked) : 0);
   static constexpr size_t beta = dsw2 + (PERHEAD ? al(4 * (size_t)TM * (HP + 1)) : 0);
-  static constexpr size_t bytes =
-      beta + (FUSED ? al(4 * (size_t)kFusedMaxSpecies * kFusedMaxSpecies * kS * kMaxBasis) : 0);
+  // fused: per-atom context and first pair group of each of the 32 lanes
+  static constexpr size_t pctx = beta + (FUSED ? al(4 * (size_t)kFusedMaxSpecies * kFusedMaxSpecies * kS * kMaxBasis) : 0);
+  static constexpr size_t ppv = pctx + (FUSED ? al(sizeof(AtomCtx) * (size_t)TM) : 0);
+  static constexpr size_t bytes = ppv + (FUSED ? al(sizeof(float4) * (size_t)TM * 32 * kPairUnroll) : 0);
 };
 
 // psibar_out: [nh][N][100] (unfused); gpair: [nh][gstride][3] (fused);
@@ -80,6 +82,8 @@ __global__ void __launch_bounds__(kTileThreads)
   float* sPsibar = (float*)(lds + L::psibar);
   float* sDsw2 = (float*)(lds + L::dsw2);
   float* s_beta = (float*)(lds + L::beta);
+  AtomCtx* sCtx = (AtomCtx*)(lds + L::pctx);
+  float4* sPv = (float4*)(lds + L::ppv);
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
@@ -101,7 +105,7 @@ __global__ void __launch_bounds__(kTileThreads)
     float v[128];
 #pragma unroll
     for (int k = 0; k < 128; ++k) v[k] = 0.0f;
-    if (fa < n_rows) atom_moments<32>(m, sys, s_beta, row0 + fa, fq, v);
+    if (fa < n_rows) atom_moments<32>(m, sys, s_beta, row0 + fa, fq, v, PairCache{sCtx + fa, sPv + fa * 32 * kPairUnroll});
     reduce_scatter_128<32>(v, fq);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -191,7 +195,8 @@ __global__ void __launch_bounds__(kTileThreads)
           float pb[kS * kPacked];
 #pragma unroll
           for (int k = 0; k < kS * kPacked; ++k) pb[k] = sPsibar[fa * (kS * kPacked) + k];
-          atom_pair_backward<32>(m, sys, s_beta, row0 + fa, fq, pb, g_head, vir);
+          atom_pair_backward<32>(m, sys, s_beta, row0 + fa, fq, pb, g_head, vir,
+                                 PairCache{sCtx + fa, sPv + fa * 32 * kPairUnroll});
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) vir[k] = atom_sum<32>(vir[k]);
