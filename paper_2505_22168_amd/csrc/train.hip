@@ -194,17 +194,33 @@ __global__ void __launch_bounds__(kTrainThreads)
     sScale[a] = sc;
     sA[a] = aa;
   }
-  for (int t = tid; t < TA * kS * kFull; t += kTrainThreads) {
-    const int a = t % TA, e = t / TA;
-    const int s = e / kFull, r = e % kFull;
-    float v = 0.0f, vd = 0.0f;
-    if (a < n_rows) {
-      const int64_t o = (int64_t)(row0 + a) * (kS * kPacked) + s * kPacked + c_full_to_packed[r];
-      v = psi[o];
-      vd = psidot[o];
+  {
+    // the tile's packed moments and tangents are contiguous runs: every load
+    // issued at once, then expanded into the full tensors
+    constexpr int NP = kS * kPacked;
+    constexpr int NU = (TA * NP + kTrainThreads - 1) / kTrainThreads;
+    float v[NU], vd[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int t = tid + u * kTrainThreads;
+      const bool ok = t < n_rows * NP;
+      v[u] = ok ? psi[(int64_t)row0 * NP + t] : 0.0f;
+      vd[u] = ok ? psidot[(int64_t)row0 * NP + t] : 0.0f;
     }
-    sPsi[a * PS + e] = v;
-    sPd[a * PS + e] = vd;
+    __syncthreads();  // the tables are in LDS
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int t = tid + u * kTrainThreads;
+      if (t < TA * NP) {
+        const int a = t / NP, e = t % NP;
+        const int s = e / kPacked, c = e % kPacked;
+        const int n = tb.packed_mult[c];
+        for (int q = 0; q < n; ++q) {
+          sPsi[a * PS + s * kFull + tb.packed_full[c][q]] = v[u];
+          sPd[a * PS + s * kFull + tb.packed_full[c][q]] = vd[u];
+        }
+      }
+    }
   }
   __syncthreads();
   // per-atom step t = |Psi| / |Psidot| for the exact polynomial differences
