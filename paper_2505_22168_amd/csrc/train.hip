@@ -609,29 +609,57 @@ __global__ void __launch_bounds__(256) weight_grad(const float* __restrict__ A, 
       }
 }
 
-// out[i] = scale * sum_c partial[c][i] (chunks in order); optionally strided copies
+// out[i] = sum_c partial[c][i], chunks in order (eight loads in flight)
 __global__ void sum_partials(const float* __restrict__ partial, int nchunks, int64_t n, float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float v = 0.0f;
-  for (int c = 0; c < nchunks; ++c) v += partial[(int64_t)c * n + i];
+  int c = 0;
+  for (; c + 8 <= nchunks; c += 8) {
+    float x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = partial[(int64_t)(c + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += x[u];
+  }
+  for (; c < nchunks; ++c) v += partial[(int64_t)c * n + i];
   out[i] = v;
 }
 
 // column sums, stage 1: partial[chunk][c] = sum of Y[k][c] over the rows k
 // of the chunk (with primal_only, the rows with (k & 15) < 8: the primal
-// halves of the dual-number tiles); grid (ceil(ncols / 256), chunks)
-constexpr int kColChunk = 256;
-__global__ void column_partials(const float* __restrict__ Y, int ld, int64_t nrows, int ncols, bool primal_only,
-                                float* __restrict__ partial) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  const int64_t k0 = (int64_t)blockIdx.y * kColChunk;
-  const int64_t k1 = min(nrows, k0 + kColChunk);
+// halves of the dual-number tiles).  Block = 64 columns x 4 row lanes; lane
+// r takes rows r, r + 4, ... of the chunk; the four lane sums are added in
+// lane order.  Grid (ceil(ncols / 64), chunks).
+constexpr int kColChunks = 128;  // at most this many row chunks
+__global__ void __launch_bounds__(256) column_partials(const float* __restrict__ Y, int ld, int64_t nrows,
+                                                       int64_t rows_per_chunk, int ncols, bool primal_only,
+                                                       float* __restrict__ partial) {
+  __shared__ float red[4][64];
+  const int cl = threadIdx.x & 63, r = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int64_t k0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t k1 = min(nrows, k0 + rows_per_chunk);
   float v = 0.0f;
-  for (int64_t k = k0; k < k1; ++k)
-    if (!primal_only || (k & 15) < 8) v += Y[k * ld + c];
-  partial[(int64_t)blockIdx.y * ncols + c] = v;
+  if (c < ncols) {
+    int64_t k = k0 + r;
+    for (; k + 28 < k1; k += 32) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t kk = k + 4 * u;
+        x[u] = (!primal_only || (kk & 15) < 8) ? Y[kk * ld + c] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    for (; k < k1; k += 4)
+      if (!primal_only || (k & 15) < 8) v += Y[k * ld + c];
+  }
+  red[r][cl] = v;
+  __syncthreads();
+  if (r == 0 && c < ncols)
+    partial[(int64_t)blockIdx.y * ncols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
 // per-species sums, stage 1: block b takes atoms [b*256, b*256+256) and
@@ -740,6 +768,7 @@ struct TrainLayout {
   size_t psi, psidot, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, part1, part2, sum1, sum2, bpart, bsum;
   size_t cpart, w3sum, spart, bytes;
   int ccK, ccN;        // row chunks of the column sums over K rows / over N atoms
+  int64_t rcK, rcN;    // rows per chunk of those sums
   int sp_blocks;       // blocks of the per-species sums
   int64_t K;           // weight-product rows
   int kchunks;
@@ -776,8 +805,10 @@ TrainLayout train_layout(int n_atoms, int HP, int nsp) {
   const size_t nslots = (size_t)nsp * nsp * kS * kMaxBasis;
   L.bpart = take(4 * (size_t)L.beta_blocks * nslots);
   L.bsum = take(4 * nslots);
-  L.ccK = (int)((L.K + kColChunk - 1) / kColChunk);
-  L.ccN = (int)((N + kColChunk - 1) / kColChunk);
+  L.rcK = L.K > 0 ? (L.K + kColChunks - 1) / kColChunks : 1;
+  L.rcN = N > 0 ? ((int64_t)N + kColChunks - 1) / kColChunks : 1;
+  L.ccK = (int)((L.K + L.rcK - 1) / L.rcK);
+  L.ccN = (int)(((int64_t)N + L.rcN - 1) / L.rcN);
   L.cpart = take(4 * (size_t)HP * (size_t)(L.ccK > L.ccN ? L.ccK : L.ccN));
   L.w3sum = take(4 * (size_t)HP);
   L.sp_blocks = (int)((N + kSpeciesChunk - 1) / kSpeciesChunk);
@@ -875,14 +906,16 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
   double* spart = (double*)(W + L.spart);
   // (with no atoms there are no chunks: the sums of zero partials are zero)
   if (N > 0)
-    hipLaunchKernelGGL(column_partials, dim3((H1 + 255) / 256, L.ccK), dim3(256), 0, s, Y1, HP, L.K, H1, true, cpart);
+    hipLaunchKernelGGL(column_partials, dim3((H1 + 63) / 64, L.ccK), dim3(256), 0, s, Y1, HP, L.K, L.rcK, H1, true,
+                       cpart);
   hipLaunchKernelGGL(sum_partials, dim3((H1 + 255) / 256), dim3(256), 0, s, cpart, L.ccK, (int64_t)H1, g->b1);
   if (N > 0)
-    hipLaunchKernelGGL(column_partials, dim3((H2 + 255) / 256, L.ccK), dim3(256), 0, s, Y2, HP, L.K, H2, true, cpart);
+    hipLaunchKernelGGL(column_partials, dim3((H2 + 63) / 64, L.ccK), dim3(256), 0, s, Y2, HP, L.K, L.rcK, H2, true,
+                       cpart);
   hipLaunchKernelGGL(sum_partials, dim3((H2 + 255) / 256), dim3(256), 0, s, cpart, L.ccK, (int64_t)H2, g->b2);
   if (N > 0) {
-    hipLaunchKernelGGL(column_partials, dim3((H2 + 255) / 256, L.ccN), dim3(256), 0, s, w3g, HP, (int64_t)N, H2, false,
-                       cpart);
+    hipLaunchKernelGGL(column_partials, dim3((H2 + 63) / 64, L.ccN), dim3(256), 0, s, w3g, HP, (int64_t)N, L.rcN, H2,
+                       false, cpart);
     hipLaunchKernelGGL(species_partials, dim3(L.sp_blocks), dim3(kSpeciesChunk), 0, s, m, sys, ebar, qsig, spart);
   }
   hipLaunchKernelGGL(sum_partials, dim3((H2 + 255) / 256), dim3(256), 0, s, cpart, L.ccN, (int64_t)H2, w3sum);
