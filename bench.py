@@ -141,6 +141,7 @@ def run_path(g, A, model, system, nl, precision, steps, warmup, events, plan="au
     torch.cuda.synchronize()
     stage_ms = {name: float(np.mean([events.elapsed_ms(e[2 * s], e[2 * s + 1]) for e in evs]))
                 for s, name in enumerate(STAGES)}
+
     # cost of an event bracket around nothing (the same stream, same steps)
     empty = []
     for _ in range(steps):
@@ -157,10 +158,24 @@ def run_path(g, A, model, system, nl, precision, steps, warmup, events, plan="au
         stage_ms = {"fused_tile": stage_ms["pair_moments"], "finish": stage_ms["finish"]}
     stage_ms = {k: max(v - overhead, 0.0) for k, v in stage_ms.items()}
     stage_ms["_event_overhead"] = overhead
+    # each step on its own between two events (nothing else inside): median and
+    # interquartile range, the empty-bracket cost subtracted
+    brackets = [events.create(2) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for e in brackets:
+        events.record(e[0], stream)
+        ev()
+        events.record(e[1], stream)
+    torch.cuda.synchronize()
+    per_step = np.array([events.elapsed_ms(e[0], e[1]) for e in brackets]) - overhead
+    for e in brackets:
+        events.destroy(e)
+    q1, med, q3 = np.percentile(per_step, [25, 50, 75])
     for e in evs:
         events.destroy(e)
     out = ev(sync=True)
     stage_ms["_plan"] = ev.plan
+    stage_ms["_step_stats"] = {"median_us": med * 1e3, "iqr_us": (q3 - q1) * 1e3, "n": int(len(per_step))}
     # the same K steps replayed from HIP graphs of GRAPH_EVALS evaluations each
     per = GRAPH_EVALS if steps % GRAPH_EVALS == 0 else 1
     ev.capture(per)
@@ -188,21 +203,69 @@ def errors_vs_oracle(out, ref, n_atoms, nb):
     }
 
 
+def time_neighbor_build(g, A, system, nl, cutoff, skin, events, reps=20):
+    """The neighbour list build on its own (reported beside the evaluation):
+    median and IQR of hipEvent-timed rebuilds into the same list."""
+    import torch
+    lib = A.load()
+    sysc = system.c()
+    nbytes = lib.gmnn_neighbors_workspace_bytes(C.byref(sysc), cutoff, skin)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=system.device)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ts = []
+    for k in range(reps + 3):
+        e = events.create(2)
+        events.record(e[0], stream)
+        nlc = nl.c()
+        A.check(lib.gmnn_build_neighbors(C.byref(sysc), cutoff, skin, C.byref(nlc), 0, C.c_void_p(ws.data_ptr()),
+                                         nbytes, stream), "gmnn_build_neighbors")
+        events.record(e[1], stream)
+        torch.cuda.synchronize()
+        if k >= 3:
+            ts.append(events.elapsed_ms(e[0], e[1]))
+        events.destroy(e)
+    q1, med, q3 = np.percentile(ts, [25, 50, 75])
+    return {"median_us": med * 1e3, "iqr_us": (q3 - q1) * 1e3, "reps": reps, "cutoff_plus_skin": cutoff + skin,
+            "n_pairs": nl.n_pairs}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(batch, params, nl_ref, budget_s):
+    """The FP64 oracle (energy, forces, stress; list excluded) on the host
+    cores, repeated for about budget_s seconds with all threads, then once
+    more with one thread (reported beside it)."""
     import torch
     from oracle import evaluate
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        evaluate(batch, params, nl_ref)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    return {"value": batch.n_atoms * reps / el, "unit": "atom-evals/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+
+    def run(budget):
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            evaluate(batch, params, nl_ref)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return reps, el
+    cores = torch.get_num_threads()
+    reps, el = run(budget_s)
+    torch.set_num_threads(1)
+    try:
+        reps1, el1 = run(budget_s / 2)
+    finally:
+        torch.set_num_threads(cores)
+    return {"value": batch.n_atoms * reps / el, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{reps} FP64 oracle evaluations (energy, forces, stress; list excluded) of the "
-                      f"{batch.n_atoms}-atom workload, {el:.1f} s"}
+                      f"{batch.n_atoms}-atom workload, {el:.1f} s",
+            "cpu_model": _cpu_model(), "value_1_thread": batch.n_atoms * reps1 / el1}
 
 
 def run_md(args):
@@ -420,17 +483,19 @@ def main():
     nl = g.build_neighbors(system, spec.model.r_cut, spec.skin)
     model = g.Model.from_params(params, dev)
     events = HipEvents()
+    nl_stats = time_neighbor_build(g, A, system, nl, spec.model.r_cut, spec.skin, events)
     N, P = batch.n_atoms, nl.n_pairs
     print(f"[bench] workload {args.workload}: {N} atoms, {P} pairs, {batch.n_structs} structures", file=sys.stderr,
           flush=True)
 
     res = {}
-    eager_ms, graph_ms = {}, {}
+    eager_ms, graph_ms, step_stats = {}, {}, {}
     for prec in ("bf16", "fp32"):
         wall, stage_ms, out = run_path(g, A, model, system, nl, prec, args.steps, args.warmup, events,
                                        plan=None if args.plan == "builtin" else "auto")
         plan = stage_ms.pop("_plan")
         gwall = stage_ms.pop("_graph_wall")
+        step_stats[prec] = stage_ms.pop("_step_stats")
         res[prec] = (min(wall, gwall), stage_ms, out, plan)
         eager_ms[prec] = wall / args.steps * 1e3
         graph_ms[prec] = gwall / args.steps * 1e3
@@ -484,6 +549,7 @@ def main():
                    "launch": (f"HIP graph of {GRAPH_EVALS} evaluations" if graph_ms["bf16"] < eager_ms["bf16"]
                               else "eager launches")},
         "ms_per_step_eager": eager_ms["bf16"], "ms_per_step_graph": graph_ms["bf16"],
+        "step_event_stats": step_stats, "neighbor_build": nl_stats,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages_us": {k: v * 1e3 for k, v in stage_ms.items()},
