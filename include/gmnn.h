@@ -219,7 +219,9 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
 /* Execution plans.  Every plan computes the same quantities (up to FP32
  * summation order); they differ in how the work is cut into kernels:
  *   FUSED  one tile kernel computes the moments, the readout and the pair
- *          backward of 16 atoms, then one kernel gathers the forces and sums
+ *          backward of a tile of tile_atoms atoms (16, or 8: twice the
+ *          blocks, each with half the pair and invariant work and the same
+ *          network products), then one kernel gathers the forces and sums
  *          per structure (latency-bound small systems; needs <= 8 species,
  *          no force variance, every structure <= 8192 atoms);
  *   SPLIT  pair moments -> readout -> pair backward -> gather/sums, with the
@@ -232,7 +234,9 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
  * lanes_per_atom (8, 16, 32 or 64) is the number of lanes that share one atom's
  * neighbour row in the pair and gather kernels.  Zero fields mean "built-in
  * choice": FUSED with 64 lanes below 8192 atoms, SPLIT with 16 beyond, the
- * STREAM readout from 16384 atoms on where it is allowed. */
+ * STREAM readout from 16384 atoms on where it is allowed, 8-atom fused
+ * tiles while 16-atom ones would number fewer than 256 (the compute units
+ * of one MI355X). */
 #define GMNN_SCHEDULE_AUTO 0
 #define GMNN_SCHEDULE_FUSED 1
 #define GMNN_SCHEDULE_SPLIT 2
@@ -243,6 +247,8 @@ typedef struct gmnn_plan {
   int32_t schedule;        /* GMNN_SCHEDULE_* */
   int32_t lanes_per_atom;  /* 0, 8, 16, 32 or 64 */
   int32_t readout;         /* GMNN_READOUT_* (SPLIT schedule) */
+  int32_t tile_atoms;      /* FUSED schedule: atoms per tile, 0 (auto), 8 or 16;
+                              must be 0 when the plan resolves to SPLIT */
 } gmnn_plan;
 
 /* Resolve the zero fields of `plan` (NULL: all zero) for these shapes and

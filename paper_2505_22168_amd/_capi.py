@@ -71,7 +71,21 @@ class gmnn_md(C.Structure):
 
 
 class gmnn_plan(C.Structure):
-    _fields_ = [("schedule", C.c_int32), ("lanes_per_atom", C.c_int32), ("readout", C.c_int32)]
+    _fields_ = [("schedule", C.c_int32), ("lanes_per_atom", C.c_int32), ("readout", C.c_int32),
+                ("tile_atoms", C.c_int32)]
+
+    FIELDS = ("schedule", "lanes_per_atom", "readout", "tile_atoms")
+
+    @classmethod
+    def of(cls, plan) -> "gmnn_plan":
+        """From a dict with these field names (missing: 0) or a tuple in field order."""
+        if isinstance(plan, dict):
+            plan = tuple(int(plan.get(k, 0)) for k in cls.FIELDS)
+        plan = tuple(int(v) for v in plan) + (0,) * (len(cls.FIELDS) - len(plan))
+        return cls(*plan)
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k in self.FIELDS}
 
 
 class gmnn_tune_entry(C.Structure):

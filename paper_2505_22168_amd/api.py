@@ -207,8 +207,9 @@ class EnergyForces:
                  stress: bool = True, force_var: bool = False, plan=None):
         """plan: None (the library's built-in choice), "auto" (the autotuned
         plan of this shape class, cached; tunes on first use), or a dict /
-        tuple (schedule, lanes_per_atom[, readout]) with GMNN_SCHEDULE_*,
-        8/16/32/64 and GMNN_READOUT_* (0 = built-in choice)."""
+        tuple (schedule, lanes_per_atom[, readout[, tile_atoms]]) with
+        GMNN_SCHEDULE_*, 8/16/32/64, GMNN_READOUT_* and 8/16 (0 = built-in
+        choice)."""
         self.model, self.system, self.nl = model, system, nl
         self.flags = (A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32)
         if precision not in ("bf16", "fp32"):
@@ -249,10 +250,7 @@ class EnergyForces:
         if plan is None:
             self._plan = None
             return
-        if isinstance(plan, dict):
-            plan = (plan["schedule"], plan["lanes_per_atom"], plan.get("readout", 0))
-        plan = tuple(plan) + (0,) * (3 - len(plan))
-        self._plan = A.gmnn_plan(int(plan[0]), int(plan[1]), int(plan[2]))
+        self._plan = A.gmnn_plan.of(plan)
         A.check(A.load().gmnn_resolve_plan(C.byref(self._mc), C.byref(self._sc), self.flags,
                                            C.byref(self._plan), None), "gmnn_resolve_plan")
 
@@ -263,7 +261,7 @@ class EnergyForces:
         A.check(A.load().gmnn_resolve_plan(C.byref(self._mc), C.byref(self._sc), self.flags,
                                            None if self._plan is None else C.byref(self._plan), C.byref(r)),
                 "gmnn_resolve_plan")
-        return {"schedule": r.schedule, "lanes_per_atom": r.lanes_per_atom, "readout": r.readout}
+        return r.as_dict()
 
     def capture(self, n_evals: int = 1):
         """Capture n_evals evaluations into a HIP graph (replayed by replay())."""

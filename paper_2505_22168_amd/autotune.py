@@ -40,12 +40,12 @@ def shape_key(model, system, nl, flags: int) -> str:
     mean_row = nl.n_pairs / max(n, 1)
     dev = torch.cuda.get_device_name(system.device)
     s = model.spec
-    return "|".join(str(v) for v in (dev, flags & ~A.GMNN_SYNC, s.n_species, s.hidden[0], s.hidden[1], s.n_heads,
+    return "|".join(str(v) for v in ("plan4", dev, flags & ~A.GMNN_SYNC, s.n_species, s.hidden[0], s.hidden[1], s.n_heads,
                                       _pow2(n), _pow2(biggest), _pow2(mean_row)))
 
 
 class TuneCache:
-    """JSON file of shape key -> {"schedule", "lanes_per_atom", "readout", "table"}."""
+    """JSON file of shape key -> {"schedule", "lanes_per_atom", "readout", "tile_atoms", "table"}."""
 
     def __init__(self, path: str | None = None):
         self.path = path or default_path()
@@ -76,19 +76,20 @@ class TuneCache:
 
 def run_autotune(ev, reps: int = 20):
     """gmnn_autotune for an EnergyForces evaluator: returns (plan, table) with
-    plan = {"schedule", "lanes_per_atom", "readout"} and table = [(plan, median_us, min_us)]."""
+    plan = {"schedule", "lanes_per_atom", "readout", "tile_atoms"} and
+    table = [(plan, median_us, min_us)]."""
     lib = A.load()
     best = A.gmnn_plan()
-    entries = (A.gmnn_tune_entry * 16)()
+    cap = 32
+    entries = (A.gmnn_tune_entry * cap)()
     n = C.c_int32(0)
     st = lib.gmnn_autotune(C.byref(ev._mc), C.byref(ev._sc), C.byref(ev._nc), ev.flags, C.byref(ev._oc),
                            C.c_void_p(ev.workspace.data_ptr()), ev.ws_bytes,
-                           C.c_void_p(torch.cuda.current_stream().cuda_stream), reps, C.byref(best), entries, 16,
+                           C.c_void_p(torch.cuda.current_stream().cuda_stream), reps, C.byref(best), entries, cap,
                            C.byref(n))
     A.check(st, "gmnn_autotune")
-    table = [({"schedule": e.plan.schedule, "lanes_per_atom": e.plan.lanes_per_atom, "readout": e.plan.readout},
-              e.median_us, e.min_us) for e in entries[: min(n.value, 16)]]
-    return {"schedule": best.schedule, "lanes_per_atom": best.lanes_per_atom, "readout": best.readout}, table
+    table = [(e.plan.as_dict(), e.median_us, e.min_us) for e in entries[: min(n.value, cap)]]
+    return best.as_dict(), table
 
 
 def tuned_plan(ev, cache: TuneCache | None = None, reps: int = 20) -> dict:
@@ -97,9 +98,7 @@ def tuned_plan(ev, cache: TuneCache | None = None, reps: int = 20) -> dict:
     key = shape_key(ev.model, ev.system, ev.nl, ev.flags)
     hit = cache.get(key)
     if hit is not None:
-        return {"schedule": int(hit["schedule"]), "lanes_per_atom": int(hit["lanes_per_atom"]),
-                "readout": int(hit.get("readout", 0))}
+        return A.gmnn_plan.of(hit).as_dict()
     plan, table = run_autotune(ev, reps)
-    cache.put(key, dict(plan, table=[[p["schedule"], p["lanes_per_atom"], p["readout"], med, mn]
-                                     for p, med, mn in table]))
+    cache.put(key, dict(plan, table=[[p[k] for k in A.gmnn_plan.FIELDS] + [med, mn] for p, med, mn in table]))
     return plan

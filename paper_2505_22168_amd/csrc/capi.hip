@@ -21,7 +21,7 @@ template <int LPA, bool VAR>
 __global__ void finish(int M, DevSystem sys, const float* gpair, const float* atomic_e, const float* virial,
                        int want_stress, int nb_gather, int64_t gstride, int nchunk, double* partial, int* counters,
                        float* forces, float* force_var, double* energy, double* energy_var, double* stress);
-gmnn_status launch_tile(bool fused, bool perhead, const DevModel& m, const DevSystem& sys, bool bf16,
+gmnn_status launch_tile(bool fused, bool perhead, int tile_atoms, const DevModel& m, const DevSystem& sys, bool bf16,
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
                         int64_t gstride, hipStream_t stream);
 bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead);
@@ -57,9 +57,13 @@ static int reduce_chunks(const gmnn_system* sys) {
 // ---------------------------------------------------------------------------
 struct Plan {
   bool fused;   // one tile kernel for moments + readout + pair backward
+  int ta;       // fused schedule: atoms per tile (8 or 16); 0 otherwise
   int lpa;      // lanes per atom row in the pair and gather kernels
   bool stream;  // split schedule: readout as three launches (64-row network tiles)
 };
+// the built-in fused plan halves its tiles (8 atoms) while 16-atom tiles
+// would leave compute units idle
+constexpr int kComputeUnits = 256;
 // at and above this many atoms the built-in plan streams the readout
 constexpr int kStreamMinAtoms = 16384;
 
@@ -73,7 +77,8 @@ static bool fused_allowed(const gmnn_model* m, const gmnn_system* sys, uint32_t 
 
 // fills the AUTO fields of `in` (built-in heuristic: the fused schedule for
 // systems of fewer than kFusedMaxAtoms atoms, 64 lanes per atom there and 16
-// beyond); UNSUPPORTED for a plan these shapes cannot run
+// beyond, 8-atom fused tiles below one 16-atom tile per compute unit);
+// UNSUPPORTED for a plan these shapes cannot run
 static gmnn_status resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint32_t flags, const gmnn_plan* in,
                                 Plan& out) {
   const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
@@ -89,6 +94,10 @@ static gmnn_status resolve_plan(const gmnn_model* m, const gmnn_system* sys, uin
   if (!out.fused && tile_lds_bytes(L.HP1, (flags & GMNN_PREC_BF16) != 0, false, (flags & GMNN_WANT_FORCE_VAR) != 0) >
                         160 * 1024)
     return GMNN_ERR_UNSUPPORTED;
+  const int ta = in ? in->tile_atoms : 0;
+  if (ta != 0 && ta != 8 && ta != 16) return GMNN_ERR_INVALID_ARG;
+  if (ta != 0 && !out.fused) return GMNN_ERR_UNSUPPORTED;
+  out.ta = !out.fused ? 0 : ta ? ta : ((sys->n_atoms + 15) / 16 < kComputeUnits ? 8 : 16);
   out.lpa = lpa ? lpa : (small ? 64 : 16);
   const int ro = in ? in->readout : GMNN_READOUT_AUTO;
   if (ro != GMNN_READOUT_AUTO && ro != GMNN_READOUT_TILE && ro != GMNN_READOUT_STREAM) return GMNN_ERR_INVALID_ARG;
@@ -390,6 +399,7 @@ gmnn_status gmnn_resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint3
     resolved->schedule = p.fused ? GMNN_SCHEDULE_FUSED : GMNN_SCHEDULE_SPLIT;
     resolved->lanes_per_atom = p.lpa;
     resolved->readout = p.stream ? GMNN_READOUT_STREAM : GMNN_READOUT_TILE;
+    resolved->tile_atoms = p.ta;
   }
   return GMNN_OK;
 }
@@ -439,7 +449,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   if (N > 0) {
     if (fused) {
       mark(0);
-      st = launch_tile(true, false, dm, ds, bf16, nullptr, atomic_e, nullptr, gpair, virial, gstride, s);
+      st = launch_tile(true, false, P.ta, dm, ds, bf16, nullptr, atomic_e, nullptr, gpair, virial, gstride, s);
       if (st != GMNN_OK) return st;
       mark(1);
       mark(2);
@@ -461,7 +471,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
       if (P.stream)
         st = launch_stream(dm, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s);
       else
-        st = launch_tile(false, var, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, s);
+        st = launch_tile(false, var, 16, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, s);
       if (st != GMNN_OK) return st;
       mark(3);
       mark(4);
@@ -527,8 +537,9 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
   if (!best || reps < 1 || reps > 1000 || max_entries < 0 || (max_entries > 0 && !entries))
     return GMNN_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  static const int kSched[3] = {GMNN_SCHEDULE_FUSED, GMNN_SCHEDULE_SPLIT, GMNN_SCHEDULE_SPLIT};
-  static const int kReadout[3] = {GMNN_READOUT_TILE, GMNN_READOUT_TILE, GMNN_READOUT_STREAM};
+  static const int kSched[4] = {GMNN_SCHEDULE_FUSED, GMNN_SCHEDULE_FUSED, GMNN_SCHEDULE_SPLIT, GMNN_SCHEDULE_SPLIT};
+  static const int kTileAtoms[4] = {16, 8, 0, 0};
+  static const int kReadout[4] = {GMNN_READOUT_TILE, GMNN_READOUT_TILE, GMNN_READOUT_TILE, GMNN_READOUT_STREAM};
   static const int kLanes[4] = {8, 16, 32, 64};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return GMNN_ERR_HIP;
@@ -540,9 +551,9 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
   float best_us = 0.0f;
   bool have = false;
   std::vector<float> t(reps);
-  for (int si = 0; si < 3 && st == GMNN_OK; ++si) {
+  for (int si = 0; si < 4 && st == GMNN_OK; ++si) {
     for (int li = 0; li < 4 && st == GMNN_OK; ++li) {
-      const gmnn_plan cand = {kSched[si], kLanes[li], kReadout[si]};
+      const gmnn_plan cand = {kSched[si], kLanes[li], kReadout[si], kTileAtoms[si]};
       Plan P;
       if (resolve_plan(m, sys, flags, &cand, P) != GMNN_OK) continue;
       // warm-up (also surfaces argument errors before anything is timed)

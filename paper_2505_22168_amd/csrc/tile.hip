@@ -1,9 +1,11 @@
 // Tile kernels of the GMNN energy/force path (gfx950, wave64, MFMA).
 //
-// One block of 512 threads (8 waves) owns a tile of TM = 16 atoms and keeps
-// everything of the tile in LDS:
+// One block of 512 threads (8 waves) owns a tile of TA atoms (16, or 8 in
+// the fused kernel) and keeps everything of the tile in LDS; the network
+// products always run on TM = 16 rows (the MFMA block), rows past TA zero:
 //   [FUSED only] pair moments of its atoms (Section 2.1, eq. basis_fn), two
-//                atoms per wave, 32 lanes each
+//                atoms per wave with 32 lanes each (TA = 16) or one atom per
+//                wave with 64 lanes (TA = 8)
 //   invariants  (Section 2.1, eq. contraction): families 1-4 and the
 //               intermediates T7, V8, M5, v6 in one pass, families 5-8 in a
 //               second pass
@@ -12,10 +14,12 @@
 //   invariants backward: intermediates U8, Y, Qv, then every entry of
 //               dE/dPsi in one pass, folded onto the packed components
 //   [FUSED only] pair backward of its atoms (Section 3.3): per-pair
-//               gradients and the per-atom virial, two atoms per wave
+//               gradients and the per-atom virial, on the moment stage's lanes
 // The fused kernel serves small systems, where the whole step is latency
-// bound and one launch per stage would dominate; the unfused readout serves
-// large systems between the high-occupancy pair kernels.
+// bound and one launch per stage would dominate (8-atom tiles spread such a
+// system over twice the blocks: half the pair and contraction work per
+// block, the same network products); the unfused readout serves large
+// systems between the high-occupancy pair kernels.
 #include "common.h"
 #include "contraction.h"
 #include "mfma.h"
@@ -29,17 +33,18 @@ constexpr int kTileWaves = kTileThreads / 64;
 constexpr int kTM = 16;
 constexpr int kFusedMaxSpecies = 8;
 
-template <int HP, bool BF16, bool FUSED, bool PERHEAD>
+template <int HP, bool BF16, bool FUSED, bool PERHEAD, int TA>
 struct TileLds {
   using St = NetStrides<HP, BF16>;
   static constexpr int TM = kTM;
+  static constexpr int LPA = kTileThreads / TA;  // fused pair stages: lanes per atom
   static constexpr int ESZ = BF16 ? 2 : 4;
   static constexpr size_t al(size_t x) { return (x + 255) & ~size_t(255); }
   static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
   static constexpr size_t tables = 0;
   static constexpr size_t psi = al(sizeof(Tables));
-  static constexpr size_t inter = psi + al(4 * (size_t)TM * PS);
-  static constexpr size_t regb = inter + al(4 * (size_t)TM * IS);
+  static constexpr size_t inter = psi + al(4 * (size_t)TA * PS);
+  static constexpr size_t regb = inter + al(4 * (size_t)TA * IS);
   static constexpr size_t regb_bytes =
       mx(mx((size_t)ESZ * TM * St::G, (size_t)ESZ * TM * St::H), 4 * (size_t)TM * St::GB);
   static constexpr size_t regc = regb + al(regb_bytes);
@@ -47,25 +52,27 @@ struct TileLds {
   static constexpr size_t ep = regc + al(regc_bytes);
   static constexpr size_t rowsc = ep + al(4 * (size_t)kTileWaves * 16 * kMaxHeads);
   static constexpr size_t vir = rowsc + al(4 * 2 * (size_t)TM);
-  static constexpr size_t psibar = vir + al(4 * 9 * (size_t)TM);
-  static constexpr size_t dsw2 = psibar + (FUSED ? al(4 * (size_t)TM * kS * kPacked) : 0);
+  static constexpr size_t psibar = vir + al(4 * 9 * (size_t)TA);
+  static constexpr size_t dsw2 = psibar + (FUSED ? al(4 * (size_t)TA * kS * kPacked) : 0);
   static constexpr size_t beta = dsw2 + (PERHEAD ? al(4 * (size_t)TM * (HP + 1)) : 0);
-  // fused: per-atom context and first pair group of each of the 32 lanes
+  // fused: per-atom context and first pair group of each of the LPA lanes
   static constexpr size_t pctx = beta + (FUSED ? al(4 * (size_t)kFusedMaxSpecies * kFusedMaxSpecies * kS * kMaxBasis) : 0);
-  static constexpr size_t ppv = pctx + (FUSED ? al(sizeof(AtomCtx) * (size_t)TM) : 0);
-  static constexpr size_t bytes = ppv + (FUSED ? al(sizeof(float4) * (size_t)TM * 32 * kPairUnroll) : 0);
+  static constexpr size_t ppv = pctx + (FUSED ? al(sizeof(AtomCtx) * (size_t)TA) : 0);
+  static constexpr size_t bytes = ppv + (FUSED ? al(sizeof(float4) * (size_t)TA * LPA * kPairUnroll) : 0);
 };
 
 // psibar_out: [nh][N][100] (unfused); gpair: [nh][gstride][3] (fused);
 // nh = n_heads with PERHEAD (one backward per head), else 1 (head mean)
-template <int HP, bool BF16, bool FUSED, bool PERHEAD>
+template <int HP, bool BF16, bool FUSED, bool PERHEAD, int TA>
 __global__ void __launch_bounds__(kTileThreads)
     tile_kernel(DevModel m, DevSystem sys, const float* __restrict__ psi_in, float* __restrict__ atomic_e,
                 float* __restrict__ psibar_out, float* __restrict__ gpair, float* __restrict__ virial,
                 int64_t gstride) {
-  using L = TileLds<HP, BF16, FUSED, PERHEAD>;
+  using L = TileLds<HP, BF16, FUSED, PERHEAD, TA>;
   using Sh = NetShape<kTM, HP, kTileWaves>;
   constexpr int TM = kTM;
+  constexpr int LPA = L::LPA;
+  static_assert(TA == 16 || (FUSED && TA == 8), "16-atom tiles, or 8-atom fused tiles");
   extern __shared__ __attribute__((aligned(16))) char lds[];
   Tables& tb = *(Tables*)(lds + L::tables);
   float* sPsi = (float*)(lds + L::psi);
@@ -87,29 +94,38 @@ __global__ void __launch_bounds__(kTileThreads)
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
-  const int row0 = xcd_block(blockIdx.x, gridDim.x) * TM;
-  const int n_rows = min(TM, sys.n_atoms - row0);
+  const int row0 = xcd_block(blockIdx.x, gridDim.x) * TA;
+  const int n_rows = min(TA, sys.n_atoms - row0);
   const int nh = PERHEAD ? m.M : 1;
 
   load_tables(&tb);
-  for (int t = tid; t < TM * 9; t += kTileThreads) sVir[t] = 0.0f;
+  for (int t = tid; t < TA * 9; t += kTileThreads) sVir[t] = 0.0f;
+  if (TA < TM) {
+    // network rows past the tile's atoms read zero invariants
+    constexpr int ESZ = BF16 ? 2 : 4;
+    constexpr int W0 = TA * NetStrides<HP, BF16>::G * ESZ / 4, W1 = TM * NetStrides<HP, BF16>::G * ESZ / 4;
+    for (int t = W0 + tid; t < W1; t += kTileThreads) ((uint32_t*)sG)[t] = 0u;
+  }
   if (FUSED) stage_beta(m, s_beta);
   __syncthreads();
 
   // ---- moments -> full tensors in LDS ------------------------------------
-  // fused pair stages: each wave runs two atoms at once, 32 lanes each
-  static_assert(TM == 2 * kTileWaves, "two atoms per wave");
-  const int fa = w + kTileWaves * (l >> 5);  // this half wave's atom
-  const int fq = l & 31;
+  // fused pair stages: each wave runs two atoms at once with 32 lanes each
+  // (TA = 16), or one atom with all 64 lanes (TA = 8)
+  static_assert(TA * LPA == kTileThreads && (LPA == 32 || LPA == 64), "whole waves per atom pair");
+  const int fa = LPA == 32 ? w + kTileWaves * (l >> 5) : w;  // this lane's atom
+  const int fq = l & (LPA - 1);
   if (FUSED) {
     float v[128];
 #pragma unroll
     for (int k = 0; k < 128; ++k) v[k] = 0.0f;
-    if (fa < n_rows) atom_moments<32>(m, sys, s_beta, row0 + fa, fq, v, PairCache{sCtx + fa, sPv + fa * 32 * kPairUnroll});
-    reduce_scatter_128<32>(v, fq);
+    if (fa < n_rows)
+      atom_moments<LPA>(m, sys, s_beta, row0 + fa, fq, v, PairCache{sCtx + fa, sPv + fa * LPA * kPairUnroll});
+    reduce_scatter_128<LPA>(v, fq);
+    constexpr int PER = 128 / LPA;  // values each lane owns after the reduce-scatter
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = 4 * fq + e;
+    for (int e = 0; e < PER; ++e) {
+      const int k = PER * fq + e;
       if (k < kS * kPacked) {
         const int s = k / kPacked, t = k % kPacked;
         const int n = tb.packed_mult[t];
@@ -120,7 +136,7 @@ __global__ void __launch_bounds__(kTileThreads)
     // the tile's packed moments are one contiguous run: all loads issued at
     // once, coalesced, then expanded into the full tensors
     constexpr int NP = kS * kPacked;
-    constexpr int NU = (TM * NP + kTileThreads - 1) / kTileThreads;
+    constexpr int NU = (TA * NP + kTileThreads - 1) / kTileThreads;
     float v[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -130,7 +146,7 @@ __global__ void __launch_bounds__(kTileThreads)
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int t = tid + u * kTileThreads;
-      if (t < TM * NP) {
+      if (t < TA * NP) {
         const int a = t / NP, e = t % NP;
         const int s = e / kPacked, c = e % kPacked;
         const int n = tb.packed_mult[c];
@@ -146,7 +162,7 @@ __global__ void __launch_bounds__(kTileThreads)
   constexpr int kDepth = PERHEAD ? 2 : prefetch_depth<Sh::TPW>();
   BRing<BF16, Sh::TPW, kDepth> ring;
   ring_fill(ring, m.w1_bf16, m.w1_f32, kFP, (tid >> 6) / Sh::MB, Sh::WPR, Sh::NBH);
-  contract_forward_a<TM, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  contract_forward_a<TA, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
   // per-atom scale / shift, by the last wave (idle in the phase above), for
   // the network epilogue
   if (tid >= kTileThreads - 64 && tid - (kTileThreads - 64) < TM) {
@@ -161,7 +177,7 @@ __global__ void __launch_bounds__(kTileThreads)
     sShift[a] = sh;
   }
   __syncthreads();
-  contract_forward_b<TM, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  contract_forward_b<TA, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
   __syncthreads();
 
   // ---- network forward ---------------------------------------------------------
@@ -178,12 +194,12 @@ __global__ void __launch_bounds__(kTileThreads)
     }
     network_backward<TM, HP, BF16, kTileWaves, kDepth>(m, sD2, sH, sGb, dsw1, ring);
     // ---- invariants backward ---------------------------------------------------
-    contract_backward_a<TM, kTileThreads>(sPsi, sGb, LDGB, sI, tb);
+    contract_backward_a<TA, kTileThreads>(sPsi, sGb, LDGB, sI, tb);
     __syncthreads();
-    contract_backward_b<TM, kTileThreads>(sPsi, sGb, LDGB, sI, sPb, tb);
+    contract_backward_b<TA, kTileThreads>(sPsi, sGb, LDGB, sI, sPb, tb);
     __syncthreads();
     if (FUSED) {
-      fold_packed<TM, kTileThreads>(sPb, tb, [&](int a, int e, float v) { sPsibar[a * (kS * kPacked) + e] = v; });
+      fold_packed<TA, kTileThreads>(sPb, tb, [&](int a, int e, float v) { sPsibar[a * (kS * kPacked) + e] = v; });
       __syncthreads();
       // ---- pair backward -----------------------------------------------------
       float* g_head = gpair + (int64_t)hm * gstride * 3;
@@ -195,11 +211,11 @@ __global__ void __launch_bounds__(kTileThreads)
           float pb[kS * kPacked];
 #pragma unroll
           for (int k = 0; k < kS * kPacked; ++k) pb[k] = sPsibar[fa * (kS * kPacked) + k];
-          atom_pair_backward<32>(m, sys, s_beta, row0 + fa, fq, pb, g_head, vir,
-                                 PairCache{sCtx + fa, sPv + fa * 32 * kPairUnroll});
+          atom_pair_backward<LPA>(m, sys, s_beta, row0 + fa, fq, pb, g_head, vir,
+                                  PairCache{sCtx + fa, sPv + fa * LPA * kPairUnroll});
         }
 #pragma unroll
-        for (int k = 0; k < 9; ++k) vir[k] = atom_sum<32>(vir[k]);
+        for (int k = 0; k < 9; ++k) vir[k] = atom_sum<LPA>(vir[k]);
         if (fq < 9) {
           float vk = vir[0];
 #pragma unroll
@@ -211,7 +227,7 @@ __global__ void __launch_bounds__(kTileThreads)
       __syncthreads();
     } else {
       float* pbo = psibar_out + (int64_t)hm * sys.n_atoms * (kS * kPacked);
-      fold_packed<TM, kTileThreads>(sPb, tb, [&](int a, int e, float v) {
+      fold_packed<TA, kTileThreads>(sPb, tb, [&](int a, int e, float v) {
         if (a < n_rows) pbo[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
       });
       __syncthreads();
@@ -224,33 +240,34 @@ __global__ void __launch_bounds__(kTileThreads)
 }
 
 // ---------------------------------------------------------------------------
-template <int HP, bool BF16, bool FUSED, bool PERHEAD>
+template <int HP, bool BF16, bool FUSED, bool PERHEAD, int TA>
 static gmnn_status launch_tile_t(const DevModel& m, const DevSystem& sys, const float* psi, float* atomic_e,
                                  float* psibar, float* gpair, float* virial, int64_t gstride, hipStream_t stream) {
-  using L = TileLds<HP, BF16, FUSED, PERHEAD>;
+  using L = TileLds<HP, BF16, FUSED, PERHEAD, TA>;
   if (L::bytes > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
-  auto k = tile_kernel<HP, BF16, FUSED, PERHEAD>;
+  auto k = tile_kernel<HP, BF16, FUSED, PERHEAD, TA>;
   static bool attr_set = false;
   if (!attr_set) {
     if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes) != hipSuccess)
       return GMNN_ERR_HIP;
     attr_set = true;
   }
-  const int grid = (sys.n_atoms + kTM - 1) / kTM;
+  const int grid = (sys.n_atoms + TA - 1) / TA;
   if (grid == 0) return GMNN_OK;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kTileThreads), L::bytes, stream, m, sys, psi, atomic_e, psibar, gpair,
                      virial, gstride);
   return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
 }
 
+// LDS bytes of the tile kernel (the fused one with 16-atom tiles, the larger)
 size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead) {
 #define SZ(HP) \
   if (hp == HP) { \
     if (fused && perhead) return ~size_t(0); \
-    if (bf16) return fused ? TileLds<HP, true, true, false>::bytes \
-                           : (perhead ? TileLds<HP, true, false, true>::bytes : TileLds<HP, true, false, false>::bytes); \
-    return fused ? TileLds<HP, false, true, false>::bytes \
-                 : (perhead ? TileLds<HP, false, false, true>::bytes : TileLds<HP, false, false, false>::bytes); \
+    if (bf16) return fused ? TileLds<HP, true, true, false, 16>::bytes \
+                           : (perhead ? TileLds<HP, true, false, true, 16>::bytes : TileLds<HP, true, false, false, 16>::bytes); \
+    return fused ? TileLds<HP, false, true, false, 16>::bytes \
+                 : (perhead ? TileLds<HP, false, false, true, 16>::bytes : TileLds<HP, false, false, false, 16>::bytes); \
   }
   SZ(64) SZ(128) SZ(256) SZ(512)
 #undef SZ
@@ -264,28 +281,34 @@ bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead) {
   return !perhead && n_species <= kFusedMaxSpecies && tile_lds_bytes(hp, bf16, true, false) <= 160 * 1024;
 }
 
-// fused: moments + readout + pair backward in one launch (gpair, virial out);
-// otherwise the readout alone (psi in, psibar out)
-gmnn_status launch_tile(bool fused, bool perhead, const DevModel& m, const DevSystem& sys, bool bf16,
+// fused: moments + readout + pair backward in one launch (gpair, virial out)
+// on tiles of tile_atoms (8 or 16) atoms; otherwise the readout alone (psi in,
+// psibar out) on 16-atom tiles
+gmnn_status launch_tile(bool fused, bool perhead, int tile_atoms, const DevModel& m, const DevSystem& sys, bool bf16,
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
                         int64_t gstride, hipStream_t stream) {
   if (fused && !tile_fused_supported(m.n_species, m.HP1, bf16, perhead)) return GMNN_ERR_UNSUPPORTED;
-#define CASE4(HP, BF, FU)                                                                                          \
-  return perhead ? launch_tile_t<HP, BF, FU, true>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream)  \
-                 : launch_tile_t<HP, BF, FU, false>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream);
-#define CASE(HP)                                                                                        \
-  if (m.HP1 == HP) {                                                                                    \
-    if (fused) {                                                                                        \
-      if (perhead) return GMNN_ERR_UNSUPPORTED;                                                         \
-      return bf16 ? launch_tile_t<HP, true, true, false>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream) \
-                  : launch_tile_t<HP, false, true, false>(m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream); \
-    }                                                                                                   \
-    if (bf16) { CASE4(HP, true, false) }                                                                \
-    CASE4(HP, false, false)                                                                             \
+  if (fused && tile_atoms != 8 && tile_atoms != 16) return GMNN_ERR_INVALID_ARG;
+#define ARGS m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream
+#define FUSED_CASE(HP, BF) \
+  return tile_atoms == 8 ? launch_tile_t<HP, BF, true, false, 8>(ARGS) : launch_tile_t<HP, BF, true, false, 16>(ARGS);
+#define CASE4(HP, BF) \
+  return perhead ? launch_tile_t<HP, BF, false, true, 16>(ARGS) : launch_tile_t<HP, BF, false, false, 16>(ARGS);
+#define CASE(HP)                                         \
+  if (m.HP1 == HP) {                                     \
+    if (fused) {                                         \
+      if (perhead) return GMNN_ERR_UNSUPPORTED;          \
+      if (bf16) { FUSED_CASE(HP, true) }                 \
+      FUSED_CASE(HP, false)                              \
+    }                                                    \
+    if (bf16) { CASE4(HP, true) }                        \
+    CASE4(HP, false)                                     \
   }
   CASE(64) CASE(128) CASE(256) CASE(512)
 #undef CASE
 #undef CASE4
+#undef FUSED_CASE
+#undef ARGS
   return GMNN_ERR_UNSUPPORTED;
 }
 

@@ -1,5 +1,6 @@
-"""Every execution plan (fused / split schedule, 8 / 16 / 32 / 64 lanes per atom)
-against the FP64 oracle, and the autotuner's choice.
+"""Every execution plan (fused schedule on 16- or 8-atom tiles / split
+schedule, 8 / 16 / 32 / 64 lanes per atom) against the FP64 oracle, and the
+autotuner's choice.
 
 The plans only re-cut the same arithmetic into kernels, so each is held to
 the FP32 bound (|dE|/N <= 1e-5 eV/atom, max|dF| <= 1e-4 eV/A, stress 1e-6)
@@ -16,7 +17,7 @@ from gpu_helpers import gpu, need_gpu
 
 pytestmark = gpu
 
-PLANS = [(1, 8), (1, 16), (1, 32), (1, 64), (2, 8), (2, 16), (2, 32), (2, 64)]
+PLANS = [(1, lanes, ta) for ta in (16, 8) for lanes in (8, 16, 32, 64)] + [(2, lanes, 0) for lanes in (8, 16, 32, 64)]
 
 
 def _setup(g, name, kw):
@@ -40,15 +41,32 @@ def _check(out, ref, batch, var=False):
         assert np.allclose(out.energy_var.cpu().numpy(), ref.energy_var, rtol=1e-5, atol=1e-6)
 
 
-@pytest.mark.parametrize("sched,lanes", PLANS)
-def test_every_plan_matches_oracle(sched, lanes):
+@pytest.mark.parametrize("sched,lanes,ta", PLANS)
+def test_every_plan_matches_oracle(sched, lanes, ta):
     g = need_gpu()
     batch, params, spec, system, nl, model = _setup(g, "ensemble", dict(n_structs=6))
     ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
-    print(f"plan schedule={sched} lanes={lanes} ensemble n_structs=6", flush=True)
-    ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(sched, lanes))
-    assert ev.plan == {"schedule": sched, "lanes_per_atom": lanes, "readout": 1}
+    print(f"plan schedule={sched} lanes={lanes} tile_atoms={ta} ensemble n_structs=6", flush=True)
+    ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(sched, lanes, 0, ta))
+    assert ev.plan == {"schedule": sched, "lanes_per_atom": lanes, "readout": 1, "tile_atoms": ta}
     _check(ev(sync=True), ref, batch)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fused_tile_sizes_agree(precision):
+    """8- and 16-atom fused tiles run the same per-atom arithmetic; only the
+    lanes that sum each atom's pairs differ (64 vs 32), so energies and
+    forces agree to FP32 summation order, and the BF16 network rounds the
+    same operands."""
+    g = need_gpu()
+    batch, params, spec, system, nl, model = _setup(g, "liquid", dict(n=700))
+    print(f"fused tile sizes {precision} N={batch.n_atoms}", flush=True)
+    o16 = g.EnergyForces(model, system, nl, precision=precision, stress=True, plan=(1, 64, 0, 16))(sync=True)
+    e16, f16 = o16.energy.cpu().numpy().copy(), o16.forces.cpu().numpy().copy()
+    o8 = g.EnergyForces(model, system, nl, precision=precision, stress=True, plan=(1, 64, 0, 8))(sync=True)
+    n = batch.n_atoms
+    assert np.abs(o8.energy.cpu().numpy() - e16).max() / n < 1e-6
+    assert np.abs(o8.forces.cpu().numpy()[:n] - f16[:n]).max() < (1e-4 if precision == "fp32" else 2e-3)
 
 
 @pytest.mark.parametrize("lanes", [8, 16, 32, 64])
@@ -76,7 +94,7 @@ def test_autotune_choice_and_cache(tmp_path, monkeypatch):
     ref = evaluate(batch, params, brute_force_neighbors(batch, spec.model.r_cut))
     ev = g.EnergyForces(model, system, nl, precision="bf16", stress=True)
     plan, table = autotune.run_autotune(ev, reps=5)
-    assert len(table) == 12  # fused, split with tile readout, split streamed; x four lane counts
+    assert len(table) == 16  # fused on 16- and 8-atom tiles, split with tile / streamed readout; x four lane counts
     assert plan in [p for p, _, _ in table]
     best = min(table, key=lambda t: t[1])
     assert best[0] == plan
@@ -126,7 +144,7 @@ def test_streamed_readout_large_system():
     nl = g.build_neighbors(system, spec.model.r_cut, 0.0)
     model = g.Model.from_params(params, "cuda")
     ev = g.EnergyForces(model, system, nl, precision="fp32", stress=True)
-    assert ev.plan == {"schedule": 2, "lanes_per_atom": 16, "readout": 2}
+    assert ev.plan == {"schedule": 2, "lanes_per_atom": 16, "readout": 2, "tile_atoms": 0}
     out = ev(sync=True)
     tile = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(2, 16, 1))(sync=True)
     assert torch.equal(out.forces, tile.forces) and torch.equal(out.energy, tile.energy)

@@ -29,13 +29,13 @@ class _Sys:
                                FAKE, self.cell.ctypes.data_as(C.c_void_p), FAKE, self.pbc.ctypes.data_as(C.c_void_p))
 
 
-def _resolve(model, sysobj, flags, sched=None, lanes=0, readout=0, full=False):
+def _resolve(model, sysobj, flags, sched=None, lanes=0, readout=0, full=False, ta=0):
     lib = A.load()
     out = A.gmnn_plan()
-    plan = None if sched is None else C.byref(A.gmnn_plan(sched, lanes, readout))
+    plan = None if sched is None else C.byref(A.gmnn_plan(sched, lanes, readout, ta))
     st = lib.gmnn_resolve_plan(C.byref(model), C.byref(sysobj.c), flags, plan, C.byref(out))
     if full:
-        return st, (out.schedule, out.lanes_per_atom, out.readout)
+        return st, (out.schedule, out.lanes_per_atom, out.readout, out.tile_atoms)
     return st, (out.schedule, out.lanes_per_atom)
 
 
@@ -69,21 +69,38 @@ def test_readout_choice():
     TILE, STREAM = A.GMNN_READOUT_TILE, A.GMNN_READOUT_STREAM
     SPLIT, FUSED = A.GMNN_SCHEDULE_SPLIT, A.GMNN_SCHEDULE_FUSED
     # built-in: tile readout below 16384 atoms, streamed from there on
-    assert _resolve(m, _Sys([12000]), 0, full=True) == (A.GMNN_OK, (SPLIT, 16, TILE))
-    assert _resolve(m, _Sys([100000]), A.GMNN_PREC_BF16, full=True) == (A.GMNN_OK, (SPLIT, 16, STREAM))
-    assert _resolve(_model(), _Sys([1536]), 0, full=True)[1] == (FUSED, 64, TILE)
+    assert _resolve(m, _Sys([12000]), 0, full=True) == (A.GMNN_OK, (SPLIT, 16, TILE, 0))
+    assert _resolve(m, _Sys([100000]), A.GMNN_PREC_BF16, full=True) == (A.GMNN_OK, (SPLIT, 16, STREAM, 0))
+    assert _resolve(_model(), _Sys([1536]), 0, full=True)[1] == (FUSED, 64, TILE, 8)
     # force variance needs one backward per head: the tile readout only
-    assert _resolve(_model(), _Sys([100000]), A.GMNN_WANT_FORCE_VAR, full=True)[1] == (SPLIT, 16, TILE)
+    assert _resolve(_model(), _Sys([100000]), A.GMNN_WANT_FORCE_VAR, full=True)[1] == (SPLIT, 16, TILE, 0)
     assert _resolve(m, _Sys([200]), A.GMNN_WANT_FORCE_VAR, SPLIT, 16, STREAM)[0] == A.GMNN_ERR_UNSUPPORTED
     # the streamed readout belongs to the split schedule
     assert _resolve(m, _Sys([200]), 0, FUSED, 16, STREAM)[0] == A.GMNN_ERR_UNSUPPORTED
-    assert _resolve(m, _Sys([200]), 0, SPLIT, 32, STREAM, full=True) == (A.GMNN_OK, (SPLIT, 32, STREAM))
-    assert _resolve(m, _Sys([100000]), 0, SPLIT, 16, TILE, full=True) == (A.GMNN_OK, (SPLIT, 16, TILE))
+    assert _resolve(m, _Sys([200]), 0, SPLIT, 32, STREAM, full=True) == (A.GMNN_OK, (SPLIT, 32, STREAM, 0))
+    assert _resolve(m, _Sys([100000]), 0, SPLIT, 16, TILE, full=True) == (A.GMNN_OK, (SPLIT, 16, TILE, 0))
     # sixteen heads fit the network block's LDS at every width and precision
     for hidden in (64, 256, 512):
         for flags in (0, A.GMNN_PREC_BF16):
             assert _resolve(_model(hidden=hidden, heads=16), _Sys([200]), flags, SPLIT, 16, STREAM)[0] == A.GMNN_OK
     assert _resolve(m, _Sys([200]), 0, SPLIT, 16, 5)[0] == A.GMNN_ERR_INVALID_ARG
+
+
+def test_fused_tile_atoms():
+    m = _model()
+    FUSED, SPLIT, TILE = A.GMNN_SCHEDULE_FUSED, A.GMNN_SCHEDULE_SPLIT, A.GMNN_READOUT_TILE
+    # built-in: 8-atom tiles while 16-atom ones would number fewer than the 256 compute units
+    assert _resolve(m, _Sys([4080]), 0, full=True)[1] == (FUSED, 64, TILE, 8)
+    assert _resolve(m, _Sys([4096]), 0, full=True)[1] == (FUSED, 64, TILE, 16)
+    for ta in (8, 16):
+        assert _resolve(m, _Sys([1536]), 0, FUSED, 32, 0, full=True, ta=ta) == (A.GMNN_OK, (FUSED, 32, TILE, ta))
+        # tile sizes belong to the fused schedule
+        assert _resolve(m, _Sys([1536]), 0, SPLIT, 16, 0, ta=ta)[0] == A.GMNN_ERR_UNSUPPORTED
+        assert _resolve(m, _Sys([100000]), 0, 0, 0, 0, ta=ta)[0] == A.GMNN_ERR_UNSUPPORTED
+    assert _resolve(m, _Sys([1536]), 0, FUSED, 32, 0, ta=12)[0] == A.GMNN_ERR_INVALID_ARG
+    assert A.gmnn_plan.of({"schedule": 1, "lanes_per_atom": 32}).as_dict() == {
+        "schedule": 1, "lanes_per_atom": 32, "readout": 0, "tile_atoms": 0}
+    assert A.gmnn_plan.of((2, 16, 2)).as_dict()["readout"] == 2
 
 
 def test_invalid_plans():
