@@ -20,10 +20,11 @@ __global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, fl
 template <int LPA, bool VAR>
 __global__ void finish(int M, DevSystem sys, const float* gpair, const float* atomic_e, const float* virial,
                        int want_stress, int nb_gather, int64_t gstride, int nchunk, double* partial, int* counters,
-                       float* forces, float* force_var, double* energy, double* energy_var, double* stress);
+                       float* forces, float* force_var, double* energy, double* energy_var, double* stress,
+                       const double* tile_part, int tile_atoms);
 gmnn_status launch_tile(bool fused, bool perhead, int tile_atoms, const DevModel& m, const DevSystem& sys, bool bf16,
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
-                        int64_t gstride, hipStream_t stream);
+                        int64_t gstride, double* tile_rec, hipStream_t stream);
 bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead);
 gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,
                           float* atomic_e, float* psibar, hipStream_t s);
@@ -39,16 +40,21 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
 constexpr int kPairThreads = 256;
 // below this many atoms the built-in plan takes the fused (latency) schedule
 constexpr int kFusedMaxAtoms = 8192;
-// per-structure reductions split into chunks of at most this many atoms
-constexpr int kReduceChunk = 8192;
+// per-structure reductions of per-atom values split into chunks of at most
+// this many atoms (one block each)
+constexpr int kReduceChunk = 2048;
 
-static int reduce_chunks(const gmnn_system* sys) {
+static int64_t largest_structure(const gmnn_system* sys) {
   int64_t mx = 0;
   for (int b = 0; b < sys->n_structs; ++b) {
     const int64_t n = sys->atom_ptr_host[b + 1] - sys->atom_ptr_host[b];
     if (n > mx) mx = n;
   }
-  const int64_t c = (mx + kReduceChunk - 1) / kReduceChunk;
+  return mx;
+}
+
+static int reduce_chunks(const gmnn_system* sys) {
+  const int64_t c = (largest_structure(sys) + kReduceChunk - 1) / kReduceChunk;
   return c < 1 ? 1 : (int)c;
 }
 
@@ -68,11 +74,11 @@ constexpr int kComputeUnits = 256;
 constexpr int kStreamMinAtoms = 16384;
 
 // the fused tile needs few species (beta staged in its LDS), the head-mean
-// backward only, and one reduction chunk per structure (its chunk counters
-// are zeroed by the split schedule's first kernel)
+// backward only, and structures of at most kFusedMaxAtoms atoms (one block
+// sums each structure from the tiles' records)
 static bool fused_allowed(const gmnn_model* m, const gmnn_system* sys, uint32_t flags, int HP1) {
   return tile_fused_supported(m->n_species, HP1, (flags & GMNN_PREC_BF16) != 0, (flags & GMNN_WANT_FORCE_VAR) != 0) &&
-         reduce_chunks(sys) == 1;
+         largest_structure(sys) <= kFusedMaxAtoms;
 }
 
 // fills the AUTO fields of `in` (built-in heuristic: the fused schedule for
@@ -252,7 +258,8 @@ static DevSystem dev_system(const gmnn_system* s, const gmnn_neighbors* nl) {
 }
 
 struct EfLayout {
-  size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, g = 0, dg = 0, partial = 0, counters = 0, bytes = 0;
+  size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, g = 0, dg = 0, partial = 0, counters = 0,
+         tilerec = 0, bytes = 0;
 };
 
 static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags) {
@@ -274,6 +281,7 @@ static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmn
   L.dg = take(stream_dg_bytes((int)N));
   L.partial = take(8 * (size_t)(kMaxHeads + 9) * sys->n_structs * reduce_chunks(sys));
   L.counters = take(4 * (size_t)sys->n_structs);
+  L.tilerec = take(8 * (size_t)(kMaxHeads + 9) * ((N + 7) / 8));  // fused: one record per tile of >= 8 atoms
   L.bytes = off;
   return L;
 }
@@ -427,7 +435,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   float* virial = (float*)(W + L.virial);
   double* partial = (double*)(W + L.partial);
   int* counters = (int*)(W + L.counters);
-  const int nchunk = reduce_chunks(sys);
+  double* tilerec = (double*)(W + L.tilerec);
   const DevModel dm = dev_model(m);
   const DevSystem ds = dev_system(sys, nl);
   const bool bf16 = (flags & GMNN_PREC_BF16) != 0;
@@ -443,13 +451,16 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   if (st != GMNN_OK) return st;
   const bool fused = P.fused;
   const int lpa = P.lpa;
+  // the fused schedule sums each structure in one block from the tiles'
+  // records; the split one from per-atom values in chunks of kReduceChunk
+  const int nchunk = fused ? 1 : reduce_chunks(sys);
   const int nb_gather = (N + kPairThreads / lpa - 1) / (kPairThreads / lpa);
   const int64_t gstride = nl->capacity;
   const int nh = var ? m->n_heads : 1;
   if (N > 0) {
     if (fused) {
       mark(0);
-      st = launch_tile(true, false, P.ta, dm, ds, bf16, nullptr, atomic_e, nullptr, gpair, virial, gstride, s);
+      st = launch_tile(true, false, P.ta, dm, ds, bf16, nullptr, atomic_e, nullptr, gpair, virial, gstride, tilerec, s);
       if (st != GMNN_OK) return st;
       mark(1);
       mark(2);
@@ -471,7 +482,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
       if (P.stream)
         st = launch_stream(dm, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s);
       else
-        st = launch_tile(false, var, 16, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, s);
+        st = launch_tile(false, var, 16, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, nullptr, s);
       if (st != GMNN_OK) return st;
       mark(3);
       mark(4);
@@ -493,7 +504,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
 #define FINISH(LPA, VAR)                                                                                       \
   hipLaunchKernelGGL((finish<LPA, VAR>), fgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial, \
                      want_stress, nbg, gstride, nchunk, partial, counters, out->forces, out->force_var, out->energy, \
-                     out->energy_var, out->stress)
+                     out->energy_var, out->stress, fused ? tilerec : nullptr, fused ? P.ta : 0)
   if (lpa == 64) {
     if (var) FINISH(64, true);
     else FINISH(64, false);

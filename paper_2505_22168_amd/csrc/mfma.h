@@ -181,7 +181,8 @@ struct NetShape {
 
 // Network forward for the TM rows of a tile (all NW waves):
 //   z1 = G W1 + b1, h1 = swish(z1); z2 = h1 W2 + b2, h2 = swish(z2);
-//   y_m = h2 . W3[:,m] + b3[m], E_m = sigma y_m + mu  (written for rows < n_rows)
+//   y_m = h2 . W3[:,m] + b3[m], E_m = sigma y_m + mu  (written for rows < n_rows,
+//   also to sEa[row][m] in LDS when sEa is not null)
 // sG: invariants (read).  sH: h1 out.  swish'(z1) is returned in dsw1 (the
 // backward product hands each wave exactly these output fragments again).
 // MEAN: delta2 = swish'(z2) sigma mean_m W3[:,m] -> sD2 (the head-mean
@@ -190,7 +191,7 @@ struct NetShape {
 template <int TM, int HP, bool BF16, int NW, bool MEAN, int DEPTH>
 __device__ __forceinline__ void network_forward(const DevModel& m, const void* sG, void* sH, void* sD2, float* sDsw2,
                                        float* sEp, const float* sScale, const float* sShift, int row0, int n_rows,
-                                       float* __restrict__ atomic_e,
+                                       float* __restrict__ atomic_e, float* sEa,
                                        floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW],
                                        BRing<BF16, NetShape<TM, HP, NW>::TPW, DEPTH>& ring) {
   using St = NetStrides<HP, BF16>;
@@ -282,7 +283,9 @@ __device__ __forceinline__ void network_forward(const DevModel& m, const void* s
 #pragma unroll
       for (int ww = 0; ww < NW; ++ww)
         if (ww % MB == a / 16) y += sEp[(ww * 16 + a % 16) * kMaxHeads + hm];
-      atomic_e[(int64_t)(row0 + a) * M + hm] = sScale[a] * y + sShift[a];
+      const float e = sScale[a] * y + sShift[a];
+      atomic_e[(int64_t)(row0 + a) * M + hm] = e;
+      if (sEa) sEa[a * M + hm] = e;
     }
   }
 }

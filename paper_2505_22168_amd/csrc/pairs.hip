@@ -95,6 +95,163 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
 // the last nb_gather blocks: force gather, LPA lanes per atom; with VAR, gpair
 // holds one gradient set per head ([M][gstride][3]) and the kernel writes the
 // mean force and the per-atom force variance (1/M) sum_m |F^m - Fbar|^2
+// float4 q of x (elements 4q .. 4q+3) with the elements outside [e0, e1)
+// read as zero; the float4 that ends past the array (end elements), or any
+// float4 of an array that is not 16-byte aligned, is read element by element
+__device__ inline float4 load4_range(const float* __restrict__ x, int64_t q, int64_t e0, int64_t e1, int64_t end,
+                                     bool on, bool aligned) {
+  const int64_t i = 4 * q;
+  float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (!on || i + 4 <= e0 || i >= e1) return v;
+  if (aligned && i + 4 <= end) {
+    v = *(const float4*)(x + i);
+  } else {
+    if (i < end) v.x = x[i];
+    if (i + 1 < end) v.y = x[i + 1];
+    if (i + 2 < end) v.z = x[i + 2];
+    if (i + 3 < end) v.w = x[i + 3];
+  }
+  if (i < e0 || i + 4 > e1) {
+    v.x = (i >= e0 && i < e1) ? v.x : 0.0f;
+    v.y = (i + 1 >= e0 && i + 1 < e1) ? v.y : 0.0f;
+    v.z = (i + 2 >= e0 && i + 2 < e1) ? v.z : 0.0f;
+    v.w = (i + 3 >= e0 && i + 3 < e1) ? v.w : 0.0f;
+  }
+  return v;
+}
+
+// Per-structure sums of atom rows [a0, a1): vals[h] = sum of the atomic
+// energies of head h < M, vals[kMaxHeads + k] = sum of the virial entries k
+// (want_stress), other entries 0.  All threads of the block take part.
+//
+// From per-atom values: the energies ([n][M]) and virials ([n][9]) are two
+// flat runs of floats read as float4; thread t takes every T-th float4 from
+// t on, T a multiple of the column count C, so each of its four components
+// always falls in the same column, and issues its loads of both runs
+// kVec at a time before adding; the 4T partials of a run then meet in a
+// fixed-order tree in LDS (fan-in kFan per level).
+__device__ inline void structure_sums_atoms(int M, int want_stress, int64_t a0, int64_t a1, int n_atoms,
+                                            const float* __restrict__ atomic_e, const float* __restrict__ virial,
+                                            double* vals) {
+  constexpr int kVec = 4, kFan = 8, kLvl = 4 * kPairBlock / kFan + kMaxHeads;
+  __shared__ double lvl0[2][4 * kPairBlock];
+  __shared__ double lvl[2][2][kLvl];
+  const int t = threadIdx.x;
+  const int CE = M, CV = 9;
+  const int TE = (kPairBlock / CE) * CE, TV = (kPairBlock / CV) * CV;
+  const int64_t e0 = a0 * CE, e1 = a1 * CE, v0 = a0 * CV, v1 = want_stress ? a1 * CV : v0;
+  const int64_t qe = e0 >> 2, qv = v0 >> 2;
+  const int64_t endE = (int64_t)n_atoms * CE, endV = (int64_t)n_atoms * CV;
+  const bool alE = ((uintptr_t)atomic_e & 15) == 0, alV = ((uintptr_t)virial & 15) == 0;
+  double sE[4] = {0.0, 0.0, 0.0, 0.0}, sV[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = 0; 4 * (qe + k0 * TE) < e1 || 4 * (qv + k0 * TV) < v1; k0 += kVec) {
+    float4 xe[kVec], xv[kVec];
+#pragma unroll
+    for (int u = 0; u < kVec; ++u) {
+      xe[u] = load4_range(atomic_e, qe + t + (k0 + u) * TE, e0, e1, endE, t < TE, alE);
+      xv[u] = load4_range(virial, qv + t + (k0 + u) * TV, v0, v1, endV, t < TV, alV);
+    }
+#pragma unroll
+    for (int u = 0; u < kVec; ++u) {
+      sE[0] += (double)xe[u].x; sE[1] += (double)xe[u].y; sE[2] += (double)xe[u].z; sE[3] += (double)xe[u].w;
+      sV[0] += (double)xv[u].x; sV[1] += (double)xv[u].y; sV[2] += (double)xv[u].z; sV[3] += (double)xv[u].w;
+    }
+  }
+  // partial idx = 4t + c4 sums elements of column (4 q + idx) % C: the rows
+  // j = idx / C of a [4T / C][C] table whose column r is (4 q + r) % C
+#pragma unroll
+  for (int c4 = 0; c4 < 4; ++c4) {
+    lvl0[0][4 * t + c4] = sE[c4];
+    lvl0[1][4 * t + c4] = sV[c4];
+  }
+  int rowsE = 4 * TE / CE, rowsV = 4 * TV / CV, cur = -1;
+  while (rowsE > 1 || rowsV > 1) {  // uniform
+    __syncthreads();
+    const double* inE = cur < 0 ? lvl0[0] : lvl[cur][0];
+    const double* inV = cur < 0 ? lvl0[1] : lvl[cur][1];
+    const int nx = cur < 0 ? 0 : cur ^ 1;
+    const int nE = (rowsE + kFan - 1) / kFan, nV = (rowsV + kFan - 1) / kFan;
+    if (t < nE * CE) {
+      const int g = t / CE, r = t % CE;
+      double x = 0.0;
+      for (int j = g * kFan; j < min(rowsE, g * kFan + kFan); ++j) x += inE[j * CE + r];
+      lvl[nx][0][g * CE + r] = x;
+    }
+    if (t < nV * CV) {
+      const int g = t / CV, r = t % CV;
+      double x = 0.0;
+      for (int j = g * kFan; j < min(rowsV, g * kFan + kFan); ++j) x += inV[j * CV + r];
+      lvl[nx][1][g * CV + r] = x;
+    }
+    rowsE = nE;
+    rowsV = nV;
+    cur = nx;
+  }
+  __syncthreads();
+  if (t < kMaxHeads + 9) {
+    const double* outE = cur < 0 ? lvl0[0] : lvl[cur][0];
+    const double* outV = cur < 0 ? lvl0[1] : lvl[cur][1];
+    double x = 0.0;
+    if (t < CE) x = outE[((t - (int)((4 * qe) % CE)) % CE + CE) % CE];
+    else if (t >= kMaxHeads && want_stress) x = outV[((t - kMaxHeads - (int)((4 * qv) % CV)) % CV + CV) % CV];
+    vals[t] = x;
+  }
+}
+
+// From the fused tile's records: tile k (atom rows [k TA, k TA + TA)) left
+// in rec[k][kMaxHeads + 9] the FP64 sums of its atoms' energies and virials.
+// Rows [a0, a1) = head rows before the first whole tile, the whole tiles,
+// tail rows after the last; head and tail rows are read per atom.  Column c
+// < C = M (+ 9 with stress) is summed by kG = kPairBlock / C thread groups,
+// group g taking every kG-th head row, tile and tail row from g on (kVec
+// record loads in flight), then the groups in order.
+__device__ inline void structure_sums_tiled(int M, int want_stress, int64_t a0, int64_t a1, int TA,
+                                            const float* __restrict__ atomic_e, const float* __restrict__ virial,
+                                            const double* __restrict__ rec, double* vals) {
+  constexpr int kVec = 8, NR = kMaxHeads + 9;
+  __shared__ double grp[kPairBlock];
+  const int t = threadIdx.x;
+  const int C = M + (want_stress ? 9 : 0);
+  const int G = kPairBlock / C;
+  int64_t k0 = (a0 + TA - 1) / TA, k1 = a1 / TA;
+  int64_t h1 = a1, t0 = a1;  // head rows [a0, h1), tiles [k0, k1), tail rows [t0, a1)
+  if (k0 < k1) {
+    h1 = k0 * TA;
+    t0 = k1 * TA;
+  } else {
+    k0 = k1 = 0;
+  }
+  if (t < G * C) {
+    const int c = t % C, g = t / C;
+    const int rc = c < M ? c : kMaxHeads + (c - M);  // record column
+    auto row_value = [&](int64_t a) -> double {
+      return c < M ? (double)atomic_e[a * M + c] : (double)virial[a * 9 + (c - M)];
+    };
+    double x = 0.0;
+    for (int64_t a = a0 + g; a < h1; a += G) x += row_value(a);
+    for (int64_t k = k0 + g; k < k1; k += (int64_t)kVec * G) {
+      double y[kVec];
+#pragma unroll
+      for (int u = 0; u < kVec; ++u) {
+        const int64_t kk = k + (int64_t)u * G;
+        y[u] = kk < k1 ? rec[kk * NR + rc] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kVec; ++u) x += y[u];
+    }
+    for (int64_t a = t0 + g; a < a1; a += G) x += row_value(a);
+    grp[g * C + c] = x;
+  }
+  __syncthreads();
+  if (t < kMaxHeads + 9) {
+    const int c = t < kMaxHeads ? t : (want_stress ? M + (t - kMaxHeads) : C);
+    double x = 0.0;
+    if ((t < kMaxHeads && t < M) || (t >= kMaxHeads && want_stress))
+      for (int g = 0; g < G; ++g) x += grp[g * C + c];
+    vals[t] = x;
+  }
+}
+
 template <int LPA, bool VAR>
 __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const float* __restrict__ gpair,
                                                      const float* __restrict__ atomic_e,
@@ -102,7 +259,8 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
                                                      int64_t gstride, int nchunk, double* __restrict__ partial,
                                                      int* __restrict__ counters, float* __restrict__ forces,
                                                      float* __restrict__ force_var, double* __restrict__ energy,
-                                                     double* __restrict__ energy_var, double* __restrict__ stress) {
+                                                     double* __restrict__ energy_var, double* __restrict__ stress,
+                                                     const double* __restrict__ tile_part, int tile_atoms) {
   const int n_red = (int)gridDim.x - nb_gather;
   if ((int)blockIdx.x >= n_red) {
     const int q = threadIdx.x & (LPA - 1);
@@ -174,10 +332,9 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   // ---- per-structure FP64 sums: structure b = rb / nchunk, atom chunk
   // rb % nchunk; with nchunk > 1 the chunk partials go to `partial` and the
   // last chunk block of the structure (arrival counter) adds them in chunk
-  // order, so the result does not depend on block scheduling
-  constexpr int NW = kPairBlock / 64;
+  // order, so the result does not depend on block scheduling.  Every sum
+  // below has a fixed order.
   constexpr int NV = kMaxHeads + 9;
-  __shared__ double part[NW][NV];
   __shared__ double vals[NV];
   __shared__ int last;
   const int rb = blockIdx.x;
@@ -185,7 +342,7 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
   const int64_t s0 = sys.atom_ptr[b], s1 = sys.atom_ptr[b + 1];
   const int64_t csz = (s1 - s0 + nchunk - 1) / nchunk;
   const int64_t a0 = s0 + chunk * csz;
-  const int64_t a1 = min(s1, a0 + csz);
+  const int64_t a1 = max(a0, min(s1, a0 + csz));
   // the cell (for the stress) is read now, its latency hidden by the sums
   double cell_det = 1.0;
   if (want_stress && threadIdx.x < 9) {
@@ -193,38 +350,11 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
     cell_det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) +
                h[2] * (h[3] * h[7] - h[4] * h[6]);
   }
-  double accE[kMaxHeads], accV[9];
-#pragma unroll
-  for (int v = 0; v < kMaxHeads; ++v) accE[v] = 0.0;
-#pragma unroll
-  for (int v = 0; v < 9; ++v) accV[v] = 0.0;
-#pragma unroll 4
-  for (int64_t a = a0 + threadIdx.x; a < a1; a += kPairBlock) {
-#pragma unroll
-    for (int v = 0; v < kMaxHeads; ++v)
-      if (v < M) accE[v] += (double)atomic_e[a * M + v];
-    if (want_stress) {
-#pragma unroll
-      for (int v = 0; v < 9; ++v) accV[v] += (double)virial[a * 9 + v];
-    }
-  }
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    if (v < kMaxHeads ? v >= M : !want_stress) continue;  // uniform: unused heads / no stress
-    double x = v < kMaxHeads ? accE[v] : accV[v - kMaxHeads];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (l == 0) part[w][v] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double x = 0.0;
-    const int v = threadIdx.x;
-    if (v < kMaxHeads ? v < M : want_stress != 0)
-#pragma unroll
-      for (int ww = 0; ww < NW; ++ww) x += part[ww][v];
-    vals[v] = x;
+  const int t = threadIdx.x;
+  if (tile_part) {
+    structure_sums_tiled(M, want_stress, a0, a1, tile_atoms, atomic_e, virial, tile_part, vals);
+  } else {
+    structure_sums_atoms(M, want_stress, a0, a1, sys.n_atoms, atomic_e, virial, vals);
   }
   if (nchunk > 1) {
     __syncthreads();
@@ -265,7 +395,8 @@ template __global__ void pair_backward<32>(DevModel, DevSystem, const float*, fl
 template __global__ void pair_backward<64>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
 #define FIN(LPA, VAR)                                                                                         \
   template __global__ void finish<LPA, VAR>(int, DevSystem, const float*, const float*, const float*, int, int, \
-                                            int64_t, int, double*, int*, float*, float*, double*, double*, double*);
+                                            int64_t, int, double*, int*, float*, float*, double*, double*, double*, \
+                                            const double*, int);
 FIN(8, false) FIN(16, false) FIN(32, false) FIN(64, false) FIN(8, true) FIN(16, true) FIN(32, true) FIN(64, true)
 #undef FIN
 

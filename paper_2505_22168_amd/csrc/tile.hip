@@ -58,16 +58,20 @@ struct TileLds {
   // fused: per-atom context and first pair group of each of the LPA lanes
   static constexpr size_t pctx = beta + (FUSED ? al(4 * (size_t)kFusedMaxSpecies * kFusedMaxSpecies * kS * kMaxBasis) : 0);
   static constexpr size_t ppv = pctx + (FUSED ? al(sizeof(AtomCtx) * (size_t)TA) : 0);
-  static constexpr size_t bytes = ppv + (FUSED ? al(sizeof(float4) * (size_t)TA * LPA * kPairUnroll) : 0);
+  static constexpr size_t ea = ppv + (FUSED ? al(sizeof(float4) * (size_t)TA * LPA * kPairUnroll) : 0);
+  static constexpr size_t bytes = ea + (FUSED ? al(4 * (size_t)TM * kMaxHeads) : 0);
 };
 
 // psibar_out: [nh][N][100] (unfused); gpair: [nh][gstride][3] (fused);
-// nh = n_heads with PERHEAD (one backward per head), else 1 (head mean)
+// nh = n_heads with PERHEAD (one backward per head), else 1 (head mean).
+// tile_rec (fused, may be null): [tile][kMaxHeads + 9] FP64 sums over the
+// tile's atoms of the energies (heads 0 .. M-1) and of the virial entries,
+// each in atom order, for the per-structure sums
 template <int HP, bool BF16, bool FUSED, bool PERHEAD, int TA>
 __global__ void __launch_bounds__(kTileThreads)
     tile_kernel(DevModel m, DevSystem sys, const float* __restrict__ psi_in, float* __restrict__ atomic_e,
                 float* __restrict__ psibar_out, float* __restrict__ gpair, float* __restrict__ virial,
-                int64_t gstride) {
+                int64_t gstride, double* __restrict__ tile_rec) {
   using L = TileLds<HP, BF16, FUSED, PERHEAD, TA>;
   using Sh = NetShape<kTM, HP, kTileWaves>;
   constexpr int TM = kTM;
@@ -91,6 +95,7 @@ __global__ void __launch_bounds__(kTileThreads)
   float* s_beta = (float*)(lds + L::beta);
   AtomCtx* sCtx = (AtomCtx*)(lds + L::pctx);
   float4* sPv = (float4*)(lds + L::ppv);
+  float* sEa = FUSED ? (float*)(lds + L::ea) : nullptr;
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
@@ -183,7 +188,7 @@ __global__ void __launch_bounds__(kTileThreads)
   // ---- network forward ---------------------------------------------------------
   floatx4 dsw1[Sh::TPW];
   network_forward<TM, HP, BF16, kTileWaves, !PERHEAD, kDepth>(m, sG, sH, sD2, sDsw2, sEp, sScale, sShift, row0, n_rows,
-                                                       atomic_e, dsw1, ring);
+                                                       atomic_e, sEa, dsw1, ring);
   constexpr int LDGB = NetStrides<HP, BF16>::GB;
   for (int hm = 0; hm < nh; ++hm) {
     // ---- network backward (head mean, or head hm) ------------------------------
@@ -236,13 +241,22 @@ __global__ void __launch_bounds__(kTileThreads)
   if (FUSED) {
     const float inv = 1.0f / (float)nh;
     for (int t = tid; t < n_rows * 9; t += kTileThreads) virial[(int64_t)row0 * 9 + t] = sVir[t] * inv;
+    if (tile_rec && tid < kMaxHeads + 9) {
+      double x = 0.0;
+      if (tid < m.M)
+        for (int a = 0; a < n_rows; ++a) x += (double)sEa[a * m.M + tid];
+      else if (tid >= kMaxHeads)
+        for (int a = 0; a < n_rows; ++a) x += (double)(sVir[a * 9 + tid - kMaxHeads] * inv);
+      tile_rec[(int64_t)(row0 / TA) * (kMaxHeads + 9) + tid] = x;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 template <int HP, bool BF16, bool FUSED, bool PERHEAD, int TA>
 static gmnn_status launch_tile_t(const DevModel& m, const DevSystem& sys, const float* psi, float* atomic_e,
-                                 float* psibar, float* gpair, float* virial, int64_t gstride, hipStream_t stream) {
+                                 float* psibar, float* gpair, float* virial, int64_t gstride, double* tile_rec,
+                                 hipStream_t stream) {
   using L = TileLds<HP, BF16, FUSED, PERHEAD, TA>;
   if (L::bytes > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
   auto k = tile_kernel<HP, BF16, FUSED, PERHEAD, TA>;
@@ -255,7 +269,7 @@ static gmnn_status launch_tile_t(const DevModel& m, const DevSystem& sys, const 
   const int grid = (sys.n_atoms + TA - 1) / TA;
   if (grid == 0) return GMNN_OK;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kTileThreads), L::bytes, stream, m, sys, psi, atomic_e, psibar, gpair,
-                     virial, gstride);
+                     virial, gstride, tile_rec);
   return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
 }
 
@@ -281,15 +295,15 @@ bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead) {
   return !perhead && n_species <= kFusedMaxSpecies && tile_lds_bytes(hp, bf16, true, false) <= 160 * 1024;
 }
 
-// fused: moments + readout + pair backward in one launch (gpair, virial out)
-// on tiles of tile_atoms (8 or 16) atoms; otherwise the readout alone (psi in,
-// psibar out) on 16-atom tiles
+// fused: moments + readout + pair backward in one launch (gpair, virial,
+// tile records out) on tiles of tile_atoms (8 or 16) atoms; otherwise the
+// readout alone (psi in, psibar out) on 16-atom tiles
 gmnn_status launch_tile(bool fused, bool perhead, int tile_atoms, const DevModel& m, const DevSystem& sys, bool bf16,
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
-                        int64_t gstride, hipStream_t stream) {
+                        int64_t gstride, double* tile_rec, hipStream_t stream) {
   if (fused && !tile_fused_supported(m.n_species, m.HP1, bf16, perhead)) return GMNN_ERR_UNSUPPORTED;
   if (fused && tile_atoms != 8 && tile_atoms != 16) return GMNN_ERR_INVALID_ARG;
-#define ARGS m, sys, psi, atomic_e, psibar, gpair, virial, gstride, stream
+#define ARGS m, sys, psi, atomic_e, psibar, gpair, virial, gstride, tile_rec, stream
 #define FUSED_CASE(HP, BF) \
   return tile_atoms == 8 ? launch_tile_t<HP, BF, true, false, 8>(ARGS) : launch_tile_t<HP, BF, true, false, 16>(ARGS);
 #define CASE4(HP, BF) \
