@@ -339,12 +339,29 @@ __device__ inline void contract_backward_a(const float* __restrict__ P, const fl
 //   Psi3 task (a, i, b):  the 15 entries (x, i, b, c), sharing the Psi2/Psi3
 //                         entries of every channel across x
 //   Psi01 task (a, x):    Psi0 and the 3 Psi1 entries of channel x
-template <int TM, int NT>
+// KS = 2 (a block with twice as many threads as tasks) splits every task's
+// sum into two halves run by two threads: the first half's partial gradient
+// goes to Pb, the second's to Pb2 (every entry written in both), and
+// fold_packed adds the two.  The halves: Psi2 = families 3, 5-7 of p < 11 |
+// families 5-7 of p >= 11 and 8; Psi3 = channels s' < 3 | s' >= 3; Psi01 =
+// families 0, 2, 6 | family 8.
+template <int TM, int NT, int KS = 1>
 __device__ inline void contract_backward_b(const float* __restrict__ P, const float* __restrict__ Gb, int ldgb,
-                                           const float* __restrict__ I, float* __restrict__ Pb, const Tables& tb) {
+                                           const float* __restrict__ I, float* __restrict__ Pb, const Tables& tb,
+                                           float* __restrict__ Pb2 = nullptr) {
   constexpr int ISTR = IS;
   constexpr int n2 = TM * 15, n3 = TM * 9, n1 = TM * 5;
-  for (int t = threadIdx.x; t < n2 + n3 + n1; t += NT) {
+  // with KS = 2 each half's tasks start on a wave boundary, so a wave runs
+  // one half only
+  constexpr int NTASK = n2 + n3 + n1, NHALF = KS == 1 ? NTASK : (NTASK + 63) / 64 * 64;
+  static_assert(KS == 1 || KS == 2, "one or two halves");
+  constexpr int kPSplit = 11;
+  for (int tt = threadIdx.x; tt < KS * NHALF; tt += NT) {
+    const int half = KS == 1 ? 0 : tt / NHALF;
+    const int t = KS == 1 ? tt : tt % NHALF;
+    if (t >= NTASK) continue;
+    const bool h0 = KS == 1 || half == 0, h1 = KS == 1 || half == 1;
+    float* __restrict__ out = half ? Pb2 : Pb;
     if (t < n2) {
       const int a = t % TM, e = t / TM;
       const int x = e / 3, i = e % 3;
@@ -356,14 +373,17 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
         for (int j = 0; j < 3; ++j) p1[s][j] = GM_P1(a, s, j);
       }
       float v[3] = {0.0f, 0.0f, 0.0f};
+      if (h0) {
 #pragma unroll
-      for (int sp = 0; sp < kS; ++sp) {
-        const float g = (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam3 + pair_idx(x, sp));
+        for (int sp = 0; sp < kS; ++sp) {
+          const float g = (x == sp ? 2.0f : 1.0f) * GM_GB(a, kFam3 + pair_idx(x, sp));
 #pragma unroll
-        for (int j = 0; j < 3; ++j) v[j] += g * GM_P2(a, sp, 3 * i + j);
+          for (int j = 0; j < 3; ++j) v[j] += g * GM_P2(a, sp, 3 * i + j);
+        }
       }
 #pragma unroll
       for (int p = 0; p < 15; ++p) {
+        if (!(p < kPSplit ? h0 : h1)) continue;
         const int s1 = pair_first(p), s2 = pair_second(p);
         const float g5 = tb.c5[x * 15 + p] * GM_GB(a, kFam5 + tb.tri_xp[x * 15 + p]);
         const float g6 = GM_GB(a, kFam6 + p * 5 + x) * p1i[s1];
@@ -372,14 +392,16 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
         for (int j = 0; j < 3; ++j)
           v[j] += g5 * GM_I(a, kM5 + p * 9 + 3 * i + j) + g7 * GM_I(a, kT7 + p * 9 + 3 * i + j) + g6 * p1[s2][j];
       }
+      if (h1) {
 #pragma unroll
-      for (int s12 = 0; s12 < 25; ++s12) {
-        const float g8 = GM_GB(a, kFam8 + s12 * 5 + x);
+        for (int s12 = 0; s12 < 25; ++s12) {
+          const float g8 = GM_GB(a, kFam8 + s12 * 5 + x);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) v[j] += g8 * GM_I(a, kU8 + s12 * 9 + 3 * i + j);
+          for (int j = 0; j < 3; ++j) v[j] += g8 * GM_I(a, kU8 + s12 * 9 + 3 * i + j);
+        }
       }
 #pragma unroll
-      for (int j = 0; j < 3; ++j) Pb[a * PS + x * kFull + 4 + 3 * i + j] = v[j];
+      for (int j = 0; j < 3; ++j) out[a * PS + x * kFull + 4 + 3 * i + j] = v[j];
     } else if (t < n2 + n3) {
       const int u = t - n2;
       const int a = u % TM, e = u / TM;
@@ -389,6 +411,7 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
       for (int x = 0; x < kS; ++x) v[x][0] = v[x][1] = v[x][2] = 0.0f;
 #pragma unroll
       for (int sp = 0; sp < kS; ++sp) {
+        if (!(sp < 3 ? h0 : h1)) continue;
         float p3i[3], p3d[3][3], p2b[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -412,59 +435,71 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
 #pragma unroll
       for (int x = 0; x < kS; ++x)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Pb[a * PS + x * kFull + 13 + i * 9 + b * 3 + c] = v[x][c];
+        for (int c = 0; c < 3; ++c) out[a * PS + x * kFull + 13 + i * 9 + b * 3 + c] = v[x][c];
     } else {
       const int u = t - n2 - n3;
       const int a = u % TM, x = u / TM;
       float v[3] = {0.0f, 0.0f, 0.0f};
+      if (h0) {
 #pragma unroll
-      for (int sp = 0; sp < kS; ++sp) {
-        const int p = pair_idx(x, sp);
-        const float f2 = (x == sp) ? 2.0f : 1.0f;
-        const float g2 = f2 * GM_GB(a, kFam2 + p);
+        for (int sp = 0; sp < kS; ++sp) {
+          const int p = pair_idx(x, sp);
+          const float f2 = (x == sp) ? 2.0f : 1.0f;
+          const float g2 = f2 * GM_GB(a, kFam2 + p);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) v[k] += g2 * GM_P1(a, sp, k);
+          for (int k = 0; k < 3; ++k) v[k] += g2 * GM_P1(a, sp, k);
 #pragma unroll
-        for (int s3 = 0; s3 < kS; ++s3) {
-          const float g6 = f2 * GM_GB(a, kFam6 + p * 5 + s3);
+          for (int s3 = 0; s3 < kS; ++s3) {
+            const float g6 = f2 * GM_GB(a, kFam6 + p * 5 + s3);
 #pragma unroll
-          for (int k = 0; k < 3; ++k) v[k] += g6 * GM_I(a, kV6 + (s3 * 5 + sp) * 3 + k);
+            for (int k = 0; k < 3; ++k) v[k] += g6 * GM_I(a, kV6 + (s3 * 5 + sp) * 3 + k);
+          }
         }
       }
+      if (h1) {
 #pragma unroll
-      for (int s23 = 0; s23 < 25; ++s23) {
-        const float g8 = GM_GB(a, kFam8 + x * 25 + s23);
+        for (int s23 = 0; s23 < 25; ++s23) {
+          const float g8 = GM_GB(a, kFam8 + x * 25 + s23);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) v[k] += g8 * GM_I(a, kV8 + s23 * 3 + k);
+          for (int k = 0; k < 3; ++k) v[k] += g8 * GM_I(a, kV8 + s23 * 3 + k);
+        }
       }
-      Pb[a * PS + x * kFull] = GM_GB(a, x);
+      out[a * PS + x * kFull] = h0 ? GM_GB(a, x) : 0.0f;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) Pb[a * PS + x * kFull + 1 + k] = v[k];
+      for (int k = 0; k < 3; ++k) out[a * PS + x * kFull + 1 + k] = v[k];
     }
   }
 }
 
 // Fold the full-tensor gradient onto the packed components: out(a, k) for
 // k = s*20 + t receives the sum of the full entries packed component t
-// stands for.
-// One task per (atom, channel), compile-time component indices: the 40 full
-// entries of the channel are read once each.
+// stands for, in the table's order.  Each wave takes whole packed
+// components (wave-uniform: its table entries are LDS broadcasts) and its
+// lanes the (atom, channel) pairs.  With Pb2 (the second half of a split
+// contract_backward_b) every entry is Pb + Pb2.
 template <int TM, int NT, typename Out>
-__device__ inline void fold_packed(const float* __restrict__ Pb, const Tables& tb, Out out) {
-  constexpr unsigned char mult[kPacked] = {1, 1, 1, 1, 1, 2, 2, 1, 2, 1, 1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
-  constexpr unsigned char full[kPacked][6] = {
-      {0}, {1}, {2}, {3}, {4}, {5, 7}, {6, 10}, {8}, {9, 11}, {12},
-      {13}, {14, 16, 22}, {15, 19, 31}, {17, 23, 25}, {18, 20, 24, 28, 32, 34}, {21, 33, 37},
-      {26}, {27, 29, 35}, {30, 36, 38}, {39}};
-  for (int t = threadIdx.x; t < TM * kS; t += NT) {
-    const int a = t % TM, s = t / TM;
-    const float* f = Pb + a * PS + s * kFull;
+__device__ inline void fold_packed(const float* __restrict__ Pb, const Tables& tb, Out out,
+                                   const float* __restrict__ Pb2 = nullptr) {
+  constexpr int NWV = NT / 64;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  for (int c = w; c < kPacked; c += NWV) {
+    const int n = tb.packed_mult[c];
+    int e[6];
 #pragma unroll
-    for (int c = 0; c < kPacked; ++c) {
-      float v = f[full[c][0]];
+    for (int q = 0; q < 6; ++q) e[q] = tb.packed_full[c][q];
+    for (int t = l; t < TM * kS; t += 64) {
+      const int a = t % TM, s = t / TM;
+      const float* f = Pb + a * PS + s * kFull;
+      const float* f2 = Pb2 ? Pb2 + a * PS + s * kFull : nullptr;
+      float x[6];
 #pragma unroll
-      for (int k = 1; k < 6; ++k)
-        if (k < mult[c]) v += f[full[c][k]];
+      for (int q = 0; q < 6; ++q) {
+        if (q < n) x[q] = f2 ? f[e[q]] + f2[e[q]] : f[e[q]];
+      }
+      float v = x[0];
+#pragma unroll
+      for (int q = 1; q < 6; ++q)
+        if (q < n) v += x[q];
       out(a, s * kPacked + c, v);
     }
   }

@@ -274,17 +274,20 @@ struct PairCache {
 
 // ---------------------------------------------------------------------------
 // moment partial sums of lane q of an atom: pairs p0+q, p0+q+LPA, ...
-// v[s*20 + t] += R_s(r) mono_t(u)   (v must be zeroed by the caller)
+// v[s*20 + t] += R_s(r) mono_t(u)   (v must be zeroed by the caller).
+// atom_moments_from takes the atom's context and the lane's first pair group
+// already loaded (a caller can issue those loads early); atom_moments loads
+// them itself.
 template <int LPA>
-__device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta, int i,
-                                    int q, float (&v)[128], PairCache cache = PairCache{nullptr, nullptr}) {
-  AtomCtx c;
-  load_atom(sys, i, c);
+__device__ inline void atom_moments_from(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta,
+                                         const AtomCtx& c, int q, const PairGroup& first, float (&v)[128],
+                                         PairCache cache = PairCache{nullptr, nullptr}) {
   if (cache.ctx && q == 0) *cache.ctx = c;
   const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
   for (int64_t p = c.p0 + q; p < c.p1; p += kPairUnroll * LPA) {
     PairGroup g;
-    fetch_pairs<LPA>(sys, c, p, g);
+    if (p == c.p0 + q) g = first;
+    else fetch_pairs<LPA>(sys, c, p, g);
     if (cache.pv && p == c.p0 + q) {
 #pragma unroll
       for (int u = 0; u < kPairUnroll; ++u)
@@ -307,6 +310,16 @@ __device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, con
         for (int t = 0; t < kPacked; ++t) v[s * kPacked + t] += rad.R[s] * mo[t];
     }
   }
+}
+
+template <int LPA>
+__device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta, int i,
+                                    int q, float (&v)[128], PairCache cache = PairCache{nullptr, nullptr}) {
+  AtomCtx c;
+  load_atom(sys, i, c);
+  PairGroup g;
+  fetch_pairs<LPA>(sys, c, c.p0 + q, g);
+  atom_moments_from<LPA>(m, sys, s_beta, c, q, g, v, cache);
 }
 
 // dE/dd_p for every pair of lane q of atom i, given pb = dE_i/dPsi_i (packed

@@ -103,6 +103,17 @@ __global__ void __launch_bounds__(kTileThreads)
   const int n_rows = min(TA, sys.n_atoms - row0);
   const int nh = PERHEAD ? m.M : 1;
 
+  // fused: this lane's atom context and first pair group are requested
+  // before the tables and beta are staged, so their memory round trips overlap
+  static_assert(TA * LPA == kTileThreads && (LPA == 32 || LPA == 64), "whole waves per atom pair");
+  const int fa = LPA == 32 ? w + kTileWaves * (l >> 5) : w;  // this lane's atom
+  const int fq = l & (LPA - 1);
+  AtomCtx actx{};
+  PairGroup g0{};
+  if (FUSED && fa < n_rows) {
+    load_atom(sys, row0 + fa, actx);
+    fetch_pairs<LPA>(sys, actx, actx.p0 + fq, g0);
+  }
   load_tables(&tb);
   for (int t = tid; t < TA * 9; t += kTileThreads) sVir[t] = 0.0f;
   if (TA < TM) {
@@ -117,15 +128,12 @@ __global__ void __launch_bounds__(kTileThreads)
   // ---- moments -> full tensors in LDS ------------------------------------
   // fused pair stages: each wave runs two atoms at once with 32 lanes each
   // (TA = 16), or one atom with all 64 lanes (TA = 8)
-  static_assert(TA * LPA == kTileThreads && (LPA == 32 || LPA == 64), "whole waves per atom pair");
-  const int fa = LPA == 32 ? w + kTileWaves * (l >> 5) : w;  // this lane's atom
-  const int fq = l & (LPA - 1);
   if (FUSED) {
     float v[128];
 #pragma unroll
     for (int k = 0; k < 128; ++k) v[k] = 0.0f;
     if (fa < n_rows)
-      atom_moments<LPA>(m, sys, s_beta, row0 + fa, fq, v, PairCache{sCtx + fa, sPv + fa * LPA * kPairUnroll});
+      atom_moments_from<LPA>(m, sys, s_beta, actx, fq, g0, v, PairCache{sCtx + fa, sPv + fa * LPA * kPairUnroll});
     reduce_scatter_128<LPA>(v, fq);
     constexpr int PER = 128 / LPA;  // values each lane owns after the reduce-scatter
 #pragma unroll
@@ -201,10 +209,16 @@ __global__ void __launch_bounds__(kTileThreads)
     // ---- invariants backward ---------------------------------------------------
     contract_backward_a<TA, kTileThreads>(sPsi, sGb, LDGB, sI, tb);
     __syncthreads();
-    contract_backward_b<TA, kTileThreads>(sPsi, sGb, LDGB, sI, sPb, tb);
+    // an 8-atom tile has threads for both halves of every task; the second
+    // half's gradient lands in the rows of sPb past the tile's atoms
+    constexpr int KS = (TA * 29 * 2 <= kTileThreads) ? 2 : 1;
+    static_assert(KS == 1 || 2 * TA <= TM, "both halves fit the 16-row gradient region");
+    float* sPb2 = KS == 2 ? sPb + TA * PS : nullptr;
+    contract_backward_b<TA, kTileThreads, KS>(sPsi, sGb, LDGB, sI, sPb, tb, sPb2);
     __syncthreads();
     if (FUSED) {
-      fold_packed<TA, kTileThreads>(sPb, tb, [&](int a, int e, float v) { sPsibar[a * (kS * kPacked) + e] = v; });
+      fold_packed<TA, kTileThreads>(
+          sPb, tb, [&](int a, int e, float v) { sPsibar[a * (kS * kPacked) + e] = v; }, sPb2);
       __syncthreads();
       // ---- pair backward -----------------------------------------------------
       float* g_head = gpair + (int64_t)hm * gstride * 3;
@@ -232,9 +246,12 @@ __global__ void __launch_bounds__(kTileThreads)
       __syncthreads();
     } else {
       float* pbo = psibar_out + (int64_t)hm * sys.n_atoms * (kS * kPacked);
-      fold_packed<TA, kTileThreads>(sPb, tb, [&](int a, int e, float v) {
-        if (a < n_rows) pbo[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
-      });
+      fold_packed<TA, kTileThreads>(
+          sPb, tb,
+          [&](int a, int e, float v) {
+            if (a < n_rows) pbo[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+          },
+          sPb2);
       __syncthreads();
     }
   }
