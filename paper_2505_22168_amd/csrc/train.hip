@@ -412,20 +412,29 @@ __global__ void __launch_bounds__(kTrainThreads)
   // ---- invariant backward ---------------------------------------------------------
   const float* Gbar = sGb;
   const float* Gdbar = sGb + 8 * L::LDGB;
+  // 8 atoms leave threads for both halves of every task of the invariant
+  // backward; the second halves go to the G tile, free from here on
+  constexpr int KS = (TA * 29 * 2 <= kTrainThreads) ? 2 : 1;
+  static_assert(KS == 1 || 2 * TA * PS <= 16 * L::LDG, "both second halves fit the G tile");
+  float* sPbS2 = KS == 2 ? sGT : nullptr;
+  float* sPbA2 = KS == 2 ? sGT + TA * PS : nullptr;
   // Psidotbar = B(Psi; Gdotbar)
   contract_forward_a<TA, kTrainThreads, false, false>(sPsi, sI, nullptr, 0, tb);  // intermediates of Psi
   __syncthreads();
   contract_backward_a<TA, kTrainThreads>(sPsi, Gdbar, L::LDGB, sI, tb);
   __syncthreads();
-  contract_backward_b<TA, kTrainThreads>(sPsi, Gdbar, L::LDGB, sI, sPbS, tb);
+  contract_backward_b<TA, kTrainThreads, KS>(sPsi, Gdbar, L::LDGB, sI, sPbS, tb, sPbS2);
   __syncthreads();
-  fold_packed<TA, kTrainThreads>(sPbS, tb, [&](int a, int e, float v) {
-    if (a < n_rows) psidotbar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
-  });
+  fold_packed<TA, kTrainThreads>(
+      sPbS, tb,
+      [&](int a, int e, float v) {
+        if (a < n_rows) psidotbar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+      },
+      sPbS2);
   // Psibar = B(Psi; Gbar) + [B(Psi + t Psidot; Gdotbar) - B(Psi - t Psidot; Gdotbar)] / (2t)
   contract_backward_a<TA, kTrainThreads>(sPsi, Gbar, L::LDGB, sI, tb);
   __syncthreads();
-  contract_backward_b<TA, kTrainThreads>(sPsi, Gbar, L::LDGB, sI, sPbA, tb);
+  contract_backward_b<TA, kTrainThreads, KS>(sPsi, Gbar, L::LDGB, sI, sPbA, tb, sPbA2);
   __syncthreads();
   for (int ev = 0; ev < 2; ++ev) {
     const float sgn = ev == 0 ? 1.0f : -1.0f;
@@ -438,17 +447,21 @@ __global__ void __launch_bounds__(kTrainThreads)
     __syncthreads();
     contract_backward_a<TA, kTrainThreads>(sPt, Gdbar, L::LDGB, sI, tb);
     __syncthreads();
-    contract_backward_b<TA, kTrainThreads>(sPt, Gdbar, L::LDGB, sI, sPbS, tb);
+    contract_backward_b<TA, kTrainThreads, KS>(sPt, Gdbar, L::LDGB, sI, sPbS, tb, sPbS2);
     __syncthreads();
     for (int t = tid; t < TA * kS * kFull; t += kTrainThreads) {
       const int a = t % TA, e = t / TA;
-      sPbA[a * PS + e] += sgn * sPbS[a * PS + e] / (2.0f * sT[a]);
+      const float d = KS == 2 ? sPbS[a * PS + e] + sPbS2[a * PS + e] : sPbS[a * PS + e];
+      sPbA[a * PS + e] += sgn * d / (2.0f * sT[a]);
     }
     __syncthreads();
   }
-  fold_packed<TA, kTrainThreads>(sPbA, tb, [&](int a, int e, float v) {
-    if (a < n_rows) psibar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
-  });
+  fold_packed<TA, kTrainThreads>(
+      sPbA, tb,
+      [&](int a, int e, float v) {
+        if (a < n_rows) psibar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+      },
+      sPbA2);
 }
 
 // ---------------------------------------------------------------------------
