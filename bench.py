@@ -100,10 +100,18 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counted_traffic(workload, stage, precision):
+def plan_tag(plan):
+    """Short name of an execution plan: fused8 / fused16 / split-tile / split-stream."""
+    if plan["schedule"] == 1:
+        return f"fused{plan['tile_atoms']}"
+    return "split-stream" if plan["readout"] == 2 else "split-tile"
+
+
+def counted_traffic(workload, stage, precision, plan):
     """HBM bytes per launch of a stage as counted by rocprofv3 (FETCH_SIZE +
     WRITE_SIZE, scaled by a plain copy) from the summary committed under
-    profiles/, or None when that summary was taken on other kernel sources."""
+    profiles/, or None when that summary was taken on other kernel sources
+    or under another execution plan."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.md")
     try:
         text = open(path).read()
@@ -113,7 +121,7 @@ def counted_traffic(workload, stage, precision):
         return None
     if data.get("source_sha256") != kernel_source_hash():
         return None
-    entry = data.get("stages", {}).get(f"{workload}:{stage}:{precision}")
+    entry = data.get("stages", {}).get(f"{workload}:{stage}:{precision}:{plan_tag(plan)}")
     return None if entry is None else entry["fetch_bytes"] + entry["write_bytes"]
 
 
@@ -517,7 +525,7 @@ def main():
     else:
         achieved, peak, unit = amount / dur_s / 1e12, MFMA_PEAK_TFLOPS["bf16"], "TFLOP/s"
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": counted_traffic(args.workload, dom, "bf16"),
+                "frac": achieved / peak, "traffic": counted_traffic(args.workload, dom, "bf16", plan16),
                 "per_launch": {"amount": amount, "what": "bytes" if bound == "hbm" else "flops",
                                "avg_duration_us": stage_ms[dom] * 1e3,
                                "event_bracket_overhead_us_subtracted": overhead_ms * 1e3}}
