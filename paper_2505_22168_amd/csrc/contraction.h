@@ -473,33 +473,57 @@ __device__ inline void contract_backward_b(const float* __restrict__ P, const fl
 
 // Fold the full-tensor gradient onto the packed components: out(a, k) for
 // k = s*20 + t receives the sum of the full entries packed component t
-// stands for, in the table's order.  Each wave takes whole packed
-// components (wave-uniform: its table entries are LDS broadcasts) and its
-// lanes the (atom, channel) pairs.  With Pb2 (the second half of a split
-// contract_backward_b) every entry is Pb + Pb2.
-template <int TM, int NT, typename Out>
+// stands for, in the table's order.  With Pb2 (the second half of a split
+// contract_backward_b) every entry is Pb + Pb2.  Two item orders:
+//   default        one task per (atom, channel) with compile-time component
+//                  indices: the 40 full entries of the channel are read once
+//   WAVE_UNIFORM   each wave takes whole packed components t (its table
+//                  entries are LDS broadcasts), its lanes the (atom, channel)
+//                  pairs: more, shorter items, for few atoms and two halves
+template <int TM, int NT, typename Out, bool WAVE_UNIFORM = false>
 __device__ inline void fold_packed(const float* __restrict__ Pb, const Tables& tb, Out out,
                                    const float* __restrict__ Pb2 = nullptr) {
-  constexpr int NWV = NT / 64;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
-  for (int c = w; c < kPacked; c += NWV) {
-    const int n = tb.packed_mult[c];
-    int e[6];
+  if (WAVE_UNIFORM) {
+    constexpr int NWV = NT / 64;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+    for (int c = w; c < kPacked; c += NWV) {
+      const int n = tb.packed_mult[c];
+      int e[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) e[q] = tb.packed_full[c][q];
-    for (int t = l; t < TM * kS; t += 64) {
-      const int a = t % TM, s = t / TM;
-      const float* f = Pb + a * PS + s * kFull;
-      const float* f2 = Pb2 ? Pb2 + a * PS + s * kFull : nullptr;
-      float x[6];
+      for (int q = 0; q < 6; ++q) e[q] = tb.packed_full[c][q];
+      for (int t = l; t < TM * kS; t += 64) {
+        const int a = t % TM, s = t / TM;
+        const float* f = Pb + a * PS + s * kFull;
+        const float* f2 = Pb2 ? Pb2 + a * PS + s * kFull : nullptr;
+        float x[6];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        if (q < n) x[q] = f2 ? f[e[q]] + f2[e[q]] : f[e[q]];
+        for (int q = 0; q < 6; ++q)
+          if (q < n) x[q] = f2 ? f[e[q]] + f2[e[q]] : f[e[q]];
+        float v = x[0];
+#pragma unroll
+        for (int q = 1; q < 6; ++q)
+          if (q < n) v += x[q];
+        out(a, s * kPacked + c, v);
       }
-      float v = x[0];
+    }
+    return;
+  }
+  constexpr unsigned char mult[kPacked] = {1, 1, 1, 1, 1, 2, 2, 1, 2, 1, 1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
+  constexpr unsigned char full[kPacked][6] = {
+      {0}, {1}, {2}, {3}, {4}, {5, 7}, {6, 10}, {8}, {9, 11}, {12},
+      {13}, {14, 16, 22}, {15, 19, 31}, {17, 23, 25}, {18, 20, 24, 28, 32, 34}, {21, 33, 37},
+      {26}, {27, 29, 35}, {30, 36, 38}, {39}};
+  for (int t = threadIdx.x; t < TM * kS; t += NT) {
+    const int a = t % TM, s = t / TM;
+    const float* f = Pb + a * PS + s * kFull;
+    const float* f2 = Pb2 ? Pb2 + a * PS + s * kFull : nullptr;
+    auto entry = [&](int e) { return f2 ? f[e] + f2[e] : f[e]; };
 #pragma unroll
-      for (int q = 1; q < 6; ++q)
-        if (q < n) v += x[q];
+    for (int c = 0; c < kPacked; ++c) {
+      float v = entry(full[c][0]);
+#pragma unroll
+      for (int k = 1; k < 6; ++k)
+        if (k < mult[c]) v += entry(full[c][k]);
       out(a, s * kPacked + c, v);
     }
   }

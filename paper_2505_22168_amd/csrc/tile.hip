@@ -217,8 +217,8 @@ __global__ void __launch_bounds__(kTileThreads)
     contract_backward_b<TA, kTileThreads, KS>(sPsi, sGb, LDGB, sI, sPb, tb, sPb2);
     __syncthreads();
     if (FUSED) {
-      fold_packed<TA, kTileThreads>(
-          sPb, tb, [&](int a, int e, float v) { sPsibar[a * (kS * kPacked) + e] = v; }, sPb2);
+      auto to_lds = [&](int a, int e, float v) { sPsibar[a * (kS * kPacked) + e] = v; };
+      fold_packed<TA, kTileThreads, decltype(to_lds), KS == 2>(sPb, tb, to_lds, sPb2);
       __syncthreads();
       // ---- pair backward -----------------------------------------------------
       float* g_head = gpair + (int64_t)hm * gstride * 3;

@@ -425,12 +425,10 @@ __global__ void __launch_bounds__(kTrainThreads)
   __syncthreads();
   contract_backward_b<TA, kTrainThreads, KS>(sPsi, Gdbar, L::LDGB, sI, sPbS, tb, sPbS2);
   __syncthreads();
-  fold_packed<TA, kTrainThreads>(
-      sPbS, tb,
-      [&](int a, int e, float v) {
-        if (a < n_rows) psidotbar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
-      },
-      sPbS2);
+  auto to_psidotbar = [&](int a, int e, float v) {
+    if (a < n_rows) psidotbar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+  };
+  fold_packed<TA, kTrainThreads, decltype(to_psidotbar), KS == 2>(sPbS, tb, to_psidotbar, sPbS2);
   // Psibar = B(Psi; Gbar) + [B(Psi + t Psidot; Gdotbar) - B(Psi - t Psidot; Gdotbar)] / (2t)
   contract_backward_a<TA, kTrainThreads>(sPsi, Gbar, L::LDGB, sI, tb);
   __syncthreads();
@@ -456,12 +454,10 @@ __global__ void __launch_bounds__(kTrainThreads)
     }
     __syncthreads();
   }
-  fold_packed<TA, kTrainThreads>(
-      sPbA, tb,
-      [&](int a, int e, float v) {
-        if (a < n_rows) psibar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
-      },
-      sPbA2);
+  auto to_psibar = [&](int a, int e, float v) {
+    if (a < n_rows) psibar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
+  };
+  fold_packed<TA, kTrainThreads, decltype(to_psibar), KS == 2>(sPbA, tb, to_psibar, sPbA2);
 }
 
 // ---------------------------------------------------------------------------
