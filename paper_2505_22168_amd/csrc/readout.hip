@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kRoThreads) readout_features(DevSystem sys, co
 template <int MB, int TPW>
 __device__ inline void mma_rows_bf16(const __bf16* __restrict__ A, int lda, const bf16x8* __restrict__ Bp, int KB,
                                      int nb0, int nbs, int NB, floatx4 (&acc)[MB][TPW]) {
-  constexpr int PF = 2;
+  constexpr int PF = 3;  // k-steps of B in flight (measured best on the 2x512 network)
   const int l = threadIdx.x & 63;
   const __bf16* abase = A + (l & 15) * lda + (l >> 4) * 8;
   bf16x8 b[PF][TPW];
