@@ -98,102 +98,119 @@ __host__ __device__ constexpr int pair_second(int p) {
 //   pair task (a, p = (s1 <= s2)):  T7[p], M5[p]; fam4[p] = tr T7[p] and
 //                                   fam3[p] = tr M5[p] (Psi2 is symmetric)
 //   channel task (a, s):            V8[s, .], v6[s, .]; fam1[s]; fam2[(s, s2 >= s)]
-template <int TM, int NT, bool BF16, bool FEATURES = true, int ISTR = IS>
+// KS = 2 (a block with twice as many threads as tasks) runs each task's two
+// independent halves on two threads: T7 + fam4 | M5 + fam3, and
+// V8 | v6 + fam1 + fam2.
+template <int TM, int NT, bool BF16, bool FEATURES = true, int ISTR = IS, int KS = 1>
 __device__ inline void contract_forward_a(const float* __restrict__ P, float* __restrict__ I, void* G, int ldg,
                                           const Tables& tb) {
+  static_assert(KS == 1 || KS == 2, "one or two halves");
   const int tid = threadIdx.x;
   for (int t = tid; t < (FEATURES ? TM * (kFP - kF) : 0); t += NT)
     store_feature<BF16>(G, (t % TM) * ldg + kF + t / TM, 0.0f);
   constexpr int np = TM * 15, ns = TM * kS;
-  for (int t = tid; t < np + ns; t += NT) {
+  // with KS = 2 each half's tasks start on a wave boundary
+  constexpr int NTASK = np + ns, NHALF = KS == 1 ? NTASK : (NTASK + 63) / 64 * 64;
+  for (int tt = tid; tt < KS * NHALF; tt += NT) {
+    const int half = KS == 1 ? 0 : tt / NHALF;
+    const int t = KS == 1 ? tt : tt % NHALF;
+    if (t >= NTASK) continue;
+    const bool h0 = KS == 1 || half == 0, h1 = KS == 1 || half == 1;
     if (t < np) {
       const int a = t % TM, p = t / TM;
       const int s1 = pair_first(p), s2 = pair_second(p);
-      float A3[27], B3[27];
+      if (h0) {
+        float A3[27], B3[27];
 #pragma unroll
-      for (int k = 0; k < 27; ++k) {
-        A3[k] = GM_P3(a, s1, k);
-        B3[k] = GM_P3(a, s2, k);
-      }
-      float tr4 = 0.0f;
-#pragma unroll
-      for (int ia = 0; ia < 3; ++ia)
-#pragma unroll
-        for (int ib = 0; ib < 3; ++ib) {
-          float v = 0.0f;
-#pragma unroll
-          for (int cd = 0; cd < 9; ++cd) v += A3[ia * 9 + cd] * B3[ib * 9 + cd];
-          GM_I(a, kT7 + p * 9 + ia * 3 + ib) = v;
-          if (ia == ib) tr4 += v;
+        for (int k = 0; k < 27; ++k) {
+          A3[k] = GM_P3(a, s1, k);
+          B3[k] = GM_P3(a, s2, k);
         }
-      float A2[9], B2[9];
+        float tr4 = 0.0f;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        A2[k] = GM_P2(a, s1, k);
-        B2[k] = GM_P2(a, s2, k);
+        for (int ia = 0; ia < 3; ++ia)
+#pragma unroll
+          for (int ib = 0; ib < 3; ++ib) {
+            float v = 0.0f;
+#pragma unroll
+            for (int cd = 0; cd < 9; ++cd) v += A3[ia * 9 + cd] * B3[ib * 9 + cd];
+            GM_I(a, kT7 + p * 9 + ia * 3 + ib) = v;
+            if (ia == ib) tr4 += v;
+          }
+        if (FEATURES) store_feature<BF16>(G, a * ldg + kFam4 + p, tr4);
       }
-      float tr3 = 0.0f;
+      if (h1) {
+        float A2[9], B2[9];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          float v = 0.0f;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) v += A2[i * 3 + c] * B2[c * 3 + j];
-          GM_I(a, kM5 + p * 9 + i * 3 + j) = v;
-          if (i == j) tr3 += v;
+        for (int k = 0; k < 9; ++k) {
+          A2[k] = GM_P2(a, s1, k);
+          B2[k] = GM_P2(a, s2, k);
         }
-      if (FEATURES) {
-        store_feature<BF16>(G, a * ldg + kFam3 + p, tr3);
-        store_feature<BF16>(G, a * ldg + kFam4 + p, tr4);
+        float tr3 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            float v = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v += A2[i * 3 + c] * B2[c * 3 + j];
+            GM_I(a, kM5 + p * 9 + i * 3 + j) = v;
+            if (i == j) tr3 += v;
+          }
+        if (FEATURES) store_feature<BF16>(G, a * ldg + kFam3 + p, tr3);
       }
     } else {
       const int u = t - np;
       const int a = u % TM, sc = u / TM;
-      float A3[27], C2[9];
+      if (h0) {
+        float A3[27];
 #pragma unroll
-      for (int k = 0; k < 27; ++k) A3[k] = GM_P3(a, sc, k);
+        for (int k = 0; k < 27; ++k) A3[k] = GM_P3(a, sc, k);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) C2[k] = GM_P2(a, sc, k);
+        for (int s3 = 0; s3 < kS; ++s3) {
+          float B2[9];
 #pragma unroll
-      for (int s3 = 0; s3 < kS; ++s3) {
-        float B2[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) B2[k] = GM_P2(a, s3, k);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          float v = 0.0f;
-#pragma unroll
-          for (int bc = 0; bc < 9; ++bc) v += A3[i * 9 + bc] * B2[bc];
-          GM_I(a, kV8 + (sc * 5 + s3) * 3 + i) = v;
-        }
-      }
-      float p1[kS][3];
-#pragma unroll
-      for (int s1 = 0; s1 < kS; ++s1)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) p1[s1][j] = GM_P1(a, s1, j);
-#pragma unroll
-      for (int s1 = 0; s1 < kS; ++s1)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          float v = 0.0f;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) v += C2[i * 3 + j] * p1[s1][j];
-          GM_I(a, kV6 + (sc * 5 + s1) * 3 + i) = v;
-        }
-      if (FEATURES) {
-        store_feature<BF16>(G, a * ldg + sc, GM_P0(a, sc));
-#pragma unroll
-        for (int s2 = 0; s2 < kS; ++s2) {
-          if (s2 < sc) continue;
-          float v = 0.0f;
+          for (int k = 0; k < 9; ++k) B2[k] = GM_P2(a, s3, k);
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            // p1[sc][i] with sc a runtime index: read it again from LDS
-            v += GM_P1(a, sc, i) * p1[s2][i];
+            float v = 0.0f;
+#pragma unroll
+            for (int bc = 0; bc < 9; ++bc) v += A3[i * 9 + bc] * B2[bc];
+            GM_I(a, kV8 + (sc * 5 + s3) * 3 + i) = v;
           }
-          store_feature<BF16>(G, a * ldg + kFam2 + pair_idx(sc, s2), v);
+        }
+      }
+      if (h1) {
+        float C2[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) C2[k] = GM_P2(a, sc, k);
+        float p1[kS][3];
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) p1[s1][j] = GM_P1(a, s1, j);
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) v += C2[i * 3 + j] * p1[s1][j];
+            GM_I(a, kV6 + (sc * 5 + s1) * 3 + i) = v;
+          }
+        if (FEATURES) {
+          store_feature<BF16>(G, a * ldg + sc, GM_P0(a, sc));
+#pragma unroll
+          for (int s2 = 0; s2 < kS; ++s2) {
+            if (s2 < sc) continue;
+            float v = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              // p1[sc][i] with sc a runtime index: read it again from LDS
+              v += GM_P1(a, sc, i) * p1[s2][i];
+            }
+            store_feature<BF16>(G, a * ldg + kFam2 + pair_idx(sc, s2), v);
+          }
         }
       }
     }

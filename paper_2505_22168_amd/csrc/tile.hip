@@ -175,7 +175,9 @@ __global__ void __launch_bounds__(kTileThreads)
   constexpr int kDepth = PERHEAD ? 2 : prefetch_depth<Sh::TPW>();
   BRing<BF16, Sh::TPW, kDepth> ring;
   ring_fill(ring, m.w1_bf16, m.w1_f32, kFP, (tid >> 6) / Sh::MB, Sh::WPR, Sh::NBH);
-  contract_forward_a<TA, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  // 8 atoms leave threads for both halves of every task of the first pass
+  constexpr int KSF = 2 * ((TA * 20 + 63) / 64 * 64) <= kTileThreads ? 2 : 1;
+  contract_forward_a<TA, kTileThreads, BF16, true, IS, KSF>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
   // per-atom scale / shift, by the last wave (idle in the phase above), for
   // the network epilogue
   if (tid >= kTileThreads - 64 && tid - (kTileThreads - 64) < TM) {

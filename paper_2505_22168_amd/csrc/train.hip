@@ -36,6 +36,8 @@ namespace gmnn {
 constexpr int kTrainThreads = 512;
 constexpr int kTrainWaves = kTrainThreads / 64;
 constexpr int kTA = 8;  // atoms per training tile (16 MFMA rows: primal + tangent)
+// 8 atoms leave threads for both halves of every task of the invariants' first pass
+constexpr int kFwdSplit = 2 * ((kTA * 20 + 63) / 64 * 64) <= kTrainThreads ? 2 : 1;
 
 // directional derivative of every monomial at u along v
 __device__ inline void dmonomials(float x, float y, float z, float vx, float vy, float vz, float* d) {
@@ -237,7 +239,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   __syncthreads();
 
   // ---- invariants G (rows 0-7) and Gdot (rows 8-15) ---------------------------
-  contract_forward_a<TA, kTrainThreads, false>(sPsi, sI, sGT, L::LDG, tb);
+  contract_forward_a<TA, kTrainThreads, false, true, IS, kFwdSplit>(sPsi, sI, sGT, L::LDG, tb);
   __syncthreads();
   contract_forward_b<TA, kTrainThreads, false>(sPsi, sI, sGT, L::LDG, tb);
   __syncthreads();
@@ -250,7 +252,7 @@ __global__ void __launch_bounds__(kTrainThreads)
       sPt[a * PS + e] = sPsi[a * PS + e] + cf[ev] * sT[a] * sPd[a * PS + e];
     }
     __syncthreads();
-    contract_forward_a<TA, kTrainThreads, false>(sPt, sI, sGtmp, L::LDG, tb);
+    contract_forward_a<TA, kTrainThreads, false, true, IS, kFwdSplit>(sPt, sI, sGtmp, L::LDG, tb);
     __syncthreads();
     contract_forward_b<TA, kTrainThreads, false>(sPt, sI, sGtmp, L::LDG, tb);
     __syncthreads();
@@ -419,7 +421,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   float* sPbS2 = KS == 2 ? sGT : nullptr;
   float* sPbA2 = KS == 2 ? sGT + TA * PS : nullptr;
   // Psidotbar = B(Psi; Gdotbar)
-  contract_forward_a<TA, kTrainThreads, false, false>(sPsi, sI, nullptr, 0, tb);  // intermediates of Psi
+  contract_forward_a<TA, kTrainThreads, false, false, IS, kFwdSplit>(sPsi, sI, nullptr, 0, tb);  // intermediates of Psi
   __syncthreads();
   contract_backward_a<TA, kTrainThreads>(sPsi, Gdbar, L::LDGB, sI, tb);
   __syncthreads();
@@ -441,7 +443,7 @@ __global__ void __launch_bounds__(kTrainThreads)
       sPt[a * PS + e] = sPsi[a * PS + e] + sgn * sT[a] * sPd[a * PS + e];
     }
     __syncthreads();
-    contract_forward_a<TA, kTrainThreads, false, false>(sPt, sI, nullptr, 0, tb);  // intermediates of Psi +- t Psidot
+    contract_forward_a<TA, kTrainThreads, false, false, IS, kFwdSplit>(sPt, sI, nullptr, 0, tb);  // intermediates of Psi +- t Psidot
     __syncthreads();
     contract_backward_a<TA, kTrainThreads>(sPt, Gdbar, L::LDGB, sI, tb);
     __syncthreads();
