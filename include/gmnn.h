@@ -305,9 +305,11 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
  * NULL.  With GMNN_PREC_BF16 the network products of the forward and
  * reverse passes (primal and tangent rows) run in BF16 on MFMA with FP32
  * accumulation, the operands rounded as in gmnn_energy_forces; the products
- * that form the parameter gradients stay FP32.  Requires the workspace of
- * gmnn_energy_forces for the same inputs; recomputes the forward pass
- * itself. */
+ * that form the weight gradients split each FP32 operand into a BF16 high
+ * and low part and add the three products hi.hi + hi.lo + lo.hi (about 16
+ * significant bits per product).  Without it everything is FP32.  Requires
+ * the workspace of gmnn_energy_forces for the same inputs; recomputes the
+ * forward pass itself. */
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
                           const double* dL_dE, const float* dL_dF, uint32_t flags,
                           gmnn_param_grads* grads, float* dL_dpos,

@@ -567,11 +567,18 @@ __global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSyst
 
 // ---------------------------------------------------------------------------
 // C[M][N] = sum_k A[k][M]^T B[k][N] over the rows k of chunk blockIdx.y
-// (split-K; partial[chunk][M][N]), FP32 MFMA 16x16x4.  Each wave owns a
-// 64 x 64 block of C as 4 x 4 MFMA tiles, so every value loaded feeds four
-// MFMAs; four k-steps of loads are issued before their MFMAs.  M and N are
-// multiples of 64.
+// (split-K; partial[chunk][M][N]).  Each wave owns a 64 x 64 block of C as
+// 4 x 4 MFMA tiles, so every value loaded feeds four (SPLIT: twelve) MFMAs.
+// M and N are multiples of 64.
+//   SPLIT = false: FP32 MFMA 16x16x4, four k-steps of loads issued before
+//                  their MFMAs.
+//   SPLIT = true:  each FP32 operand x is split into hi = bf16(x) and
+//                  lo = bf16(x - hi) (nearest even), and a.b is taken as
+//                  hi.hi + hi.lo + lo.hi on BF16 MFMA 16x16x32 with FP32
+//                  accumulation: about 16 significant bits per product (the
+//                  dropped lo.lo is below 2^-16 of |a b|) at the BF16 rate.
 constexpr int kWgRows = 1024;  // rows per split-K chunk
+template <bool SPLIT>
 __global__ void __launch_bounds__(256) weight_grad(const float* __restrict__ A, int ldA, const float* __restrict__ B,
                                                    int ldB, int Mdim, int Ndim, int64_t K, int64_t kchunk,
                                                    float* __restrict__ partial) {
@@ -587,27 +594,63 @@ __global__ void __launch_bounds__(256) weight_grad(const float* __restrict__ A, 
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  // lane l supplies A^T[m = l&15][k = l>>4] = A[k][m] and B[k = l>>4][n = l&15]
   const float* ap = A + m0 + (l & 15);
   const float* bp = B + n0 + (l & 15);
-  for (int64_t k = kb; k < ke; k += 16) {
-    float a[4][4], b[4][4];
+  if (!SPLIT) {
+    // lane l supplies A^T[m = l&15][k = l>>4] = A[k][m] and B[k = l>>4][n = l&15]
+    for (int64_t k = kb; k < ke; k += 16) {
+      float a[4][4], b[4][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t kk = k + 4 * u + (l >> 4);
-      const bool ok = kk < ke;
+      for (int u = 0; u < 4; ++u) {
+        const int64_t kk = k + 4 * u + (l >> 4);
+        const bool ok = kk < ke;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[u][r] = ok ? ap[kk * ldA + r * 16] : 0.0f;
-        b[u][r] = ok ? bp[kk * ldB + r * 16] : 0.0f;
+        for (int r = 0; r < 4; ++r) {
+          a[u][r] = ok ? ap[kk * ldA + r * 16] : 0.0f;
+          b[u][r] = ok ? bp[kk * ldB + r * 16] : 0.0f;
+        }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][r], b[u][c], acc[r][c], 0, 0, 0);
+    }
+  } else {
+    // lane l supplies A^T[m = l&15][k = 8 (l>>4) + e] and B[k = 8 (l>>4) + e][n = l&15], e < 8
+    for (int64_t k = kb; k < ke; k += 32) {
+      float a[4][8], b[4][8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t kk = k + 8 * (l >> 4) + e;
+        const bool ok = kk < ke;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          a[r][e] = ok ? ap[kk * ldA + r * 16] : 0.0f;
+          b[r][e] = ok ? bp[kk * ldB + r * 16] : 0.0f;
+        }
+      }
+      bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][r], b[u][c], acc[r][c], 0, 0, 0);
+        for (int e = 0; e < 8; ++e) {
+          const __bf16 x = (__bf16)a[r][e], y = (__bf16)b[r][e];
+          ah[r][e] = x;
+          al[r][e] = (__bf16)(a[r][e] - (float)x);
+          bh[r][e] = y;
+          bl[r][e] = (__bf16)(b[r][e] - (float)y);
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh[c], acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bl[c], acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bh[c], acc[r][c], 0, 0, 0);
+        }
+    }
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -900,9 +943,11 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
     const int t1 = (kFP / 64) * (HP / 64);
     const int t2 = (HP / 64) * (HP / 64);
     if (L.kchunks > 0) {
-      hipLaunchKernelGGL(weight_grad, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
+      // the BF16 path takes the split-BF16 products, the FP32 path plain FP32
+      auto wg = bf16 ? weight_grad<true> : weight_grad<false>;
+      hipLaunchKernelGGL(wg, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
                          (int64_t)kWgRows, part1);
-      hipLaunchKernelGGL(weight_grad, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
+      hipLaunchKernelGGL(wg, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
                          (int64_t)kWgRows, part2);
     }
     const int64_t n1 = (int64_t)kFP * HP, n2 = (int64_t)HP * HP;
