@@ -404,7 +404,9 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
                 precision: str = "fp32"):
     """Gradients of a loss w.r.t. every model parameter (gmnn_backward), given
     dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3];
-    precision "bf16" runs the network products of the double backward in BF16."""
+    precision "bf16" runs the network products of the double backward in BF16
+    and the weight-gradient products as three BF16 products of split FP32
+    operands (about 16 significant bits per product)."""
     if precision not in ("fp32", "bf16"):
         raise ValueError(precision)
     flags = A.GMNN_PREC_BF16 if precision == "bf16" else 0
