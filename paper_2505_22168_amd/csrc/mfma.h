@@ -109,14 +109,14 @@ __device__ inline void mma_f32(const float* __restrict__ A, int lda, int rb, con
 
 // BF16 product with the A tile kept in FP32 in LDS: the 8 values of each A
 // fragment are rounded to BF16 (nearest even) as they are loaded (the
-// training tile keeps its activations in FP32 for the parameter products)
-template <int TPW>
-__device__ __forceinline__ void mma_bf16_a32(const float* __restrict__ A, int lda, int rb,
-                                             const bf16x8* __restrict__ Bp, int K, int nb0, int nbs, int NB,
-                                             floatx4 (&acc)[TPW]) {
-  BRing<true, TPW> r;
-  ring_fill(r, Bp, nullptr, K, nb0, nbs, NB);
-  constexpr int PF = BRing<true, TPW>::PF;
+// training tile keeps its activations in FP32 for the parameter products).
+// The _ring form takes the ring already holding k-steps 0..PF-1 (filled ahead
+// with ring_fill), so its first fragments can arrive during earlier work.
+template <int TPW, int DEPTH>
+__device__ __forceinline__ void mma_bf16_a32_ring(BRing<true, TPW, DEPTH>& r, const float* __restrict__ A, int lda,
+                                                  int rb, const bf16x8* __restrict__ Bp, int K, int nb0, int nbs,
+                                                  int NB, floatx4 (&acc)[TPW]) {
+  constexpr int PF = DEPTH;
   const int l = threadIdx.x & 63;
   const int KB = K / 32;
   const float* arow = A + (rb * 16 + (l & 15)) * lda + (l >> 4) * 8;
@@ -141,6 +141,15 @@ __device__ __forceinline__ void mma_bf16_a32(const float* __restrict__ A, int ld
       }
     }
   }
+}
+
+template <int TPW>
+__device__ __forceinline__ void mma_bf16_a32(const float* __restrict__ A, int lda, int rb,
+                                             const bf16x8* __restrict__ Bp, int K, int nb0, int nbs, int NB,
+                                             floatx4 (&acc)[TPW]) {
+  BRing<true, TPW> r;
+  ring_fill(r, Bp, nullptr, K, nb0, nbs, NB);
+  mma_bf16_a32_ring(r, A, lda, rb, Bp, K, nb0, nbs, NB, acc);
 }
 
 template <int TPW>

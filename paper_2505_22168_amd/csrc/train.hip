@@ -122,11 +122,13 @@ __device__ inline void swish_d2(float z, float& s, float& d1, float& d2) {
 
 // network products of the training tile: FP32 MFMA, or BF16 MFMA on the
 // BF16 weight copies with the FP32 activation tile rounded on load
-template <bool BF16, int TPW>
-__device__ __forceinline__ void train_mma(const DevModel& m, const float* A, int lda, const bf16x8* Bbf,
+// one network product of the training tile (16 rows: primal + tangent) from
+// a ring filled ahead with the first k-steps of its weights
+template <bool BF16, int TPW, int DEPTH>
+__device__ __forceinline__ void train_mma(BRing<BF16, TPW, DEPTH>& ring, const float* A, int lda, const bf16x8* Bbf,
                                           const float* Bf, int K, int nb0, int nbs, int NB, floatx4 (&acc)[TPW]) {
-  if constexpr (BF16) mma_bf16_a32<TPW>(A, lda, 0, Bbf, K, nb0, nbs, NB, acc);
-  else mma_f32<TPW>(A, lda, 0, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
+  if constexpr (BF16) mma_bf16_a32_ring(ring, A, lda, 0, Bbf, K, nb0, nbs, NB, acc);
+  else mma_ring(ring, A, lda, 0, nullptr, Bf, K, nb0, nbs, NB, acc);
 }
 
 template <int HP>
@@ -263,6 +265,11 @@ __global__ void __launch_bounds__(kTrainThreads)
     }
     __syncthreads();
   }
+  // the first weight fragments of the network start loading now; each
+  // product then fills the ring of the next one as soon as its own
+  // fragments are consumed, ahead of its epilogue and barrier
+  BRing<BF16, TPW> ring;
+  ring_fill(ring, m.w1_bf16, m.w1_f32, kFP, w, WPR, NBH);
   // weight-product rows X1 = [G; Gdot]
   for (int t = tid; t < 16 * kFP; t += kTrainThreads) {
     const int r = t / kFP, f = t % kFP;
@@ -278,7 +285,8 @@ __global__ void __launch_bounds__(kTrainThreads)
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    train_mma<BF16, TPW>(m, sGT, L::LDG, m.w1_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
+    train_mma(ring, sGT, L::LDG, m.w1_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
+    ring_fill(ring, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = cw + i * WPR;
@@ -307,7 +315,8 @@ __global__ void __launch_bounds__(kTrainThreads)
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    train_mma<BF16, TPW>(m, sH, L::LDH, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
+    train_mma(ring, sH, L::LDH, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
+    ring_fill(ring, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH);
     float ypart[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // primal lanes: h2 . w3bar, tangent lanes: h2dot . w3bar
     floatx4 d2out[TPW];
 #pragma unroll
@@ -372,10 +381,12 @@ __global__ void __launch_bounds__(kTrainThreads)
     Y2[(k0 + r) * HP + c] = ((r & 7) < n_rows) ? sH[r * L::LDH + c] : 0.0f;
   }
   // ---- network reverse ------------------------------------------------------------
+  BRing<BF16, TPW_G> ring_g;
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    train_mma<BF16, TPW>(m, sH, L::LDH, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH, acc);
+    train_mma(ring, sH, L::LDH, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH, acc);
+    ring_fill(ring_g, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG);
     __syncthreads();  // all reads of [z2bar; z2dotbar] done before the tile is overwritten
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
@@ -399,7 +410,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   {
     floatx4 acc[TPW_G];
     zero_acc(acc);
-    train_mma<BF16, TPW_G>(m, sH, L::LDH, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG, acc);
+    train_mma(ring_g, sH, L::LDH, m.w1t_bf16, m.w1t_f32, HP, cw, WPR, NBG, acc);
 #pragma unroll
     for (int i = 0; i < TPW_G; ++i) {
       const int nb = cw + i * WPR;
