@@ -383,10 +383,11 @@ __global__ void __launch_bounds__(kRoThreads)
 
 // ---------------------------------------------------------------------------
 // 3. invariant backward: dE/dG and the moments -> dE/dPsi (packed).  Blocks of
-// 8 atoms (256 threads, about one task per thread in every phase), two per
-// CU, so one block's loads overlap the other's arithmetic.
+// 8 atoms and 512 threads: the first forward pass runs each task's two
+// independent halves on two threads; two blocks per CU, so one block's loads
+// overlap the other's arithmetic.
 constexpr int kBkAtoms = 8;
-constexpr int kBkThreads = 256;
+constexpr int kBkThreads = 512;
 
 struct BackLds {
   static constexpr int LDGB = kFP + 1;
@@ -413,17 +414,16 @@ __global__ void __launch_bounds__(kBkThreads) readout_backward(DevSystem sys, co
   const int row0 = xcd_block(blockIdx.x, gridDim.x) * TB;
   const int n_rows = min(TB, sys.n_atoms - row0);
   // all loads of the tile (dE/dG rows, packed moments) issued up front
-  constexpr int NG = TB * kFP / 4 / NT;  // float4 per thread (exact)
+  constexpr int NG = (TB * kFP / 4 + NT - 1) / NT;  // float4 per thread
   constexpr int NP = kS * kPacked;
   constexpr int NM = (TB * NP + NT - 1) / NT;
-  static_assert(TB * kFP / 4 % NT == 0, "dE/dG tile in whole float4 per thread");
   float4 gv[NG];
   float mv[NM];
   const float4* gsrc = (const float4*)(dG + (int64_t)row0 * kFP);
 #pragma unroll
   for (int u = 0; u < NG; ++u) {
     const int t = tid + u * NT;
-    gv[u] = (t * 4 / kFP < n_rows) ? gsrc[t] : float4{0.0f, 0.0f, 0.0f, 0.0f};
+    gv[u] = (t < TB * kFP / 4 && t * 4 / kFP < n_rows) ? gsrc[t] : float4{0.0f, 0.0f, 0.0f, 0.0f};
   }
 #pragma unroll
   for (int u = 0; u < NM; ++u) {
@@ -434,6 +434,7 @@ __global__ void __launch_bounds__(kBkThreads) readout_backward(DevSystem sys, co
 #pragma unroll
   for (int u = 0; u < NG; ++u) {
     const int t = (tid + u * NT) * 4;
+    if (t >= TB * kFP) continue;
     const int a = t / kFP, f = t % kFP;
     float* d = sGb + a * L::LDGB + f;
     d[0] = gv[u].x;
@@ -453,15 +454,20 @@ __global__ void __launch_bounds__(kBkThreads) readout_backward(DevSystem sys, co
     }
   }
   __syncthreads();
-  contract_forward_a<TB, NT, false, false>(sPsi, sI, nullptr, 0, tb);
+  constexpr int KSF = 2 * ((TB * 20 + 63) / 64 * 64) <= NT ? 2 : 1;
+  // the entry pass stays unsplit: its sums then run in the tile readout's
+  // order, so both readouts give bit-identical results
+  constexpr int KS = 1;
+  contract_forward_a<TB, NT, false, false, IS, KSF>(sPsi, sI, nullptr, 0, tb);
   __syncthreads();
   contract_backward_a<TB, NT>(sPsi, sGb, L::LDGB, sI, tb);
   __syncthreads();
-  contract_backward_b<TB, NT>(sPsi, sGb, L::LDGB, sI, sPb, tb);
+  contract_backward_b<TB, NT, KS>(sPsi, sGb, L::LDGB, sI, sPb, tb);
   __syncthreads();
-  fold_packed<TB, NT>(sPb, tb, [&](int a, int e, float v) {
+  auto to_psibar = [&](int a, int e, float v) {
     if (a < n_rows) psibar[(int64_t)(row0 + a) * (kS * kPacked) + e] = v;
-  });
+  };
+  fold_packed<TB, NT>(sPb, tb, to_psibar);
 }
 
 // ---------------------------------------------------------------------------
