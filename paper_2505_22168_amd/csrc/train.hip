@@ -25,6 +25,8 @@
 //                   W2bar = [h1;h1dot]^T [z2bar;z2dotbar] as split-K MFMA
 //                   products over all atoms, partials summed in a fixed order
 //   reductions      bias, W3, scale and shift gradients (fixed order)
+#include <algorithm>
+
 #include "common.h"
 #include "contraction.h"
 #include "mfma.h"
@@ -482,7 +484,10 @@ __global__ void __launch_bounds__(kTrainThreads)
 // values, lane k owning slot k, and adds them to the wave's LDS copy of the
 // gradient (one writer per slot); per-block copies are summed in wave order
 // and written as block partials.
-__global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSystem sys, const float* __restrict__ lambda,
+// Blocks of up to 16 waves (four per SIMD hide the per-atom memory round
+// trips), as many as the per-wave LDS copies of the gradient allow.
+constexpr int kBetaMaxThreads = 1024;
+__global__ void __launch_bounds__(kBetaMaxThreads) pair_beta_grad(DevModel m, DevSystem sys, const float* __restrict__ lambda,
                                                              const float* __restrict__ psibar,
                                                              const float* __restrict__ psidotbar,
                                                              float* __restrict__ beta_partial) {
@@ -491,9 +496,9 @@ __global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSyst
   const int nslots = nsp * nsp * kS * kMaxBasis;
   float* s_beta = sm;
   float* s_acc = sm + nslots;  // [waves][nslots]
-  constexpr int NW = kPairBlock / 64;
+  const int NW = (int)blockDim.x / 64;
   stage_beta(m, s_beta);
-  for (int t = threadIdx.x; t < NW * nslots; t += kPairBlock) s_acc[t] = 0.0f;
+  for (int t = threadIdx.x; t < NW * nslots; t += blockDim.x) s_acc[t] = 0.0f;
   __syncthreads();
   const int w = threadIdx.x >> 6, q = threadIdx.x & 63;
   for (int i = blockIdx.x * NW + w; i < sys.n_atoms; i += gridDim.x * NW) {
@@ -569,7 +574,7 @@ __global__ void __launch_bounds__(kPairBlock) pair_beta_grad(DevModel m, DevSyst
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < nslots; t += kPairBlock) {
+  for (int t = threadIdx.x; t < nslots; t += blockDim.x) {
     float v = 0.0f;
     for (int ww = 0; ww < NW; ++ww) v += s_acc[ww * nslots + t];
     beta_partial[(int64_t)blockIdx.x * nslots + t] = v;
@@ -886,7 +891,7 @@ template <int LPA>
 __global__ void pair_moments(DevModel m, DevSystem sys, float* psi, int* counters, int n_counters);
 
 bool train_supported(const DevModel& m) {
-  return m.n_species <= 8 && TrainLds<512>::bytes <= 160 * 1024 &&
+  return m.n_species <= kMaxSpecies && TrainLds<512>::bytes <= 160 * 1024 &&
          (m.HP1 == 64 || m.HP1 == 128 || m.HP1 == 256 || m.HP1 == 512);
 }
 
@@ -947,7 +952,18 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
     }
     if (st != GMNN_OK) return st;
   }
-  hipLaunchKernelGGL(pair_beta_grad, dim3(L.beta_blocks), dim3(kPairBlock), beta_lds * (1 + kPairBlock / 64), s, m, sys,
+  // waves per block: the beta table plus one gradient copy per wave in 160 KB
+  const int beta_waves = (int)std::min<size_t>(kBetaMaxThreads / 64, std::max<size_t>(1, 160 * 1024 / beta_lds - 1));
+  {
+    static bool attr = false;
+    if (!attr) {
+      if (hipFuncSetAttribute((const void*)pair_beta_grad, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
+          hipSuccess)
+        return GMNN_ERR_HIP;
+      attr = true;
+    }
+  }
+  hipLaunchKernelGGL(pair_beta_grad, dim3(L.beta_blocks), dim3(64 * beta_waves), beta_lds * (1 + beta_waves), s, m, sys,
                      lambda, psibar, psidotbar, bpart);
   // weight products, split over chunks of kWgRows rows, partials summed in chunk order
   {

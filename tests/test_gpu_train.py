@@ -44,6 +44,35 @@ def test_param_gradients_match_oracle(hidden):
         assert err < 1e-4, (k, err)
 
 
+@pytest.mark.parametrize("n_species", [12, 16])
+def test_param_gradients_many_species(n_species):
+    """Up to the model's 16 species: the beta-gradient kernel's per-wave LDS
+    copies of the [n_sp, n_sp, S, K] table exceed the default 64 KB of
+    dynamic LDS (fewer waves per block as the table grows)."""
+    import dataclasses
+    g = need_gpu()
+    batch, params, spec = make_workload("train", n_structs=2, n_lo=40, n_hi=60)
+    rng = np.random.default_rng(11)
+    batch = dataclasses.replace(batch, species=rng.integers(0, n_species, batch.n_atoms).astype(np.int32))
+    s2 = dataclasses.replace(spec.model, n_species=n_species, hidden=(32, 32))
+    params = make_params(s2, 7)
+    teacher = make_params(s2, 107)
+    onl = brute_force_neighbors(batch, s2.r_cut)
+    rt = evaluate(batch, teacher, onl)
+    L, gref, dLdE, dLdF = loss_and_param_grads(batch, params, onl, rt.energy_mean, rt.forces)
+    print("many species:", n_species, "atoms", batch.n_atoms, flush=True)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, s2.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    grads = g.param_grads(model, system, nl, dLdE, dLdF)
+    torch.cuda.synchronize()
+    for k in PARAM_NAMES:
+        got = grads[k].cpu().numpy().astype(np.float64).reshape(np.shape(gref[k]))
+        ref = gref[k]
+        err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+        assert err < 1e-4, (k, err)
+
+
 def test_autograd_function_matches_oracle_loss_gradient():
     g = need_gpu()
     batch, params, onl, Er, Fr = _case(hidden=(64, 64), n_structs=2, n_lo=40, n_hi=60)
