@@ -223,7 +223,7 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
  *          blocks, each with half the pair and invariant work and the same
  *          network products), then one kernel gathers the forces and sums
  *          per structure (latency-bound small systems; needs <= 8 species,
- *          no force variance, every structure <= 8192 atoms);
+ *          no force variance, every structure <= 16384 atoms);
  *   SPLIT  pair moments -> readout -> pair backward -> gather/sums, with the
  *          readout (invariants, network, their backward) either
  *            TILE    one kernel per 16 atoms, or
@@ -233,10 +233,11 @@ gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
  *                    backward only: not with GMNN_WANT_FORCE_VAR).
  * lanes_per_atom (8, 16, 32 or 64) is the number of lanes that share one atom's
  * neighbour row in the pair and gather kernels.  Zero fields mean "built-in
- * choice": FUSED with 64 lanes below 8192 atoms, SPLIT with 16 beyond, the
- * STREAM readout from 16384 atoms on where it is allowed, 8-atom fused
- * tiles while 16-atom ones would number fewer than 256 (the compute units
- * of one MI355X). */
+ * choice": FUSED with 64 lanes below 16384 atoms where it is allowed (else
+ * SPLIT, with 64 lanes below 8192 atoms and 16 beyond), SPLIT with 16 lanes
+ * and the STREAM readout from 16384 atoms on (TILE where STREAM is not
+ * allowed), 8-atom fused tiles while 16-atom ones would number fewer than
+ * 256 (the compute units of one MI355X). */
 #define GMNN_SCHEDULE_AUTO 0
 #define GMNN_SCHEDULE_FUSED 1
 #define GMNN_SCHEDULE_SPLIT 2

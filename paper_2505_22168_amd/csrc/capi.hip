@@ -38,8 +38,13 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
                            const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s);
 
 constexpr int kPairThreads = 256;
-// below this many atoms the built-in plan takes the fused (latency) schedule
-constexpr int kFusedMaxAtoms = 8192;
+// below this many atoms the built-in plan takes the fused (latency) schedule,
+// and no structure of a fused evaluation may be larger (one block sums each
+// structure from its tiles' records); measured: the fused schedule still
+// wins at 11,000 atoms, the streamed readout takes over from 16384
+constexpr int kFusedMaxAtoms = 16384;
+// below this many atoms the split schedule's pair kernels take 64 lanes per row
+constexpr int kWideLanesMaxAtoms = 8192;
 // per-structure reductions of per-atom values split into chunks of at most
 // this many atoms (one block each)
 constexpr int kReduceChunk = 2048;
@@ -82,8 +87,9 @@ static bool fused_allowed(const gmnn_model* m, const gmnn_system* sys, uint32_t 
 }
 
 // fills the AUTO fields of `in` (built-in heuristic: the fused schedule for
-// systems of fewer than kFusedMaxAtoms atoms, 64 lanes per atom there and 16
-// beyond, 8-atom fused tiles below one 16-atom tile per compute unit);
+// systems of fewer than kFusedMaxAtoms atoms, 64 lanes per atom there and for
+// split systems below kWideLanesMaxAtoms, 16 beyond, 8-atom fused tiles below
+// one 16-atom tile per compute unit);
 // UNSUPPORTED for a plan these shapes cannot run
 static gmnn_status resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint32_t flags, const gmnn_plan* in,
                                 Plan& out) {
@@ -104,7 +110,9 @@ static gmnn_status resolve_plan(const gmnn_model* m, const gmnn_system* sys, uin
   if (ta != 0 && ta != 8 && ta != 16) return GMNN_ERR_INVALID_ARG;
   if (ta != 0 && !out.fused) return GMNN_ERR_UNSUPPORTED;
   out.ta = !out.fused ? 0 : ta ? ta : ((sys->n_atoms + 15) / 16 < kComputeUnits ? 8 : 16);
-  out.lpa = lpa ? lpa : (small ? 64 : 16);
+  // 64 lanes per row for the fused schedule and small split evaluations, 16
+  // for large ones (fuller waves over long lists)
+  out.lpa = lpa ? lpa : ((out.fused || sys->n_atoms < kWideLanesMaxAtoms) ? 64 : 16);
   const int ro = in ? in->readout : GMNN_READOUT_AUTO;
   if (ro != GMNN_READOUT_AUTO && ro != GMNN_READOUT_TILE && ro != GMNN_READOUT_STREAM) return GMNN_ERR_INVALID_ARG;
   const bool can_stream = !out.fused && !(flags & GMNN_WANT_FORCE_VAR) &&

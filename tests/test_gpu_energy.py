@@ -173,16 +173,16 @@ def _oracle_force_on(batch, params, k, rc):
 
 
 def test_large_structure_chunked_reduction_and_sampled_parity():
-    """An 8712-atom lattice takes the unfused high-occupancy path and the
-    chunked per-structure reduction; atomic energies and forces of sampled
-    atoms are checked against the oracle one by one."""
+    """An 8712-atom lattice on the split schedule (high-occupancy pair
+    kernels, chunked per-structure reduction); atomic energies and forces of
+    sampled atoms are checked against the oracle one by one."""
     g = need_gpu()
     batch, params, spec = make_workload("solid", reps=(22, 22, 18))
     system = g.System.from_batch(batch, "cuda")
     nl = g.build_neighbors(system, 6.0, 1.0)
     model = g.Model.from_params(params, "cuda")
-    out = g.energy_forces(model, system, nl, precision="fp32", stress=True)
-    torch.cuda.synchronize()
+    # the split schedule explicitly: its per-atom sums run in 2048-atom chunks
+    out = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=(2, 16, 1))(sync=True)
     Ei = _np(out.atomic_energy)[: batch.n_atoms, 0].astype(np.float64)
     assert abs(_np(out.energy)[0, 0] - Ei.sum()) < 1e-9 * abs(Ei.sum())
     F = _np(out.forces)[: batch.n_atoms]

@@ -57,8 +57,9 @@ def test_explicit_plans():
     # the fused tile on a large batch of small structures is allowed (one
     # reduction chunk per structure) ...
     assert _resolve(m, _Sys([200] * 100), 0, A.GMNN_SCHEDULE_FUSED, 16)[0] == A.GMNN_OK
-    # ... but not for a structure that needs chunked reductions
-    assert _resolve(m, _Sys([9000]), 0, A.GMNN_SCHEDULE_FUSED, 16)[0] == A.GMNN_ERR_UNSUPPORTED
+    # ... but not for a structure above the fused schedule's limit
+    assert _resolve(m, _Sys([16385]), 0, A.GMNN_SCHEDULE_FUSED, 16)[0] == A.GMNN_ERR_UNSUPPORTED
+    assert _resolve(m, _Sys([16384]), 0, A.GMNN_SCHEDULE_FUSED, 16)[0] == A.GMNN_OK
     assert _resolve(m, small, A.GMNN_WANT_FORCE_VAR, A.GMNN_SCHEDULE_FUSED, 0)[0] == A.GMNN_ERR_UNSUPPORTED
     assert _resolve(_model(n_species=9), small, 0, A.GMNN_SCHEDULE_FUSED, 0)[0] == A.GMNN_ERR_UNSUPPORTED
     assert _resolve(_model(n_species=9), small, 0)[1][0] == A.GMNN_SCHEDULE_SPLIT
@@ -68,8 +69,12 @@ def test_readout_choice():
     m = _model(hidden=512)
     TILE, STREAM = A.GMNN_READOUT_TILE, A.GMNN_READOUT_STREAM
     SPLIT, FUSED = A.GMNN_SCHEDULE_SPLIT, A.GMNN_SCHEDULE_FUSED
-    # built-in: tile readout below 16384 atoms, streamed from there on
+    # built-in: fused below 16384 atoms (BF16 2x512 fits the fused tile's LDS,
+    # FP32 2x512 does not), split with the streamed readout from there on
+    assert _resolve(m, _Sys([12000]), A.GMNN_PREC_BF16, full=True) == (A.GMNN_OK, (FUSED, 64, TILE, 16))
     assert _resolve(m, _Sys([12000]), 0, full=True) == (A.GMNN_OK, (SPLIT, 16, TILE, 0))
+    assert _resolve(m, _Sys([12000]), 0, SPLIT, full=True) == (A.GMNN_OK, (SPLIT, 16, TILE, 0))
+    assert _resolve(m, _Sys([6000]), 0, SPLIT, full=True) == (A.GMNN_OK, (SPLIT, 64, TILE, 0))
     assert _resolve(m, _Sys([100000]), A.GMNN_PREC_BF16, full=True) == (A.GMNN_OK, (SPLIT, 16, STREAM, 0))
     assert _resolve(_model(), _Sys([1536]), 0, full=True)[1] == (FUSED, 64, TILE, 8)
     # force variance needs one backward per head: the tile readout only
