@@ -8,6 +8,7 @@
 #include "common.h"
 #include "model.h"
 #include "neighbors.h"
+#include "pair_math.h"
 
 namespace gmnn {
 
@@ -17,6 +18,8 @@ __global__ void pair_moments(DevModel m, DevSystem sys, float* psi, int* counter
 template <int LPA>
 __global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial, int nh,
                               int64_t gstride);
+__global__ void pair_backward_heads(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial, int nh,
+                                    int64_t gstride);
 template <int LPA, bool VAR>
 __global__ void finish(int M, DevSystem sys, const float* gpair, const float* atomic_e, const float* virial,
                        int want_stress, int nb_gather, int64_t gstride, int nchunk, double* partial, int* counters,
@@ -497,7 +500,19 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
 #define PAIR_BACKWARD(LPA)                                                                                 \
   hipLaunchKernelGGL(pair_backward<LPA>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair, \
                      virial, nh, gstride)
-      if (lpa == 64) PAIR_BACKWARD(64);
+      if (nh > 1) {
+        // one backward per head: every pair's geometry serves all heads
+        const size_t lds = beta_lds + sizeof(float) * kHeadsAtoms * (size_t)nh * kS * kPacked;
+        static bool attr = false;
+        if (!attr) {
+          if (hipFuncSetAttribute((const void*)pair_backward_heads, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024) != hipSuccess)
+            return GMNN_ERR_HIP;
+          attr = true;
+        }
+        hipLaunchKernelGGL(pair_backward_heads, dim3((N + kHeadsAtoms - 1) / kHeadsAtoms), dim3(kPairThreads), lds,
+                           s, dm, ds, psibar, gpair, virial, nh, gstride);
+      } else if (lpa == 64) PAIR_BACKWARD(64);
       else if (lpa == 32) PAIR_BACKWARD(32);
       else if (lpa == 16) PAIR_BACKWARD(16);
       else PAIR_BACKWARD(8);

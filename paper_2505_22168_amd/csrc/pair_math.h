@@ -9,6 +9,7 @@
 namespace gmnn {
 
 constexpr int kPairBlock = 256;  // threads per block of the pair kernels
+constexpr int kHeadsAtoms = kPairBlock / 64;  // atoms per block of the per-head pair backward
 
 // --- DPP lane exchanges inside rows of 16 lanes ----------------------------
 __device__ inline float dpp_mirror(float v) {  // lane 15 - l
@@ -322,10 +323,43 @@ __device__ inline void atom_moments(const DevModel& m, const DevSystem& sys, con
   atom_moments_from<LPA>(m, sys, s_beta, c, q, g, v, cache);
 }
 
-// dE/dd_p for every pair of lane q of atom i, given pb = dE_i/dPsi_i (packed
-// components, each an independent variable).  With P_s(u) = sum_t pb[s][t]
-// mono_t(u) and Q(u) = sum_s R_s P_s(u):
+// dE/dd_p of one pair from dE_i/dPsi_i (pb, packed components, each an
+// independent variable) and the pair's radial basis and monomials.  With
+// P_s(u) = sum_t pb[s][t] mono_t(u) and Q(u) = sum_s R_s P_s(u):
 //   g = (sum_s dR_s/dr P_s(u)) u + (grad Q - (grad Q . u) u) / r
+// pb is indexed as pb[k]: a register array or an LDS pointer.
+template <class PB>
+__device__ __forceinline__ void pair_gradient(const PB& pb, const Radial& rad, const float (&mo)[20], float x, float y,
+                                              float z, float ir, float& gx, float& gy, float& gz) {
+  float radial_part = 0.0f;
+  float qc[kPacked];
+#pragma unroll
+  for (int t = 0; t < kPacked; ++t) qc[t] = 0.0f;
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    float A = 0.0f;
+#pragma unroll
+    for (int t = 0; t < kPacked; ++t) {
+      A += pb[s * kPacked + t] * mo[t];
+      qc[t] += rad.R[s] * pb[s * kPacked + t];
+    }
+    radial_part += A * rad.dR[s];
+  }
+  const float Gx = qc[1] + 2.0f * qc[4] * x + qc[5] * y + qc[6] * z + 3.0f * qc[10] * x * x +
+                   2.0f * qc[11] * x * y + 2.0f * qc[12] * x * z + qc[13] * y * y + qc[14] * y * z +
+                   qc[15] * z * z;
+  const float Gy = qc[2] + qc[5] * x + 2.0f * qc[7] * y + qc[8] * z + qc[11] * x * x +
+                   2.0f * qc[13] * x * y + qc[14] * x * z + 3.0f * qc[16] * y * y + 2.0f * qc[17] * y * z +
+                   qc[18] * z * z;
+  const float Gz = qc[3] + qc[6] * x + qc[8] * y + 2.0f * qc[9] * z + qc[12] * x * x + qc[14] * x * y +
+                   2.0f * qc[15] * x * z + qc[17] * y * y + 2.0f * qc[18] * y * z + 3.0f * qc[19] * z * z;
+  const float gu = Gx * x + Gy * y + Gz * z;
+  gx = radial_part * x + (Gx - gu * x) * ir;
+  gy = radial_part * y + (Gy - gu * y) * ir;
+  gz = radial_part * z + (Gz - gu * z) * ir;
+}
+
+// dE/dd_p for every pair of lane q of atom i, given pb = dE_i/dPsi_i.
 // Writes g_p and accumulates this lane's share of sum_p g_p (x) d_p into vir.
 template <int LPA>
 __device__ inline void atom_pair_backward(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta,
@@ -364,33 +398,7 @@ __device__ inline void atom_pair_backward(const DevModel& m, const DevSystem& sy
         radial<true>(m, bzi + g.zj[u] * kS * kMaxBasis, r, rad);
         float mo[20];
         monomials(ux, uy, uz, mo);
-        float radial_part = 0.0f;
-        float qc[kPacked];
-#pragma unroll
-        for (int t = 0; t < kPacked; ++t) qc[t] = 0.0f;
-#pragma unroll
-        for (int s = 0; s < kS; ++s) {
-          float A = 0.0f;
-#pragma unroll
-          for (int t = 0; t < kPacked; ++t) {
-            A += pb[s * kPacked + t] * mo[t];
-            qc[t] += rad.R[s] * pb[s * kPacked + t];
-          }
-          radial_part += A * rad.dR[s];
-        }
-        const float x = ux, y = uy, z = uz;
-        const float Gx = qc[1] + 2.0f * qc[4] * x + qc[5] * y + qc[6] * z + 3.0f * qc[10] * x * x +
-                         2.0f * qc[11] * x * y + 2.0f * qc[12] * x * z + qc[13] * y * y + qc[14] * y * z +
-                         qc[15] * z * z;
-        const float Gy = qc[2] + qc[5] * x + 2.0f * qc[7] * y + qc[8] * z + qc[11] * x * x +
-                         2.0f * qc[13] * x * y + qc[14] * x * z + 3.0f * qc[16] * y * y + 2.0f * qc[17] * y * z +
-                         qc[18] * z * z;
-        const float Gz = qc[3] + qc[6] * x + qc[8] * y + 2.0f * qc[9] * z + qc[12] * x * x + qc[14] * x * y +
-                         2.0f * qc[15] * x * z + qc[17] * y * y + 2.0f * qc[18] * y * z + 3.0f * qc[19] * z * z;
-        const float gu = Gx * x + Gy * y + Gz * z;
-        gx = radial_part * x + (Gx - gu * x) * ir;
-        gy = radial_part * y + (Gy - gu * y) * ir;
-        gz = radial_part * z + (Gz - gu * z) * ir;
+        pair_gradient(pb, rad, mo, ux, uy, uz, ir, gx, gy, gz);
         vir[0] += gx * dx; vir[1] += gx * dy; vir[2] += gx * dz;
         vir[3] += gy * dx; vir[4] += gy * dy; vir[5] += gy * dz;
         vir[6] += gz * dx; vir[7] += gz * dy; vir[8] += gz * dz;
@@ -399,6 +407,59 @@ __device__ inline void atom_pair_backward(const DevModel& m, const DevSystem& sy
       gpair[3 * pu] = gx;
       gpair[3 * pu + 1] = gy;
       gpair[3 * pu + 2] = gz;
+    }
+  }
+}
+
+// The same for nh heads at once (one backward per head): each pair's
+// geometry, radial basis and monomials are computed once and serve every
+// head; pbh = dE_i^h/dPsi_i for head h at pbh + h * 100 (LDS).  Head h's
+// gradients go to gpair + h * gstride * 3; vir accumulates the sum over
+// heads.  Per head the arithmetic is atom_pair_backward's.
+template <int LPA>
+__device__ inline void atom_pair_backward_heads(const DevModel& m, const DevSystem& sys,
+                                                const float* __restrict__ s_beta, int i, int q,
+                                                const float* __restrict__ pbh, int nh, float* __restrict__ gpair,
+                                                int64_t gstride, float (&vir)[9]) {
+  AtomCtx c;
+  load_atom(sys, i, c);
+  const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
+  for (int64_t p = c.p0 + q; p < c.p1; p += kPairUnroll * LPA) {
+    PairGroup g;
+    fetch_pairs<LPA>(sys, c, p, g);
+#pragma unroll
+    for (int u = 0; u < kPairUnroll; ++u) {
+      if (!g.ok[u]) continue;
+      const float dx = g.dx[u], dy = g.dy[u], dz = g.dz[u];
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const int64_t pu = p + (int64_t)u * LPA;
+      if (r2 < m.rc2 && r2 > 0.0f) {
+        float r, ir;
+        length_of(r2, r, ir);
+        const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+        Radial rad;
+        radial<true>(m, bzi + g.zj[u] * kS * kMaxBasis, r, rad);
+        float mo[20];
+        monomials(ux, uy, uz, mo);
+        for (int h = 0; h < nh; ++h) {
+          float gx, gy, gz;
+          pair_gradient(pbh + h * (kS * kPacked), rad, mo, ux, uy, uz, ir, gx, gy, gz);
+          vir[0] += gx * dx; vir[1] += gx * dy; vir[2] += gx * dz;
+          vir[3] += gy * dx; vir[4] += gy * dy; vir[5] += gy * dz;
+          vir[6] += gz * dx; vir[7] += gz * dy; vir[8] += gz * dz;
+          float* gp = gpair + (int64_t)h * gstride * 3;
+          gp[3 * pu] = gx;
+          gp[3 * pu + 1] = gy;
+          gp[3 * pu + 2] = gz;
+        }
+      } else {
+        for (int h = 0; h < nh; ++h) {
+          float* gp = gpair + (int64_t)h * gstride * 3;
+          gp[3 * pu] = 0.0f;
+          gp[3 * pu + 1] = 0.0f;
+          gp[3 * pu + 2] = 0.0f;
+        }
+      }
     }
   }
 }

@@ -89,6 +89,43 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
   }
 }
 
+// One backward per head (nh > 1): 64 lanes per atom, 4 atoms per block; the
+// block's dE/dPsi of every head are staged in LDS after beta, and each pair's
+// geometry and radial basis serve all heads.  Dynamic LDS: beta +
+// 4 * nh * 100 floats.
+__global__ void __launch_bounds__(kPairBlock) pair_backward_heads(DevModel m, DevSystem sys,
+                                                                  const float* __restrict__ psibar,
+                                                                  float* __restrict__ gpair,
+                                                                  float* __restrict__ virial, int nh,
+                                                                  int64_t gstride) {
+  extern __shared__ float s_beta[];
+  const int nbeta = m.n_species * m.n_species * kS * kMaxBasis;
+  float* s_pb = s_beta + nbeta;  // [atom][head][100]
+  const int a0 = xcd_block(blockIdx.x, gridDim.x) * kHeadsAtoms;
+  stage_beta(m, s_beta);
+  constexpr int NP = kS * kPacked;
+  for (int t = threadIdx.x; t < kHeadsAtoms * nh * NP; t += kPairBlock) {
+    const int a = t / (nh * NP), rest = t % (nh * NP);
+    const int h = rest / NP, k = rest % NP;
+    s_pb[t] = (a0 + a < sys.n_atoms) ? psibar[((int64_t)h * sys.n_atoms + a0 + a) * NP + k] : 0.0f;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, q = threadIdx.x & 63;
+  const int i = a0 + w;
+  const bool live = i < sys.n_atoms;
+  float vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0f;
+  if (live) atom_pair_backward_heads<64>(m, sys, s_beta, i, q, s_pb + w * nh * NP, nh, gpair, gstride, vir);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = atom_sum<64>(vir[k]);
+  if (live && q == 0) {
+    const float inv = 1.0f / (float)nh;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) virial[(int64_t)i * 9 + k] = vir[k] * inv;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // blocks [0, B*nchunk): FP64 sums per structure, fixed order (first in the
 // grid, so they start at once and overlap the gather);
