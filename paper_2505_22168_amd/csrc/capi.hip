@@ -16,8 +16,7 @@ namespace gmnn {
 template <int LPA>
 __global__ void pair_moments(DevModel m, DevSystem sys, float* psi, int* counters, int n_counters);
 template <int LPA>
-__global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial, int nh,
-                              int64_t gstride);
+__global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial);
 __global__ void pair_backward_heads(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial, int nh,
                                     int64_t gstride);
 template <int LPA, bool VAR>
@@ -499,7 +498,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
       mark(4);
 #define PAIR_BACKWARD(LPA)                                                                                 \
   hipLaunchKernelGGL(pair_backward<LPA>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair, \
-                     virial, nh, gstride)
+                     virial)
       if (nh > 1) {
         // one backward per head: every pair's geometry serves all heads
         const size_t lds = beta_lds + sizeof(float) * kHeadsAtoms * (size_t)nh * kS * kPacked;

@@ -7,7 +7,9 @@
 //                  as 20 packed symmetric components per channel.
 //   pair_backward  Section 3.3 (forces as gradients): given dE/dPsi (packed),
 //                  the derivative of E_i w.r.t. every pair vector d_p and the
-//                  per-atom virial sum_p g_p (x) d_p.
+//                  per-atom virial sum_p g_p (x) d_p; pair_backward_heads does
+//                  it for every head of a shallow ensemble at once (Section
+//                  2.2, force variance).
 //   finish         F_k = sum_{q in row k} (g_q - g_rev(q)) (scatter-free: every
 //                  force is one gather over the reverse pair index), and in
 //                  extra blocks of the same grid the per-structure energies
@@ -55,13 +57,11 @@ __global__ void __launch_bounds__(kPairBlock) pair_moments(DevModel m, DevSystem
 }
 
 // ---------------------------------------------------------------------------
-// nh heads (one backward each, e.g. for the force variance): psibar
-// [nh][N][100] -> gpair [nh][gstride][3]; the virial written is the mean
-// over the heads
+// one head (the head-mean backward): psibar [N][100] -> gpair [P][3] and
+// the per-atom virial
 template <int LPA>
 __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSystem sys, const float* __restrict__ psibar,
-                                                            float* __restrict__ gpair, float* __restrict__ virial,
-                                                            int nh, int64_t gstride) {
+                                                            float* __restrict__ gpair, float* __restrict__ virial) {
   extern __shared__ float s_beta[];
   stage_beta(m, s_beta);
   __syncthreads();
@@ -72,23 +72,21 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
 #pragma unroll
   for (int k = 0; k < 9; ++k) vir[k] = 0.0f;
   if (live) {
-    for (int hm = 0; hm < nh; ++hm) {
-      float pb[kS * kPacked];
-      const float* src = psibar + ((int64_t)hm * sys.n_atoms + i) * (kS * kPacked);
+    float pb[kS * kPacked];
+    const float* src = psibar + (int64_t)i * (kS * kPacked);
 #pragma unroll
-      for (int k = 0; k < kS * kPacked; ++k) pb[k] = src[k];
-      atom_pair_backward<LPA>(m, sys, s_beta, i, q, pb, gpair + (int64_t)hm * gstride * 3, vir);
-    }
+    for (int k = 0; k < kS * kPacked; ++k) pb[k] = src[k];
+    atom_pair_backward<LPA>(m, sys, s_beta, i, q, pb, gpair, vir);
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) vir[k] = atom_sum<LPA>(vir[k]);
   if (live && q == 0) {
-    const float inv = 1.0f / (float)nh;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) virial[(int64_t)i * 9 + k] = vir[k] * inv;
+    for (int k = 0; k < 9; ++k) virial[(int64_t)i * 9 + k] = vir[k];
   }
 }
 
+// ---------------------------------------------------------------------------
 // One backward per head (nh > 1): 64 lanes per atom, 4 atoms per block; the
 // block's dE/dPsi of every head are staged in LDS after beta, and each pair's
 // geometry and radial basis serve all heads.  Dynamic LDS: beta +
@@ -426,10 +424,10 @@ template __global__ void pair_moments<8>(DevModel, DevSystem, float*, int*, int)
 template __global__ void pair_moments<16>(DevModel, DevSystem, float*, int*, int);
 template __global__ void pair_moments<32>(DevModel, DevSystem, float*, int*, int);
 template __global__ void pair_moments<64>(DevModel, DevSystem, float*, int*, int);
-template __global__ void pair_backward<8>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
-template __global__ void pair_backward<16>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
-template __global__ void pair_backward<32>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
-template __global__ void pair_backward<64>(DevModel, DevSystem, const float*, float*, float*, int, int64_t);
+template __global__ void pair_backward<8>(DevModel, DevSystem, const float*, float*, float*);
+template __global__ void pair_backward<16>(DevModel, DevSystem, const float*, float*, float*);
+template __global__ void pair_backward<32>(DevModel, DevSystem, const float*, float*, float*);
+template __global__ void pair_backward<64>(DevModel, DevSystem, const float*, float*, float*);
 #define FIN(LPA, VAR)                                                                                         \
   template __global__ void finish<LPA, VAR>(int, DevSystem, const float*, const float*, const float*, int, int, \
                                             int64_t, int, double*, int*, float*, float*, double*, double*, double*, \
