@@ -457,7 +457,7 @@ def main():
                     help="training-gradient mode: energy+forces then gmnn_backward per step (FP32)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library runs on one GPU (no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
 
