@@ -286,6 +286,230 @@ __device__ inline void contract_forward_b(const float* __restrict__ P, const flo
   }
 }
 
+// Tangent of the invariants along a direction Pd of the moments (dual
+// numbers): Gd = dG/dPsi . Pd, each family by the product rule, exactly
+// (G is a polynomial of degree <= 3 in Psi).  Same task structure as the
+// primal passes.  Phase A writes the tangent intermediates Id (stride IDS:
+// T7, V8, M5, v6 at the primal offsets) and the tangents of families 1-4;
+// phase B the tangents of families 5-8 from the primal intermediates I
+// (stride IS) and Id.  Gd is FP32 with row stride ldg; the padding features
+// are zeroed.
+#define GM_D1(a, s, i) Pd[(a) * PS + (s) * kFull + 1 + (i)]
+#define GM_D2(a, s, ij) Pd[(a) * PS + (s) * kFull + 4 + (ij)]
+#define GM_D3(a, s, ijk) Pd[(a) * PS + (s) * kFull + 13 + (ijk)]
+template <int TM, int NT, int IDS, int KS = 1>
+__device__ inline void contract_forward_a_dual(const float* __restrict__ P, const float* __restrict__ Pd,
+                                               float* __restrict__ Id, float* __restrict__ Gd, int ldg) {
+  static_assert(KS == 1 || KS == 2, "one or two halves");
+  const int tid = threadIdx.x;
+  for (int t = tid; t < TM * (kFP - kF); t += NT) Gd[(t % TM) * ldg + kF + t / TM] = 0.0f;
+  constexpr int np = TM * 15, ns = TM * kS;
+  constexpr int NTASK = np + ns, NHALF = KS == 1 ? NTASK : (NTASK + 63) / 64 * 64;
+  for (int tt = tid; tt < KS * NHALF; tt += NT) {
+    const int half = KS == 1 ? 0 : tt / NHALF;
+    const int t = KS == 1 ? tt : tt % NHALF;
+    if (t >= NTASK) continue;
+    const bool h0 = KS == 1 || half == 0, h1 = KS == 1 || half == 1;
+    if (t < np) {
+      const int a = t % TM, p = t / TM;
+      const int s1 = pair_first(p), s2 = pair_second(p);
+      if (h0) {
+        float A3[27], B3[27], dA3[27], dB3[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+          A3[k] = GM_P3(a, s1, k);
+          B3[k] = GM_P3(a, s2, k);
+          dA3[k] = GM_D3(a, s1, k);
+          dB3[k] = GM_D3(a, s2, k);
+        }
+        float tr4 = 0.0f;
+#pragma unroll
+        for (int ia = 0; ia < 3; ++ia)
+#pragma unroll
+          for (int ib = 0; ib < 3; ++ib) {
+            float v = 0.0f;
+#pragma unroll
+            for (int cd = 0; cd < 9; ++cd) v += dA3[ia * 9 + cd] * B3[ib * 9 + cd] + A3[ia * 9 + cd] * dB3[ib * 9 + cd];
+            Id[a * IDS + kT7 + p * 9 + ia * 3 + ib] = v;
+            if (ia == ib) tr4 += v;
+          }
+        Gd[a * ldg + kFam4 + p] = tr4;
+      }
+      if (h1) {
+        float A2[9], B2[9], dA2[9], dB2[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          A2[k] = GM_P2(a, s1, k);
+          B2[k] = GM_P2(a, s2, k);
+          dA2[k] = GM_D2(a, s1, k);
+          dB2[k] = GM_D2(a, s2, k);
+        }
+        float tr3 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            float v = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v += dA2[i * 3 + c] * B2[c * 3 + j] + A2[i * 3 + c] * dB2[c * 3 + j];
+            Id[a * IDS + kM5 + p * 9 + i * 3 + j] = v;
+            if (i == j) tr3 += v;
+          }
+        Gd[a * ldg + kFam3 + p] = tr3;
+      }
+    } else {
+      const int u = t - np;
+      const int a = u % TM, sc = u / TM;
+      if (h0) {
+        float A3[27], dA3[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+          A3[k] = GM_P3(a, sc, k);
+          dA3[k] = GM_D3(a, sc, k);
+        }
+#pragma unroll
+        for (int s3 = 0; s3 < kS; ++s3) {
+          float B2[9], dB2[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            B2[k] = GM_P2(a, s3, k);
+            dB2[k] = GM_D2(a, s3, k);
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            float v = 0.0f;
+#pragma unroll
+            for (int bc = 0; bc < 9; ++bc) v += dA3[i * 9 + bc] * B2[bc] + A3[i * 9 + bc] * dB2[bc];
+            Id[a * IDS + kV8 + (sc * 5 + s3) * 3 + i] = v;
+          }
+        }
+      }
+      if (h1) {
+        float C2[9], dC2[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          C2[k] = GM_P2(a, sc, k);
+          dC2[k] = GM_D2(a, sc, k);
+        }
+        float p1[kS][3], d1[kS][3];
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            p1[s1][j] = GM_P1(a, s1, j);
+            d1[s1][j] = GM_D1(a, s1, j);
+          }
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) v += dC2[i * 3 + j] * p1[s1][j] + C2[i * 3 + j] * d1[s1][j];
+            Id[a * IDS + kV6 + (sc * 5 + s1) * 3 + i] = v;
+          }
+        Gd[a * ldg + sc] = Pd[a * PS + sc * kFull];
+#pragma unroll
+        for (int s2 = 0; s2 < kS; ++s2) {
+          if (s2 < sc) continue;
+          float v = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            // the sc entries with sc a runtime index: read them again from LDS
+            v += GM_D1(a, sc, i) * p1[s2][i] + GM_P1(a, sc, i) * d1[s2][i];
+          }
+          Gd[a * ldg + kFam2 + pair_idx(sc, s2)] = v;
+        }
+      }
+    }
+  }
+}
+
+template <int TM, int NT, int IDS>
+__device__ inline void contract_forward_b_dual(const float* __restrict__ P, const float* __restrict__ Pd,
+                                               const float* __restrict__ I, const float* __restrict__ Id,
+                                               float* __restrict__ Gd, int ldg, const Tables& tb) {
+  constexpr int ISTR = IS;
+  constexpr int np = TM * 15, ns = TM * kS;
+  for (int t = threadIdx.x; t < np + ns; t += NT) {
+    if (t < np) {
+      const int a = t % TM, p = t / TM;
+      const int s1 = pair_first(p), s2 = pair_second(p);
+      float t7[9], m5[9], dt7[9], dm5[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        t7[k] = GM_I(a, kT7 + p * 9 + k);
+        m5[k] = GM_I(a, kM5 + p * 9 + k);
+        dt7[k] = Id[a * IDS + kT7 + p * 9 + k];
+        dm5[k] = Id[a * IDS + kM5 + p * 9 + k];
+      }
+#pragma unroll
+      for (int sq = 0; sq < kS; ++sq) {
+        float q[9], dq[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          q[k] = GM_P2(a, sq, k);
+          dq[k] = GM_D2(a, sq, k);
+        }
+        float f7 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f7 += dq[k] * t7[k] + q[k] * dt7[k];
+        Gd[a * ldg + kFam7 + sq * 15 + p] = f7;
+        if (sq >= s2) {
+          float f5 = 0.0f;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) f5 += dm5[k] * q[k] + m5[k] * dq[k];
+          Gd[a * ldg + kFam5 + tb.tri_index[s1 * 25 + s2 * 5 + sq]] = f5;
+        }
+      }
+      float r[3], dr[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        r[i] = GM_P1(a, s2, i);
+        dr[i] = GM_D1(a, s2, i);
+      }
+#pragma unroll
+      for (int s3 = 0; s3 < kS; ++s3) {
+        float f6 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          f6 += Id[a * IDS + kV6 + (s3 * 5 + s1) * 3 + i] * r[i] + GM_I(a, kV6 + (s3 * 5 + s1) * 3 + i) * dr[i];
+        Gd[a * ldg + kFam6 + p * 5 + s3] = f6;
+      }
+    } else {
+      const int u = t - np;
+      const int a = u % TM, s2 = u / TM;
+      float p1[kS][3], d1[kS][3];
+#pragma unroll
+      for (int s1 = 0; s1 < kS; ++s1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          p1[s1][i] = GM_P1(a, s1, i);
+          d1[s1][i] = GM_D1(a, s1, i);
+        }
+#pragma unroll
+      for (int s3 = 0; s3 < kS; ++s3) {
+        float w[3], dw[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          w[i] = GM_I(a, kV8 + (s2 * 5 + s3) * 3 + i);
+          dw[i] = Id[a * IDS + kV8 + (s2 * 5 + s3) * 3 + i];
+        }
+#pragma unroll
+        for (int s1 = 0; s1 < kS; ++s1) {
+          float f8 = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) f8 += d1[s1][i] * w[i] + p1[s1][i] * dw[i];
+          Gd[a * ldg + kFam8 + s1 * 25 + s2 * 5 + s3] = f8;
+        }
+      }
+    }
+  }
+}
+#undef GM_D1
+#undef GM_D2
+#undef GM_D3
+
 #define GM_GB(a, f) Gb[(a) * ldgb + (f)]
 
 // Phase A of the backward: intermediates U8, Y, Qv (read P and dE/dG).

@@ -147,8 +147,9 @@ struct TrainLds {
   static constexpr size_t ptmp = psid + al(4 * (size_t)TA * PS);
   static constexpr size_t inter = ptmp + al(4 * (size_t)TA * PS);
   static constexpr size_t gt = inter + al(4 * (size_t)TA * IS);           // [16][LDG]: G rows 0-7, Gdot rows 8-15
-  static constexpr size_t gtmp = gt + al(4 * (size_t)16 * LDG);           // [8][LDG] scratch invariants; later Gbar [16][LDGB]
-  static constexpr size_t gtmp_bytes = mx(4 * (size_t)TA * LDG, 4 * (size_t)16 * LDGB);
+  static constexpr size_t gtmp = gt + al(4 * (size_t)16 * LDG);           // scratch (see gtmp_bytes)
+  // scratch: the tangent intermediates [8][ISF], later Gbar [16][LDGB]
+  static constexpr size_t gtmp_bytes = mx(4 * (size_t)TA * ISF, 4 * (size_t)16 * LDGB);
   static constexpr size_t ht = gtmp + al(gtmp_bytes);                      // [16][LDH]: h1 / delta tiles
   static constexpr size_t pba = ht + al(4 * (size_t)16 * LDH);            // Psibar accumulator [8][PS]
   static constexpr size_t pbs = pba + al(4 * (size_t)TA * PS);            // scratch full gradient [8][PS]
@@ -247,26 +248,12 @@ __global__ void __launch_bounds__(kTrainThreads)
   __syncthreads();
   contract_forward_b<TA, kTrainThreads, false>(sPsi, sI, sGT, L::LDG, tb);
   __syncthreads();
-  // Gdot = [8 (G(+t) - G(-t)) - (G(+2t) - G(-2t))] / (12 t)
-  const float cf[4] = {1.0f, -1.0f, 2.0f, -2.0f};
-  const float wf[4] = {8.0f, -8.0f, -1.0f, 1.0f};
-  for (int ev = 0; ev < 4; ++ev) {
-    for (int t = tid; t < TA * kS * kFull; t += kTrainThreads) {
-      const int a = t % TA, e = t / TA;
-      sPt[a * PS + e] = sPsi[a * PS + e] + cf[ev] * sT[a] * sPd[a * PS + e];
-    }
-    __syncthreads();
-    contract_forward_a<TA, kTrainThreads, false, true, IS, kFwdSplit>(sPt, sI, sGtmp, L::LDG, tb);
-    __syncthreads();
-    contract_forward_b<TA, kTrainThreads, false>(sPt, sI, sGtmp, L::LDG, tb);
-    __syncthreads();
-    for (int t = tid; t < TA * kFP; t += kTrainThreads) {
-      const int a = t / kFP, f = t % kFP;
-      const float v = wf[ev] * sGtmp[a * L::LDG + f] / (12.0f * sT[a]);
-      sGT[(8 + a) * L::LDG + f] = (ev == 0 ? 0.0f : sGT[(8 + a) * L::LDG + f]) + v;
-    }
-    __syncthreads();
-  }
+  // Gdot = dG/dPsi . Psidot in dual numbers (exact: G is a polynomial in
+  // Psi); the tangent intermediates use the scratch region
+  contract_forward_a_dual<TA, kTrainThreads, ISF, kFwdSplit>(sPsi, sPd, sGtmp, sGT + 8 * L::LDG, L::LDG);
+  __syncthreads();
+  contract_forward_b_dual<TA, kTrainThreads, ISF>(sPsi, sPd, sI, sGtmp, sGT + 8 * L::LDG, L::LDG, tb);
+  __syncthreads();
   // the first weight fragments of the network start loading now; each
   // product then fills the ring of the next one as soon as its own
   // fragments are consumed, ahead of its epilogue and barrier
