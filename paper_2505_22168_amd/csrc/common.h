@@ -46,6 +46,18 @@ __device__ inline int xcd_block(int b, int nb) {
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return __lane_id(); }
 
+// Sum over the 16 lanes of a row by DPP row rotations (8, 4, 2, 1), in
+// registers.  Lane 0 of the row ends with the same value, bit for bit, as
+// an xor butterfly over the row (at each level it adds the same two partial
+// sums); other lanes hold other orderings of the row sum.
+__device__ inline float row16_rot_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, false));  // row_ror:8
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, false));  // row_ror:4
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xf, 0xf, false));  // row_ror:2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, false));  // row_ror:1
+  return v;
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll

@@ -321,10 +321,7 @@ __global__ void __launch_bounds__(kRoThreads)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float v = part[j];
-          v += __shfl_xor(v, 8, 16);
-          v += __shfl_xor(v, 4, 16);
-          v += __shfl_xor(v, 2, 16);
-          v += __shfl_xor(v, 1, 16);
+          v = row16_rot_sum(v);  // lane 0 of the row: the xor-butterfly sum
           if ((l & 15) == 0) sEp[(w * TM + r * 16 + 4 * (l >> 4) + j) * M + hm] = v;
         }
       }

@@ -337,10 +337,7 @@ __global__ void __launch_bounds__(kTrainThreads)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float v = ypart[j];
-      v += __shfl_xor(v, 8, 16);
-      v += __shfl_xor(v, 4, 16);
-      v += __shfl_xor(v, 2, 16);
-      v += __shfl_xor(v, 1, 16);
+      v = row16_rot_sum(v);  // lane 0 of the row: the xor-butterfly sum
       if ((l & 15) == 0) sEp[w * 16 + 4 * (l >> 4) + j] = v;
     }
     __syncthreads();  // everyone has read h1 (sH) for the product above
