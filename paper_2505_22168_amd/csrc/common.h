@@ -46,6 +46,21 @@ __device__ inline int xcd_block(int b, int nb) {
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return __lane_id(); }
 
+// The value held by lane l ^ 32 (lane_xor32) or l ^ 16 (lane_xor16), in
+// registers: a permlane swap of the value with itself hands every lane its
+// partner's copy in one of the two outputs (no LDS round trip, unlike a
+// shuffle).
+__device__ inline float lane_xor32(float v) {
+  const unsigned u = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return __uint_as_float(lane_id() < 32 ? r[1] : r[0]);
+}
+__device__ inline float lane_xor16(float v) {
+  const unsigned u = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return __uint_as_float(((lane_id() >> 4) & 1) ? r[0] : r[1]);
+}
+
 // Sum over the 16 lanes of a row by DPP row rotations (8, 4, 2, 1), in
 // registers.  Lane 0 of the row ends with the same value, bit for bit, as
 // an xor butterfly over the row (at each level it adds the same two partial

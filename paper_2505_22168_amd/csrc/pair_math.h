@@ -115,8 +115,8 @@ __device__ inline float atom_sum(float v) {
     return v;
   }
   v = row16_sum(v);
-  if (LPA >= 32) v += __shfl_xor(v, 16, 64);
-  if (LPA == 64) v += __shfl_xor(v, 32, 64);
+  if (LPA >= 32) v += lane_xor16(v);
+  if (LPA == 64) v += lane_xor32(v);
   return v;
 }
 

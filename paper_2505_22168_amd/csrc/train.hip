@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(kTrainThreads)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float zv = acc[i][j] + (prim ? bias : 0.0f);
-        const float other = __shfl_xor(zv, 32, 64);
+        const float other = lane_xor32(zv);
         const float z1 = prim ? zv : other, zd = prim ? other : zv;
         float s, d1, d2;
         swish_d2(z1, s, d1, d2);
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(kTrainThreads)
         const int row = 4 * (l >> 4) + j;
         const int a = row & 7;
         const float zv = acc[i][j] + (prim ? bias : 0.0f);
-        const float other = __shfl_xor(zv, 32, 64);
+        const float other = lane_xor32(zv);
         const float z2 = prim ? zv : other, zd = prim ? other : zv;
         float h2, d1, dd;
         swish_d2(z2, h2, d1, dd);
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(kTrainThreads)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float hv = acc[i][j];                // primal lanes: h1bar, tangent lanes: h1dotbar
-        const float other = __shfl_xor(hv, 32, 64);
+        const float other = lane_xor32(hv);
         const float hbar = prim ? hv : other, hdbar = prim ? other : hv;
         const float out = prim ? (hbar * s1d[i][j] + hdbar * s1dd[i][j] * z1dot[i][j]) : (hdbar * s1d[i][j]);
         if (nb < NBH) sH[(4 * (l >> 4) + j) * L::LDH + col] = out;
