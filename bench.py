@@ -413,10 +413,11 @@ def run_train(args):
     grads = {}
     for prec in ("bf16", "fp32"):
         ev = g.EnergyForces(model, system, nl, precision=prec, stress=False)
+        gout = {k: torch.empty_like(v) for k, v in model.tensors.items()}
 
         def step():
             ev()
-            return g.param_grads(model, system, nl, dE, dF, workspace=ws, precision=prec)
+            return g.param_grads(model, system, nl, dE, dF, workspace=ws, precision=prec, out=gout)
         t = _wall(step, args.steps, args.warmup)
         t_fwd = _wall(ev, args.steps, args.warmup)
         grads[prec] = step()

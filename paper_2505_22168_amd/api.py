@@ -401,12 +401,16 @@ def maxwell_boltzmann(masses, temperature: float, seed: int):
 
 # ---------------------------------------------------------------------------
 def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, workspace=None,
-                precision: str = "fp32"):
+                precision: str = "fp32", out=None):
     """Gradients of a loss w.r.t. every model parameter (gmnn_backward), given
     dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3];
     precision "bf16" runs the network products of the double backward in BF16
     and the weight-gradient products as three BF16 products of split FP32
-    operands (about 16 significant bits per product)."""
+    operands (about 16 significant bits per product).
+
+    `out` (a dict of FP32 device tensors shaped like model.tensors) receives
+    the gradients; the call overwrites every element, so neither `out` nor a
+    freshly allocated result needs clearing first."""
     if precision not in ("fp32", "bf16"):
         raise ValueError(precision)
     flags = A.GMNN_PREC_BF16 if precision == "bf16" else 0
@@ -414,7 +418,14 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
     dev = system.device
     dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=dev).contiguous()
     dF = torch.as_tensor(dL_dF, dtype=torch.float32, device=dev).reshape(-1, 3).contiguous()
-    grads = {k: torch.zeros_like(v) for k, v in model.tensors.items()}
+    if out is None:
+        grads = {k: torch.empty_like(v) for k, v in model.tensors.items()}
+    else:
+        grads = out
+        for k, v in model.tensors.items():
+            g = grads[k]
+            if g.shape != v.shape or g.dtype != torch.float32 or g.device != v.device or not g.is_contiguous():
+                raise ValueError(f"out[{k!r}] must be a contiguous float32 tensor of shape {tuple(v.shape)} on {v.device}")
     gc = A.gmnn_param_grads(*[_ptr(grads[k]) for k in PARAM_NAMES])
     mc, sc, nc = model.c(), system.c(), nl.c()
     nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), 0)

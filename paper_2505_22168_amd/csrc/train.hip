@@ -10,9 +10,9 @@
 // the position perturbation lambda.  D is evaluated in forward (tangent)
 // mode and Phi differentiated in reverse mode:
 //   pair_tangent    Psidot_i = sum_p dPsi/dd_p . delta_p
-//   train_tile      per 8 atoms: invariants G and their tangent Gdot (the
-//                   invariants are cubic in Psi, so Gdot is the exact 4-point
-//                   difference of G along Psidot); the network forward in
+//   train_tile      per 8 atoms: invariants G and their tangent Gdot (in
+//                   dual numbers: the product rule on every contraction
+//                   family, exact since G is a polynomial); the network forward in
 //                   dual numbers with primal and tangent rows stacked into one
 //                   16-row MFMA tile; its reverse pass; the invariant
 //                   backward Psibar = J^T Gbar + (d/dPsi J Psidot)^T Gdotbar
@@ -760,10 +760,25 @@ __global__ void species_finish(DevModel m, const double* __restrict__ sp, int nb
   const int t = threadIdx.x;
   const int nsp = m.n_species;
   if (t > nsp) return;
+  // block partials added in block order; the loads of 8 blocks are issued
+  // before their adds so they overlap
+  constexpr int kBatch = 8;
   double s1 = 0.0, s2 = 0.0;
-  for (int b = 0; b < nblocks; ++b) {
-    s1 += sp[((int64_t)b * (kMaxSpecies + 1) + t) * 2];
-    s2 += sp[((int64_t)b * (kMaxSpecies + 1) + t) * 2 + 1];
+  for (int b0 = 0; b0 < nblocks; b0 += kBatch) {
+    double x[kBatch], y[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int64_t o = ((int64_t)std::min(b0 + j, nblocks - 1) * (kMaxSpecies + 1) + t) * 2;
+      x[j] = sp[o];
+      y[j] = sp[o + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      if (b0 + j < nblocks) {
+        s1 += x[j];
+        s2 += y[j];
+      }
+    }
   }
   if (t < nsp) {
     gscale[t] = (float)s1;

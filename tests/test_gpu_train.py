@@ -117,3 +117,27 @@ def test_bf16_param_gradients_within_budget():
         print(f"{k}: bf16 rel err {e16:.2e}, fp32 rel err {e32:.2e}")
         assert e16 < 3e-2, (k, e16)
         assert e32 < 1e-4, (k, e32)
+
+
+def test_param_gradients_overwrite_every_element():
+    """gmnn_backward overwrites every element of every gradient array: arrays
+    filled with NaN beforehand come back finite and equal, bit for bit, to a
+    fresh call's, on two calls in a row in each precision."""
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(hidden=(64, 64), n_structs=3, n_lo=30, n_hi=70)
+    _, _, dLdE, dLdF = loss_and_param_grads(batch, params, onl, Er, Fr)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, params.spec.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    for prec in ("fp32", "bf16"):
+        fresh = g.param_grads(model, system, nl, dLdE, dLdF, precision=prec)
+        out = {k: torch.full_like(v, float("nan")) for k, v in model.tensors.items()}
+        for _ in range(2):
+            got = g.param_grads(model, system, nl, dLdE, dLdF, precision=prec, out=out)
+            assert got is out
+            torch.cuda.synchronize()
+            for k in PARAM_NAMES:
+                assert torch.isfinite(out[k]).all(), (prec, k)
+                assert torch.equal(out[k], fresh[k]), (prec, k)
+    with pytest.raises(ValueError):
+        g.param_grads(model, system, nl, dLdE, dLdF, out={k: v.double() for k, v in model.tensors.items()})
