@@ -308,9 +308,9 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
  * accumulation, the operands rounded as in gmnn_energy_forces; the products
  * that form the weight gradients split each FP32 operand into a BF16 high
  * and low part and add the three products hi.hi + hi.lo + lo.hi (about 16
- * significant bits per product).  Without it everything is FP32.  Requires
- * the workspace of gmnn_energy_forces for the same inputs; recomputes the
- * forward pass itself. */
+ * significant bits per product).  Without it everything is FP32.  The
+ * workspace must hold gmnn_workspace_bytes(GMNN_OP_BACKWARD, ...).
+ * Recomputes the forward pass itself. */
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
                           const double* dL_dE, const float* dL_dF, uint32_t flags,
                           gmnn_param_grads* grads, float* dL_dpos,
