@@ -663,6 +663,100 @@ __global__ void __launch_bounds__(256) weight_grad(const float* __restrict__ A, 
       }
 }
 
+// The split product of weight_grad<true> for M and N multiples of 128, with
+// the operand rows staged through LDS: a block of 4 waves owns a 128 x 128
+// block of C (2 x 2 waves of 64 x 64, with the fragments and the MFMA
+// sequence of weight_grad<true>).  Per k-step of 32
+// rows every thread loads 16 rows of one column of A and of B, splits them
+// once for the whole block, and writes them to LDS as k-contiguous hi and lo
+// runs; the next k-step's loads are issued before the current step's MFMAs.
+constexpr int kWgBlk = 128;  // block tile edge
+constexpr int kWgLdk = 40;   // LDS row stride in bf16 (32 k + 8 pad)
+__global__ void __launch_bounds__(256) weight_grad_staged(const float* __restrict__ A, int ldA,
+                                                          const float* __restrict__ B, int ldB, int Mdim, int Ndim,
+                                                          int64_t K, int64_t kchunk, float* __restrict__ partial) {
+  // [Ahi, Alo, Bhi, Blo][column][k]
+  __shared__ __attribute__((aligned(16))) __bf16 sm[4][kWgBlk * kWgLdk];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int tiles_n = Ndim / kWgBlk;
+  const int mb = (blockIdx.x / tiles_n) * kWgBlk, nb = (blockIdx.x % tiles_n) * kWgBlk;
+  const int m0 = (w >> 1) * 64, n0 = (w & 1) * 64;  // the wave's block inside the block tile
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  // staging: thread tid loads rows 16 h .. 16 h + 15 of column col of the step
+  const int col = tid & (kWgBlk - 1), h = tid >> 7;
+  const float* ap = A + mb + col;
+  const float* bp = B + nb + col;
+  float ra[16], rb[16];
+  auto fetch = [&](int64_t k) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int64_t kk = k + 16 * h + e;
+      const bool ok = kk < ke;
+      ra[e] = ok ? ap[kk * ldA] : 0.0f;
+      rb[e] = ok ? bp[kk * ldB] : 0.0f;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k = kb; k < ke; k += 32) {
+    __syncthreads();  // the previous step's fragment reads are done
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      bf16x8 ah, al, bh, bl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = ra[8 * half + e], y = rb[8 * half + e];
+        const __bf16 xh = (__bf16)x, yh = (__bf16)y;
+        ah[e] = xh;
+        al[e] = (__bf16)(x - (float)xh);
+        bh[e] = yh;
+        bl[e] = (__bf16)(y - (float)yh);
+      }
+      const int o = col * kWgLdk + 16 * h + 8 * half;
+      *(bf16x8*)&sm[0][o] = ah;
+      *(bf16x8*)&sm[1][o] = al;
+      *(bf16x8*)&sm[2][o] = bh;
+      *(bf16x8*)&sm[3][o] = bl;
+    }
+    __syncthreads();
+    if (k + 32 < ke) fetch(k + 32);
+    // lane l supplies A^T[m = l&15][k = 8 (l>>4) + e] and B[k = 8 (l>>4) + e][n = l&15]
+    bf16x8 bh[4], bl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int o = (n0 + 16 * c + (l & 15)) * kWgLdk + 8 * (l >> 4);
+      bh[c] = *(const bf16x8*)&sm[2][o];
+      bl[c] = *(const bf16x8*)&sm[3][o];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = (m0 + 16 * r + (l & 15)) * kWgLdk + 8 * (l >> 4);
+      const bf16x8 ah = *(const bf16x8*)&sm[0][o];
+      const bf16x8 al = *(const bf16x8*)&sm[1][o];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[c], acc[r][c], 0, 0, 0);
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[c], acc[r][c], 0, 0, 0);
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[c], acc[r][c], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = mb + m0 + r * 16 + 4 * (l >> 4) + j, cc = nb + n0 + c * 16 + (l & 15);
+        partial[((int64_t)blockIdx.y * Mdim + row) * Ndim + cc] = acc[r][c][j];
+      }
+}
+
 // out[i] = sum_c partial[c][i], chunks in order (eight loads in flight)
 __global__ void sum_partials(const float* __restrict__ partial, int nchunks, int64_t n, float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -970,11 +1064,19 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
     const int t2 = (HP / 64) * (HP / 64);
     if (L.kchunks > 0) {
       // the BF16 path takes the split-BF16 products, the FP32 path plain FP32
-      auto wg = bf16 ? weight_grad<true> : weight_grad<false>;
-      hipLaunchKernelGGL(wg, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
-                         (int64_t)kWgRows, part1);
-      hipLaunchKernelGGL(wg, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
-                         (int64_t)kWgRows, part2);
+      if (bf16 && HP % kWgBlk == 0) {
+        // kFP and HP are multiples of the staged kernel's 128-wide block tile
+        hipLaunchKernelGGL(weight_grad_staged, dim3((kFP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0, s,
+                           X1, kFP, Y1, HP, kFP, HP, L.K, (int64_t)kWgRows, part1);
+        hipLaunchKernelGGL(weight_grad_staged, dim3((HP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0, s,
+                           X2, HP, Y2, HP, HP, HP, L.K, (int64_t)kWgRows, part2);
+      } else {
+        auto wg = bf16 ? weight_grad<true> : weight_grad<false>;
+        hipLaunchKernelGGL(wg, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
+                           (int64_t)kWgRows, part1);
+        hipLaunchKernelGGL(wg, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
+                           (int64_t)kWgRows, part2);
+      }
     }
     const int64_t n1 = (int64_t)kFP * HP, n2 = (int64_t)HP * HP;
     hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part1, L.kchunks, n1, sum1);
