@@ -757,10 +757,8 @@ __global__ void __launch_bounds__(256) weight_grad_staged(const float* __restric
       }
 }
 
-// out[i] = sum_c partial[c][i], chunks in order (eight loads in flight)
-__global__ void sum_partials(const float* __restrict__ partial, int nchunks, int64_t n, float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// sum_c partial[c][i], chunks in order (eight loads in flight)
+__device__ inline float sum_chunks(const float* __restrict__ partial, int nchunks, int64_t n, int64_t i) {
   float v = 0.0f;
   int c = 0;
   for (; c + 8 <= nchunks; c += 8) {
@@ -771,7 +769,24 @@ __global__ void sum_partials(const float* __restrict__ partial, int nchunks, int
     for (int u = 0; u < 8; ++u) v += x[u];
   }
   for (; c < nchunks; ++c) v += partial[(int64_t)c * n + i];
-  out[i] = v;
+  return v;
+}
+
+// out[i] = sum_c partial[c][i]
+__global__ void sum_partials(const float* __restrict__ partial, int nchunks, int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = sum_chunks(partial, nchunks, n, i);
+}
+
+// the same sums of a padded [.][ld] gradient (n = padded size), written
+// unpadded into the caller's [rows][cols] array
+__global__ void sum_partials_unpad(const float* __restrict__ partial, int nchunks, int64_t n, int ld, int rows,
+                                   int cols, float* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * cols) return;
+  const int r = (int)(t / cols), c = (int)(t % cols);
+  dst[t] = sum_chunks(partial, nchunks, n, (int64_t)r * ld + c);
 }
 
 // column sums, stage 1: partial[chunk][c] = sum of Y[k][c] over the rows k
@@ -890,14 +905,6 @@ __global__ void w3_broadcast(const float* __restrict__ w3sum, int H2, int M, flo
   for (int hm = 0; hm < M; ++hm) gw3[(int64_t)h * M + hm] = w3sum[h];
 }
 
-// unpad a [HP or kFP rows][HP cols] gradient into the caller's [F][H1] / [H1][H2] array
-__global__ void unpad_copy(const float* __restrict__ src, int ld, int rows, int cols, float* __restrict__ dst) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)rows * cols) return;
-  const int r = (int)(t / cols), c = (int)(t % cols);
-  dst[t] = src[(int64_t)r * ld + c];
-}
-
 // beta gradient: sum of block partials in block order
 __global__ void beta_unpack(const float* __restrict__ summed, int nsp, int K, float* __restrict__ gbeta) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -928,7 +935,7 @@ static gmnn_status launch_train_tile_t(const DevModel& m, const DevSystem& sys, 
 }
 
 struct TrainLayout {
-  size_t psi, psidot, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, part1, part2, sum1, sum2, bpart, bsum;
+  size_t psi, psidot, psibar, psidotbar, X1, Y1, X2, Y2, w3g, qsig, part1, part2, bpart, bsum;
   size_t cpart, w3sum, spart, bytes;
   int ccK, ccN;        // row chunks of the column sums over K rows / over N atoms
   int64_t rcK, rcN;    // rows per chunk of those sums
@@ -963,8 +970,6 @@ TrainLayout train_layout(int n_atoms, int HP, int nsp) {
   L.qsig = take(4 * N);
   L.part1 = take(4 * (size_t)L.kchunks * kFP * HP);
   L.part2 = take(4 * (size_t)L.kchunks * HP * HP);
-  L.sum1 = take(4 * (size_t)kFP * HP);
-  L.sum2 = take(4 * (size_t)HP * HP);
   const size_t nslots = (size_t)nsp * nsp * kS * kMaxBasis;
   L.bpart = take(4 * (size_t)L.beta_blocks * nslots);
   L.bsum = take(4 * nslots);
@@ -1006,8 +1011,6 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
   float* qsig = (float*)(W + L.qsig);
   float* part1 = (float*)(W + L.part1);
   float* part2 = (float*)(W + L.part2);
-  float* sum1 = (float*)(W + L.sum1);
-  float* sum2 = (float*)(W + L.sum2);
   float* bpart = (float*)(W + L.bpart);
   float* bsum = (float*)(W + L.bsum);
   const int N = sys.n_atoms;
@@ -1079,10 +1082,11 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
       }
     }
     const int64_t n1 = (int64_t)kFP * HP, n2 = (int64_t)HP * HP;
-    hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, part1, L.kchunks, n1, sum1);
-    hipLaunchKernelGGL(sum_partials, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, part2, L.kchunks, n2, sum2);
-    hipLaunchKernelGGL(unpad_copy, dim3((kF * H1 + 255) / 256), dim3(256), 0, s, sum1, HP, kF, H1, g->W1);
-    hipLaunchKernelGGL(unpad_copy, dim3((H1 * H2 + 255) / 256), dim3(256), 0, s, sum2, HP, H1, H2, g->W2);
+    // [kFP][HP] and [HP][HP] partials summed straight into the caller's [F][H1] and [H1][H2]
+    hipLaunchKernelGGL(sum_partials_unpad, dim3((kF * H1 + 255) / 256), dim3(256), 0, s, part1, L.kchunks, n1, HP,
+                       kF, H1, g->W1);
+    hipLaunchKernelGGL(sum_partials_unpad, dim3((H1 * H2 + 255) / 256), dim3(256), 0, s, part2, L.kchunks, n2, HP,
+                       H1, H2, g->W2);
   }
   // bias, W3, scale/shift gradients: two-stage sums with chunk partials added in order
   float* cpart = (float*)(W + L.cpart);
