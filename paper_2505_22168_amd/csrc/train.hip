@@ -757,6 +757,91 @@ __global__ void __launch_bounds__(256) weight_grad_staged(const float* __restric
       }
 }
 
+// The FP32 product of weight_grad<false> for M and N multiples of 128,
+// staged through LDS like weight_grad_staged (128 x 128 block tile, 2 x 2
+// waves of 64 x 64, k-steps of 32 rows, the next step's rows in flight
+// during the MFMAs).  A column's 32 rows are stored permuted, row k at
+// 8 (k % 4) + k / 4, so that the 8 values lane l supplies over the step's
+// eight 16x16x4 products (rows 4 u + (l >> 4), u < 8) are contiguous.  The
+// MFMA sequence per element is weight_grad<false>'s.
+constexpr int kWgLdkF = 36;  // LDS row stride in floats (32 k + 4 pad)
+__global__ void __launch_bounds__(256) weight_grad_staged_f32(const float* __restrict__ A, int ldA,
+                                                              const float* __restrict__ B, int ldB, int Mdim,
+                                                              int Ndim, int64_t K, int64_t kchunk,
+                                                              float* __restrict__ partial) {
+  // [A, B][column][permuted k]
+  __shared__ __attribute__((aligned(16))) float sm[2][kWgBlk * kWgLdkF];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int tiles_n = Ndim / kWgBlk;
+  const int mb = (blockIdx.x / tiles_n) * kWgBlk, nb = (blockIdx.x % tiles_n) * kWgBlk;
+  const int m0 = (w >> 1) * 64, n0 = (w & 1) * 64;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int col = tid & (kWgBlk - 1), h = tid >> 7;
+  const float* ap = A + mb + col;
+  const float* bp = B + nb + col;
+  float ra[16], rb[16];
+  auto fetch = [&](int64_t k) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int64_t kk = k + 16 * h + e;
+      const bool ok = kk < ke;
+      ra[e] = ok ? ap[kk * ldA] : 0.0f;
+      rb[e] = ok ? bp[kk * ldB] : 0.0f;
+    }
+  };
+  if (kb < ke) fetch(kb);
+  for (int64_t k = kb; k < ke; k += 32) {
+    __syncthreads();  // the previous step's fragment reads are done
+    // rows 16 h + e, e = q + 4 j (j < 4), go to 8 q + 4 h + j: one float4 per q
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = col * kWgLdkF + 8 * q + 4 * h;
+      *(floatx4*)&sm[0][o] = floatx4{ra[q], ra[q + 4], ra[q + 8], ra[q + 12]};
+      *(floatx4*)&sm[1][o] = floatx4{rb[q], rb[q + 4], rb[q + 8], rb[q + 12]};
+    }
+    __syncthreads();
+    if (k + 32 < ke) fetch(k + 32);
+    // lane l's values for products u < 8: rows 4 u + (l >> 4), stored at 8 (l >> 4) + u
+    floatx4 bf[4][2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int o = (n0 + 16 * c + (l & 15)) * kWgLdkF + 8 * (l >> 4);
+      bf[c][0] = *(const floatx4*)&sm[1][o];
+      bf[c][1] = *(const floatx4*)&sm[1][o + 4];
+    }
+    floatx4 af[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = (m0 + 16 * r + (l & 15)) * kWgLdkF + 8 * (l >> 4);
+      af[r][0] = *(const floatx4*)&sm[0][o];
+      af[r][1] = *(const floatx4*)&sm[0][o + 4];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r][u >> 2][u & 3], bf[c][u >> 2][u & 3], acc[r][c], 0,
+                                                           0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = mb + m0 + r * 16 + 4 * (l >> 4) + j, cc = nb + n0 + c * 16 + (l & 15);
+        partial[((int64_t)blockIdx.y * Mdim + row) * Ndim + cc] = acc[r][c][j];
+      }
+}
+
 // sum_c partial[c][i], chunks in order (eight loads in flight)
 __device__ inline float sum_chunks(const float* __restrict__ partial, int nchunks, int64_t n, int64_t i) {
   float v = 0.0f;
@@ -1073,6 +1158,11 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
                            X1, kFP, Y1, HP, kFP, HP, L.K, (int64_t)kWgRows, part1);
         hipLaunchKernelGGL(weight_grad_staged, dim3((HP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0, s,
                            X2, HP, Y2, HP, HP, HP, L.K, (int64_t)kWgRows, part2);
+      } else if (HP % kWgBlk == 0) {
+        hipLaunchKernelGGL(weight_grad_staged_f32, dim3((kFP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0,
+                           s, X1, kFP, Y1, HP, kFP, HP, L.K, (int64_t)kWgRows, part1);
+        hipLaunchKernelGGL(weight_grad_staged_f32, dim3((HP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0,
+                           s, X2, HP, Y2, HP, HP, HP, L.K, (int64_t)kWgRows, part2);
       } else {
         auto wg = bf16 ? weight_grad<true> : weight_grad<false>;
         hipLaunchKernelGGL(wg, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
