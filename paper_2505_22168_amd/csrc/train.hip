@@ -577,7 +577,8 @@ __global__ void __launch_bounds__(kBetaMaxThreads) pair_beta_grad(DevModel m, De
 //                  hi.hi + hi.lo + lo.hi on BF16 MFMA 16x16x32 with FP32
 //                  accumulation: about 16 significant bits per product (the
 //                  dropped lo.lo is below 2^-16 of |a b|) at the BF16 rate.
-constexpr int kWgRows = 1024;  // rows per split-K chunk
+constexpr int kWgRows = 1024;    // rows per split-K chunk
+constexpr int kWgRowsF32 = 512;  // rows per chunk of weight_grad_staged_f32 (twice the blocks)
 template <bool SPLIT>
 __global__ void __launch_bounds__(256) weight_grad(const float* __restrict__ A, int ldA, const float* __restrict__ B,
                                                    int ldB, int Mdim, int Ndim, int64_t K, int64_t kchunk,
@@ -1026,7 +1027,7 @@ struct TrainLayout {
   int64_t rcK, rcN;    // rows per chunk of those sums
   int sp_blocks;       // blocks of the per-species sums
   int64_t K;           // weight-product rows
-  int kchunks;
+  int kchunks;          // split-K chunks the partial buffers hold (the larger count)
   int beta_blocks;
 };
 
@@ -1041,7 +1042,7 @@ TrainLayout train_layout(int n_atoms, int HP, int nsp) {
   const size_t N = (size_t)n_atoms;
   const int64_t tiles = (n_atoms + kTA - 1) / kTA;
   L.K = tiles * 16;
-  L.kchunks = (int)((L.K + kWgRows - 1) / kWgRows);
+  L.kchunks = (int)((L.K + kWgRowsF32 - 1) / kWgRowsF32);
   L.beta_blocks = 256;
   L.psi = take(4 * N * 100);
   L.psidot = take(4 * N * 100);
@@ -1146,36 +1147,39 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
   }
   hipLaunchKernelGGL(pair_beta_grad, dim3(L.beta_blocks), dim3(64 * beta_waves), beta_lds * (1 + beta_waves), s, m, sys,
                      lambda, psibar, psidotbar, bpart);
-  // weight products, split over chunks of kWgRows rows, partials summed in chunk order
+  // weight products, split over chunks of rows, partials summed in chunk order
+  const bool staged = HP % kWgBlk == 0;
+  const int64_t wg_rows = (staged && !bf16) ? kWgRowsF32 : kWgRows;
+  const int kch = (int)((L.K + wg_rows - 1) / wg_rows);
   {
     const int t1 = (kFP / 64) * (HP / 64);
     const int t2 = (HP / 64) * (HP / 64);
-    if (L.kchunks > 0) {
+    if (kch > 0) {
       // the BF16 path takes the split-BF16 products, the FP32 path plain FP32
-      if (bf16 && HP % kWgBlk == 0) {
+      if (bf16 && staged) {
         // kFP and HP are multiples of the staged kernel's 128-wide block tile
-        hipLaunchKernelGGL(weight_grad_staged, dim3((kFP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0, s,
-                           X1, kFP, Y1, HP, kFP, HP, L.K, (int64_t)kWgRows, part1);
-        hipLaunchKernelGGL(weight_grad_staged, dim3((HP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0, s,
-                           X2, HP, Y2, HP, HP, HP, L.K, (int64_t)kWgRows, part2);
-      } else if (HP % kWgBlk == 0) {
-        hipLaunchKernelGGL(weight_grad_staged_f32, dim3((kFP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0,
-                           s, X1, kFP, Y1, HP, kFP, HP, L.K, (int64_t)kWgRows, part1);
-        hipLaunchKernelGGL(weight_grad_staged_f32, dim3((HP / kWgBlk) * (HP / kWgBlk), L.kchunks), dim3(256), 0,
-                           s, X2, HP, Y2, HP, HP, HP, L.K, (int64_t)kWgRows, part2);
+        hipLaunchKernelGGL(weight_grad_staged, dim3((kFP / kWgBlk) * (HP / kWgBlk), kch), dim3(256), 0, s,
+                           X1, kFP, Y1, HP, kFP, HP, L.K, wg_rows, part1);
+        hipLaunchKernelGGL(weight_grad_staged, dim3((HP / kWgBlk) * (HP / kWgBlk), kch), dim3(256), 0, s,
+                           X2, HP, Y2, HP, HP, HP, L.K, wg_rows, part2);
+      } else if (staged) {
+        hipLaunchKernelGGL(weight_grad_staged_f32, dim3((kFP / kWgBlk) * (HP / kWgBlk), kch), dim3(256), 0,
+                           s, X1, kFP, Y1, HP, kFP, HP, L.K, wg_rows, part1);
+        hipLaunchKernelGGL(weight_grad_staged_f32, dim3((HP / kWgBlk) * (HP / kWgBlk), kch), dim3(256), 0,
+                           s, X2, HP, Y2, HP, HP, HP, L.K, wg_rows, part2);
       } else {
         auto wg = bf16 ? weight_grad<true> : weight_grad<false>;
-        hipLaunchKernelGGL(wg, dim3((t1 + 3) / 4, L.kchunks), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
-                           (int64_t)kWgRows, part1);
-        hipLaunchKernelGGL(wg, dim3((t2 + 3) / 4, L.kchunks), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
-                           (int64_t)kWgRows, part2);
+        hipLaunchKernelGGL(wg, dim3((t1 + 3) / 4, kch), dim3(256), 0, s, X1, kFP, Y1, HP, kFP, HP, L.K,
+                           wg_rows, part1);
+        hipLaunchKernelGGL(wg, dim3((t2 + 3) / 4, kch), dim3(256), 0, s, X2, HP, Y2, HP, HP, HP, L.K,
+                           wg_rows, part2);
       }
     }
     const int64_t n1 = (int64_t)kFP * HP, n2 = (int64_t)HP * HP;
     // [kFP][HP] and [HP][HP] partials summed straight into the caller's [F][H1] and [H1][H2]
-    hipLaunchKernelGGL(sum_partials_unpad, dim3((kF * H1 + 255) / 256), dim3(256), 0, s, part1, L.kchunks, n1, HP,
+    hipLaunchKernelGGL(sum_partials_unpad, dim3((kF * H1 + 255) / 256), dim3(256), 0, s, part1, kch, n1, HP,
                        kF, H1, g->W1);
-    hipLaunchKernelGGL(sum_partials_unpad, dim3((H1 * H2 + 255) / 256), dim3(256), 0, s, part2, L.kchunks, n2, HP,
+    hipLaunchKernelGGL(sum_partials_unpad, dim3((H1 * H2 + 255) / 256), dim3(256), 0, s, part2, kch, n2, HP,
                        H1, H2, g->W2);
   }
   // bias, W3, scale/shift gradients: two-stage sums with chunk partials added in order
