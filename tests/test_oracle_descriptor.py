@@ -50,6 +50,55 @@ def _R(params, zi, zj, r):
     return radial_functions(_t([r]), torch.tensor([zi]), torch.tensor([zj]), _t(params.beta), params.spec)[0].numpy()
 
 
+def test_species_pair_coefficients_by_hand():
+    """R_s of a pair seen from atom i uses beta[Z_i, Z_j] (Section 2.1: the
+    radial functions depend on the species of the centre and of the
+    neighbour, in that order).  One-hot coefficient tables on an asymmetric
+    species pair, with R_s written out from exp and cos alone:
+      beta[0, 1, s, k] = 1 only at (s, k) = (2, 3), beta[1, 0, s, k] = 1 only at
+      (s, k) = (4, 0), every other entry zero;
+      atom 0 (species 0): Psi0[0, s] = c f_c(r) exp(-gamma (r - mu_3)^2) at s = 2,
+      atom 1 (species 1): Psi0[1, s] = c f_c(r) exp(-gamma (r - mu_0)^2) at s = 4,
+      zero in every other channel."""
+    import copy
+    p = copy.deepcopy(make_params(SPEC, 3))
+    p.beta = np.zeros_like(p.beta)
+    p.beta[0, 1, 2, 3] = 1.0
+    p.beta[1, 0, 4, 0] = 1.0
+    b = make_cluster([[10, 10, 10], [10.0, 12.6, 11.1]], [0, 1])
+    _, _, (P0, P1, _, _) = _psi(b, p)
+    r = float(np.linalg.norm(b.pos[1].astype(np.float64) - b.pos[0]))
+    delta = (5.0 - 0.5) / 6.0
+    gamma = 1.0 / (2.0 * delta * delta)
+    fc = 0.5 * (math.cos(math.pi * r / 5.0) + 1.0)
+    want0 = np.zeros(5)
+    want0[2] = 0.37 * fc * math.exp(-gamma * (r - (0.5 + 3 * delta)) ** 2)
+    want1 = np.zeros(5)
+    want1[4] = 0.37 * fc * math.exp(-gamma * (r - 0.5) ** 2)
+    assert np.allclose(P0[0], want0, rtol=1e-13, atol=1e-300)
+    assert np.allclose(P0[1], want1, rtol=1e-13, atol=1e-300)
+    # the same numbers with the tables swapped move to the other atom
+    p.beta = np.ascontiguousarray(p.beta.transpose(1, 0, 2, 3))
+    _, _, (Q0, _, _, _) = _psi(b, p)
+    h0, h1 = _hand_R(r, 2, 3, 4, 0)
+    assert np.allclose(Q0[0], h0, rtol=1e-13, atol=1e-300)
+    assert np.allclose(Q0[1], h1, rtol=1e-13, atol=1e-300)
+
+
+def _hand_R(r, s01, k01, s10, k10):
+    """Psi0 rows of the dimer for the transposed one-hot tables: atom 0 now
+    sees beta[0, 1] = old beta[1, 0] (channel s10, basis k10), atom 1 sees the
+    old beta[0, 1] (channel s01, basis k01)."""
+    delta = (5.0 - 0.5) / 6.0
+    gamma = 1.0 / (2.0 * delta * delta)
+    fc = 0.5 * (math.cos(math.pi * r / 5.0) + 1.0)
+    a0 = np.zeros(5)
+    a0[s10] = 0.37 * fc * math.exp(-gamma * (r - (0.5 + k10 * delta)) ** 2)
+    a1 = np.zeros(5)
+    a1[s01] = 0.37 * fc * math.exp(-gamma * (r - (0.5 + k01 * delta)) ** 2)
+    return a0, a1
+
+
 def test_dimer_closed_form():
     p = make_params(SPEC, 1)
     u = np.array([0.3, -0.5, 0.8]); u /= np.linalg.norm(u)
