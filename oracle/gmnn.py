@@ -159,31 +159,45 @@ def _bf16(x):
     return x.to(torch.bfloat16).to(x.dtype)
 
 
+def _bf16_parts(x):
+    """High and low bfloat16 parts of x: hi = bf16(x), lo = bf16(x - hi)."""
+    hi = _bf16(x)
+    return hi, _bf16(x - hi)
+
+
+def split_matmul(a, b):
+    """a @ b from bfloat16 parts, hi_a hi_b + hi_a lo_b + lo_a hi_b: the three
+    bfloat16 products of the mixed-precision arm's forward layers (the
+    lo_a lo_b term, 2^-16 relative, is dropped)."""
+    ah, al = _bf16_parts(a)
+    bh, bl = _bf16_parts(b)
+    return ah @ bh + ah @ bl + al @ bh
+
+
+def _forward_z(G, W1, b1, W2, b2, bf16):
+    """Pre-activations of both hidden layers.  bf16=True forms the two forward
+    products from bfloat16 parts (split_matmul), as the mixed-precision GPU
+    arm does."""
+    mm = split_matmul if bf16 else (lambda a, b: a @ b)
+    z1 = mm(G, W1) + b1
+    z2 = mm(swish(z1), W2) + b2
+    return z1, z2
+
+
 def mlp(G, W1, b1, W2, b2, W3, b3, bf16=False):
-    """NN(G) = W3^T swish(W2^T swish(W1^T G + b1) + b2) + b3, [N, heads].
-    bf16=True rounds the inputs of the first two products (G, h1) and their
-    weights to bfloat16, as the mixed-precision GPU arm does."""
-    if bf16:
-        z1 = _bf16(G) @ _bf16(W1) + b1
-        h1 = swish(z1)
-        z2 = _bf16(h1) @ _bf16(W2) + b2
-    else:
-        z1 = G @ W1 + b1
-        h1 = swish(z1)
-        z2 = h1 @ W2 + b2
-    h2 = swish(z2)
-    return h2 @ W3 + b3
+    """NN(G) = W3^T swish(W2^T swish(W1^T G + b1) + b2) + b3, [N, heads]."""
+    _, z2 = _forward_z(G, W1, b1, W2, b2, bf16)
+    return swish(z2) @ W3 + b3
 
 
 def mlp_input_grad(G, W1, b1, W2, b2, W3, b3, ybar, bf16=False):
     """dNN/dG contracted with ybar [N, heads], written out by hand so the
     bfloat16 arm can round the operands of the backward products (delta2,
-    delta1 and the weights) exactly where the GPU arm rounds them."""
+    delta1 and the weights) to bfloat16 exactly where the GPU arm rounds them
+    (its forward products are the split ones of _forward_z)."""
     rd = _bf16 if bf16 else (lambda t: t)
-    z1 = rd(G) @ rd(W1) + b1
+    z1, z2 = _forward_z(G, W1, b1, W2, b2, bf16)
     s1 = torch.sigmoid(z1)
-    h1 = z1 * s1
-    z2 = rd(h1) @ rd(W2) + b2
     s2 = torch.sigmoid(z2)
     dsw1 = s1 * (1.0 + z1 * (1.0 - s1))
     dsw2 = s2 * (1.0 + z2 * (1.0 - s2))

@@ -139,7 +139,8 @@ __device__ inline float wsrc(int which, const float* W1, const float* W2, int F,
 }
 
 __global__ void pack_weights(int which, const float* __restrict__ W1, const float* __restrict__ W2, int F, int H1,
-                             int H2, int Kp, int Np, float* __restrict__ out_f32, __bf16* __restrict__ out_bf16) {
+                             int H2, int Kp, int Np, float* __restrict__ out_f32, __bf16* __restrict__ out_bf16,
+                             __bf16* __restrict__ out_bf16_lo) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)Kp * Np;
   if (t >= total) return;
@@ -159,7 +160,11 @@ __global__ void pack_weights(int which, const float* __restrict__ W1, const floa
     const int64_t l = rest % 64, rest2 = rest / 64;
     const int64_t kb = rest2 % KB32, nb = rest2 / KB32;
     const int k = (int)(kb * 32 + 8 * (l >> 4) + e), n = (int)(nb * 16 + (l & 15));
-    out_bf16[t] = (__bf16)wsrc(which, W1, W2, F, H1, H2, k, n);
+    const float w = wsrc(which, W1, W2, F, H1, H2, k, n);
+    const __bf16 hi = (__bf16)w;
+    out_bf16[t] = hi;
+    // w - hi is exact in FP32 (hi is w's nearest bf16)
+    if (out_bf16_lo) out_bf16_lo[t] = (__bf16)(w - (float)hi);
   }
 }
 
@@ -212,6 +217,8 @@ static DevModel dev_model(const gmnn_model* m) {
   d.w1t_bf16 = (const bf16x8*)(P + L.w1t_bf16);
   d.w2_bf16 = (const bf16x8*)(P + L.w2_bf16);
   d.w2t_bf16 = (const bf16x8*)(P + L.w2t_bf16);
+  d.w1lo_bf16 = (const bf16x8*)(P + L.w1lo_bf16);
+  d.w2lo_bf16 = (const bf16x8*)(P + L.w2lo_bf16);
   d.b1 = (const float*)(P + L.b1);
   d.b2 = (const float*)(P + L.b2);
   d.w3 = (const float*)(P + L.w3);
@@ -335,15 +342,16 @@ gmnn_status gmnn_model_prepare(gmnn_model* m, void* stream) {
   const int F = kF, H1 = m->hidden1, H2 = m->hidden2;
   struct Job {
     int which, Kp, Np;
-    size_t f, b;
-  } jobs[4] = {{0, kFP, L.HP1, L.w1_f32, L.w1_bf16},
-               {1, L.HP1, kFP, L.w1t_f32, L.w1t_bf16},
-               {2, L.HP1, L.HP2, L.w2_f32, L.w2_bf16},
-               {3, L.HP2, L.HP1, L.w2t_f32, L.w2t_bf16}};
+    size_t f, b, lo;  // lo = 0: no low part (the backward products)
+  } jobs[4] = {{0, kFP, L.HP1, L.w1_f32, L.w1_bf16, L.w1lo_bf16},
+               {1, L.HP1, kFP, L.w1t_f32, L.w1t_bf16, 0},
+               {2, L.HP1, L.HP2, L.w2_f32, L.w2_bf16, L.w2lo_bf16},
+               {3, L.HP2, L.HP1, L.w2t_f32, L.w2t_bf16, 0}};
   for (auto& j : jobs) {
     const int64_t total = (int64_t)j.Kp * j.Np;
     hipLaunchKernelGGL(pack_weights, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, j.which, m->W1, m->W2, F,
-                       H1, H2, j.Kp, j.Np, (float*)(P + j.f), (__bf16*)(P + j.b));
+                       H1, H2, j.Kp, j.Np, (float*)(P + j.f), (__bf16*)(P + j.b),
+                       j.lo ? (__bf16*)(P + j.lo) : nullptr);
   }
   const int nv = L.HP1 > L.HP2 ? L.HP1 : L.HP2;
   hipLaunchKernelGGL(pack_vectors, dim3((nv + 255) / 256), dim3(256), 0, s, m->b1, m->b2, m->W3, m->b3, H1, H2, L.HP1,

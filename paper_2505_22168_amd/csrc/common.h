@@ -42,6 +42,19 @@ __device__ inline int xcd_block(int b, int nb) {
 }
 
 // ---------------------------------------------------------------------------
+// split-BF16 operands
+// ---------------------------------------------------------------------------
+// v - hi for the low bf16 part of v (hi = bf16(v)), with v taken as the
+// rounded FP32 value: the empty asm keeps the compiler from fusing the
+// product that produced v into the subtraction (an FMA there would give the
+// low part of the unrounded product, and kernels that fuse differently would
+// disagree in the last bits)
+__device__ inline float split_low(float v, __bf16 hi) {
+  asm("" : "+v"(v));
+  return v - (float)hi;
+}
+
+// ---------------------------------------------------------------------------
 // wave-level helpers
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return __lane_id(); }

@@ -76,10 +76,18 @@ __device__ inline void load_tables(Tables* t) {
 #define GM_P3(a, s, ijk) P[(a) * PS + (s) * kFull + 13 + (ijk)]
 #define GM_I(a, off) I[(a) * ISTR + (off)]
 
+// an invariant into the network operand G: FP32, or bf16 (G[idx] = bf16(v));
+// with glo > 0 also the low part G[idx + glo] = bf16(v - bf16(v)) for the
+// split-BF16 first product
 template <bool BF16>
-__device__ inline void store_feature(void* G, int idx, float v) {
-  if (BF16) ((__bf16*)G)[idx] = (__bf16)v;
-  else ((float*)G)[idx] = v;
+__device__ inline void store_feature(void* G, int idx, float v, int glo = 0) {
+  if (BF16) {
+    const __bf16 h = (__bf16)v;
+    ((__bf16*)G)[idx] = h;
+    if (glo) ((__bf16*)G)[idx + glo] = (__bf16)split_low(v, h);
+  } else {
+    ((float*)G)[idx] = v;
+  }
 }
 
 // pair index of (s1 <= s2) in the lexicographic pair order, as arithmetic
@@ -103,11 +111,11 @@ __host__ __device__ constexpr int pair_second(int p) {
 // V8 | v6 + fam1 + fam2.
 template <int TM, int NT, bool BF16, bool FEATURES = true, int ISTR = IS, int KS = 1>
 __device__ inline void contract_forward_a(const float* __restrict__ P, float* __restrict__ I, void* G, int ldg,
-                                          const Tables& tb) {
+                                          const Tables& tb, int glo = 0) {
   static_assert(KS == 1 || KS == 2, "one or two halves");
   const int tid = threadIdx.x;
   for (int t = tid; t < (FEATURES ? TM * (kFP - kF) : 0); t += NT)
-    store_feature<BF16>(G, (t % TM) * ldg + kF + t / TM, 0.0f);
+    store_feature<BF16>(G, (t % TM) * ldg + kF + t / TM, 0.0f, glo);
   constexpr int np = TM * 15, ns = TM * kS;
   // with KS = 2 each half's tasks start on a wave boundary
   constexpr int NTASK = np + ns, NHALF = KS == 1 ? NTASK : (NTASK + 63) / 64 * 64;
@@ -137,7 +145,7 @@ __device__ inline void contract_forward_a(const float* __restrict__ P, float* __
             GM_I(a, kT7 + p * 9 + ia * 3 + ib) = v;
             if (ia == ib) tr4 += v;
           }
-        if (FEATURES) store_feature<BF16>(G, a * ldg + kFam4 + p, tr4);
+        if (FEATURES) store_feature<BF16>(G, a * ldg + kFam4 + p, tr4, glo);
       }
       if (h1) {
         float A2[9], B2[9];
@@ -157,7 +165,7 @@ __device__ inline void contract_forward_a(const float* __restrict__ P, float* __
             GM_I(a, kM5 + p * 9 + i * 3 + j) = v;
             if (i == j) tr3 += v;
           }
-        if (FEATURES) store_feature<BF16>(G, a * ldg + kFam3 + p, tr3);
+        if (FEATURES) store_feature<BF16>(G, a * ldg + kFam3 + p, tr3, glo);
       }
     } else {
       const int u = t - np;
@@ -199,7 +207,7 @@ __device__ inline void contract_forward_a(const float* __restrict__ P, float* __
             GM_I(a, kV6 + (sc * 5 + s1) * 3 + i) = v;
           }
         if (FEATURES) {
-          store_feature<BF16>(G, a * ldg + sc, GM_P0(a, sc));
+          store_feature<BF16>(G, a * ldg + sc, GM_P0(a, sc), glo);
 #pragma unroll
           for (int s2 = 0; s2 < kS; ++s2) {
             if (s2 < sc) continue;
@@ -209,7 +217,7 @@ __device__ inline void contract_forward_a(const float* __restrict__ P, float* __
               // p1[sc][i] with sc a runtime index: read it again from LDS
               v += GM_P1(a, sc, i) * p1[s2][i];
             }
-            store_feature<BF16>(G, a * ldg + kFam2 + pair_idx(sc, s2), v);
+            store_feature<BF16>(G, a * ldg + kFam2 + pair_idx(sc, s2), v, glo);
           }
         }
       }
@@ -223,7 +231,7 @@ __device__ inline void contract_forward_a(const float* __restrict__ P, float* __
 //   channel task (a, s2):           fam8[(s1, s2, s3)] for every s1, s3
 template <int TM, int NT, bool BF16, int ISTR = IS>
 __device__ inline void contract_forward_b(const float* __restrict__ P, const float* __restrict__ I, void* G, int ldg,
-                                          const Tables& tb) {
+                                          const Tables& tb, int glo = 0) {
   constexpr int np = TM * 15, ns = TM * kS;
   for (int t = threadIdx.x; t < np + ns; t += NT) {
     if (t < np) {
@@ -243,12 +251,12 @@ __device__ inline void contract_forward_b(const float* __restrict__ P, const flo
         float f7 = 0.0f;
 #pragma unroll
         for (int k = 0; k < 9; ++k) f7 += q[k] * t7[k];
-        store_feature<BF16>(G, a * ldg + kFam7 + sq * 15 + p, f7);
+        store_feature<BF16>(G, a * ldg + kFam7 + sq * 15 + p, f7, glo);
         if (sq >= s2) {
           float f5 = 0.0f;
 #pragma unroll
           for (int k = 0; k < 9; ++k) f5 += m5[k] * q[k];
-          store_feature<BF16>(G, a * ldg + kFam5 + tb.tri_index[s1 * 25 + s2 * 5 + sq], f5);
+          store_feature<BF16>(G, a * ldg + kFam5 + tb.tri_index[s1 * 25 + s2 * 5 + sq], f5, glo);
         }
       }
       float r[3];
@@ -259,7 +267,7 @@ __device__ inline void contract_forward_b(const float* __restrict__ P, const flo
         float f6 = 0.0f;
 #pragma unroll
         for (int i = 0; i < 3; ++i) f6 += GM_I(a, kV6 + (s3 * 5 + s1) * 3 + i) * r[i];
-        store_feature<BF16>(G, a * ldg + kFam6 + p * 5 + s3, f6);
+        store_feature<BF16>(G, a * ldg + kFam6 + p * 5 + s3, f6, glo);
       }
     } else {
       const int u = t - np;
@@ -279,7 +287,7 @@ __device__ inline void contract_forward_b(const float* __restrict__ P, const flo
           float f8 = 0.0f;
 #pragma unroll
           for (int i = 0; i < 3; ++i) f8 += p1[s1][i] * w[i];
-          store_feature<BF16>(G, a * ldg + kFam8 + s1 * 25 + s2 * 5 + s3, f8);
+          store_feature<BF16>(G, a * ldg + kFam8 + s1 * 25 + s2 * 5 + s3, f8, glo);
         }
       }
     }

@@ -152,6 +152,108 @@ __device__ __forceinline__ void mma_bf16_a32(const float* __restrict__ A, int ld
   mma_bf16_a32_ring(r, A, lda, rb, Bp, K, nb0, nbs, NB, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 products (the network's forward products in BF16 mode).  Each
+// FP32 operand x is held as two bf16 parts, hi = bf16(x) and lo = bf16(x - hi)
+// (x - hi is exact in FP32), and
+//   acc += Ahi Bhi + Ahi Blo + Alo Bhi        (per k-step, in this order)
+// keeps about 16 significant bits of every operand; the dropped Alo Blo term
+// is 2^-16 relative.  Three BF16 MFMAs per k-step instead of one, FP32
+// accumulation.  The A parts live in LDS (high and low parts in two arrays
+// of the same layout); the B fragments stream through a ring whose slot i < TPW
+// holds the high fragment of column block nb0 + i nbs and slot TPW + i its
+// low fragment (same fragment layout, separate arrays).
+template <bool BF16, int TPW, int DEPTH>
+struct FwdRingT {
+  using type = BRing<false, TPW, DEPTH>;
+};
+template <int TPW, int DEPTH>
+struct FwdRingT<true, TPW, DEPTH> {
+  using type = BRing<true, 2 * TPW, (DEPTH / 2 > 0 ? DEPTH / 2 : 1)>;
+};
+template <bool BF16, int TPW, int DEPTH>
+using FwdRing = typename FwdRingT<BF16, TPW, DEPTH>::type;
+
+template <int TPW, int SD>
+__device__ __forceinline__ void split_ring_load(BRing<true, 2 * TPW, SD>& r, int slot, const bf16x8* Bhi,
+                                                const bf16x8* Blo, int KB, int kb, int nb0, int nbs, int NB) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int nb = nb0 + i * nbs;
+    if (nb < NB && kb < KB) {
+      const size_t o = ((size_t)nb * KB + kb) * 64 + l;
+      r.b[slot][i] = Bhi[o];
+      r.b[slot][TPW + i] = Blo[o];
+    }
+  }
+}
+
+// first k-steps of a forward product: split fragments (BF16) or FP32 chunks
+template <bool BF16, int TPW, int DEPTH>
+__device__ __forceinline__ void fwd_ring_fill(FwdRing<BF16, TPW, DEPTH>& r, const bf16x8* Bhi, const bf16x8* Blo,
+                                              const float* Bf, int K, int nb0, int nbs, int NB) {
+  if constexpr (BF16) {
+    constexpr int SD = DEPTH / 2 > 0 ? DEPTH / 2 : 1;
+#pragma unroll
+    for (int s = 0; s < SD; ++s) split_ring_load<TPW, SD>(r, s, Bhi, Blo, K / 32, s, nb0, nbs, NB);
+  } else {
+    ring_fill(r, nullptr, Bf, K, nb0, nbs, NB);
+  }
+}
+
+// acc += A B for a forward product: split-BF16 (bf16 parts of A at A and
+// Alo) or plain FP32 (A; Alo unused)
+template <bool BF16, int TPW, int DEPTH>
+__device__ __forceinline__ void fwd_mma(FwdRing<BF16, TPW, DEPTH>& r, const void* A, const void* Alo, int lda, int rb,
+                                        const bf16x8* Bhi, const bf16x8* Blo, const float* Bf, int K, int nb0,
+                                        int nbs, int NB, floatx4 (&acc)[TPW]) {
+  if constexpr (BF16) {
+    constexpr int SD = DEPTH / 2 > 0 ? DEPTH / 2 : 1;
+    const int l = threadIdx.x & 63;
+    const int KB = K / 32;
+    const int aoff = (rb * 16 + (l & 15)) * lda + (l >> 4) * 8;
+    const __bf16* ahi = (const __bf16*)A + aoff;
+    const __bf16* alo_p = (const __bf16*)Alo + aoff;
+    auto step = [&](int slot, int kb) {
+      const bf16x8 ah = *(const bf16x8*)(ahi + kb * 32);
+      const bf16x8 al = *(const bf16x8*)(alo_p + kb * 32);
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int nb = nb0 + i * nbs;
+        if (nb >= NB) continue;
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, r.b[slot][i], acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, r.b[slot][TPW + i], acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, r.b[slot][i], acc[i], 0, 0, 0);
+      }
+    };
+    for (int kb = 0; kb < KB; kb += SD) {
+#pragma unroll
+      for (int s = 0; s < SD; ++s) {
+        if (kb + s < KB) {
+          step(s, kb + s);
+          split_ring_load<TPW, SD>(r, s, Bhi, Blo, KB, kb + s + SD, nb0, nbs, NB);
+        }
+      }
+    }
+  } else {
+    mma_ring(r, A, lda, rb, nullptr, Bf, K, nb0, nbs, NB, acc);
+  }
+}
+
+// store of a forward activation: FP32 (base), or its bf16 high part (base)
+// and low part (lo, same layout)
+template <bool BF16>
+__device__ inline void st_split(void* base, void* lo, int idx, float v) {
+  if constexpr (BF16) {
+    const __bf16 h = (__bf16)v;
+    ((__bf16*)base)[idx] = h;
+    ((__bf16*)lo)[idx] = (__bf16)split_low(v, h);
+  } else {
+    ((float*)base)[idx] = v;
+  }
+}
+
 template <int TPW>
 __device__ inline void zero_acc(floatx4 (&acc)[TPW]) {
 #pragma unroll
@@ -197,11 +299,20 @@ struct NetShape {
 // MEAN: delta2 = swish'(z2) sigma mean_m W3[:,m] -> sD2 (the head-mean
 // backward); otherwise swish'(z2) -> sDsw2 (FP32, row stride HP + 1) for
 // per-head backwards.  sEp: [NW][16][kMaxHeads] partial sums.
+// BF16 mode: both forward products are split-BF16 (fwd_mma), with the low
+// parts of G at sGlo and of h1 at sHlo; fring holds the first k-steps of W1
+// on entry.  sHlo may overlap sG and sD2 (the tile keeps h1's low part where
+// G was and delta2 goes): barriers after each forward product's MFMAs keep
+// those stores behind every wave's reads.  The backward products stay plain
+// BF16: the first k-steps of W2^T are issued into `ring` before the second
+// epilogue.
 template <int TM, int HP, bool BF16, int NW, bool MEAN, int DEPTH>
-__device__ __forceinline__ void network_forward(const DevModel& m, const void* sG, void* sH, void* sD2, float* sDsw2,
+__device__ __forceinline__ void network_forward(const DevModel& m, const void* sG, const void* sGlo, void* sH,
+                                       void* sHlo, void* sD2, float* sDsw2,
                                        float* sEp, const float* sScale, const float* sShift, int row0, int n_rows,
                                        float* __restrict__ atomic_e, float* sEa,
                                        floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW],
+                                       FwdRing<BF16, NetShape<TM, HP, NW>::TPW, DEPTH>& fring,
                                        BRing<BF16, NetShape<TM, HP, NW>::TPW, DEPTH>& ring) {
   using St = NetStrides<HP, BF16>;
   using Sh = NetShape<TM, HP, NW>;
@@ -224,8 +335,9 @@ __device__ __forceinline__ void network_forward(const DevModel& m, const void* s
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma_ring(ring, sG, St::G, rb, m.w1_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
-    ring_fill(ring, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH);
+    fwd_mma<BF16, TPW, DEPTH>(fring, sG, sGlo, St::G, rb, m.w1_bf16, m.w1lo_bf16, m.w1_f32, kFP, cw, WPR, NBH, acc);
+    fwd_ring_fill<BF16, TPW, DEPTH>(fring, m.w2_bf16, m.w2lo_bf16, m.w2_f32, HP, cw, WPR, NBH);
+    if (BF16) __syncthreads();  // every wave is done with G before h1's low part is stored
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = cw + i * WPR;
@@ -237,7 +349,7 @@ __device__ __forceinline__ void network_forward(const DevModel& m, const void* s
         float d;
         const float hv = swish_parts(acc[i][j] + b1v[i], d);
         dsw1[i][j] = d;
-        st_act<BF16>(sH, row * St::H + col, hv);
+        st_split<BF16>(sH, sHlo, row * St::H + col, hv);
       }
     }
   }
@@ -245,9 +357,10 @@ __device__ __forceinline__ void network_forward(const DevModel& m, const void* s
   {
     floatx4 acc[TPW];
     zero_acc(acc);
-    mma_ring(ring, sH, St::H, rb, m.w2_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
+    fwd_mma<BF16, TPW, DEPTH>(fring, sH, sHlo, St::H, rb, m.w2_bf16, m.w2lo_bf16, m.w2_f32, HP, cw, WPR, NBH, acc);
     // the backward's first product (W2^T) starts loading now
     ring_fill(ring, m.w2t_bf16, m.w2t_f32, HP, cw, WPR, NBH);
+    if (BF16) __syncthreads();  // every wave is done with h1's low part before delta2 is stored
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = cw + i * WPR;

@@ -16,12 +16,16 @@ constexpr int kMaxHeads = 16;
 // Offsets (bytes) of the packed buffer filled by gmnn_model_prepare.
 //   fp32 MFMA B fragments (16x16x4):  [n/16][k/4][64] floats
 //   bf16 MFMA B fragments (16x16x32): [n/16][k/32][64][8] bf16
+//   W1 and W2 (the forward products) also carry a low part in the bf16
+//   layout: lo = bf16(w - hi) with hi = bf16(w), so hi + lo holds w to about
+//   16 significant bits (the split-BF16 forward products)
 // Hidden widths are padded to HP (multiple of 64) with zero weights and
 // biases, which leaves every output unchanged (swish(0) = 0).
 struct PackedLayout {
   int HP1 = 0, HP2 = 0, M = 0;
   size_t w1_f32 = 0, w1t_f32 = 0, w2_f32 = 0, w2t_f32 = 0;
   size_t w1_bf16 = 0, w1t_bf16 = 0, w2_bf16 = 0, w2t_bf16 = 0;
+  size_t w1lo_bf16 = 0, w2lo_bf16 = 0;
   size_t b1 = 0, b2 = 0, w3 = 0, w3bar = 0, b3 = 0;
   size_t bytes = 0;
 };
@@ -47,6 +51,8 @@ inline PackedLayout packed_layout(int H1, int H2, int M) {
   L.w1t_bf16 = take(2 * (size_t)kFP * L.HP1);
   L.w2_bf16 = take(2 * (size_t)L.HP1 * L.HP2);
   L.w2t_bf16 = take(2 * (size_t)L.HP1 * L.HP2);
+  L.w1lo_bf16 = take(2 * (size_t)kFP * L.HP1);
+  L.w2lo_bf16 = take(2 * (size_t)L.HP1 * L.HP2);
   L.b1 = take(4 * (size_t)L.HP1);
   L.b2 = take(4 * (size_t)L.HP2);
   L.w3 = take(4 * (size_t)L.HP2 * M);
@@ -73,6 +79,8 @@ struct DevModel {
   const bf16x8* w1t_bf16;
   const bf16x8* w2_bf16;
   const bf16x8* w2t_bf16;
+  const bf16x8* w1lo_bf16;  // low parts of the forward weights (split products)
+  const bf16x8* w2lo_bf16;
   const float* b1;      // [HP1]
   const float* b2;      // [HP2]
   const float* w3;      // [HP2][M]

@@ -2,7 +2,8 @@
 //
 //   readout_features  invariants of the moments (Section 2.1, eq.
 //                     contraction), 16 atoms per block -> G [N][384] in HBM
-//                     (BF16 or FP32: the operand precision of the network)
+//                     (FP32, or for the BF16 network its bf16 high parts
+//                     [N][384] followed by the low parts [N][384])
 //   readout_network   the network, its scale/shift (eq. scale_shift) and its
 //                     input gradient dE/dG, for row tiles of 32 to 64 atoms:
 //                     every weight fragment fetched from L2 feeds 2 to 4 MFMA
@@ -61,7 +62,7 @@ struct FeatLds {
   static constexpr size_t psi = ro_al(sizeof(Tables));
   static constexpr size_t inter = psi + ro_al(4 * (size_t)kRoAtoms * PS);
   static constexpr size_t g = inter + ro_al(4 * (size_t)kRoAtoms * ISF);
-  static constexpr size_t bytes = g + ro_al((size_t)ESZ * kRoAtoms * kFP);
+  static constexpr size_t bytes = g + ro_al((BF16 ? 2 : 1) * (size_t)ESZ * kRoAtoms * kFP);
 };
 
 template <bool BF16>
@@ -79,14 +80,21 @@ __global__ void __launch_bounds__(kRoThreads) readout_features(DevSystem sys, co
   __syncthreads();
   ro_load_moments(psi, row0, n_rows, sPsi, tb);
   __syncthreads();
-  contract_forward_a<kRoAtoms, kRoThreads, BF16, true, ISF>(sPsi, sI, sG, kFP, tb);
+  constexpr int glo = BF16 ? kRoAtoms * kFP : 0;  // low parts after the high ones
+  contract_forward_a<kRoAtoms, kRoThreads, BF16, true, ISF>(sPsi, sI, sG, kFP, tb, glo);
   __syncthreads();
-  contract_forward_b<kRoAtoms, kRoThreads, BF16, ISF>(sPsi, sI, sG, kFP, tb);
+  contract_forward_b<kRoAtoms, kRoThreads, BF16, ISF>(sPsi, sI, sG, kFP, tb, glo);
   __syncthreads();
-  // rows of G are contiguous: 16-byte copies
+  // rows of G are contiguous: 16-byte copies (BF16: the high plane, then the
+  // low plane N rows further)
   const int n16 = n_rows * kFP * L::ESZ / 16;
   uint4* dst = (uint4*)((char*)G + (size_t)row0 * kFP * L::ESZ);
   for (int t = threadIdx.x; t < n16; t += kRoThreads) dst[t] = ((const uint4*)sG)[t];
+  if (BF16) {
+    uint4* dlo = (uint4*)((char*)G + ((size_t)sys.n_atoms + row0) * kFP * L::ESZ);
+    const uint4* slo = (const uint4*)(sG + (size_t)glo * L::ESZ);
+    for (int t = threadIdx.x; t < n16; t += kRoThreads) dlo[t] = slo[t];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -127,6 +135,57 @@ __device__ inline void mma_rows_bf16(const __bf16* __restrict__ A, int lda, cons
       if (kb + s < KB) {
         step(b[s], kb + s);
         load(b[s], kb + s + PF);
+      }
+    }
+  }
+}
+
+// split-BF16 rows product (the forward products of the BF16 network):
+// acc += Ahi Bhi + Ahi Blo + Alo Bhi per k-step, in the order of fwd_mma,
+// with the low part of A at A + alo elements
+template <int MB, int TPW>
+__device__ inline void mma_rows_split(const __bf16* __restrict__ A, int alo, int lda, const bf16x8* __restrict__ Bhi,
+                                      const bf16x8* __restrict__ Blo, int KB, int nb0, int nbs, int NB,
+                                      floatx4 (&acc)[MB][TPW]) {
+  constexpr int PF = 2;  // k-steps of B (high and low fragments) in flight
+  const int l = threadIdx.x & 63;
+  const __bf16* abase = A + (l & 15) * lda + (l >> 4) * 8;
+  bf16x8 bh[PF][TPW], bl[PF][TPW];
+  auto load = [&](bf16x8 (&dh)[TPW], bf16x8 (&dl)[TPW], int kb) {
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB && kb < KB) {
+        const size_t o = ((size_t)nb * KB + kb) * 64 + l;
+        dh[i] = Bhi[o];
+        dl[i] = Blo[o];
+      }
+    }
+  };
+  auto step = [&](const bf16x8 (&h)[TPW], const bf16x8 (&lo)[TPW], int kb) {
+    // one row block's A parts at a time (fewer registers live)
+#pragma unroll
+    for (int r = 0; r < MB; ++r) {
+      const bf16x8 ah = *(const bf16x8*)(abase + r * 16 * lda + kb * 32);
+      const bf16x8 al = *(const bf16x8*)(abase + alo + r * 16 * lda + kb * 32);
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int nb = nb0 + i * nbs;
+        if (nb >= NB) continue;
+        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, h[i], acc[r][i], 0, 0, 0);
+        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, lo[i], acc[r][i], 0, 0, 0);
+        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, h[i], acc[r][i], 0, 0, 0);
+      }
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < PF; ++s) load(bh[s], bl[s], s);
+  for (int kb = 0; kb < KB; kb += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      if (kb + s < KB) {
+        step(bh[s], bl[s], kb + s);
+        load(bh[s], bl[s], kb + s + PF);
       }
     }
   }
@@ -187,6 +246,19 @@ __device__ inline void mma_rows(const void* A, int lda, const void* Bbf, const v
   else mma_rows_f32<MB, TPW>((const float*)A, lda, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
 }
 
+// forward product: split-BF16 (low parts `alo` elements after the high ones)
+// or FP32
+template <bool BF16, int MB, int TPW>
+__device__ inline void mma_rows_fwd(const void* A, int alo, int lda, const bf16x8* Bhi, const bf16x8* Blo,
+                                    const float* Bf, int K, int nb0, int nbs, int NB, floatx4 (&acc)[MB][TPW]) {
+#pragma unroll
+  for (int r = 0; r < MB; ++r)
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acc[r][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  if (BF16) mma_rows_split<MB, TPW>((const __bf16*)A, alo, lda, Bhi, Blo, K / 32, nb0, nbs, NB, acc);
+  else mma_rows_f32<MB, TPW>((const float*)A, lda, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
+}
+
 // rows per network block: as many 16-row MFMA blocks as the register file
 // holds with swish'(z1) kept for the backward (8 waves, 256 registers each)
 template <int HP, bool BF16>
@@ -197,14 +269,21 @@ struct NetLds {
   using St = NetStrides<HP, BF16>;
   static constexpr int TM = net_rows<HP, BF16>();
   static constexpr int ESZ = BF16 ? 2 : 4;
+  static constexpr int NS = BF16 ? 2 : 1;  // parts of a forward operand (bf16 high and low)
   static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
-  // region A: G, later delta2; region H: h1, later delta1; then the row
-  // scale/shift and the per-wave energy partials [NW][TM][M] (sized by M)
-  static constexpr size_t a = 0;
-  static constexpr size_t h = ro_al(mx((size_t)ESZ * TM * St::G, (size_t)ESZ * TM * St::H));
-  static constexpr size_t rows = h + ro_al((size_t)ESZ * TM * St::H);
-  static constexpr size_t ep = rows + ro_al(4 * 2 * (size_t)TM);
-  static constexpr size_t bytes(int M) { return ep + ro_al(4 * (size_t)kRoWaves * TM * M); }
+  // region B: delta2; the row scale/shift; region A: G (all parts), then h1
+  // (all parts), then delta1 at its start and the per-wave energy partials
+  // [NW][TM][M] right after delta1 (sized by M)
+  static constexpr int GLO = TM * St::G;  // element offsets of the low parts in region A
+  static constexpr int HLO = TM * St::H;
+  static constexpr size_t b = 0;
+  static constexpr size_t rows = b + ro_al((size_t)ESZ * TM * St::H);
+  static constexpr size_t a = rows + ro_al(4 * 2 * (size_t)TM);
+  static constexpr size_t ep = a + ro_al((size_t)ESZ * TM * St::H);
+  static constexpr size_t bytes(int M) {
+    return mx(a + ro_al((size_t)ESZ * NS * mx((size_t)TM * St::G, (size_t)TM * St::H)),
+              ep + ro_al(4 * (size_t)kRoWaves * TM * M));
+  }
 };
 
 template <int HP, bool BF16>
@@ -218,7 +297,7 @@ __global__ void __launch_bounds__(kRoThreads)
   constexpr int TPW = (NBH + NW - 1) / NW, TPW_G = (NBG + NW - 1) / NW;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   char* sA = lds + L::a;
-  char* sH = lds + L::h;
+  char* sB = lds + L::b;
   float* sEp = (float*)(lds + L::ep);
   float* sScale = (float*)(lds + L::rows);
   float* sShift = sScale + TM;
@@ -228,23 +307,27 @@ __global__ void __launch_bounds__(kRoThreads)
   const int n_rows = min(TM, sys.n_atoms - row0);
   const int M = m.M;
 
-  // G rows -> region A (row stride St::G), zero rows beyond the system; every
-  // load of the tile is issued before the first store
+  // G rows (each part) -> region A (row stride St::G), zero rows beyond the
+  // system; every load of the tile is issued before the first store
   {
     constexpr int C16 = kFP * L::ESZ / 16;  // 16-byte chunks per row
-    constexpr int NU = (TM * C16 + kRoThreads - 1) / kRoThreads;
-    const uint4* src = (const uint4*)((const char*)G + (size_t)row0 * kFP * L::ESZ);
+    constexpr int NU = (L::NS * TM * C16 + kRoThreads - 1) / kRoThreads;
+    const char* gbase = (const char*)G;
     uint4 v[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int t = tid + u * kRoThreads;
+      const int part = t / (TM * C16), tt = t % (TM * C16);
       v[u] = uint4{0u, 0u, 0u, 0u};
-      if (t < n_rows * C16) v[u] = src[t];
+      if (part < L::NS && tt < n_rows * C16)
+        v[u] = ((const uint4*)(gbase + ((size_t)part * sys.n_atoms + row0) * kFP * L::ESZ))[tt];
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int t = tid + u * kRoThreads;
-      if (t < TM * C16) *(uint4*)(sA + (size_t)(t / C16) * St::G * L::ESZ + (t % C16) * 16) = v[u];
+      const int part = t / (TM * C16), tt = t % (TM * C16);
+      if (part < L::NS)
+        *(uint4*)(sA + ((size_t)part * L::GLO + (size_t)(tt / C16) * St::G) * L::ESZ + (tt % C16) * 16) = v[u];
     }
     for (int a = tid; a < TM; a += kRoThreads) {
       float sc = 0.0f, sh = 0.0f;
@@ -259,11 +342,12 @@ __global__ void __launch_bounds__(kRoThreads)
   }
   __syncthreads();
 
-  // z1 = G W1 + b1, h1 = swish(z1) -> region H; swish'(z1) stays in registers
+  // z1 = G W1 + b1 (split-BF16 or FP32), h1 = swish(z1) -> region A once every
+  // wave is done with G; swish'(z1) stays in registers
   floatx4 dsw1[MB][TPW];
   {
     floatx4 acc[MB][TPW];
-    mma_rows<BF16, MB, TPW>(sA, St::G, m.w1_bf16, m.w1_f32, kFP, w, NW, NBH, acc);
+    mma_rows_fwd<BF16, MB, TPW>(sA, L::GLO, St::G, m.w1_bf16, m.w1lo_bf16, m.w1_f32, kFP, w, NW, NBH, acc);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = w + i * NW;
@@ -274,21 +358,35 @@ __global__ void __launch_bounds__(kRoThreads)
       for (int r = 0; r < MB; ++r)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int row = r * 16 + 4 * (l >> 4) + j;
           float d;
-          const float hv = swish_parts(acc[r][i][j] + bias, d);
+          acc[r][i][j] = swish_parts(acc[r][i][j] + bias, d);
           dsw1[r][i][j] = d;
-          st_act<BF16>(sH, row * St::H + col, hv);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = w + i * NW;
+      if (nb >= NBH) continue;
+      const int col = nb * 16 + (l & 15);
+#pragma unroll
+      for (int r = 0; r < MB; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = r * 16 + 4 * (l >> 4) + j;
+          st_split<BF16>(sA, (__bf16*)sA + L::HLO, row * St::H + col, acc[r][i][j]);
         }
     }
   }
   __syncthreads();
 
-  // z2 = h1 W2 + b2, h2 = swish(z2); delta2 = swish'(z2) sigma wbar -> region A
-  // (G is dead); per-wave partial sums of h2 . W3[:,m] -> sEp
+  // z2 = h1 W2 + b2, h2 = swish(z2); delta2 = swish'(z2) sigma wbar -> region
+  // B; per-wave partial sums of h2 . W3[:,m] -> sEp (in region A, once every
+  // wave is done with h1)
   {
     floatx4 acc[MB][TPW];
-    mma_rows<BF16, MB, TPW>(sH, St::H, m.w2_bf16, m.w2_f32, HP, w, NW, NBH, acc);
+    mma_rows_fwd<BF16, MB, TPW>(sA, L::HLO, St::H, m.w2_bf16, m.w2lo_bf16, m.w2_f32, HP, w, NW, NBH, acc);
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = w + i * NW;
@@ -303,7 +401,7 @@ __global__ void __launch_bounds__(kRoThreads)
           const int row = r * 16 + 4 * (l >> 4) + j;
           float d;
           acc[r][i][j] = swish_parts(acc[r][i][j] + bias, d);
-          st_act<BF16>(sA, row * St::H + col, d * sScale[row] * wb);
+          st_act<BF16>(sB, row * St::H + col, d * sScale[row] * wb);
         }
     }
     for (int hm = 0; hm < M; ++hm) {
@@ -338,10 +436,10 @@ __global__ void __launch_bounds__(kRoThreads)
     }
   }
 
-  // delta1 = swish'(z1) (delta2 W2^T) -> region H
+  // delta1 = swish'(z1) (delta2 W2^T) -> region A (h1 is dead)
   {
     floatx4 acc[MB][TPW];
-    mma_rows<BF16, MB, TPW>(sA, St::H, m.w2t_bf16, m.w2t_f32, HP, w, NW, NBH, acc);
+    mma_rows<BF16, MB, TPW>(sB, St::H, m.w2t_bf16, m.w2t_f32, HP, w, NW, NBH, acc);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = w + i * NW;
@@ -352,7 +450,7 @@ __global__ void __launch_bounds__(kRoThreads)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int row = r * 16 + 4 * (l >> 4) + j;
-          st_act<BF16>(sH, row * St::H + col, acc[r][i][j] * dsw1[r][i][j]);
+          st_act<BF16>(sA, row * St::H + col, acc[r][i][j] * dsw1[r][i][j]);
         }
     }
   }
@@ -361,7 +459,7 @@ __global__ void __launch_bounds__(kRoThreads)
   // dE/dG = delta1 W1^T -> HBM [N][kFP] (FP32)
   {
     floatx4 acc[MB][TPW_G];
-    mma_rows<BF16, MB, TPW_G>(sH, St::H, m.w1t_bf16, m.w1t_f32, HP, w, NW, NBG, acc);
+    mma_rows<BF16, MB, TPW_G>(sA, St::H, m.w1t_bf16, m.w1t_f32, HP, w, NW, NBG, acc);
 #pragma unroll
     for (int i = 0; i < TPW_G; ++i) {
       const int nb = w + i * NW;
@@ -513,9 +611,9 @@ size_t stream_lds_bytes(int hp, bool bf16, int n_heads) {
   return n;
 }
 
-// workspace of the streamed readout: G [N][kFP] (network operand type) and
-// dE/dG [N][kFP] FP32
-size_t stream_g_bytes(int n_atoms, bool bf16) { return (size_t)n_atoms * kFP * (bf16 ? 2 : 4); }
+// workspace of the streamed readout: G [N][kFP] (FP32, or bf16 high and low
+// planes) and dE/dG [N][kFP] FP32
+size_t stream_g_bytes(int n_atoms, bool bf16) { return (size_t)n_atoms * kFP * (bf16 ? 2 * 2 : 4); }
 size_t stream_dg_bytes(int n_atoms) { return (size_t)n_atoms * kFP * 4; }
 
 gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,

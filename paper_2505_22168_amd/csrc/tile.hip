@@ -45,8 +45,11 @@ struct TileLds {
   static constexpr size_t psi = al(sizeof(Tables));
   static constexpr size_t inter = psi + al(4 * (size_t)TA * PS);
   static constexpr size_t regb = inter + al(4 * (size_t)TA * IS);
+  // BF16: G and h1 are held as bf16 high and low parts (split products); G's
+  // two parts, later h1's low part, later delta2 and dE/dG share region b
+  static constexpr size_t NSPLIT = BF16 ? 2 : 1;
   static constexpr size_t regb_bytes =
-      mx(mx((size_t)ESZ * TM * St::G, (size_t)ESZ * TM * St::H), 4 * (size_t)TM * St::GB);
+      mx(mx(NSPLIT * ESZ * TM * St::G, (size_t)ESZ * TM * St::H), 4 * (size_t)TM * St::GB);
   static constexpr size_t regc = regb + al(regb_bytes);
   static constexpr size_t regc_bytes = mx((size_t)ESZ * TM * St::H, 4 * (size_t)TM * PS);
   static constexpr size_t ep = regc + al(regc_bytes);
@@ -120,7 +123,10 @@ __global__ void __launch_bounds__(kTileThreads)
     // network rows past the tile's atoms read zero invariants
     constexpr int ESZ = BF16 ? 2 : 4;
     constexpr int W0 = TA * NetStrides<HP, BF16>::G * ESZ / 4, W1 = TM * NetStrides<HP, BF16>::G * ESZ / 4;
-    for (int t = W0 + tid; t < W1; t += kTileThreads) ((uint32_t*)sG)[t] = 0u;
+    for (int t = W0 + tid; t < W1; t += kTileThreads) {
+      ((uint32_t*)sG)[t] = 0u;
+      if (BF16) ((uint32_t*)sG)[W1 + t] = 0u;  // low parts
+    }
   }
   if (FUSED) stage_beta(m, s_beta);
   __syncthreads();
@@ -173,11 +179,18 @@ __global__ void __launch_bounds__(kTileThreads)
   // the first weight fragments of the network start loading now
   // (one backward per head keeps more live state: a shallower ring there)
   constexpr int kDepth = PERHEAD ? 2 : prefetch_depth<Sh::TPW>();
+  // BF16: split-BF16 forward products (high and low parts of G, h1, W1, W2);
+  // G's low part follows its high part, h1's low part goes where G was
+  constexpr int kGlo = BF16 ? TM * NetStrides<HP, BF16>::G : 0;
+  void* sGlo = (void*)((__bf16*)sG + kGlo);
+  void* sHlo = sG;
+  FwdRing<BF16, Sh::TPW, kDepth> fring;
   BRing<BF16, Sh::TPW, kDepth> ring;
-  ring_fill(ring, m.w1_bf16, m.w1_f32, kFP, (tid >> 6) / Sh::MB, Sh::WPR, Sh::NBH);
+  fwd_ring_fill<BF16, Sh::TPW, kDepth>(fring, m.w1_bf16, m.w1lo_bf16, m.w1_f32, kFP, (tid >> 6) / Sh::MB, Sh::WPR,
+                                       Sh::NBH);
   // 8 atoms leave threads for both halves of every task of the first pass
   constexpr int KSF = 2 * ((TA * 20 + 63) / 64 * 64) <= kTileThreads ? 2 : 1;
-  contract_forward_a<TA, kTileThreads, BF16, true, IS, KSF>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  contract_forward_a<TA, kTileThreads, BF16, true, IS, KSF>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb, kGlo);
   // per-atom scale / shift, by the last wave (idle in the phase above), for
   // the network epilogue
   if (tid >= kTileThreads - 64 && tid - (kTileThreads - 64) < TM) {
@@ -192,13 +205,13 @@ __global__ void __launch_bounds__(kTileThreads)
     sShift[a] = sh;
   }
   __syncthreads();
-  contract_forward_b<TA, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb);
+  contract_forward_b<TA, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb, kGlo);
   __syncthreads();
 
   // ---- network forward ---------------------------------------------------------
   floatx4 dsw1[Sh::TPW];
-  network_forward<TM, HP, BF16, kTileWaves, !PERHEAD, kDepth>(m, sG, sH, sD2, sDsw2, sEp, sScale, sShift, row0, n_rows,
-                                                       atomic_e, sEa, dsw1, ring);
+  network_forward<TM, HP, BF16, kTileWaves, !PERHEAD, kDepth>(m, sG, sGlo, sH, sHlo, sD2, sDsw2, sEp, sScale, sShift,
+                                                              row0, n_rows, atomic_e, sEa, dsw1, fring, ring);
   constexpr int LDGB = NetStrides<HP, BF16>::GB;
   for (int hm = 0; hm < nh; ++hm) {
     // ---- network backward (head mean, or head hm) ------------------------------

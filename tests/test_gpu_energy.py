@@ -2,9 +2,10 @@
 
 Tolerances: FP32 arm |dE|/N <= 1e-5 eV/atom and max|dF| <= 1e-4 eV/A against
 the FP64 oracle (the bound the method's FP32 evaluation is held to); the BF16
-arm against the oracle's BF16-rounding arm (same rounding points) within
-FP32-accumulation error, and against FP64 within the stated BF16 budget
-(force RMSE <= 1% of RMS |F|, |dE|/N <= 5e-3 eV/atom)."""
+arm against the oracle's BF16 arm (same rounding points: split-BF16 forward
+products, bf16 backward operands) element by element, and against FP64
+within the stated BF16 budget (force RMSE <= 1% of RMS |F|, |dE|/N <= 1e-3
+eV/atom)."""
 import numpy as np
 import pytest
 import torch
@@ -52,7 +53,12 @@ def test_fp32_matches_fp64_oracle(name, kw):
     assert dEi.max() < 1e-4
 
 
-@pytest.mark.parametrize("name,kw", CASES)
+# the BF16 budget is checked on every 2x512 workload as well: the training
+# batch (two structures here) and a 294-atom cut of the solid-like lattice
+BF16_CASES = CASES + [("solid", dict(reps=(7, 7, 6))), ("ensemble", dict(n_structs=40))]
+
+
+@pytest.mark.parametrize("name,kw", BF16_CASES)
 def test_bf16_matches_bf16_oracle_and_budget(name, kw):
     g = need_gpu()
     batch, params, spec = make_workload(name, **kw)
@@ -63,13 +69,23 @@ def test_bf16_matches_bf16_oracle_and_budget(name, kw):
     F = _np(out.forces)[: batch.n_atoms]
     nb = np.diff(batch.atom_ptr)
     rms = np.sqrt((ref64.forces ** 2).mean())
-    # same rounding points as the oracle's bf16 arm: differences come from
-    # FP32 accumulation and rare bf16 rounding flips
-    assert np.sqrt(((F - ref16.forces) ** 2).mean()) < 2e-3 * rms
-    assert (np.abs(_np(out.energy) - ref16.energy) / nb[:, None]).max() < 1e-4
+    d16F = np.abs(F - ref16.forces)
+    d16E = np.abs(_np(out.energy) - ref16.energy) / nb[:, None]
+    d64E = np.abs(_np(out.energy) - ref64.energy) / nb[:, None]
+    d64F = np.sqrt(((F - ref64.forces) ** 2).mean())
+    print(f"{name}: RMS|F| {rms:.3f}; vs bf16 arm max|dF| {d16F.max() / rms:.2e} of RMS, RMSE "
+          f"{np.sqrt((d16F ** 2).mean()) / rms:.2e} of RMS, max|dE|/N {d16E.max():.2e}; "
+          f"vs fp64 force RMSE {d64F / rms:.2e} of RMS, max|dE|/N {d64E.max():.2e} eV/atom")
+    # same rounding points as the oracle's bf16 arm: differences come from FP32
+    # accumulation order and the rare bf16 rounding flips of backward operands
+    # it causes (one flip moves one operand by 2^-8 relative); bounded element
+    # by element and in the mean
+    assert d16F.max() < 1e-2 * rms, d16F.max()
+    assert np.sqrt((d16F ** 2).mean()) < 1e-3 * rms
+    assert d16E.max() < 1e-5, d16E.max()
     # stated budget against FP64
-    assert np.sqrt(((F - ref64.forces) ** 2).mean()) < 1e-2 * rms
-    assert (np.abs(_np(out.energy) - ref64.energy) / nb[:, None]).max() < 5e-3
+    assert d64F < 1e-2 * rms, d64F
+    assert d64E.max() < 1e-3, d64E.max()
 
 
 def test_energy_variance_over_heads():

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 from oracle import brute_force_neighbors, evaluate
-from oracle.gmnn import atomic_energies, mlp, mlp_input_grad, swish, _bf16
+from oracle.gmnn import atomic_energies, mlp, mlp_input_grad, swish, _bf16, split_matmul
 from workloads import make_batch, make_workload
 from workloads.configs import ModelSpec, make_params
 from conftest import make_cluster
@@ -214,3 +214,32 @@ def test_bf16_arm_is_close_to_fp64(tiny):
     rms = np.sqrt((r.forces ** 2).mean())
     assert np.sqrt(((rb.forces - r.forces) ** 2).mean()) < 0.05 * rms
     assert abs(rb.energy_mean[0] - r.energy_mean[0]) / 48 < 0.05
+
+
+def test_split_bf16_product_is_exact_on_16_bit_operands():
+    """Operands with at most 16 significant bits are hi + lo exactly, so the
+    three-term product equals the exact product minus the dropped lo.lo term
+    (hand-made values: hi and lo parts chosen directly)."""
+    hi_a = torch.tensor([[1.0, -2.0, 0.75]], dtype=torch.float64)
+    lo_a = torch.tensor([[2.0 ** -9, -3 * 2.0 ** -12, 2.0 ** -11]], dtype=torch.float64)
+    hi_b = torch.tensor([[0.5], [1.25], [-4.0]], dtype=torch.float64)
+    lo_b = torch.tensor([[-2.0 ** -10], [2.0 ** -9], [5 * 2.0 ** -10]], dtype=torch.float64)
+    a, b = hi_a + lo_a, hi_b + lo_b
+    got = split_matmul(a, b)
+    want = hi_a @ hi_b + hi_a @ lo_b + lo_a @ hi_b
+    assert torch.equal(got, want)
+    assert torch.allclose(a @ b - got, lo_a @ lo_b, rtol=0, atol=1e-18)
+
+
+def test_split_bf16_product_error_bound():
+    """For any operands the three-term product is within about 2^-15 relative
+    (per term |a_k b_k|) of the exact product: far below a single bf16
+    rounding (2^-9)."""
+    rng = np.random.default_rng(5)
+    a = torch.as_tensor(rng.normal(size=(64, 384)))
+    b = torch.as_tensor(rng.normal(size=(384, 32)) / 20.0)
+    err = (split_matmul(a, b) - a @ b).abs()
+    scale = a.abs() @ b.abs()
+    assert (err / scale).max() < 2.0 ** -15
+    plain = (_bf16(a) @ _bf16(b) - a @ b).abs()
+    assert (plain / scale).max() > 2.0 ** -12
