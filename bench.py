@@ -1,17 +1,24 @@
 """Throughput of the GMNN energy+force hot path on one MI355X.
 
-A step is one full pass of the path (pair moments -> invariants + network +
-backward in the tile readout -> pair backward -> force gather -> FP64
-per-structure sums) over the workload, with the neighbour list built once
-beforehand (it is reused across steps, as in MD between rebuilds) and all
-inputs resident in HBM.  The K steps are timed twice: launched one call at a
-time, and replayed from HIP graphs of 10 evaluations each (the way a loop
-over fixed buffers drives the library); the faster is the step time.  The
-headline value is the fused BF16-network path; the plain FP32 path is timed
+A step is one full pass of the path (pair moments -> invariants -> network
+forward and backward -> invariant backward -> pair backward -> force gather
+-> FP64 per-structure sums) over the workload, with the neighbour list built
+once beforehand (it is reused across steps, as in MD between rebuilds) and
+all inputs resident in HBM.  The K steps are timed twice: launched one call
+at a time, and replayed from HIP graphs of 10 evaluations each (the way a
+loop over fixed buffers drives the library); the faster is the step time.
+The headline value is the BF16-network path; the plain FP32 path is timed
 the same way and reported beside it, each with its error against the FP64
 oracle on the same inputs.
 
-    python bench.py [--steps K] [--warmup W] [--workload liquid]
+The default workload is the 100,000-atom solid-like lattice (2x512 network,
+r_c 6 A, list built at r_c + 1 A skin).  Its errors against FP64 come from
+sampled atoms: the oracle evaluates non-periodic cluster cuts around a few
+atoms, whose inner atoms carry their periodic energies and forces.  Whole MD
+steps (velocity Verlet in a HIP graph, list rebuilds included) are timed on
+the same box and reported beside the evaluation.
+
+    python bench.py [--steps K] [--warmup W] [--workload solid]
 
 Prints one JSON line (rank 0, one GPU).
 """
@@ -32,7 +39,8 @@ sys.path.insert(0, ROOT)
 METRIC = "energy+force atom-evals/s on 1 GPU, fused BF16 vs plain FP32, at force err vs FP64"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
-STAGES = ["pair_moments", "readout", "pair_backward", "finish"]
+# the stages gmnn_energy_forces_timed brackets with events (GMNN_TIMED_STAGES)
+STAGES = ["pair_moments", "readout_features", "readout_network", "readout_backward", "pair_backward", "finish"]
 GRAPH_EVALS = 10  # evaluations per HIP graph in the graph-launched timing
 
 
@@ -76,7 +84,13 @@ def algorithmic_work(spec, n_atoms, n_pairs):
     return {
         # j + packed shift per pair; per atom: pos, species, row_ptr, structure id, moments out
         "pair_moments": ("hbm", 8 * n_pairs + n_atoms * (12 + 4 + 8 + 4 + 400)),
-        "readout": ("mfma", mlp_flops * n_atoms),
+        # the network (forward and input gradient) dominates the readout kernels
+        "readout_tile": ("mfma", mlp_flops * n_atoms),
+        "readout_network": ("mfma", mlp_flops * n_atoms),
+        # moments in (400 B), invariants out (1536 B: FP32, or bf16 high + low parts)
+        "readout_features": ("hbm", n_atoms * (400 + 1536)),
+        # moments and dE/dG in, dE/dPsi out
+        "readout_backward": ("hbm", n_atoms * (400 + 4 * 384 + 400)),
         # list + g out per pair; per atom: moment gradient in, virial out, pos, species, row_ptr
         "pair_backward": ("hbm", 20 * n_pairs + n_atoms * (400 + 36 + 12 + 4 + 8 + 4)),
         # the fused tile kernel does moments + readout + pair backward; its
@@ -164,6 +178,10 @@ def run_path(g, A, model, system, nl, precision, steps, warmup, events, plan="au
     if ev.plan["schedule"] == A.GMNN_SCHEDULE_FUSED:
         # small systems run moments, readout and pair backward in one launch
         stage_ms = {"fused_tile": stage_ms["pair_moments"], "finish": stage_ms["finish"]}
+    elif ev.plan["readout"] != A.GMNN_READOUT_STREAM:
+        # the tile readout is one kernel (invariants, network, invariant backward)
+        stage_ms = {"pair_moments": stage_ms["pair_moments"], "readout_tile": stage_ms["readout_features"],
+                    "pair_backward": stage_ms["pair_backward"], "finish": stage_ms["finish"]}
     stage_ms = {k: max(v - overhead, 0.0) for k, v in stage_ms.items()}
     stage_ms["_event_overhead"] = overhead
     # each step on its own between two events (nothing else inside): median and
@@ -211,6 +229,41 @@ def errors_vs_oracle(out, ref, n_atoms, nb):
     }
 
 
+def sampled_errors(outs, batch, params, spec, centers, margin=3.0):
+    """Errors against the FP64 oracle on sampled atoms of a structure too
+    large to evaluate whole: the oracle evaluates a non-periodic cluster of
+    radius 2 r_c + margin around each centre; the cluster atoms within
+    `margin` of the centre carry their periodic forces, those within
+    r_c + margin their periodic energies."""
+    from oracle import brute_force_neighbors, evaluate
+    from workloads import cluster_cut
+    rc = spec.model.r_cut
+    R = 2.0 * rc + margin
+    refs = []
+    for c in centers:
+        cut, idx, dist = cluster_cut(batch, int(c), R)
+        refs.append((idx, dist, evaluate(cut, params, brute_force_neighbors(cut, rc), want_stress=False)))
+    res = {}
+    N = batch.n_atoms
+    for prec, o in outs.items():
+        F = o.forces.cpu().numpy()[:N].astype(np.float64)
+        Ei = o.atomic_energy.cpu().numpy()[:N].astype(np.float64)
+        dF, Fr, dE = [], [], []
+        for idx, dist, r in refs:
+            fi, ei = dist < R - 2 * rc, dist < R - rc
+            dF.append(F[idx[fi]] - r.forces[fi])
+            Fr.append(r.forces[fi])
+            dE.append(Ei[idx[ei]] - r.atomic[ei])
+        dF, Fr, dE = np.concatenate(dF), np.concatenate(Fr), np.concatenate(dE)
+        rms = float(np.sqrt((Fr ** 2).mean()))
+        res[prec] = {"force_mae": float(np.abs(dF).mean()), "force_rmse": float(np.sqrt((dF ** 2).mean())),
+                     "force_max": float(np.abs(dF).max()), "force_rmse_rel": float(np.sqrt((dF ** 2).mean()) / rms),
+                     "atomic_energy_max": float(np.abs(dE).max()), "rms_force": rms,
+                     "sampled": f"forces of {len(dF)} atoms and energies of {len(dE)} atoms: the inner atoms of "
+                                f"{len(centers)} cluster cuts of radius {R:.1f} A evaluated by the FP64 oracle"}
+    return res
+
+
 def time_neighbor_build(g, A, system, nl, cutoff, skin, events, reps=20):
     """The neighbour list build on its own (reported beside the evaluation):
     median and IQR of hipEvent-timed rebuilds into the same list."""
@@ -247,10 +300,10 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(batch, params, nl_ref, budget_s):
+def cpu_baseline(batch, params, nl_ref, budget_s, what=None):
     """The FP64 oracle (energy, forces, stress; list excluded) on the host
-    cores, repeated for about budget_s seconds with all threads, then once
-    more with one thread (reported beside it)."""
+    cores, repeated for about budget_s seconds with all threads, then for half
+    that with one thread (reported beside it)."""
     import torch
     from oracle import evaluate
 
@@ -271,40 +324,40 @@ def cpu_baseline(batch, params, nl_ref, budget_s):
     finally:
         torch.set_num_threads(cores)
     return {"value": batch.n_atoms * reps / el, "unit": "atom-evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} FP64 oracle evaluations (energy, forces, stress; list excluded) of the "
-                      f"{batch.n_atoms}-atom workload, {el:.1f} s",
+            "sample": f"{reps} FP64 oracle evaluations (energy, forces, stress; list excluded) of "
+                      f"{what or f'the {batch.n_atoms}-atom workload'}, {el:.1f} s",
             "cpu_model": _cpu_model(), "value_1_thread": batch.n_atoms * reps1 / el1}
 
 
-def run_md(args):
+def measure_md(workload, steps, graph_steps, sigma0, precisions=("bf16", "fp32")):
     """NVE velocity-Verlet MD of the workload (skin list, HIP graph of
-    --graph-steps steps replayed); reports atom-steps/s of whole MD steps
-    including list rebuilds, as MD step time is quoted per atom and step."""
+    graph_steps steps replayed); atom-steps/s of whole MD steps including
+    list rebuilds, as MD step time is quoted per atom and step."""
     import torch
     import paper_2505_22168_amd as g
     from workloads import make_workload
     import dataclasses
     from workloads.configs import make_params
     masses_by_species = {0: 6.94, 1: 30.974, 2: 15.999, 3: 12.011, 4: 1.008}
-    batch, params, spec = make_workload(args.workload)
+    batch, params, spec = make_workload(workload)
     # random weights make an unphysical potential: the species scale sigma0
     # sets the force magnitude (the arithmetic per step does not depend on it)
-    params = make_params(dataclasses.replace(spec.model, sigma0=args.md_sigma0), spec.seed + 1000)
+    params = make_params(dataclasses.replace(spec.model, sigma0=sigma0), spec.seed + 1000)
     masses = np.array([masses_by_species[int(z) % 5] for z in batch.species])
     v0 = g.maxwell_boltzmann(masses, 600.0, seed=3)
     system = g.System.from_batch(batch, "cuda")
     model = g.Model.from_params(params, "cuda")
     skin = spec.skin if spec.skin > 0 else 1.0
     out = {}
-    for prec in ("bf16", "fp32"):
+    for prec in precisions:
         system.pos.copy_(torch.as_tensor(batch.pos, device="cuda"))
         md = g.MD(model, system, masses, dt=0.5, skin=skin, velocities=v0, precision=prec)
         e0 = float(md.energy.sum().item()) + md.kinetic_energy(masses)
-        gs = args.graph_steps
+        gs = graph_steps
         md.capture(gs)
         md.run(1)  # warm-up replay
         torch.cuda.synchronize()
-        reps = max(1, args.steps // gs)
+        reps = max(1, steps // gs)
         t0 = time.perf_counter()
         md.run(reps)
         torch.cuda.synchronize()
@@ -319,6 +372,11 @@ def run_md(args):
                      "finite": bool(torch.isfinite(system.pos).all().item()), "T_final_K": t1}
         print(f"[bench-md] {prec}: {out[prec]}", file=sys.stderr, flush=True)
         md.release()
+    return out, batch, spec, skin
+
+
+def run_md(args):
+    out, batch, spec, skin = measure_md(args.workload, args.steps, args.graph_steps, args.md_sigma0)
     line = {"metric": "MD atom-steps/s (NVE velocity Verlet, HIP graph, skin list)", "value": out["bf16"]["value"],
             "unit": "atom-steps/s", "n_gpus": 1, "steps": out["bf16"]["steps"], "dtype": "bf16",
             "config": {"workload": args.workload, "n_atoms": batch.n_atoms, "dt_fs": 0.5, "skin": skin,
@@ -348,7 +406,7 @@ def run_ensemble(args):
     import torch
     import paper_2505_22168_amd as g
     from workloads import make_workload
-    name = args.workload if args.workload != "liquid" else "ensemble"
+    name = args.workload if args.workload not in ("liquid", "solid") else "ensemble"
     batch, params, spec = make_workload(name)
     dev = torch.device("cuda:0")
     model = g.Model.from_params(params, dev)
@@ -395,7 +453,7 @@ def run_train(args):
     import torch
     import paper_2505_22168_amd as g
     from workloads import make_workload
-    name = args.workload if args.workload != "liquid" else "train"
+    name = args.workload if args.workload not in ("liquid", "solid") else "train"
     batch, params, spec = make_workload(name)
     dev = torch.device("cuda:0")
     model = g.Model.from_params(params, dev)
@@ -442,8 +500,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="liquid")
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--workload", default="solid")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--md-steps", type=int, default=200,
+                    help="whole MD steps timed beside the evaluation (0: none)")
     ap.add_argument("--no-oracle", action="store_true", help="skip oracle errors and the CPU baseline")
     ap.add_argument("--md", action="store_true", help="time whole MD steps instead (not the headline metric)")
     ap.add_argument("--graph-steps", type=int, default=100)
@@ -531,22 +591,54 @@ def main():
                                "avg_duration_us": stage_ms[dom] * 1e3,
                                "event_bracket_overhead_us_subtracted": overhead_ms * 1e3}}
 
+    # every stage against its own bound (algorithmic work / event-timed duration)
+    stage_roofline = {}
+    for k, ms in stage_ms.items():
+        b, amt = work[k]
+        if ms > 0:
+            stage_roofline[k] = {"bound": b, "frac": (amt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if b == "hbm"
+                                 else (amt / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["bf16"])}
+
     wall32, stage32, out32, plan32 = res["fp32"]
     fp32 = {"value": N * args.steps / wall32, "ms_per_step": wall32 / args.steps * 1e3,
             "stages_us": {k: v * 1e3 for k, v in stage32.items()}, "plan": plan32,
             "ms_per_step_eager": eager_ms["fp32"], "ms_per_step_graph": graph_ms["fp32"]}
 
+    md = None
+    if args.md_steps > 0 and spec.skin > 0:
+        md_out, _, _, md_skin = measure_md(args.workload, args.md_steps, min(args.graph_steps, args.md_steps),
+                                           args.md_sigma0)
+        md = {"what": f"whole NVE velocity-Verlet steps (dt 0.5 fs, skin {md_skin} A, list rebuilds decided on the "
+                      f"device) in HIP graphs of {min(args.graph_steps, args.md_steps)} steps; species energy scale "
+                      f"{args.md_sigma0} keeps the random-weight potential stable (same arithmetic per step)",
+              **md_out}
+
     accuracy = None
     cpu = None
     if not args.no_oracle:
-        from oracle import brute_force_neighbors, evaluate
+        from oracle import brute_force_neighbors
         t0 = time.perf_counter()
-        nl_ref = brute_force_neighbors(batch, spec.model.r_cut)
-        ref = evaluate(batch, params, nl_ref)
-        print(f"[bench] oracle reference in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-        nb = np.diff(batch.atom_ptr)
-        accuracy = {"bf16": errors_vs_oracle(out16, ref, N, nb), "fp32": errors_vs_oracle(out32, ref, N, nb)}
-        cpu = cpu_baseline(batch, params, nl_ref, args.cpu_budget)
+        outs = {"bf16": out16, "fp32": res["fp32"][2]}
+        if N > 20000:
+            # too large for one oracle evaluation: sampled atoms (cluster cuts)
+            centers = np.random.default_rng(11).choice(N, 3, replace=False)
+            accuracy = sampled_errors(outs, batch, params, spec, centers)
+            # the CPU baseline: the oracle on a periodic cut of the same lattice
+            # (same density, species ratio, cutoff and network)
+            cut_kw = {"solid": dict(reps=(10, 10, 8))}.get(args.workload, {})
+            cb, cp, cs = make_workload(args.workload, **cut_kw)
+            cnl = brute_force_neighbors(cb, cs.model.r_cut)
+            cpu = cpu_baseline(cb, cp, cnl, args.cpu_budget,
+                               what=f"a {cb.n_atoms}-atom periodic cut of the same workload (same density, species "
+                                    f"ratio, cutoff and network)")
+        else:
+            from oracle import evaluate
+            nl_ref = brute_force_neighbors(batch, spec.model.r_cut)
+            ref = evaluate(batch, params, nl_ref)
+            nb = np.diff(batch.atom_ptr)
+            accuracy = {k: errors_vs_oracle(o, ref, N, nb) for k, o in outs.items()}
+            cpu = cpu_baseline(batch, params, nl_ref, args.cpu_budget)
+        print(f"[bench] oracle legs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC, "value": value, "unit": "atom-evals/s", "n_gpus": 1, "steps": args.steps,
@@ -560,11 +652,13 @@ def main():
         "ms_per_step_eager": eager_ms["bf16"], "ms_per_step_graph": graph_ms["bf16"],
         "step_event_stats": step_stats, "neighbor_build": nl_stats,
         "roofline": roofline,
+        "stage_roofline": stage_roofline,
         "cpu_baseline": cpu,
         "stages_us": {k: v * 1e3 for k, v in stage_ms.items()},
         "fp32": fp32,
         "bf16_over_fp32": value / fp32["value"],
         "accuracy_vs_fp64": accuracy,
+        "md": md,
     }
     print(json.dumps(line))
 

@@ -148,6 +148,12 @@ typedef struct gmnn_outputs {
   double* energy_var;     /* [B] population variance over heads, may be NULL */
   float* force_var;       /* [N] (1/M) sum_m |F_i^m - Fbar_i|^2, with GMNN_WANT_FORCE_VAR */
   float* atomic_energy;   /* [N, n_heads] E_i^m, may be NULL */
+  double* energy_mean;    /* [B] mean over heads of energy (eq. uncertainty), may be NULL */
+  uint32_t* status;       /* [1] device status word, may be NULL: GMNN_FLAG_COINCIDENT for a
+                           * listed pair at zero distance, GMNN_FLAG_NONFINITE for a non-finite
+                           * separation, energy or force.  Bits are OR-ed and kept until the
+                           * caller clears the word; with GMNN_SYNC a raised bit turns into
+                           * GMNN_ERR_DEVICE_FLAG. */
 } gmnn_outputs;
 
 /* ---------------------------------------------------------------------- */
@@ -270,10 +276,17 @@ gmnn_status gmnn_energy_forces_plan(const gmnn_model* m, const gmnn_system* sys,
 
 /* gmnn_energy_forces_plan with a hipEvent_t recorded on `stream` right before
  * and right after each kernel stage, for profiling: stage_events[2k] /
- * [2k+1] bracket stage k = 0 pair moments (FUSED: the tile kernel, which also
- * covers stages 1 and 2), 1 readout (invariants + network + invariant
- * backward), 2 pair backward, 3 force gather + per-structure reductions
- * (8 events, created by the caller with hipEventCreate; NULL: none). */
+ * [2k+1] bracket stage k =
+ *   0 pair moments (FUSED: the tile kernel, which also covers stages 1-4)
+ *   1 invariants (streamed readout; the tile readout's one kernel covers 1-3)
+ *   2 network forward and backward (streamed readout)
+ *   3 invariant backward (streamed readout)
+ *   4 pair backward
+ *   5 force gather + per-structure reductions
+ * (GMNN_TIMED_EVENTS = 12 events, created by the caller with hipEventCreate;
+ * NULL: none).  A stage a plan does not run gets two adjacent events. */
+#define GMNN_TIMED_STAGES 6
+#define GMNN_TIMED_EVENTS (2 * GMNN_TIMED_STAGES)
 gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys,
                                      const gmnn_neighbors* nl, uint32_t flags, const gmnn_plan* plan,
                                      gmnn_outputs* out, void* workspace, size_t workspace_bytes,

@@ -94,7 +94,7 @@ class gmnn_tune_entry(C.Structure):
 
 class gmnn_outputs(C.Structure):
     _fields_ = [("energy", vp), ("forces", vp), ("stress", vp), ("energy_var", vp),
-                ("force_var", vp), ("atomic_energy", vp)]
+                ("force_var", vp), ("atomic_energy", vp), ("energy_mean", vp), ("status", vp)]
 
 
 EXPORTS = {

@@ -183,10 +183,23 @@ class Model:
         """The FP32 parameter tensors in C-ABI order (beta, W1, b1, W2, b2, W3, b3, scale, shift)."""
         return [self.tensors[k] for k in PARAM_NAMES]
 
+    # parameters the packed buffer copies (beta, scale and shift are read live)
+    _PACKED = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def _versions(self):
+        return tuple(self.tensors[k]._version for k in self._PACKED)
+
     def prepare(self):
         """Refresh the packed weights after the FP32 parameters changed."""
         c = self.c()
         A.check(A.load().gmnn_model_prepare(C.byref(c), _stream()), "gmnn_model_prepare")
+        self._packed_versions = self._versions()
+
+    def ensure_packed(self):
+        """Re-pack if any packed parameter was modified in place since the
+        last prepare() (e.g. by an optimiser step on params())."""
+        if self._versions() != self._packed_versions:
+            self.prepare()
 
 
 @dataclass
@@ -197,6 +210,8 @@ class Outputs:
     energy_var: torch.Tensor | None
     force_var: torch.Tensor | None
     atomic_energy: torch.Tensor
+    energy_mean: torch.Tensor     # [B] float64, mean over heads
+    status: torch.Tensor          # [1] int32 device status word (GMNN_FLAG_* bits)
 
 
 class EnergyForces:
@@ -226,7 +241,9 @@ class EnergyForces:
             stress=torch.zeros((B, 3, 3), dtype=torch.float64, device=dev) if stress else None,
             energy_var=torch.zeros(B, dtype=torch.float64, device=dev),
             force_var=torch.zeros(max(N, 1), dtype=torch.float32, device=dev) if force_var else None,
-            atomic_energy=torch.zeros((max(N, 1), M), dtype=torch.float32, device=dev))
+            atomic_energy=torch.zeros((max(N, 1), M), dtype=torch.float32, device=dev),
+            energy_mean=torch.zeros(B, dtype=torch.float64, device=dev),
+            status=torch.zeros(1, dtype=torch.int32, device=dev))
         lib = A.load()
         self._mc = model.c()
         self._sc = system.c()
@@ -237,7 +254,7 @@ class EnergyForces:
         self.ws_bytes = nbytes
         o = self.out
         self._oc = A.gmnn_outputs(_ptr(o.energy), _ptr(o.forces), _ptr(o.stress), _ptr(o.energy_var),
-                                  _ptr(o.force_var), _ptr(o.atomic_energy))
+                                  _ptr(o.force_var), _ptr(o.atomic_energy), _ptr(o.energy_mean), _ptr(o.status))
         self._plan = None
         self.set_plan(plan)
 
@@ -427,6 +444,7 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
             if g.shape != v.shape or g.dtype != torch.float32 or g.device != v.device or not g.is_contiguous():
                 raise ValueError(f"out[{k!r}] must be a contiguous float32 tensor of shape {tuple(v.shape)} on {v.device}")
     gc = A.gmnn_param_grads(*[_ptr(grads[k]) for k in PARAM_NAMES])
+    model.ensure_packed()
     mc, sc, nc = model.c(), system.c(), nl.c()
     nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), 0)
     if workspace is None or workspace.numel() < nbytes:
@@ -448,9 +466,13 @@ class EnergyForcesFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, model, system, nl, *params):
+        own = model.params()
+        if len(params) != len(own) or any(p is not q for p, q in zip(params, own)):
+            raise ValueError("EnergyForcesFunction takes the model's own parameter tensors (model.params())")
+        model.ensure_packed()  # an in-place optimiser step since the last call
         out = energy_forces(model, system, nl, precision=model.train_precision, stress=False)
         ctx.model, ctx.system, ctx.nl = model, system, nl
-        return out.energy.mean(1), out.forces[: system.n_atoms].clone()
+        return out.energy_mean.clone(), out.forces[: system.n_atoms].clone()
 
     @staticmethod
     def backward(ctx, gE, gF):

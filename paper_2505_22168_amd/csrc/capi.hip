@@ -22,14 +22,14 @@ __global__ void pair_backward_heads(DevModel m, DevSystem sys, const float* psib
 template <int LPA, bool VAR>
 __global__ void finish(int M, DevSystem sys, const float* gpair, const float* atomic_e, const float* virial,
                        int want_stress, int nb_gather, int64_t gstride, int nchunk, double* partial, int* counters,
-                       float* forces, float* force_var, double* energy, double* energy_var, double* stress,
-                       const double* tile_part, int tile_atoms);
+                       float* forces, float* force_var, double* energy, double* energy_var, double* energy_mean,
+                       double* stress, const double* tile_part, int tile_atoms);
 gmnn_status launch_tile(bool fused, bool perhead, int tile_atoms, const DevModel& m, const DevSystem& sys, bool bf16,
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
                         int64_t gstride, double* tile_rec, hipStream_t stream);
 bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead);
 gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,
-                          float* atomic_e, float* psibar, hipStream_t s);
+                          float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev);
 size_t stream_lds_bytes(int hp, bool bf16, int n_heads);
 size_t stream_g_bytes(int n_atoms, bool bf16);
 size_t stream_dg_bytes(int n_atoms);
@@ -271,6 +271,7 @@ static DevSystem dev_system(const gmnn_system* s, const gmnn_neighbors* nl) {
   d.nj = nl->j;
   d.nshift = nl->shift;
   d.rev = nl->rev;
+  d.status = nullptr;
   return d;
 }
 
@@ -455,7 +456,8 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   int* counters = (int*)(W + L.counters);
   double* tilerec = (double*)(W + L.tilerec);
   const DevModel dm = dev_model(m);
-  const DevSystem ds = dev_system(sys, nl);
+  DevSystem ds = dev_system(sys, nl);
+  ds.status = out->status;
   const bool bf16 = (flags & GMNN_PREC_BF16) != 0;
   const int N = sys->n_atoms;
   const size_t beta_lds = sizeof(float) * (size_t)m->n_species * m->n_species * kS * kMaxBasis;
@@ -480,11 +482,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
       mark(0);
       st = launch_tile(true, false, P.ta, dm, ds, bf16, nullptr, atomic_e, nullptr, gpair, virial, gstride, tilerec, s);
       if (st != GMNN_OK) return st;
-      mark(1);
-      mark(2);
-      mark(3);
-      mark(4);
-      mark(5);
+      for (int k = 1; k < 10; ++k) mark(k);
     } else {
       mark(0);
       const int nzc = nchunk > 1 ? sys->n_structs : 0;
@@ -496,27 +494,23 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
       else MOMENTS(8);
 #undef MOMENTS
       mark(1);
-      mark(2);
-      if (P.stream)
-        st = launch_stream(dm, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s);
-      else
+      if (P.stream) {
+        st = launch_stream(dm, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s, ev ? ev + 2 : nullptr);
+      } else {
+        mark(2);
         st = launch_tile(false, var, 16, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, nullptr, s);
+        for (int k = 3; k < 8; ++k) mark(k);
+      }
       if (st != GMNN_OK) return st;
-      mark(3);
-      mark(4);
+      mark(8);
 #define PAIR_BACKWARD(LPA)                                                                                 \
   hipLaunchKernelGGL(pair_backward<LPA>, dim3(nb_gather), dim3(kPairThreads), beta_lds, s, dm, ds, psibar, gpair, \
                      virial)
       if (nh > 1) {
         // one backward per head: every pair's geometry serves all heads
         const size_t lds = beta_lds + sizeof(float) * kHeadsAtoms * (size_t)nh * kS * kPacked;
-        static bool attr = false;
-        if (!attr) {
-          if (hipFuncSetAttribute((const void*)pair_backward_heads, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024) != hipSuccess)
-            return GMNN_ERR_HIP;
-          attr = true;
-        }
+        st = ensure_lds_limit((const void*)pair_backward_heads, lds);
+        if (st != GMNN_OK) return st;
         hipLaunchKernelGGL(pair_backward_heads, dim3((N + kHeadsAtoms - 1) / kHeadsAtoms), dim3(kPairThreads), lds,
                            s, dm, ds, psibar, gpair, virial, nh, gstride);
       } else if (lpa == 64) PAIR_BACKWARD(64);
@@ -524,17 +518,17 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
       else if (lpa == 16) PAIR_BACKWARD(16);
       else PAIR_BACKWARD(8);
 #undef PAIR_BACKWARD
-      mark(5);
+      mark(9);
     }
   }
-  mark(6);
+  mark(10);
   const int want_stress = (flags & GMNN_WANT_STRESS) ? 1 : 0;
   const int nbg = N > 0 ? nb_gather : 0;
   const dim3 fgrid(nbg + sys->n_structs * nchunk);
 #define FINISH(LPA, VAR)                                                                                       \
   hipLaunchKernelGGL((finish<LPA, VAR>), fgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial, \
                      want_stress, nbg, gstride, nchunk, partial, counters, out->forces, out->force_var, out->energy, \
-                     out->energy_var, out->stress, fused ? tilerec : nullptr, fused ? P.ta : 0)
+                     out->energy_var, out->energy_mean, out->stress, fused ? tilerec : nullptr, fused ? P.ta : 0)
   if (lpa == 64) {
     if (var) FINISH(64, true);
     else FINISH(64, false);
@@ -549,10 +543,15 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
     else FINISH(8, false);
   }
 #undef FINISH
-  mark(7);
+  mark(11);
   if (hipGetLastError() != hipSuccess) return GMNN_ERR_HIP;
   if (flags & GMNN_SYNC) {
     if (hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
+    if (out->status) {
+      uint32_t word = 0;
+      if (hipMemcpy(&word, out->status, 4, hipMemcpyDeviceToHost) != hipSuccess) return GMNN_ERR_HIP;
+      if (word) return GMNN_ERR_DEVICE_FLAG;
+    }
   }
   return GMNN_OK;
 }

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "../../include/gmnn.h"
 
 #define GMNN_WAVE 64
@@ -39,6 +43,27 @@ __device__ inline int xcd_block(int b, int nb) {
   const int q = nb / kXcds, r = nb % kXcds;
   const int x = b % kXcds, k = b / kXcds;
   return x * q + (x < r ? x : r) + k;
+}
+
+// ---------------------------------------------------------------------------
+// Dynamic-LDS limit of a kernel on the current device, raised to `bytes` the
+// first time a launch needs it.  One process-wide record of (device, kernel)
+// -> limit set, guarded by a mutex: safe from several host threads, and each
+// device gets its own attribute call.
+// ---------------------------------------------------------------------------
+inline gmnn_status ensure_lds_limit(const void* kernel, size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GMNN_ERR_HIP;
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(dev, kernel);
+  const auto it = done.find(key);
+  if (it != done.end() && it->second >= bytes) return GMNN_OK;
+  if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    return GMNN_ERR_HIP;
+  done[key] = bytes;
+  return GMNN_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -100,6 +100,7 @@ struct DevSystem {
   const int32_t* nj;
   const int32_t* nshift;
   const int32_t* rev;
+  uint32_t* status;  // device status word (GMNN_FLAG_*), may be null
 };
 
 }  // namespace gmnn

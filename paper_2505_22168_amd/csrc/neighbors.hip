@@ -358,7 +358,9 @@ __global__ void __launch_bounds__(64 * kRowsWaves) nl_rows(
   if (MODE == 0) {
     count = wave_sum(count);
     if (l == 0) {
-      row_count[i] = count;
+      // a row past the limit is truncated (and flagged): its slots are exactly
+      // the ones the collect pass fills, so the list stays well formed
+      row_count[i] = count < GMNN_MAX_ROW ? count : GMNN_MAX_ROW;
       if (count > GMNN_MAX_ROW) raise_flag(status, GMNN_FLAG_ROW_TOO_LONG);
     }
     return;

@@ -298,7 +298,14 @@ __device__ inline void atom_moments_from(const DevModel& m, const DevSystem& sys
     for (int u = 0; u < kPairUnroll; ++u) {
       const float dx = g.dx[u], dy = g.dy[u], dz = g.dz[u];
       const float r2 = dx * dx + dy * dy + dz * dz;
-      if (!g.ok[u] || !(r2 < m.rc2) || r2 == 0.0f) continue;
+      if (!g.ok[u]) continue;
+      if (!(r2 < m.rc2) || r2 == 0.0f) {
+        // a listed pair at zero distance, or with a non-finite separation (a
+        // non-finite position), is left out and flagged
+        if (sys.status && r2 == 0.0f) raise_flag(sys.status, GMNN_FLAG_COINCIDENT);
+        if (sys.status && !(r2 <= 3.402823466e38f)) raise_flag(sys.status, GMNN_FLAG_NONFINITE);
+        continue;
+      }
       float r, ir;
       length_of(r2, r, ir);
       Radial rad;

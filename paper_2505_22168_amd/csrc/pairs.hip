@@ -294,7 +294,8 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
                                                      int64_t gstride, int nchunk, double* __restrict__ partial,
                                                      int* __restrict__ counters, float* __restrict__ forces,
                                                      float* __restrict__ force_var, double* __restrict__ energy,
-                                                     double* __restrict__ energy_var, double* __restrict__ stress,
+                                                     double* __restrict__ energy_var,
+                                                     double* __restrict__ energy_mean, double* __restrict__ stress,
                                                      const double* __restrict__ tile_part, int tile_atoms) {
   const int n_red = (int)gridDim.x - nb_gather;
   if ((int)blockIdx.x >= n_red) {
@@ -318,6 +319,8 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
         forces[3 * (int64_t)i] = f[0];
         forces[3 * (int64_t)i + 1] = f[1];
         forces[3 * (int64_t)i + 2] = f[2];
+        if (sys.status && !(fabsf(f[0]) + fabsf(f[1]) + fabsf(f[2]) <= 3.402823466e38f))
+          raise_flag(sys.status, GMNN_FLAG_NONFINITE);
       }
     } else {
       float f[kMaxHeads][3];
@@ -360,6 +363,8 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
         forces[3 * (int64_t)i + 1] = mean[1];
         forces[3 * (int64_t)i + 2] = mean[2];
         force_var[i] = var * invM;
+        if (sys.status && !(fabsf(mean[0]) + fabsf(mean[1]) + fabsf(mean[2]) + var <= 3.402823466e38f))
+          raise_flag(sys.status, GMNN_FLAG_NONFINITE);
       }
     }
     return;
@@ -408,15 +413,23 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
     if (threadIdx.x == 0) counters[b] = 0;  // ready for the next evaluation
   }
   __syncthreads();
-  if (threadIdx.x < M) energy[(int64_t)b * M + threadIdx.x] = vals[threadIdx.x];
+  if (threadIdx.x < M) {
+    const double e = vals[threadIdx.x];
+    energy[(int64_t)b * M + threadIdx.x] = e;
+    if (sys.status && !(fabs(e) <= 1.7976931348623157e308)) raise_flag(sys.status, GMNN_FLAG_NONFINITE);
+  }
   if (want_stress && threadIdx.x < 9) stress[(int64_t)b * 9 + threadIdx.x] = vals[kMaxHeads + threadIdx.x] / fabs(cell_det);
-  if (energy_var && threadIdx.x == 0) {
+  if ((energy_var || energy_mean) && threadIdx.x == 0) {
+    // head mean and population variance (1/M), heads in order
     double mean = 0.0;
     for (int v = 0; v < M; ++v) mean += vals[v];
     mean /= (double)M;
-    double var = 0.0;
-    for (int v = 0; v < M; ++v) var += (vals[v] - mean) * (vals[v] - mean);
-    energy_var[b] = var / (double)M;
+    if (energy_mean) energy_mean[b] = mean;
+    if (energy_var) {
+      double var = 0.0;
+      for (int v = 0; v < M; ++v) var += (vals[v] - mean) * (vals[v] - mean);
+      energy_var[b] = var / (double)M;
+    }
   }
 }
 
@@ -431,7 +444,7 @@ template __global__ void pair_backward<64>(DevModel, DevSystem, const float*, fl
 #define FIN(LPA, VAR)                                                                                         \
   template __global__ void finish<LPA, VAR>(int, DevSystem, const float*, const float*, const float*, int, int, \
                                             int64_t, int, double*, int*, float*, float*, double*, double*, double*, \
-                                            const double*, int);
+                                            double*, const double*, int);
 FIN(8, false) FIN(16, false) FIN(32, false) FIN(64, false) FIN(8, true) FIN(16, true) FIN(32, true) FIN(64, true)
 #undef FIN
 

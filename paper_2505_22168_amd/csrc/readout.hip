@@ -566,35 +566,35 @@ __global__ void __launch_bounds__(kBkThreads) readout_backward(DevSystem sys, co
 }
 
 // ---------------------------------------------------------------------------
-template <class K>
-static bool ro_set_lds(K k, size_t bytes) {
-  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
-}
-
 constexpr size_t kLdsMax = 160 * 1024;
 
 template <int HP, bool BF16>
 static gmnn_status launch_stream_t(const DevModel& m, const DevSystem& sys, const float* psi, void* G, float* dG,
-                                   float* atomic_e, float* psibar, hipStream_t s) {
+                                   float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev) {
+  auto mark = [&](int k) {
+    if (ev) (void)hipEventRecord(ev[k], s);
+  };
   using NL = NetLds<HP, BF16>;
   if (NL::bytes(m.M) > kLdsMax) return GMNN_ERR_UNSUPPORTED;
-  static bool attr = false;
-  if (!attr) {
-    const size_t net_max = NL::bytes(kMaxHeads) < kLdsMax ? NL::bytes(kMaxHeads) : kLdsMax;
-    if (!ro_set_lds(readout_features<BF16>, FeatLds<BF16>::bytes) ||
-        !ro_set_lds(readout_network<HP, BF16>, net_max) || !ro_set_lds(readout_backward, BackLds::bytes))
-      return GMNN_ERR_HIP;
-    attr = true;
-  }
+  gmnn_status st = ensure_lds_limit((const void*)readout_features<BF16>, FeatLds<BF16>::bytes);
+  if (st == GMNN_OK) st = ensure_lds_limit((const void*)readout_network<HP, BF16>, NL::bytes(m.M));
+  if (st == GMNN_OK) st = ensure_lds_limit((const void*)readout_backward, BackLds::bytes);
+  if (st != GMNN_OK) return st;
   const int N = sys.n_atoms;
   const int g16 = (N + kRoAtoms - 1) / kRoAtoms;
   const int gn = (N + NL::TM - 1) / NL::TM;
   const int gb = (N + kBkAtoms - 1) / kBkAtoms;
+  mark(0);
   hipLaunchKernelGGL(readout_features<BF16>, dim3(g16), dim3(kRoThreads), FeatLds<BF16>::bytes, s, sys, psi, G);
+  mark(1);
+  mark(2);
   hipLaunchKernelGGL((readout_network<HP, BF16>), dim3(gn), dim3(kRoThreads), NL::bytes(m.M), s, m, sys, (const void*)G,
                      atomic_e, dG);
+  mark(3);
+  mark(4);
   hipLaunchKernelGGL(readout_backward, dim3(gb), dim3(kBkThreads), BackLds::bytes, s, sys, psi, (const float*)dG,
                      psibar);
+  mark(5);
   return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
 }
 
@@ -616,13 +616,14 @@ size_t stream_lds_bytes(int hp, bool bf16, int n_heads) {
 size_t stream_g_bytes(int n_atoms, bool bf16) { return (size_t)n_atoms * kFP * (bf16 ? 2 * 2 : 4); }
 size_t stream_dg_bytes(int n_atoms) { return (size_t)n_atoms * kFP * 4; }
 
+// ev (may be null): 6 events recorded around the three kernels
 gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,
-                          float* atomic_e, float* psibar, hipStream_t s) {
+                          float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev) {
   if (sys.n_atoms == 0) return GMNN_OK;
 #define CASE(HP)                                                                                          \
   if (m.HP1 == HP)                                                                                        \
-    return bf16 ? launch_stream_t<HP, true>(m, sys, psi, G, dG, atomic_e, psibar, s)                      \
-                : launch_stream_t<HP, false>(m, sys, psi, G, dG, atomic_e, psibar, s);
+    return bf16 ? launch_stream_t<HP, true>(m, sys, psi, G, dG, atomic_e, psibar, s, ev)                  \
+                : launch_stream_t<HP, false>(m, sys, psi, G, dG, atomic_e, psibar, s, ev);
   CASE(64) CASE(128) CASE(256) CASE(512)
 #undef CASE
   return GMNN_ERR_UNSUPPORTED;

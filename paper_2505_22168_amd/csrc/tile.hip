@@ -292,12 +292,8 @@ static gmnn_status launch_tile_t(const DevModel& m, const DevSystem& sys, const 
   using L = TileLds<HP, BF16, FUSED, PERHEAD, TA>;
   if (L::bytes > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
   auto k = tile_kernel<HP, BF16, FUSED, PERHEAD, TA>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes) != hipSuccess)
-      return GMNN_ERR_HIP;
-    attr_set = true;
-  }
+  const gmnn_status st = ensure_lds_limit((const void*)k, L::bytes);
+  if (st != GMNN_OK) return st;
   const int grid = (sys.n_atoms + TA - 1) / TA;
   if (grid == 0) return GMNN_OK;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kTileThreads), L::bytes, stream, m, sys, psi, atomic_e, psibar, gpair,

@@ -1008,12 +1008,8 @@ static gmnn_status launch_train_tile_t(const DevModel& m, const DevSystem& sys, 
   using L = TrainLds<HP>;
   if (L::bytes > 160 * 1024) return GMNN_ERR_UNSUPPORTED;
   auto k = train_tile<HP, BF16>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes) != hipSuccess)
-      return GMNN_ERR_HIP;
-    attr_set = true;
-  }
+  const gmnn_status sa = ensure_lds_limit((const void*)k, L::bytes);
+  if (sa != GMNN_OK) return sa;
   const int grid = (sys.n_atoms + kTA - 1) / kTA;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kTrainThreads), L::bytes, s, m, sys, psi, psidot, ebar, psibar, psidotbar,
                      X1, Y1, X2, Y2, w3g, qsig);
@@ -1137,13 +1133,8 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
   // waves per block: the beta table plus one gradient copy per wave in 160 KB
   const int beta_waves = (int)std::min<size_t>(kBetaMaxThreads / 64, std::max<size_t>(1, 160 * 1024 / beta_lds - 1));
   {
-    static bool attr = false;
-    if (!attr) {
-      if (hipFuncSetAttribute((const void*)pair_beta_grad, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
-          hipSuccess)
-        return GMNN_ERR_HIP;
-      attr = true;
-    }
+    const gmnn_status sa = ensure_lds_limit((const void*)pair_beta_grad, beta_lds * (1 + beta_waves));
+    if (sa != GMNN_OK) return sa;
   }
   hipLaunchKernelGGL(pair_beta_grad, dim3(L.beta_blocks), dim3(64 * beta_waves), beta_lds * (1 + beta_waves), s, m, sys,
                      lambda, psibar, psidotbar, bpart);

@@ -75,6 +75,10 @@ def test_row_too_long_flagged_list_well_formed():
     lib = A.load()
     sysc = system.c()
     nl = g.NeighborList(n, n * n, "cuda")  # room for every pair: the rows are filled
+    # sentinels a well-formed list cannot hold (an image code with its top byte
+    # set): every slot the list reports must be overwritten by the build
+    nl.j.fill_(n - 1)
+    nl.shift.fill_(0x7F000000)
     nbytes = lib.gmnn_neighbors_workspace_bytes(C.byref(sysc), 5.0, 0.0)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     nlc = nl.c()
@@ -92,3 +96,51 @@ def test_row_too_long_flagged_list_well_formed():
     rev = nl.rev[:P].cpu().numpy()
     assert j.min() >= 0 and j.max() < n
     assert rev.min() >= 0 and rev.max() < P
+    # truncated rows reserve exactly the slots they fill
+    lengths = np.diff(nl.row_ptr.cpu().numpy())
+    assert lengths.max() == 1024 and lengths.sum() == P
+    sh = nl.shift[:P].cpu().numpy()
+    assert not np.any(sh == 0x7F000000)
+
+
+def test_output_status_word_flags_zero_distance_and_nonfinite():
+    """A listed pair moved to zero distance, and a non-finite position, after
+    the list was built: the evaluation leaves the pair out and raises the
+    output status bits; GMNN_SYNC turns them into GMNN_ERR_DEVICE_FLAG."""
+    g = need_gpu()
+    from paper_2505_22168_amd import _capi as A
+    batch, params, spec = make_workload("tiny")
+    model = g.Model.from_params(params, "cuda")
+    for what in ("coincident", "nonfinite"):
+        system = g.System.from_batch(batch, "cuda")
+        nl = g.build_neighbors(system, spec.model.r_cut, 0.5)
+        ev = g.EnergyForces(model, system, nl, precision="fp32")
+        ev(sync=True)
+        assert int(ev.out.status.item()) == 0
+        if what == "coincident":
+            n = nl.n_pairs
+            rows = nl.rows()[:n].cpu().numpy()
+            same = np.nonzero((rows == 0) & (nl.shift[:n].cpu().numpy() == 0))[0]
+            j = int(nl.j[int(same[0])].item())  # a neighbour of atom 0 in the same image
+            system.pos[j] = system.pos[0]
+            flag = A.GMNN_FLAG_COINCIDENT
+        else:
+            system.pos[5, 1] = float("nan")
+            flag = A.GMNN_FLAG_NONFINITE
+        ev()
+        torch.cuda.synchronize()
+        assert int(ev.out.status.item()) & flag
+        with pytest.raises(A.GMNNError) as e:
+            ev(sync=True)
+        assert e.value.status == A.GMNN_ERR_DEVICE_FLAG
+
+
+def test_energy_mean_over_heads_from_the_library():
+    g = need_gpu()
+    batch, params, spec = make_workload("ensemble", n_structs=5)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, 5.0)
+    model = g.Model.from_params(params, "cuda")
+    out = g.EnergyForces(model, system, nl, precision="fp32")(sync=True)
+    E = out.energy.cpu().numpy()
+    assert np.allclose(out.energy_mean.cpu().numpy(), E.mean(1), rtol=1e-15, atol=0)

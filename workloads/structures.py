@@ -129,3 +129,38 @@ def make_batch(structs) -> Batch:
     ptr = np.zeros(len(structs) + 1, dtype=np.int64)
     ptr[1:] = np.cumsum([len(s[1]) for s in structs])
     return Batch(pos, species, cell, pbc, ptr)
+
+
+def cluster_cut(batch: Batch, center: int, radius: float):
+    """Non-periodic cluster of the atoms of ``center``'s structure whose closest
+    periodic image lies within ``radius`` of atom ``center``, each placed at
+    that image.  Needs every periodic cell width above 2 * radius (one image
+    per atom).
+
+    Positions are float64: centre position + (x_j - x_c + S h), evaluated in
+    float64 from the float32 inputs, so every separation inside the cluster
+    equals the periodic one to float64 rounding.  Returns (Batch, index of each
+    cluster atom in ``batch``, its distance from the centre); the centre is
+    cluster atom 0.
+
+    Input manipulation only.  With a finite cutoff r_c, an atom's energy
+    depends on atoms within r_c of it and an atom's force on atoms within
+    2 r_c, so cluster atoms within radius - r_c of the centre have their
+    periodic energies and those within radius - 2 r_c their periodic forces.
+    """
+    soa = batch.struct_of_atom()
+    b = int(soa[center])
+    a0, a1 = int(batch.atom_ptr[b]), int(batch.atom_ptr[b + 1])
+    h = batch.cell[b]
+    x = batch.pos[a0:a1].astype(np.float64)
+    xc = x[center - a0]
+    frac = (x - xc) @ np.linalg.inv(h)
+    S = -np.round(frac) * batch.pbc[b].astype(np.float64)
+    d = (x - xc) + S @ h
+    dist = np.sqrt((d * d).sum(1))
+    keep = np.nonzero(dist < radius)[0]
+    keep = np.concatenate([[center - a0], keep[keep != center - a0]])
+    pos = xc + d[keep]
+    cut = Batch(pos, batch.species[a0:a1][keep].copy(), h[None].copy(), np.zeros((1, 3), dtype=np.uint8),
+                np.array([0, keep.size], dtype=np.int64))
+    return cut, keep + a0, dist[keep]
