@@ -46,6 +46,7 @@ typedef int32_t gmnn_status;
 #define GMNN_ERR_HIP -4           /* a HIP runtime call failed */
 #define GMNN_ERR_DEVICE_FLAG -5   /* a device status flag was raised (SYNC mode) */
 #define GMNN_ERR_WORKSPACE -6     /* workspace smaller than gmnn_workspace_bytes() */
+#define GMNN_ERR_SCRATCH_LIMIT -7 /* input too large for gmnn_energy_forces_noalloc's fixed scratch */
 
 /* bits of the device status word */
 #define GMNN_FLAG_CAPACITY 1u      /* more pairs than nl->capacity */
@@ -220,6 +221,25 @@ gmnn_status gmnn_build_neighbors(const gmnn_system* sys, float cutoff, float ski
 gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys,
                                const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* gmnn_energy_forces for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same evaluation under the built-in plan, with the workspace
+ * taken from a fixed scratch array compiled into the library instead of a
+ * caller buffer.  The caller still passes the model, system, list and
+ * outputs.  Limit: gmnn_workspace_bytes(GMNN_OP_ENERGY_FORCES, ...) must not
+ * exceed GMNN_NOALLOC_SCRATCH_BYTES (64 MiB: for example about 15,000 atoms
+ * with 60 neighbours each), else GMNN_ERR_SCRATCH_LIMIT and nothing runs.
+ * The call allocates nothing: each GPU holds its own copy of the array
+ * (looked up on the first call on that device, with the stream's device
+ * current) until the process ends.  Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other streams, other host
+ * threads) race; calls ordered on one stream do not.  Other behaviour,
+ * arguments and errors as gmnn_energy_forces. */
+#define GMNN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gmnn_status gmnn_energy_forces_noalloc(const gmnn_model* m, const gmnn_system* sys,
+                                       const gmnn_neighbors* nl, uint32_t flags, gmnn_outputs* out,
+                                       void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Execution plans.  Every plan computes the same quantities (up to FP32

@@ -14,6 +14,8 @@ GMNN_ERR_UNSUPPORTED = -3
 GMNN_ERR_HIP = -4
 GMNN_ERR_DEVICE_FLAG = -5
 GMNN_ERR_WORKSPACE = -6
+GMNN_ERR_SCRATCH_LIMIT = -7
+GMNN_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 GMNN_FLAG_CAPACITY = 1
 GMNN_FLAG_NONFINITE = 2
@@ -107,6 +109,8 @@ EXPORTS = {
     "gmnn_neighbors_workspace_bytes": (C.c_size_t, [C.POINTER(gmnn_system), C.c_float, C.c_float]),
     "gmnn_build_neighbors": (C.c_int32, [C.POINTER(gmnn_system), C.c_float, C.c_float,
                                          C.POINTER(gmnn_neighbors), C.c_uint32, vp, C.c_size_t, vp]),
+    "gmnn_energy_forces_noalloc": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
+                                               C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_outputs), vp]),
     "gmnn_energy_forces": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
                                        C.c_uint32, C.POINTER(gmnn_outputs), vp, C.c_size_t, vp]),
     "gmnn_resolve_plan": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.c_uint32,

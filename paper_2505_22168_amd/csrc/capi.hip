@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -319,6 +320,7 @@ const char* gmnn_status_string(gmnn_status s) {
     case GMNN_ERR_HIP: return "HIP runtime error";
     case GMNN_ERR_DEVICE_FLAG: return "device status flag raised";
     case GMNN_ERR_WORKSPACE: return "workspace too small";
+    case GMNN_ERR_SCRATCH_LIMIT: return "input needs more scratch than the allocation-free entry point holds";
     default: return "unknown status";
   }
 }
@@ -559,6 +561,51 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
 gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
                                gmnn_outputs* out, void* workspace, size_t workspace_bytes, void* stream) {
   return gmnn_energy_forces_timed(m, sys, nl, flags, nullptr, out, workspace, workspace_bytes, stream, nullptr);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// the allocation-free entry point: its workspace is a file-scope device
+// array; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in)
+// ---------------------------------------------------------------------------
+namespace gmnn {
+static __device__ __align__(256) unsigned char scratch[GMNN_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_addr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// device address of this device's scratch array, looked up once per device
+static gmnn_status scratch_address(void** addr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GMNN_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return GMNN_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GMNN_ERR_HIP;
+    g_scratch_addr[dev] = p;
+  }
+  *addr = g_scratch_addr[dev];
+  return GMNN_OK;
+}
+}  // namespace gmnn
+
+extern "C" {
+
+gmnn_status gmnn_energy_forces_noalloc(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                       uint32_t flags, gmnn_outputs* out, void* stream) {
+  gmnn_status st = check_model(m);
+  if (st != GMNN_OK) return st;
+  st = check_system(sys);
+  if (st != GMNN_OK) return st;
+  if (!nl) return GMNN_ERR_INVALID_ARG;
+  if (ef_layout(m, sys, nl, flags).bytes > GMNN_NOALLOC_SCRATCH_BYTES) return GMNN_ERR_SCRATCH_LIMIT;
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != GMNN_OK) return st;
+  return gmnn_energy_forces_timed(m, sys, nl, flags, nullptr, out, ws, GMNN_NOALLOC_SCRATCH_BYTES, stream, nullptr);
 }
 
 gmnn_status gmnn_energy_forces_plan(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,

@@ -4,9 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <map>
 #include <mutex>
-#include <utility>
 
 #include "../../include/gmnn.h"
 
@@ -47,22 +45,30 @@ __device__ inline int xcd_block(int b, int nb) {
 
 // ---------------------------------------------------------------------------
 // Dynamic-LDS limit of a kernel on the current device, raised to `bytes` the
-// first time a launch needs it.  One process-wide record of (device, kernel)
-// -> limit set, guarded by a mutex: safe from several host threads, and each
-// device gets its own attribute call.
+// first time a launch needs it.  One process-wide table of (device, kernel)
+// -> limit set (fixed size, no heap allocation), guarded by a mutex: safe
+// from several host threads, and each device gets its own attribute call.
 // ---------------------------------------------------------------------------
 inline gmnn_status ensure_lds_limit(const void* kernel, size_t bytes) {
+  struct Rec {
+    int dev;
+    const void* kernel;
+    size_t bytes;
+  };
+  constexpr int kRecs = 512;
+  static Rec recs[kRecs];
+  static int n_recs = 0;
+  static std::mutex mu;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return GMNN_ERR_HIP;
-  static std::mutex mu;
-  static std::map<std::pair<int, const void*>, size_t> done;
   std::lock_guard<std::mutex> lock(mu);
-  const auto key = std::make_pair(dev, kernel);
-  const auto it = done.find(key);
-  if (it != done.end() && it->second >= bytes) return GMNN_OK;
+  int r = 0;
+  while (r < n_recs && !(recs[r].dev == dev && recs[r].kernel == kernel)) ++r;
+  if (r < n_recs && recs[r].bytes >= bytes) return GMNN_OK;
   if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
     return GMNN_ERR_HIP;
-  done[key] = bytes;
+  if (r < n_recs) recs[r].bytes = bytes;
+  else if (n_recs < kRecs) recs[n_recs++] = Rec{dev, kernel, bytes};  // a full table only costs repeated calls
   return GMNN_OK;
 }
 
