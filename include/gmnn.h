@@ -63,6 +63,8 @@ typedef int32_t gmnn_status;
 #define GMNN_WANT_STRESS 2u        /* fill outputs->stress */
 #define GMNN_WANT_FORCE_VAR 4u     /* fill outputs->force_var (one backward per head) */
 #define GMNN_SYNC 8u               /* synchronise and turn device flags into a status */
+#define GMNN_BACKWARD_LANES16 16u  /* gmnn_backward: 16 lanes per atom row in its pair kernels whatever
+                                      the atom count (built-in: 64 below 8192 atoms, 16 from there) */
 
 /* A ragged batch of B structures with N atoms in total (Section 2.1: a
  * configuration is positions R and atomic numbers Z; Section 3.5: with a
@@ -123,7 +125,17 @@ typedef struct gmnn_model {
   void* packed;           /* device buffer of gmnn_model_packed_bytes() bytes,
                              filled by gmnn_model_prepare(): MFMA-ordered FP32
                              and BF16 copies of W1, W2 and their transposes */
+  int32_t basis;          /* radial basis functions g_k (Section 2.1 names both):
+                             GMNN_BASIS_GAUSSIAN: equidistant Gaussians (r_min,
+                             gamma as above); GMNN_BASIS_BESSEL: Bessel-like
+                             g_n = a_n [sinc((n+1) x) + sinc((n+2) x)],
+                             x = pi r / r_cut, sinc(y) = sin(y)/y,
+                             a_n = (-1)^n sqrt(2) pi r_cut^(-3/2) (n+1)(n+2) /
+                             sqrt((n+1)^2 + (n+2)^2) (r_min, gamma unused).
+                             Both are multiplied by the cosine cutoff. */
 } gmnn_model;
+#define GMNN_BASIS_GAUSSIAN 0
+#define GMNN_BASIS_BESSEL 1
 
 /* Parameter gradients: FP32 device arrays with the shapes of the matching
  * gmnn_model fields; overwritten by gmnn_backward. */

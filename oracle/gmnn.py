@@ -22,7 +22,8 @@ Method (Section 2.1 of the paper):
 Readings where the paper is silent (each listed in the design notes):
   * cutoff f_c(r) = (cos(pi r / r_c) + 1)/2 for r < r_c, else 0;
   * g_k(r) = exp(-gamma (r - mu_k)^2), mu_k = r_min + k*delta,
-    delta = (r_c - r_min)/(K-1), gamma = 1/(2 delta^2);
+    delta = (r_c - r_min)/(K-1), gamma = 1/(2 delta^2); or the Bessel-like
+    f_n of bessel_basis, with the same cutoff function;
   * the contraction set has eight families (below); the paper prints the
     first (Psi1.Psi1) and the last (Psi1 Psi3 Psi2) and elides the rest;
   * activation swish(x) = x * sigmoid(x); one network shared by all species;
@@ -90,9 +91,27 @@ def cutoff_fn(r, r_cut):
 
 
 def radial_basis(r, spec):
-    """Equidistant Gaussians g_k(r) = exp(-gamma (r - mu_k)^2), [P,K]."""
+    """Basis functions g_k(r), [P,K] (Section 2.1: equidistant Gaussians or
+    the non-orthogonal Bessel-like functions of Kocer et al.)."""
+    if getattr(spec, "basis", "gaussian") == "bessel":
+        return bessel_basis(r, spec.r_cut, spec.n_basis)
     mu = spec.r_min + spec.delta * torch.arange(spec.n_basis, dtype=DT)
     return torch.exp(-spec.gamma * (r[:, None] - mu[None, :]) ** 2)
+
+
+def bessel_basis(r, r_cut, K):
+    """Bessel-like functions (reading; the paper names them without a
+    formula): for n = 0..K-1, with x = pi r / r_c and sinc(y) = sin(y)/y,
+        f_n(r) = a_n [sinc((n+1) x) + sinc((n+2) x)],
+        a_n = (-1)^n sqrt(2) pi r_c^(-3/2) (n+1)(n+2) / sqrt((n+1)^2 + (n+2)^2).
+    Neighbouring orders of the sine have opposite signs at r_c, so every f_n
+    vanishes there with zero slope."""
+    n = torch.arange(K, dtype=DT)
+    a = (-1.0) ** n * math.sqrt(2.0) * math.pi * r_cut ** -1.5 * (n + 1) * (n + 2) / torch.sqrt(
+        (n + 1) ** 2 + (n + 2) ** 2)
+    x = (math.pi / r_cut) * r[:, None]
+    y1, y2 = (n + 1) * x, (n + 2) * x
+    return a * (torch.sin(y1) / y1 + torch.sin(y2) / y2)
 
 
 def radial_functions(r, zi, zj, beta, spec):

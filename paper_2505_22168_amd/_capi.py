@@ -29,6 +29,7 @@ GMNN_PREC_BF16 = 1
 GMNN_WANT_STRESS = 2
 GMNN_WANT_FORCE_VAR = 4
 GMNN_SYNC = 8
+GMNN_BACKWARD_LANES16 = 16
 
 GMNN_SCHEDULE_AUTO = 0
 GMNN_SCHEDULE_FUSED = 1
@@ -60,7 +61,11 @@ class gmnn_model(C.Structure):
                 ("hidden1", C.c_int32), ("hidden2", C.c_int32), ("n_heads", C.c_int32),
                 ("r_min", C.c_float), ("r_cut", C.c_float), ("gamma", C.c_float), ("psi_scale", C.c_float),
                 ("beta", vp), ("W1", vp), ("b1", vp), ("W2", vp), ("b2", vp), ("W3", vp), ("b3", vp),
-                ("scale", vp), ("shift", vp), ("packed", vp)]
+                ("scale", vp), ("shift", vp), ("packed", vp), ("basis", C.c_int32)]
+
+
+GMNN_BASIS_GAUSSIAN = 0
+GMNN_BASIS_BESSEL = 1
 
 
 class gmnn_param_grads(C.Structure):

@@ -173,8 +173,9 @@ class Model:
         s = self.spec
         t = self.tensors
         H1, H2 = s.hidden
+        basis = {"gaussian": A.GMNN_BASIS_GAUSSIAN, "bessel": A.GMNN_BASIS_BESSEL}[getattr(s, "basis", "gaussian")]
         return A.gmnn_model(s.n_species, s.n_radial, s.n_basis, H1, H2, s.n_heads, s.r_min, s.r_cut, s.gamma,
-                            s.psi_scale, *[_ptr(t[k]) for k in PARAM_NAMES], _ptr(packed))
+                            s.psi_scale, *[_ptr(t[k]) for k in PARAM_NAMES], _ptr(packed), basis)
 
     def c(self):
         return self._c(self.packed)
@@ -418,7 +419,7 @@ def maxwell_boltzmann(masses, temperature: float, seed: int):
 
 # ---------------------------------------------------------------------------
 def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, workspace=None,
-                precision: str = "fp32", out=None):
+                precision: str = "fp32", out=None, lanes16: bool = False):
     """Gradients of a loss w.r.t. every model parameter (gmnn_backward), given
     dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3];
     precision "bf16" runs the network products of the double backward in BF16
@@ -430,7 +431,7 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
     freshly allocated result needs clearing first."""
     if precision not in ("fp32", "bf16"):
         raise ValueError(precision)
-    flags = A.GMNN_PREC_BF16 if precision == "bf16" else 0
+    flags = (A.GMNN_PREC_BF16 if precision == "bf16" else 0) | (A.GMNN_BACKWARD_LANES16 if lanes16 else 0)
     lib = A.load()
     dev = system.device
     dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=dev).contiguous()

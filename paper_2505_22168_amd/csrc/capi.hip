@@ -37,8 +37,9 @@ size_t stream_dg_bytes(int n_atoms);
 size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead);
 bool train_supported(const DevModel& m);
 size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
-gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, int H1, int H2, const double* ebar,
-                           const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s);
+gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
+                           const double* ebar, const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes,
+                           hipStream_t s);
 
 constexpr int kPairThreads = 256;
 // below this many atoms the built-in plan takes the fused (latency) schedule,
@@ -204,9 +205,19 @@ static DevModel dev_model(const gmnn_model* m) {
   d.gamma = m->gamma;
   d.delta = (m->r_cut - m->r_min) / (float)(m->n_basis - 1);
   d.psi_scale = m->psi_scale;
-  for (int k = 0; k < 8; ++k)
-    d.ck[k] = k < m->n_basis ? (float)std::exp(-(double)d.gamma * (double)d.delta * (double)d.delta * (double)(k * k))
-                             : 0.0f;
+  d.rc_over_pi = (float)((double)m->r_cut / M_PI);
+  d.basis = m->basis;
+  for (int k = 0; k < 8; ++k) {
+    double c = 0.0;
+    if (k < m->n_basis) {
+      if (m->basis == GMNN_BASIS_BESSEL)
+        c = (k % 2 ? -1.0 : 1.0) * std::sqrt(2.0) * M_PI * std::pow((double)m->r_cut, -1.5) * (k + 1.0) * (k + 2.0) /
+            std::sqrt((k + 1.0) * (k + 1.0) + (k + 2.0) * (k + 2.0));
+      else
+        c = std::exp(-(double)d.gamma * (double)d.delta * (double)d.delta * (double)(k * k));
+    }
+    d.ck[k] = (float)c;
+  }
   d.beta = m->beta;
   d.scale = m->scale;
   d.shift = m->shift;
@@ -235,7 +246,9 @@ static gmnn_status check_model(const gmnn_model* m) {
   if (m->n_radial != kS || m->n_basis < 2 || m->n_basis > kMaxBasis || m->n_species < 1 ||
       m->n_species > kMaxSpecies || m->n_heads < 1 || m->n_heads > kMaxHeads || m->hidden1 < 1 || m->hidden2 < 1)
     return GMNN_ERR_UNSUPPORTED;
-  if (!(m->r_cut > m->r_min) || !(m->gamma > 0.0f)) return GMNN_ERR_INVALID_ARG;
+  if (m->basis != GMNN_BASIS_GAUSSIAN && m->basis != GMNN_BASIS_BESSEL) return GMNN_ERR_INVALID_ARG;
+  if (!(m->r_cut > 0.0f)) return GMNN_ERR_INVALID_ARG;
+  if (m->basis == GMNN_BASIS_GAUSSIAN && (!(m->r_cut > m->r_min) || !(m->gamma > 0.0f))) return GMNN_ERR_INVALID_ARG;
   const PackedLayout L = packed_layout(m->hidden1, m->hidden2, m->n_heads);
   if (L.HP1 != L.HP2 || L.HP1 > 512 || (L.HP1 != 64 && L.HP1 != 128 && L.HP1 != 256 && L.HP1 != 512))
     return GMNN_ERR_UNSUPPORTED;
@@ -700,8 +713,8 @@ gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmn
   if (!train_supported(dm)) return GMNN_ERR_UNSUPPORTED;
   const DevSystem ds = dev_system(sys, nl);
   hipStream_t s = (hipStream_t)stream;
-  st = train_backward(dm, ds, (flags & GMNN_PREC_BF16) != 0, m->hidden1, m->hidden2, dL_dE, dL_dF, grads, workspace,
-                      workspace_bytes, s);
+  st = train_backward(dm, ds, (flags & GMNN_PREC_BF16) != 0, (flags & GMNN_BACKWARD_LANES16) != 0, m->hidden1,
+                      m->hidden2, dL_dE, dL_dF, grads, workspace, workspace_bytes, s);
   if (st != GMNN_OK) return st;
   if ((flags & GMNN_SYNC) && hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
   return GMNN_OK;

@@ -67,7 +67,10 @@ struct DevModel {
   int n_species, K, HP1, HP2, M;
   float r_min, r_cut, rc2, gamma, delta, psi_scale;
   float half_inv_rc;    // 0.5 / r_cut: the cutoff's cosine argument in revolutions
-  float ck[8];          // exp(-gamma delta^2 k^2) for k < K, 0 beyond
+  float rc_over_pi;     // r_cut / pi
+  int basis;            // GMNN_BASIS_GAUSSIAN or GMNN_BASIS_BESSEL
+  float ck[8];          // per-order basis constants for k < K (0 beyond): Gaussians
+                        // exp(-gamma delta^2 k^2), Bessel-like a_k
   const float* beta;    // [nsp][nsp][S][K]
   const float* scale;   // [nsp]
   const float* shift;   // [nsp]

@@ -141,22 +141,93 @@ __device__ inline void cutoff_cos_sin(const DevModel& m, float r, float& cs, flo
   sn = __builtin_amdgcn_sinf(rev);
 }
 
-// Gaussians g_k = exp(-gamma (r - mu_k)^2), mu_k = r_min + k delta, by the
-// recurrence g_k = g_0 a^k exp(-gamma delta^2 k^2) with a = exp(2 gamma delta tau)
+// Basis functions g_k (k < kMaxBasis; zero for k >= K) and, with DERIV, their
+// derivatives dg_k/dr, given cs, sn = cos, sin of x = pi r / r_c (the cutoff's
+// argument):
+//   Gaussians    g_k = exp(-gamma (r - mu_k)^2), mu_k = r_min + k delta, by
+//                the recurrence g_k = g_0 a^k exp(-gamma delta^2 k^2) with
+//                a = exp(2 gamma delta tau) (two exponentials per pair);
+//   Bessel-like  g_n = a_n [sinc((n+1) x) + sinc((n+2) x)] with sin(kx) and
+//                cos(kx) by the Chebyshev recurrence from (cs, sn): no further
+//                transcendental; d/dr sinc(kx) = (cos(kx) - sinc(kx)) / r.
+// m.ck holds the per-order constants (exp(-gamma delta^2 k^2), or a_n).
 template <bool DERIV>
-__device__ inline void radial(const DevModel& m, const float* __restrict__ bz /*[S][8]*/, float r, Radial& out) {
+__device__ inline void basis_values(const DevModel& m, float r, float cs, float sn, float (&g)[kMaxBasis],
+                                    float (&dg)[kMaxBasis]) {
+  if (m.basis == GMNN_BASIS_BESSEL) {
+    const float ir = 1.0f / r;
+    const float ix = m.rc_over_pi * ir;  // 1 / x
+    // orders k = n + 1 (a) and n + 2 (b), advanced together
+    float sa = sn, ca = cs;
+    float sb = 2.0f * cs * sn, cb = 2.0f * cs * cs - 1.0f;
+    float sinc_a = sa * ix;
+#pragma unroll
+    for (int n = 0; n < kMaxBasis; ++n) {
+      const float sinc_b = sb * ix * (1.0f / (float)(n + 2));
+      g[n] = m.ck[n] * (sinc_a + sinc_b);
+      if (DERIV) dg[n] = m.ck[n] * ((ca - sinc_a) + (cb - sinc_b)) * ir;
+      const float sc = 2.0f * cs * sb - sa, cc = 2.0f * cs * cb - ca;
+      sa = sb; ca = cb; sb = sc; cb = cc;
+      sinc_a = sinc_b;
+    }
+    return;
+  }
   const float tau = r - m.r_min;
   const float g0 = __expf(-m.gamma * tau * tau);
   const float a = __expf(2.0f * m.gamma * m.delta * tau);
-  float g[kMaxBasis];
   float p = g0;
 #pragma unroll
   for (int k = 0; k < kMaxBasis; ++k) {
     g[k] = p * m.ck[k];  // ck[k] = exp(-gamma delta^2 k^2), zero for k >= K
+    if (DERIV) dg[k] = -2.0f * m.gamma * (tau - (float)k * m.delta) * g[k];
     p *= a;
   }
+}
+
+// The same basis functions one order at a time (next() gives g_k, dg_k/dr
+// for k = 0, 1, ...), for one basis fixed at compile time: the arithmetic of
+// basis_values<true> without arrays, for kernels short of registers.
+template <int BASIS>
+struct BasisIter {
+  float p, a, tau, ir, ix, cs2, sa, ca, sb, cb, sinc_a;
+  __device__ BasisIter(const DevModel& m, float r, float cs, float sn) {
+    if (BASIS == GMNN_BASIS_BESSEL) {
+      ir = 1.0f / r;
+      ix = m.rc_over_pi * ir;
+      cs2 = 2.0f * cs;
+      sa = sn; ca = cs;
+      sb = 2.0f * cs * sn; cb = 2.0f * cs * cs - 1.0f;
+      sinc_a = sa * ix;
+    } else {
+      tau = r - m.r_min;
+      p = __expf(-m.gamma * tau * tau);
+      a = __expf(2.0f * m.gamma * m.delta * tau);
+    }
+  }
+  // order k (the calls go k = 0, 1, ... in turn)
+  __device__ __forceinline__ void next(const DevModel& m, int k, float& g, float& dg) {
+    if (BASIS == GMNN_BASIS_BESSEL) {
+      const float sinc_b = sb * ix * (1.0f / (float)(k + 2));
+      g = m.ck[k] * (sinc_a + sinc_b);
+      dg = m.ck[k] * ((ca - sinc_a) + (cb - sinc_b)) * ir;
+      const float sc = cs2 * sb - sa, cc = cs2 * cb - ca;
+      sa = sb; ca = cb; sb = sc; cb = cc;
+      sinc_a = sinc_b;
+    } else {
+      g = p * m.ck[k];
+      dg = -2.0f * m.gamma * (tau - (float)k * m.delta) * g;
+      p *= a;
+    }
+  }
+};
+
+// R_s = c f_c(r) sum_k beta[s][k] g_k(r) (and dR_s/dr with DERIV)
+template <bool DERIV>
+__device__ inline void radial(const DevModel& m, const float* __restrict__ bz /*[S][8]*/, float r, Radial& out) {
   float sn, cs;
   cutoff_cos_sin(m, r, cs, sn);
+  float g[kMaxBasis], dg[kMaxBasis];
+  basis_values<DERIV>(m, r, cs, sn, g, dg);
   const float fc = 0.5f * (cs + 1.0f) * m.psi_scale;
   const float dfc = -0.5f * (3.14159265358979f / m.r_cut) * sn * m.psi_scale;
 #pragma unroll
@@ -166,7 +237,7 @@ __device__ inline void radial(const DevModel& m, const float* __restrict__ bz /*
     for (int k = 0; k < kMaxBasis; ++k) {
       const float bk = bz[s * kMaxBasis + k];
       B += bk * g[k];
-      if (DERIV) dB += bk * (-2.0f * m.gamma * (tau - (float)k * m.delta)) * g[k];
+      if (DERIV) dB += bk * dg[k];
     }
     out.R[s] = fc * B;
     if (DERIV) out.dR[s] = dfc * B + fc * dB;

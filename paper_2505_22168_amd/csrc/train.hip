@@ -471,6 +471,7 @@ __global__ void __launch_bounds__(kTrainThreads)
 // Blocks of up to 16 waves (four per SIMD hide the per-atom memory round
 // trips), as many as the per-wave LDS copies of the gradient allow.
 constexpr int kBetaMaxThreads = 1024;
+template <int BASIS>
 __global__ void __launch_bounds__(kBetaMaxThreads) pair_beta_grad(DevModel m, DevSystem sys, const float* __restrict__ lambda,
                                                              const float* __restrict__ psibar,
                                                              const float* __restrict__ psidotbar,
@@ -513,15 +514,14 @@ __global__ void __launch_bounds__(kBetaMaxThreads) pair_beta_grad(DevModel m, De
           monomials(ux, uy, uz, mo);
           dmonomials(ux, uy, uz, (ex - ud * ux) * ir, (ey - ud * uy) * ir, (ez - ud * uz) * ir, dm);
           // basis: g_k and (f_c g_k)'
-          const float tau = r - m.r_min;
-          const float g0 = __expf(-m.gamma * tau * tau);
-          const float aa = __expf(2.0f * m.gamma * m.delta * tau);
           float sn, cs;
           cutoff_cos_sin(m, r, cs, sn);
+
           const float fc = 0.5f * (cs + 1.0f) * m.psi_scale;
           const float dfc = -0.5f * (3.14159265358979f / m.r_cut) * sn * m.psi_scale;
           const float* pb = psibar + (int64_t)i * (kS * kPacked);
           const float* pd = psidotbar + (int64_t)i * (kS * kPacked);
+          const BasisIter<BASIS> b0(m, r, cs, sn);
 #pragma unroll
           for (int s = 0; s < kS; ++s) {
             float A = 0.0f, Ad = 0.0f, Bs = 0.0f;
@@ -531,13 +531,12 @@ __global__ void __launch_bounds__(kBetaMaxThreads) pair_beta_grad(DevModel m, De
               Ad += pd[s * kPacked + t] * mo[t];
               Bs += pd[s * kPacked + t] * dm[t];
             }
-            float gk = g0;
+            BasisIter<BASIS> bi = b0;
 #pragma unroll
             for (int k = 0; k < kMaxBasis; ++k) {
-              const float g = gk * m.ck[k];
-              const float dg = -2.0f * m.gamma * (tau - (float)k * m.delta) * g;
-              val[s * kMaxBasis + k] = fc * g * (A + Bs) + (dfc * g + fc * dg) * ud * Ad;
-              gk *= aa;
+              float gk, dgk;
+              bi.next(m, k, gk, dgk);
+              val[s * kMaxBasis + k] = fc * gk * (A + Bs) + (dfc * gk + fc * dgk) * ud * Ad;
             }
           }
         }
@@ -1077,8 +1076,9 @@ bool train_supported(const DevModel& m) {
 
 size_t train_workspace_bytes(int n_atoms, int HP, int nsp) { return train_layout(n_atoms, HP, nsp).bytes; }
 
-gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, int H1, int H2, const double* ebar,
-                           const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes, hipStream_t s) {
+gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
+                           const double* ebar, const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes,
+                           hipStream_t s) {
   const int HP = m.HP1;
   const int nsp = m.n_species;
   const TrainLayout L = train_layout(sys.n_atoms, HP, nsp);
@@ -1098,7 +1098,7 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
   const int N = sys.n_atoms;
   const int nslots = nsp * nsp * kS * kMaxBasis;
   const size_t beta_lds = sizeof(float) * (size_t)nslots;
-  const int lpa = N < 8192 ? 64 : 16;
+  const int lpa = (N < 8192 && !lanes16) ? 64 : 16;
   const int nb = (N + kPairBlock / lpa - 1) / (kPairBlock / lpa);
   gmnn_status st = GMNN_OK;
   if (N > 0) {
@@ -1133,11 +1133,12 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, i
   // waves per block: the beta table plus one gradient copy per wave in 160 KB
   const int beta_waves = (int)std::min<size_t>(kBetaMaxThreads / 64, std::max<size_t>(1, 160 * 1024 / beta_lds - 1));
   {
-    const gmnn_status sa = ensure_lds_limit((const void*)pair_beta_grad, beta_lds * (1 + beta_waves));
+    auto kb = m.basis == GMNN_BASIS_BESSEL ? pair_beta_grad<GMNN_BASIS_BESSEL> : pair_beta_grad<GMNN_BASIS_GAUSSIAN>;
+    const gmnn_status sa = ensure_lds_limit((const void*)kb, beta_lds * (1 + beta_waves));
     if (sa != GMNN_OK) return sa;
+    hipLaunchKernelGGL(kb, dim3(L.beta_blocks), dim3(64 * beta_waves), beta_lds * (1 + beta_waves), s, m, sys, lambda,
+                       psibar, psidotbar, bpart);
   }
-  hipLaunchKernelGGL(pair_beta_grad, dim3(L.beta_blocks), dim3(64 * beta_waves), beta_lds * (1 + beta_waves), s, m, sys,
-                     lambda, psibar, psidotbar, bpart);
   // weight products, split over chunks of rows, partials summed in chunk order
   const bool staged = HP % kWgBlk == 0;
   const int64_t wg_rows = (staged && !bf16) ? kWgRowsF32 : kWgRows;

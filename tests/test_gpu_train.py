@@ -143,3 +143,51 @@ def test_param_gradients_overwrite_every_element():
                 assert torch.equal(out[k], fresh[k]), (prec, k)
     with pytest.raises(ValueError):
         g.param_grads(model, system, nl, dLdE, dLdF, out={k: v.double() for k, v in model.tensors.items()})
+
+
+@pytest.mark.parametrize("hidden", [(64, 64), (512, 512)])
+def test_param_gradients_multi_chunk(hidden):
+    """Over 600 atoms: the split-K weight products take several row chunks
+    (512 rows for the staged FP32 product, 1024 otherwise), and the scale /
+    shift sums several 256-atom blocks; FP32 within 1e-4 and BF16 within 3e-2
+    (relative l2) of the FP64 oracle gradient."""
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(hidden=hidden, n_structs=2, n_lo=330, n_hi=400)
+    N = batch.n_atoms
+    K = 16 * ((N + 7) // 8)  # weight-product rows: primal + tangent row per atom
+    assert N > 600 and K > 1024
+    L, gref, dLdE, dLdF = loss_and_param_grads(batch, params, onl, Er, Fr)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, params.spec.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    for prec, tol in (("fp32", 1e-4), ("bf16", 3e-2)):
+        got = g.param_grads(model, system, nl, dLdE, dLdF, precision=prec)
+        torch.cuda.synchronize()
+        for k in PARAM_NAMES:
+            ref = np.asarray(gref[k], dtype=np.float64)
+            err = np.linalg.norm(got[k].cpu().numpy().astype(np.float64).reshape(ref.shape) - ref) / max(
+                np.linalg.norm(ref), 1e-30)
+            print(f"N={N} {hidden} {prec} {k}: rel err {err:.2e}")
+            assert err < tol, (prec, k, err)
+
+
+def test_param_gradients_sixteen_lanes_per_row():
+    """The backward's pair kernels with 16 lanes per atom row (the built-in
+    choice from 8192 atoms: pair_tangent<16>, pair_moments<16>) against the
+    oracle on a small batch."""
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(hidden=(64, 64), n_structs=3, n_lo=30, n_hi=70)
+    L, gref, dLdE, dLdF = loss_and_param_grads(batch, params, onl, Er, Fr)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, params.spec.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    g16 = g.param_grads(model, system, nl, dLdE, dLdF, lanes16=True)
+    g64 = g.param_grads(model, system, nl, dLdE, dLdF)
+    torch.cuda.synchronize()
+    for k in PARAM_NAMES:
+        ref = np.asarray(gref[k], dtype=np.float64)
+        nrm = max(np.linalg.norm(ref), 1e-30)
+        e16 = np.linalg.norm(g16[k].cpu().numpy().astype(np.float64).reshape(ref.shape) - ref) / nrm
+        assert e16 < 1e-4, (k, e16)
+        d = np.linalg.norm((g16[k] - g64[k]).double().cpu().numpy()) / nrm
+        assert d < 1e-5, (k, d)

@@ -31,6 +31,7 @@ class ModelSpec:
     n_heads: int = 1
     psi_scale: float = 49.0 ** -0.25
     sigma0: float = 1.0
+    basis: str = "gaussian"    # radial basis: "gaussian" or "bessel"
 
     @property
     def delta(self) -> float:
