@@ -306,6 +306,33 @@ gmnn_status gmnn_energy_forces_plan(const gmnn_model* m, const gmnn_system* sys,
                                     gmnn_outputs* out, void* workspace, size_t workspace_bytes,
                                     void* stream);
 
+/* Uncertainty-driven bias (Section 2.3, eq. udd) on the shallow ensemble's
+ * energy variance: per structure b with N_b atoms, M heads and population
+ * variance var_b of the head energies,
+ *   E_bias,b = A [exp(-var_b / (M N_b B^2)) - 1],
+ * and the forces (and stress) become those of Ebar + E_bias:
+ *   F = -sum_m c_m dE^m/dx,  c_m = 1/M + dE_bias/dvar * 2 (E^m - Ebar) / M.
+ * The evaluation runs the split schedule in two passes: the energies of every
+ * head first (readout forward only, FP64 sums per structure), then the
+ * backward with the weights c_m (one weighted backward; with
+ * GMNN_WANT_FORCE_VAR the per-head backwards, whose forces give both the
+ * variance of the unbiased head forces and sum_m c_m F^m).  out->energy,
+ * energy_mean and energy_var stay unbiased. */
+typedef struct gmnn_udd {
+  float A;               /* bias strength, eV (finite) */
+  float B;               /* bias width, eV (> 0) */
+  double* bias_energy;   /* [B] E_bias per structure (device), may be NULL */
+} gmnn_udd;
+
+/* gmnn_energy_forces with the uncertainty-driven bias (needs n_heads >= 2;
+ * same workspace, flags and outputs).  plan: NULL for the built-in split
+ * plan, else a SPLIT (or AUTO) plan whose other fields are honoured; FUSED
+ * gives GMNN_ERR_UNSUPPORTED. */
+gmnn_status gmnn_energy_forces_udd(const gmnn_model* m, const gmnn_system* sys,
+                                   const gmnn_neighbors* nl, uint32_t flags, const gmnn_plan* plan,
+                                   const gmnn_udd* udd, gmnn_outputs* out, void* workspace,
+                                   size_t workspace_bytes, void* stream);
+
 /* gmnn_energy_forces_plan with a hipEvent_t recorded on `stream` right before
  * and right after each kernel stage, for profiling: stage_events[2k] /
  * [2k+1] bracket stage k =
@@ -377,11 +404,19 @@ typedef struct gmnn_md {
   double* energy;         /* [B, n_heads] potential energies at the current positions */
   float* ref_pos;         /* [N,3] positions at the last list build */
   uint32_t* disp;         /* [1] largest squared displacement of the step (scratch word) */
+  /* shallow-ensemble options (Section 2.3, Section 3.5); all zero: off */
+  const gmnn_udd* udd;    /* uncertainty-driven bias on the forces (gmnn_energy_forces_udd), may be NULL */
+  int32_t var_every;      /* with GMNN_WANT_FORCE_VAR in flags: the per-head force variance on every
+                             var_every-th step of a call (or of a captured graph) only, the cheap
+                             head-mean forces on the others (mode switching at a dump interval) */
+  float* force_var;       /* [N] written on those steps */
+  double* energy_var;     /* [B] energy variance over heads at every step, may be NULL */
 } gmnn_md;
 
 /* Workspace of gmnn_md_init / _steps / _graph_create (list build and
  * energy/forces); nl->cutoff must already hold r_cut + skin.  flags: the
- * precision bit only.  Returns 0 on invalid arguments. */
+ * precision bit and GMNN_WANT_FORCE_VAR (with md->var_every > 0).  Returns 0
+ * on invalid arguments. */
 size_t gmnn_md_workspace_bytes(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
                                uint32_t flags);
 

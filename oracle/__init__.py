@@ -7,7 +7,9 @@ it is a plain, slow, direct transcription of the method's definitions
 (Section 2.1 of the paper: additive energy, Gaussian radial basis with
 species-pair coefficients, Cartesian moments, full tensor contractions,
 network readout with per-element scale and shift; Section 3.3: forces and
-virials as gradients; Section 2.2: shallow-ensemble statistics).
+virials as gradients; Section 2.2: shallow-ensemble statistics; Section
+2.3: the uncertainty-driven bias; Section 2.1's Bessel-like basis as an
+alternative to the Gaussians).
 
 Every function here is pinned by tests under tests/ against closed forms,
 invariances, brute force or finite differences; none is "parity unpinned".
@@ -15,11 +17,11 @@ invariances, brute force or finite differences; none is "parity unpinned".
 from .neighbors import brute_force_neighbors, NeighborList
 from .gmnn import (
     radial_basis, cutoff_fn, pair_vectors, moments, invariants, feature_index,
-    mlp, atomic_energies, evaluate, OracleResult, loss_and_param_grads,
+    mlp, atomic_energies, evaluate, OracleResult, loss_and_param_grads, udd_bias, evaluate_udd, UddResult,
 )
 
 __all__ = [
     "brute_force_neighbors", "NeighborList", "radial_basis", "cutoff_fn", "pair_vectors",
     "moments", "invariants", "feature_index", "mlp", "atomic_energies", "evaluate",
-    "OracleResult", "loss_and_param_grads",
+    "OracleResult", "loss_and_param_grads", "udd_bias", "evaluate_udd", "UddResult",
 ]

@@ -319,6 +319,47 @@ def evaluate(batch, params, nl, bf16=False, want_force_var=False, want_stress=Tr
 
 
 # ----------------------------------------------------------------------------
+# uncertainty-driven bias (Section 2.3, eq. udd)
+# ----------------------------------------------------------------------------
+def udd_bias(energy_heads, n_atoms, A, B):
+    """E_bias = A [exp(-var / (M N B^2)) - 1] per structure, with var the
+    population variance over the M heads of the structure's energy."""
+    M = energy_heads.shape[-1]
+    var = ((energy_heads - energy_heads.mean(-1, keepdim=True)) ** 2).mean(-1)
+    return A * (torch.exp(-var / (M * n_atoms * B * B)) - 1.0)
+
+
+@dataclass
+class UddResult:
+    energy: np.ndarray        # [B, heads]   unbiased per-head energies
+    bias_energy: np.ndarray   # [B]
+    forces: np.ndarray        # [N,3]   -d(Ebar + E_bias)/dx
+    stress: np.ndarray        # [B,3,3] (1/V) d(Ebar + E_bias)/dstrain
+
+
+def evaluate_udd(batch, params, nl, A, B) -> UddResult:
+    """Energies, bias energy, and forces and stress of Ebar + E_bias
+    (autograd through the plain definition)."""
+    spec = params.spec
+    M = spec.n_heads
+    p, pos0, cell, soa, sp, i, j, S = _tensors(batch, params, nl)
+    nb = torch.as_tensor(np.diff(batch.atom_ptr), dtype=DT)
+    pos = pos0.clone().requires_grad_(True)
+    strain = torch.zeros((batch.n_structs, 3, 3), dtype=DT, requires_grad=True)
+    d = pair_vectors(pos, cell, soa, i, j, S, strain)
+    G = invariants(*moments(d, i, sp[i], sp[j], p["beta"], spec, batch.n_atoms))
+    y = mlp(G, p["W1"], p["b1"], p["W2"], p["b2"], p["W3"], p["b3"])
+    Ei = p["scale"][sp][:, None] * y + p["shift"][sp][:, None]
+    Eb = torch.zeros((batch.n_structs, M), dtype=DT).index_add(0, soa, Ei)
+    Ebias = udd_bias(Eb, nb, A, B)
+    total = (Eb.mean(1) + Ebias).sum()
+    gpos, gstrain = torch.autograd.grad(total, (pos, strain))
+    vol = torch.abs(torch.linalg.det(cell))
+    return UddResult(Eb.detach().numpy(), Ebias.detach().numpy(), (-gpos).numpy(),
+                     (gstrain / vol[:, None, None]).numpy())
+
+
+# ----------------------------------------------------------------------------
 # training loss and parameter gradients (Section 3.4: weighted sum of loss
 # terms, optionally divided by the number of atoms)
 # ----------------------------------------------------------------------------

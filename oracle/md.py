@@ -20,30 +20,38 @@ from .neighbors import brute_force_neighbors
 ACCEL_UNIT = 9.648533e-3
 
 
-def _forces(batch, params, x):
+def _forces(batch, params, x, udd=None):
+    """Forces and potential energy at x; udd = (A, B) adds the
+    uncertainty-driven bias of Section 2.3 (eq. udd) to the potential."""
     from workloads import Batch
     b = Batch(x.astype(np.float32), batch.species, batch.cell, batch.pbc, batch.atom_ptr)
     nl = brute_force_neighbors(b, params.spec.r_cut)
     # evaluate at the float64 positions (the list decisions use float32)
     import torch
-    from .gmnn import atomic_energies
+    from .gmnn import atomic_energies, udd_bias
     pos = torch.as_tensor(x).requires_grad_(True)
-    E = atomic_energies(b, params, nl, pos=pos).mean(1).sum()
+    Ei = atomic_energies(b, params, nl, pos=pos)
+    E = Ei.mean(1).sum()
+    if udd is not None:
+        soa = torch.as_tensor(b.struct_of_atom(), dtype=torch.long)
+        Eb = torch.zeros((b.n_structs, Ei.shape[1]), dtype=Ei.dtype).index_add(0, soa, Ei)
+        nb = torch.as_tensor(np.diff(b.atom_ptr), dtype=Ei.dtype)
+        E = E + udd_bias(Eb, nb, udd[0], udd[1]).sum()
     (g,) = torch.autograd.grad(E, pos)
     return -g.numpy(), float(E.detach())
 
 
-def velocity_verlet(batch, params, x0, v0, masses, dt, n_steps):
+def velocity_verlet(batch, params, x0, v0, masses, dt, n_steps, udd=None):
     """Positions, velocities and potential energies after each step (float64)."""
     x = np.asarray(x0, dtype=np.float64).copy()
     v = np.asarray(v0, dtype=np.float64).copy()
     inv_m = 1.0 / np.asarray(masses, dtype=np.float64)[:, None]
-    F, E = _forces(batch, params, x)
+    F, E = _forces(batch, params, x, udd)
     xs, vs, es = [], [], []
     for _ in range(n_steps):
         v = v + 0.5 * dt * ACCEL_UNIT * F * inv_m
         x = x + dt * v
-        F, E = _forces(batch, params, x)
+        F, E = _forces(batch, params, x, udd)
         v = v + 0.5 * dt * ACCEL_UNIT * F * inv_m
         xs.append(x.copy())
         vs.append(v.copy())

@@ -68,13 +68,18 @@ GMNN_BASIS_GAUSSIAN = 0
 GMNN_BASIS_BESSEL = 1
 
 
+class gmnn_udd(C.Structure):
+    _fields_ = [("A", C.c_float), ("B", C.c_float), ("bias_energy", vp)]
+
+
 class gmnn_param_grads(C.Structure):
     _fields_ = [(k, vp) for k in ("beta", "W1", "b1", "W2", "b2", "W3", "b3", "scale", "shift")]
 
 
 class gmnn_md(C.Structure):
     _fields_ = [("dt", C.c_float), ("skin", C.c_float), ("inv_mass", vp), ("vel", vp), ("forces", vp),
-                ("energy", vp), ("ref_pos", vp), ("disp", vp)]
+                ("energy", vp), ("ref_pos", vp), ("disp", vp), ("udd", vp), ("var_every", C.c_int32),
+                ("force_var", vp), ("energy_var", vp)]
 
 
 class gmnn_plan(C.Structure):
@@ -114,6 +119,9 @@ EXPORTS = {
     "gmnn_neighbors_workspace_bytes": (C.c_size_t, [C.POINTER(gmnn_system), C.c_float, C.c_float]),
     "gmnn_build_neighbors": (C.c_int32, [C.POINTER(gmnn_system), C.c_float, C.c_float,
                                          C.POINTER(gmnn_neighbors), C.c_uint32, vp, C.c_size_t, vp]),
+    "gmnn_energy_forces_udd": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
+                                           C.c_uint32, C.POINTER(gmnn_plan), C.POINTER(gmnn_udd),
+                                           C.POINTER(gmnn_outputs), vp, C.c_size_t, vp]),
     "gmnn_energy_forces_noalloc": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
                                                C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_outputs), vp]),
     "gmnn_energy_forces": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),

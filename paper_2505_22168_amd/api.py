@@ -213,6 +213,7 @@ class Outputs:
     atomic_energy: torch.Tensor
     energy_mean: torch.Tensor     # [B] float64, mean over heads
     status: torch.Tensor          # [1] int32 device status word (GMNN_FLAG_* bits)
+    bias_energy: torch.Tensor | None = None  # [B] float64 uncertainty-driven bias (udd=)
 
 
 class EnergyForces:
@@ -220,12 +221,14 @@ class EnergyForces:
     list / model shape, so repeated calls allocate nothing."""
 
     def __init__(self, model: Model, system: System, nl: NeighborList, precision: str = "bf16",
-                 stress: bool = True, force_var: bool = False, plan=None):
+                 stress: bool = True, force_var: bool = False, plan=None, udd=None):
         """plan: None (the library's built-in choice), "auto" (the autotuned
         plan of this shape class, cached; tunes on first use), or a dict /
         tuple (schedule, lanes_per_atom[, readout[, tile_atoms]]) with
         GMNN_SCHEDULE_*, 8/16/32/64, GMNN_READOUT_* and 8/16 (0 = built-in
-        choice)."""
+        choice).  udd: (A, B) for the uncertainty-driven bias
+        (gmnn_energy_forces_udd; forces of Ebar + E_bias, bias energies in
+        out.bias_energy; plan None or a split plan)."""
         self.model, self.system, self.nl = model, system, nl
         self.flags = (A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32)
         if precision not in ("bf16", "fp32"):
@@ -257,6 +260,12 @@ class EnergyForces:
         self._oc = A.gmnn_outputs(_ptr(o.energy), _ptr(o.forces), _ptr(o.stress), _ptr(o.energy_var),
                                   _ptr(o.force_var), _ptr(o.atomic_energy), _ptr(o.energy_mean), _ptr(o.status))
         self._plan = None
+        self._udd = None
+        if udd is not None:
+            if isinstance(plan, str):
+                raise ValueError("the biased evaluation takes None or an explicit split plan")
+            self.out.bias_energy = torch.zeros(B, dtype=torch.float64, device=dev)
+            self._udd = A.gmnn_udd(float(udd[0]), float(udd[1]), _ptr(self.out.bias_energy))
         self.set_plan(plan)
 
     def set_plan(self, plan):
@@ -314,9 +323,16 @@ class EnergyForces:
 
     def __call__(self, sync: bool = False) -> Outputs:
         flags = self.flags | (A.GMNN_SYNC if sync else 0)
+        plan = None if self._plan is None else C.byref(self._plan)
+        if self._udd is not None:
+            st = A.load().gmnn_energy_forces_udd(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), flags,
+                                                 plan, C.byref(self._udd), C.byref(self._oc), _ptr(self.workspace),
+                                                 self.ws_bytes, _stream())
+            A.check(st, "gmnn_energy_forces_udd")
+            return self.out
         st = A.load().gmnn_energy_forces_plan(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), flags,
-                                              None if self._plan is None else C.byref(self._plan),
-                                              C.byref(self._oc), _ptr(self.workspace), self.ws_bytes, _stream())
+                                              plan, C.byref(self._oc), _ptr(self.workspace), self.ws_bytes,
+                                              _stream())
         A.check(st, "gmnn_energy_forces")
         return self.out
 
@@ -337,12 +353,18 @@ class MD:
     replayed from a HIP graph.  Positions in `system.pos` are updated in place."""
 
     def __init__(self, model: Model, system: System, masses, dt: float, skin: float, velocities=None,
-                 precision: str = "fp32", capacity: int | None = None):
+                 precision: str = "fp32", capacity: int | None = None, udd=None, var_every: int = 0):
+        """udd: (A, B) of the uncertainty-driven bias (bias energies in
+        self.bias_energy); var_every > 0: the per-head force variance
+        (self.force_var) on every var_every-th step of a call or graph, the
+        head-mean forces on the others."""
         lib = A.load()
         dev = system.device
         N, B, M = system.n_atoms, system.n_structs, model.spec.n_heads
         self.model, self.system, self.lib = model, system, lib
         self.flags = A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32
+        if var_every > 0:
+            self.flags |= A.GMNN_WANT_FORCE_VAR
         cap = capacity if capacity is not None else int(estimate_capacity(system, model.spec.r_cut, skin) * 1.3)
         self.nl = NeighborList(N, cap, dev)
         self.nl.cutoff = float(np.float32(model.spec.r_cut) + np.float32(skin))
@@ -354,8 +376,14 @@ class MD:
         self.energy = torch.zeros((B, M), dtype=torch.float64, device=dev)
         self.ref_pos = torch.zeros((max(N, 1), 3), dtype=torch.float32, device=dev)
         self.disp = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.force_var = torch.zeros(max(N, 1), dtype=torch.float32, device=dev)
+        self.energy_var = torch.zeros(B, dtype=torch.float64, device=dev)
+        self.bias_energy = torch.zeros(B, dtype=torch.float64, device=dev)
+        self._udd = None if udd is None else A.gmnn_udd(float(udd[0]), float(udd[1]), _ptr(self.bias_energy))
         self._md = A.gmnn_md(dt, skin, _ptr(self.inv_mass), _ptr(self.vel), _ptr(self.forces), _ptr(self.energy),
-                             _ptr(self.ref_pos), _ptr(self.disp))
+                             _ptr(self.ref_pos), _ptr(self.disp),
+                             None if self._udd is None else C.cast(C.pointer(self._udd), C.c_void_p),
+                             int(var_every), _ptr(self.force_var), _ptr(self.energy_var))
         self._mc, self._sc, self._nc = model.c(), system.c(), self.nl.c()
         nbytes = lib.gmnn_md_workspace_bytes(C.byref(self._mc), C.byref(self._sc), C.byref(self._nc), self.flags)
         if nbytes == 0:

@@ -19,18 +19,18 @@ __global__ void pair_moments(DevModel m, DevSystem sys, float* psi, int* counter
 template <int LPA>
 __global__ void pair_backward(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial);
 __global__ void pair_backward_heads(DevModel m, DevSystem sys, const float* psibar, float* gpair, float* virial, int nh,
-                                    int64_t gstride);
+                                    int64_t gstride, const float* head_c);
 template <int LPA, bool VAR>
 __global__ void finish(int M, DevSystem sys, const float* gpair, const float* atomic_e, const float* virial,
                        int want_stress, int nb_gather, int64_t gstride, int nchunk, double* partial, int* counters,
                        float* forces, float* force_var, double* energy, double* energy_var, double* energy_mean,
-                       double* stress, const double* tile_part, int tile_atoms);
+                       double* stress, const double* tile_part, int tile_atoms, const float* head_c);
 gmnn_status launch_tile(bool fused, bool perhead, int tile_atoms, const DevModel& m, const DevSystem& sys, bool bf16,
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
                         int64_t gstride, double* tile_rec, hipStream_t stream);
 bool tile_fused_supported(int n_species, int hp, bool bf16, bool perhead);
 gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,
-                          float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev);
+                          float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev, int phases);
 size_t stream_lds_bytes(int hp, bool bf16, int n_heads);
 size_t stream_g_bytes(int n_atoms, bool bf16);
 size_t stream_dg_bytes(int n_atoms);
@@ -236,6 +236,8 @@ static DevModel dev_model(const gmnn_model* m) {
   d.w3 = (const float*)(P + L.w3);
   d.w3bar = (const float*)(P + L.w3bar);
   d.b3 = (const float*)(P + L.b3);
+  d.head_w = nullptr;
+  d.fwd_only = 0;
   return d;
 }
 
@@ -291,7 +293,7 @@ static DevSystem dev_system(const gmnn_system* s, const gmnn_neighbors* nl) {
 
 struct EfLayout {
   size_t psi = 0, psibar = 0, atomic_e = 0, gpair = 0, virial = 0, g = 0, dg = 0, partial = 0, counters = 0,
-         tilerec = 0, bytes = 0;
+         tilerec = 0, head_c = 0, head_w = 0, bytes = 0;
 };
 
 static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags) {
@@ -314,8 +316,58 @@ static EfLayout ef_layout(const gmnn_model* m, const gmnn_system* sys, const gmn
   L.partial = take(8 * (size_t)(kMaxHeads + 9) * sys->n_structs * reduce_chunks(sys));
   L.counters = take(4 * (size_t)sys->n_structs);
   L.tilerec = take(8 * (size_t)(kMaxHeads + 9) * ((N + 7) / 8));  // fused: one record per tile of >= 8 atoms
+  // uncertainty bias: head weights c [B][kMaxHeads] and weighted W3 vectors [B][HP2]
+  L.head_c = take(4 * (size_t)kMaxHeads * sys->n_structs);
+  L.head_w = take(4 * (size_t)packed_layout(m->hidden1, m->hidden2, m->n_heads).HP2 * sys->n_structs);
   L.bytes = off;
   return L;
+}
+
+// ---------------------------------------------------------------------------
+// uncertainty-driven bias (Section 2.3, eq. udd): per structure b with
+// energies E^m of the M heads, mean Ebar and population variance var,
+//   E_b = A [exp(-var / (M N_b B^2)) - 1],
+// and the force -d(Ebar + E_b)/dx = -sum_m c_m dE^m/dx with
+//   c_m = 1/M + dE_b/dvar * 2 (E^m - Ebar) / M,
+//   dE_b/dvar = -A / (M N_b B^2) exp(-var / (M N_b B^2)).
+// ---------------------------------------------------------------------------
+__global__ void udd_weights(int B, int M, const int64_t* __restrict__ atom_ptr, const double* __restrict__ energy,
+                            double A, double Bw, float* __restrict__ head_c, double* __restrict__ bias_energy) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double nb = (double)(atom_ptr[b + 1] - atom_ptr[b]);
+  double mean = 0.0;
+  for (int h = 0; h < M; ++h) mean += energy[(int64_t)b * M + h];
+  mean /= (double)M;
+  double var = 0.0;
+  for (int h = 0; h < M; ++h) {
+    const double d = energy[(int64_t)b * M + h] - mean;
+    var += d * d;
+  }
+  var /= (double)M;
+  double eb = 0.0, deb = 0.0;
+  if (nb > 0.0) {
+    const double scale = 1.0 / ((double)M * nb * Bw * Bw);
+    const double ex = exp(-var * scale);
+    eb = A * (ex - 1.0);
+    deb = -A * scale * ex;
+  }
+  if (bias_energy) bias_energy[b] = eb;
+  for (int h = 0; h < kMaxHeads; ++h)
+    head_c[(int64_t)b * kMaxHeads + h] =
+        h < M ? (float)(1.0 / (double)M + deb * 2.0 * (energy[(int64_t)b * M + h] - mean) / (double)M) : 0.0f;
+}
+
+// head_w[b][col] = sum_m c_m(b) W3[col][m] (the output weights of the biased backward)
+__global__ void udd_head_vectors(int B, int M, int HP, const float* __restrict__ head_c, const float* __restrict__ w3,
+                                 float* __restrict__ head_w) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * HP) return;
+  const int64_t b = t / HP;
+  const int col = (int)(t % HP);
+  float v = 0.0f;
+  for (int h = 0; h < M; ++h) v += head_c[b * kMaxHeads + h] * w3[(int64_t)col * M + h];
+  head_w[t] = v;
 }
 
 }  // namespace gmnn
@@ -446,9 +498,14 @@ gmnn_status gmnn_resolve_plan(const gmnn_model* m, const gmnn_system* sys, uint3
   return GMNN_OK;
 }
 
-gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
-                                     uint32_t flags, const gmnn_plan* plan, gmnn_outputs* out, void* workspace,
-                                     size_t workspace_bytes, void* stream, void* const* stage_events) {
+}  // extern "C"
+
+// one evaluation; udd (may be null): the uncertainty-driven bias, which runs
+// the split schedule in two passes (energies of every head first, then the
+// backward with the bias's head weights)
+static gmnn_status ef_run(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
+                          const gmnn_plan* plan, gmnn_outputs* out, void* workspace, size_t workspace_bytes,
+                          void* stream, void* const* stage_events, const gmnn_udd* udd) {
   gmnn_status st = check_model(m);
   if (st != GMNN_OK) return st;
   st = check_system(sys);
@@ -482,8 +539,20 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
   };
   const bool var = (flags & GMNN_WANT_FORCE_VAR) != 0;
   Plan P;
+  gmnn_plan split_plan{GMNN_SCHEDULE_SPLIT, 0, GMNN_READOUT_AUTO, 0};
+  if (udd) {
+    // the bias needs every structure's head energies before any backward:
+    // the split schedule only
+    if (!(udd->B > 0.0f) || !std::isfinite(udd->A) || m->n_heads < 2) return GMNN_ERR_INVALID_ARG;
+    if (plan && plan->schedule == GMNN_SCHEDULE_FUSED) return GMNN_ERR_UNSUPPORTED;
+    if (plan) split_plan = *plan;
+    split_plan.schedule = GMNN_SCHEDULE_SPLIT;
+    plan = &split_plan;
+  }
   st = resolve_plan(m, sys, flags, plan, P);
   if (st != GMNN_OK) return st;
+  float* head_c = (float*)(W + L.head_c);
+  float* head_w = (float*)(W + L.head_w);
   const bool fused = P.fused;
   const int lpa = P.lpa;
   // the fused schedule sums each structure in one block from the tiles'
@@ -509,11 +578,44 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
       else MOMENTS(8);
 #undef MOMENTS
       mark(1);
+      DevModel db = dm;  // the model of the backward pass
+      int phases = 7;    // streamed readout: invariants, network, invariant backward
+      if (udd) {
+        // pass 1: energies of every head (readout forward only), summed per
+        // structure; then the head weights c_m and the weighted W3 vectors
+        DevModel da = dm;
+        da.fwd_only = 1;
+        if (P.stream)
+          st = launch_stream(da, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s, nullptr, 3);
+        else
+          st = launch_tile(false, var, 16, da, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, nullptr, s);
+        if (st != GMNN_OK) return st;
+        const dim3 rgrid(sys->n_structs * nchunk);
+#define FINISH_REDUCE(VAR)                                                                                      \
+  hipLaunchKernelGGL((finish<64, VAR>), rgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial,  \
+                     0, 0, gstride, nchunk, partial, counters, out->forces, out->force_var, out->energy,           \
+                     out->energy_var, out->energy_mean, out->stress, nullptr, 0, nullptr)
+        if (var) FINISH_REDUCE(true);
+        else FINISH_REDUCE(false);
+#undef FINISH_REDUCE
+        hipLaunchKernelGGL(udd_weights, dim3((sys->n_structs + 63) / 64), dim3(64), 0, s, sys->n_structs, m->n_heads,
+                           sys->atom_ptr, out->energy, (double)udd->A, (double)udd->B, head_c, udd->bias_energy);
+        if (!var) {
+          const int64_t nw = (int64_t)sys->n_structs * dm.HP2;
+          hipLaunchKernelGGL(udd_head_vectors, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, sys->n_structs,
+                             m->n_heads, dm.HP2, head_c, dm.w3, head_w);
+          db.head_w = head_w;  // one backward with the weights c_m
+        }
+        phases = 6;  // pass 2 reuses the invariants
+        // the pair counters of the chunked sums were used by pass 1's
+        // reduction, which leaves them cleared
+      }
       if (P.stream) {
-        st = launch_stream(dm, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s, ev ? ev + 2 : nullptr);
+        st = launch_stream(db, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s, ev ? ev + 2 : nullptr,
+                           phases);
       } else {
         mark(2);
-        st = launch_tile(false, var, 16, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, nullptr, s);
+        st = launch_tile(false, var, 16, db, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, gstride, nullptr, s);
         for (int k = 3; k < 8; ++k) mark(k);
       }
       if (st != GMNN_OK) return st;
@@ -527,7 +629,7 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
         st = ensure_lds_limit((const void*)pair_backward_heads, lds);
         if (st != GMNN_OK) return st;
         hipLaunchKernelGGL(pair_backward_heads, dim3((N + kHeadsAtoms - 1) / kHeadsAtoms), dim3(kPairThreads), lds,
-                           s, dm, ds, psibar, gpair, virial, nh, gstride);
+                           s, dm, ds, psibar, gpair, virial, nh, gstride, udd ? head_c : nullptr);
       } else if (lpa == 64) PAIR_BACKWARD(64);
       else if (lpa == 32) PAIR_BACKWARD(32);
       else if (lpa == 16) PAIR_BACKWARD(16);
@@ -543,7 +645,8 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
 #define FINISH(LPA, VAR)                                                                                       \
   hipLaunchKernelGGL((finish<LPA, VAR>), fgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial, \
                      want_stress, nbg, gstride, nchunk, partial, counters, out->forces, out->force_var, out->energy, \
-                     out->energy_var, out->energy_mean, out->stress, fused ? tilerec : nullptr, fused ? P.ta : 0)
+                     out->energy_var, out->energy_mean, out->stress, fused ? tilerec : nullptr, fused ? P.ta : 0, \
+                     (udd && var) ? head_c : nullptr)
   if (lpa == 64) {
     if (var) FINISH(64, true);
     else FINISH(64, false);
@@ -569,6 +672,21 @@ gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys
     }
   }
   return GMNN_OK;
+}
+
+extern "C" {
+
+gmnn_status gmnn_energy_forces_timed(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                     uint32_t flags, const gmnn_plan* plan, gmnn_outputs* out, void* workspace,
+                                     size_t workspace_bytes, void* stream, void* const* stage_events) {
+  return ef_run(m, sys, nl, flags, plan, out, workspace, workspace_bytes, stream, stage_events, nullptr);
+}
+
+gmnn_status gmnn_energy_forces_udd(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                   uint32_t flags, const gmnn_plan* plan, const gmnn_udd* udd, gmnn_outputs* out,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+  if (!udd) return GMNN_ERR_INVALID_ARG;
+  return ef_run(m, sys, nl, flags, plan, out, workspace, workspace_bytes, stream, nullptr, udd);
 }
 
 gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,

@@ -69,6 +69,9 @@ extern "C" {
 
 gmnn_status gmnn_energy_forces(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags,
                                gmnn_outputs* out, void* workspace, size_t workspace_bytes, void* stream);
+gmnn_status gmnn_energy_forces_udd(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                   uint32_t flags, const gmnn_plan* plan, const gmnn_udd* udd, gmnn_outputs* out,
+                                   void* workspace, size_t workspace_bytes, void* stream);
 
 static size_t md_nl_bytes(const gmnn_system* sys, const gmnn_neighbors* nl) {
   return (nl_layout(sys, (double)nl->cutoff + 1.0e-4).bytes + 255) & ~size_t(255);
@@ -86,15 +89,30 @@ static gmnn_status md_check(const gmnn_model* m, const gmnn_system* sys, const g
   if (!m || !sys || !nl || !md || !md->inv_mass || !md->vel || !md->forces || !md->energy || !md->ref_pos ||
       !md->disp || !(md->dt > 0.0f) || !(md->skin >= 0.0f))
     return GMNN_ERR_INVALID_ARG;
-  if (flags & (GMNN_WANT_FORCE_VAR | GMNN_WANT_STRESS | GMNN_SYNC)) return GMNN_ERR_INVALID_ARG;
+  if (flags & (GMNN_WANT_STRESS | GMNN_SYNC)) return GMNN_ERR_INVALID_ARG;
+  if ((flags & GMNN_WANT_FORCE_VAR) && (md->var_every < 1 || !md->force_var)) return GMNN_ERR_INVALID_ARG;
+  if (md->udd && m->n_heads < 2) return GMNN_ERR_INVALID_ARG;
   if (nl->cutoff + 1e-6f < m->r_cut + md->skin) return GMNN_ERR_INVALID_ARG;
   if (ws_bytes < gmnn_md_workspace_bytes(m, sys, nl, flags)) return GMNN_ERR_WORKSPACE;
   return GMNN_OK;
 }
 
-// one step on `stream` (no host synchronisation)
+// energies and forces at the current positions: with the bias if md->udd,
+// with the per-head force variance if `var`
+static gmnn_status md_forces(const gmnn_model* m, const gmnn_system* sys, gmnn_neighbors* nl, const gmnn_md* md,
+                             uint32_t flags, bool var, char* ws, size_t ws_bytes, hipStream_t s) {
+  const uint32_t f = (flags & ~GMNN_WANT_FORCE_VAR) | (var ? GMNN_WANT_FORCE_VAR : 0u);
+  gmnn_outputs out = {md->energy, md->forces, nullptr, md->energy_var, var ? md->force_var : nullptr, nullptr,
+                      nullptr, nullptr};
+  if (md->udd) return gmnn_energy_forces_udd(m, sys, nl, f, nullptr, md->udd, &out, ws, ws_bytes, (void*)s);
+  return gmnn_energy_forces(m, sys, nl, f, &out, ws, ws_bytes, (void*)s);
+}
+
+// one step on `stream` (no host synchronisation); k: the step's index in
+// its call or graph, 1-based (the force variance runs on multiples of
+// md->var_every)
 static gmnn_status md_step(const gmnn_model* m, const gmnn_system* sys, gmnn_neighbors* nl, const gmnn_md* md,
-                           uint32_t flags, char* ws, size_t ws_bytes, hipStream_t s) {
+                           uint32_t flags, char* ws, size_t ws_bytes, hipStream_t s, int k) {
   const int N = sys->n_atoms;
   const float half = 0.5f * md->dt * kAccelUnit;
   const int nb = (N + 255) / 256;
@@ -105,8 +123,8 @@ static gmnn_status md_step(const gmnn_model* m, const gmnn_system* sys, gmnn_nei
   const float th = 0.5f * md->skin;
   gmnn_status st = nl_build(sys, m->r_cut, md->skin, nl, ws, nlb, s, md->disp, th * th, md->ref_pos);
   if (st != GMNN_OK) return st;
-  gmnn_outputs out = {md->energy, md->forces, nullptr, nullptr, nullptr, nullptr};
-  st = gmnn_energy_forces(m, sys, nl, flags, &out, ws + nlb, ws_bytes - nlb, (void*)s);
+  const bool var = (flags & GMNN_WANT_FORCE_VAR) && md->var_every > 0 && k % md->var_every == 0;
+  st = md_forces(m, sys, nl, md, flags, var, ws + nlb, ws_bytes - nlb, s);
   if (st != GMNN_OK) return st;
   if (N > 0)
     hipLaunchKernelGGL(md_kick, dim3(nb), dim3(256), 0, s, N, md->vel, md->forces, md->inv_mass, half, md->disp);
@@ -122,8 +140,7 @@ gmnn_status gmnn_md_init(const gmnn_model* m, const gmnn_system* sys, gmnn_neigh
   const size_t nlb = md_nl_bytes(sys, nl);
   st = nl_build(sys, m->r_cut, md->skin, nl, ws, nlb, s, nullptr, 0.0f, md->ref_pos);
   if (st != GMNN_OK) return st;
-  gmnn_outputs out = {md->energy, md->forces, nullptr, nullptr, nullptr, nullptr};
-  st = gmnn_energy_forces(m, sys, nl, flags, &out, ws + nlb, workspace_bytes - nlb, stream);
+  st = md_forces(m, sys, nl, md, flags, (flags & GMNN_WANT_FORCE_VAR) != 0, ws + nlb, workspace_bytes - nlb, s);
   if (st != GMNN_OK) return st;
   hipLaunchKernelGGL(md_zero_word, dim3(1), dim3(1), 0, s, md->disp);
   return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
@@ -135,7 +152,7 @@ gmnn_status gmnn_md_steps(const gmnn_model* m, const gmnn_system* sys, gmnn_neig
   if (st != GMNN_OK) return st;
   if (n_steps < 0) return GMNN_ERR_INVALID_ARG;
   for (int k = 0; k < n_steps; ++k) {
-    st = md_step(m, sys, nl, md, flags, (char*)workspace, workspace_bytes, (hipStream_t)stream);
+    st = md_step(m, sys, nl, md, flags, (char*)workspace, workspace_bytes, (hipStream_t)stream, k + 1);
     if (st != GMNN_OK) return st;
   }
   return GMNN_OK;
@@ -157,7 +174,7 @@ gmnn_status gmnn_md_graph_create(const gmnn_model* m, const gmnn_system* sys, gm
   st = GMNN_OK;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = GMNN_ERR_HIP;
   for (int k = 0; k < n_steps && st == GMNN_OK; ++k)
-    st = md_step(m, sys, nl, md, flags, (char*)workspace, workspace_bytes, cs);
+    st = md_step(m, sys, nl, md, flags, (char*)workspace, workspace_bytes, cs, k + 1);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &graph);
   if (st == GMNN_OK && (ec != hipSuccess || !graph)) st = GMNN_ERR_HIP;

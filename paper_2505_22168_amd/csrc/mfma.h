@@ -309,7 +309,8 @@ struct NetShape {
 template <int TM, int HP, bool BF16, int NW, bool MEAN, int DEPTH>
 __device__ __forceinline__ void network_forward(const DevModel& m, const void* sG, const void* sGlo, void* sH,
                                        void* sHlo, void* sD2, float* sDsw2,
-                                       float* sEp, const float* sScale, const float* sShift, int row0, int n_rows,
+                                       float* sEp, const float* sScale, const float* sShift, const int* sStruct,
+                                       int row0, int n_rows,
                                        float* __restrict__ atomic_e, float* sEa,
                                        floatx4 (&dsw1)[NetShape<TM, HP, NW>::TPW],
                                        FwdRing<BF16, NetShape<TM, HP, NW>::TPW, DEPTH>& fring,
@@ -372,7 +373,9 @@ __device__ __forceinline__ void network_forward(const DevModel& m, const void* s
         float d;
         const float hv = swish_parts(acc[i][j] + b2v[i], d);
         acc[i][j] = hv;
-        if (MEAN) st_act<BF16>(sD2, row * St::H + col, d * sScale[row] * wbv[i]);
+        if (MEAN)
+          st_act<BF16>(sD2, row * St::H + col,
+                       d * sScale[row] * (m.head_w ? m.head_w[(int64_t)sStruct[row] * HP + col] : wbv[i]));
         else sDsw2[row * (HP + 1) + col] = d;
       }
     }

@@ -89,6 +89,10 @@ struct DevModel {
   const float* w3;      // [HP2][M]
   const float* w3bar;   // [HP2] mean over heads of W3
   const float* b3;      // [M]
+  // uncertainty-driven bias: per-structure output weights [B][HP2] replacing
+  // the head mean of W3 in the backward (sum_m c_m W3[:, m]); null: the mean
+  const float* head_w;
+  int fwd_only;         // readout kernels stop after the energies (no backward)
 };
 
 // System view shared by the energy kernels.

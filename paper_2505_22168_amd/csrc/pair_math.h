@@ -494,11 +494,13 @@ __device__ inline void atom_pair_backward(const DevModel& m, const DevSystem& sy
 // head; pbh = dE_i^h/dPsi_i for head h at pbh + h * 100 (LDS).  Head h's
 // gradients go to gpair + h * gstride * 3; vir accumulates the sum over
 // heads.  Per head the arithmetic is atom_pair_backward's.
+// hw (may be null): per-head weights of the virial (sum_h hw[h] g^h (x) d);
+// null: the plain sum over heads
 template <int LPA>
 __device__ inline void atom_pair_backward_heads(const DevModel& m, const DevSystem& sys,
                                                 const float* __restrict__ s_beta, int i, int q,
                                                 const float* __restrict__ pbh, int nh, float* __restrict__ gpair,
-                                                int64_t gstride, float (&vir)[9]) {
+                                                int64_t gstride, float (&vir)[9], const float* hw = nullptr) {
   AtomCtx c;
   load_atom(sys, i, c);
   const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
@@ -522,9 +524,11 @@ __device__ inline void atom_pair_backward_heads(const DevModel& m, const DevSyst
         for (int h = 0; h < nh; ++h) {
           float gx, gy, gz;
           pair_gradient(pbh + h * (kS * kPacked), rad, mo, ux, uy, uz, ir, gx, gy, gz);
-          vir[0] += gx * dx; vir[1] += gx * dy; vir[2] += gx * dz;
-          vir[3] += gy * dx; vir[4] += gy * dy; vir[5] += gy * dz;
-          vir[6] += gz * dx; vir[7] += gz * dy; vir[8] += gz * dz;
+          const float wv = hw ? hw[h] : 1.0f;
+          const float vx = wv * gx, vy = wv * gy, vz = wv * gz;
+          vir[0] += vx * dx; vir[1] += vx * dy; vir[2] += vx * dz;
+          vir[3] += vy * dx; vir[4] += vy * dy; vir[5] += vy * dz;
+          vir[6] += vz * dx; vir[7] += vz * dy; vir[8] += vz * dz;
           float* gp = gpair + (int64_t)h * gstride * 3;
           gp[3 * pu] = gx;
           gp[3 * pu + 1] = gy;

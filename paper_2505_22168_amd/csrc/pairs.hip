@@ -91,11 +91,13 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
 // block's dE/dPsi of every head are staged in LDS after beta, and each pair's
 // geometry and radial basis serve all heads.  Dynamic LDS: beta +
 // 4 * nh * 100 floats.
+// head_c (may be null): per-structure head weights [B][kMaxHeads] of the
+// virial (an uncertainty bias); null: the mean over heads
 __global__ void __launch_bounds__(kPairBlock) pair_backward_heads(DevModel m, DevSystem sys,
                                                                   const float* __restrict__ psibar,
                                                                   float* __restrict__ gpair,
                                                                   float* __restrict__ virial, int nh,
-                                                                  int64_t gstride) {
+                                                                  int64_t gstride, const float* __restrict__ head_c) {
   extern __shared__ float s_beta[];
   const int nbeta = m.n_species * m.n_species * kS * kMaxBasis;
   float* s_pb = s_beta + nbeta;  // [atom][head][100]
@@ -114,11 +116,12 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward_heads(DevModel m, De
   float vir[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) vir[k] = 0.0f;
-  if (live) atom_pair_backward_heads<64>(m, sys, s_beta, i, q, s_pb + w * nh * NP, nh, gpair, gstride, vir);
+  const float* hw = (head_c && live) ? head_c + (int64_t)sys.atom_struct[i] * kMaxHeads : nullptr;
+  if (live) atom_pair_backward_heads<64>(m, sys, s_beta, i, q, s_pb + w * nh * NP, nh, gpair, gstride, vir, hw);
 #pragma unroll
   for (int k = 0; k < 9; ++k) vir[k] = atom_sum<64>(vir[k]);
   if (live && q == 0) {
-    const float inv = 1.0f / (float)nh;
+    const float inv = head_c ? 1.0f : 1.0f / (float)nh;
 #pragma unroll
     for (int k = 0; k < 9; ++k) virial[(int64_t)i * 9 + k] = vir[k] * inv;
   }
@@ -296,7 +299,8 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
                                                      float* __restrict__ force_var, double* __restrict__ energy,
                                                      double* __restrict__ energy_var,
                                                      double* __restrict__ energy_mean, double* __restrict__ stress,
-                                                     const double* __restrict__ tile_part, int tile_atoms) {
+                                                     const double* __restrict__ tile_part, int tile_atoms,
+                                                     const float* __restrict__ head_c) {
   const int n_red = (int)gridDim.x - nb_gather;
   if ((int)blockIdx.x >= n_red) {
     const int q = threadIdx.x & (LPA - 1);
@@ -358,12 +362,24 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
         if (h < M)
 #pragma unroll
           for (int k = 0; k < 3; ++k) var += (f[h][k] - mean[k]) * (f[h][k] - mean[k]);
+      // with an uncertainty bias the force weights the heads by c_h of the
+      // atom's structure (sum_h c_h F^h); the variance stays that of F^h
+      float fo[3] = {mean[0], mean[1], mean[2]};
+      if (head_c && live) {
+        const float* c = head_c + (int64_t)sys.atom_struct[i] * kMaxHeads;
+        fo[0] = fo[1] = fo[2] = 0.0f;
+#pragma unroll
+        for (int h = 0; h < kMaxHeads; ++h)
+          if (h < M)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fo[k] += c[h] * f[h][k];
+      }
       if (live && q == 0) {
-        forces[3 * (int64_t)i] = mean[0];
-        forces[3 * (int64_t)i + 1] = mean[1];
-        forces[3 * (int64_t)i + 2] = mean[2];
+        forces[3 * (int64_t)i] = fo[0];
+        forces[3 * (int64_t)i + 1] = fo[1];
+        forces[3 * (int64_t)i + 2] = fo[2];
         force_var[i] = var * invM;
-        if (sys.status && !(fabsf(mean[0]) + fabsf(mean[1]) + fabsf(mean[2]) + var <= 3.402823466e38f))
+        if (sys.status && !(fabsf(fo[0]) + fabsf(fo[1]) + fabsf(fo[2]) + var <= 3.402823466e38f))
           raise_flag(sys.status, GMNN_FLAG_NONFINITE);
       }
     }
@@ -444,7 +460,7 @@ template __global__ void pair_backward<64>(DevModel, DevSystem, const float*, fl
 #define FIN(LPA, VAR)                                                                                         \
   template __global__ void finish<LPA, VAR>(int, DevSystem, const float*, const float*, const float*, int, int, \
                                             int64_t, int, double*, int*, float*, float*, double*, double*, double*, \
-                                            double*, const double*, int);
+                                            double*, const double*, int, const float*);
 FIN(8, false) FIN(16, false) FIN(32, false) FIN(64, false) FIN(8, true) FIN(16, true) FIN(32, true) FIN(64, true)
 #undef FIN
 

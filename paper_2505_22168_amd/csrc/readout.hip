@@ -278,7 +278,7 @@ struct NetLds {
   static constexpr int HLO = TM * St::H;
   static constexpr size_t b = 0;
   static constexpr size_t rows = b + ro_al((size_t)ESZ * TM * St::H);
-  static constexpr size_t a = rows + ro_al(4 * 2 * (size_t)TM);
+  static constexpr size_t a = rows + ro_al(4 * 3 * (size_t)TM);  // scale, shift, structure of each row
   static constexpr size_t ep = a + ro_al((size_t)ESZ * TM * St::H);
   static constexpr size_t bytes(int M) {
     return mx(a + ro_al((size_t)ESZ * NS * mx((size_t)TM * St::G, (size_t)TM * St::H)),
@@ -301,6 +301,7 @@ __global__ void __launch_bounds__(kRoThreads)
   float* sEp = (float*)(lds + L::ep);
   float* sScale = (float*)(lds + L::rows);
   float* sShift = sScale + TM;
+  int* sStruct = (int*)(sShift + TM);
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int row0 = xcd_block(blockIdx.x, gridDim.x) * TM;
@@ -331,13 +332,16 @@ __global__ void __launch_bounds__(kRoThreads)
     }
     for (int a = tid; a < TM; a += kRoThreads) {
       float sc = 0.0f, sh = 0.0f;
+      int b = 0;
       if (a < n_rows) {
         const int z = sys.species[row0 + a];
         sc = m.scale[z];
         sh = m.shift[z];
+        b = sys.atom_struct[row0 + a];
       }
       sScale[a] = sc;
       sShift[a] = sh;
+      sStruct[a] = b;
     }
   }
   __syncthreads();
@@ -401,7 +405,8 @@ __global__ void __launch_bounds__(kRoThreads)
           const int row = r * 16 + 4 * (l >> 4) + j;
           float d;
           acc[r][i][j] = swish_parts(acc[r][i][j] + bias, d);
-          st_act<BF16>(sB, row * St::H + col, d * sScale[row] * wb);
+          const float wr = m.head_w ? m.head_w[(int64_t)sStruct[row] * HP + col] : wb;
+          st_act<BF16>(sB, row * St::H + col, d * sScale[row] * wr);
         }
     }
     for (int hm = 0; hm < M; ++hm) {
@@ -435,6 +440,8 @@ __global__ void __launch_bounds__(kRoThreads)
       atomic_e[(int64_t)(row0 + a) * M + hm] = sScale[a] * y + sShift[a];
     }
   }
+  // forward-only pass (the energies an uncertainty bias needs first)
+  if (m.fwd_only) return;
 
   // delta1 = swish'(z1) (delta2 W2^T) -> region A (h1 is dead)
   {
@@ -568,9 +575,10 @@ __global__ void __launch_bounds__(kBkThreads) readout_backward(DevSystem sys, co
 // ---------------------------------------------------------------------------
 constexpr size_t kLdsMax = 160 * 1024;
 
+// phases: bit 0 invariants, bit 1 network, bit 2 invariant backward
 template <int HP, bool BF16>
 static gmnn_status launch_stream_t(const DevModel& m, const DevSystem& sys, const float* psi, void* G, float* dG,
-                                   float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev) {
+                                   float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev, int phases) {
   auto mark = [&](int k) {
     if (ev) (void)hipEventRecord(ev[k], s);
   };
@@ -585,15 +593,18 @@ static gmnn_status launch_stream_t(const DevModel& m, const DevSystem& sys, cons
   const int gn = (N + NL::TM - 1) / NL::TM;
   const int gb = (N + kBkAtoms - 1) / kBkAtoms;
   mark(0);
-  hipLaunchKernelGGL(readout_features<BF16>, dim3(g16), dim3(kRoThreads), FeatLds<BF16>::bytes, s, sys, psi, G);
+  if (phases & 1)
+    hipLaunchKernelGGL(readout_features<BF16>, dim3(g16), dim3(kRoThreads), FeatLds<BF16>::bytes, s, sys, psi, G);
   mark(1);
   mark(2);
-  hipLaunchKernelGGL((readout_network<HP, BF16>), dim3(gn), dim3(kRoThreads), NL::bytes(m.M), s, m, sys, (const void*)G,
-                     atomic_e, dG);
+  if (phases & 2)
+    hipLaunchKernelGGL((readout_network<HP, BF16>), dim3(gn), dim3(kRoThreads), NL::bytes(m.M), s, m, sys,
+                       (const void*)G, atomic_e, dG);
   mark(3);
   mark(4);
-  hipLaunchKernelGGL(readout_backward, dim3(gb), dim3(kBkThreads), BackLds::bytes, s, sys, psi, (const float*)dG,
-                     psibar);
+  if (phases & 4)
+    hipLaunchKernelGGL(readout_backward, dim3(gb), dim3(kBkThreads), BackLds::bytes, s, sys, psi, (const float*)dG,
+                       psibar);
   mark(5);
   return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
 }
@@ -616,14 +627,16 @@ size_t stream_lds_bytes(int hp, bool bf16, int n_heads) {
 size_t stream_g_bytes(int n_atoms, bool bf16) { return (size_t)n_atoms * kFP * (bf16 ? 2 * 2 : 4); }
 size_t stream_dg_bytes(int n_atoms) { return (size_t)n_atoms * kFP * 4; }
 
-// ev (may be null): 6 events recorded around the three kernels
+// ev (may be null): 6 events recorded around the three kernels; phases:
+// which of the three run (bit 0 invariants, bit 1 network, bit 2 invariant
+// backward)
 gmnn_status launch_stream(const DevModel& m, const DevSystem& sys, bool bf16, const float* psi, void* G, float* dG,
-                          float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev) {
+                          float* atomic_e, float* psibar, hipStream_t s, hipEvent_t* ev, int phases) {
   if (sys.n_atoms == 0) return GMNN_OK;
 #define CASE(HP)                                                                                          \
   if (m.HP1 == HP)                                                                                        \
-    return bf16 ? launch_stream_t<HP, true>(m, sys, psi, G, dG, atomic_e, psibar, s, ev)                  \
-                : launch_stream_t<HP, false>(m, sys, psi, G, dG, atomic_e, psibar, s, ev);
+    return bf16 ? launch_stream_t<HP, true>(m, sys, psi, G, dG, atomic_e, psibar, s, ev, phases)          \
+                : launch_stream_t<HP, false>(m, sys, psi, G, dG, atomic_e, psibar, s, ev, phases);
   CASE(64) CASE(128) CASE(256) CASE(512)
 #undef CASE
   return GMNN_ERR_UNSUPPORTED;

@@ -54,7 +54,7 @@ struct TileLds {
   static constexpr size_t regc_bytes = mx((size_t)ESZ * TM * St::H, 4 * (size_t)TM * PS);
   static constexpr size_t ep = regc + al(regc_bytes);
   static constexpr size_t rowsc = ep + al(4 * (size_t)kTileWaves * 16 * kMaxHeads);
-  static constexpr size_t vir = rowsc + al(4 * 2 * (size_t)TM);
+  static constexpr size_t vir = rowsc + al(4 * 3 * (size_t)TM);  // scale, shift, structure of each row
   static constexpr size_t psibar = vir + al(4 * 9 * (size_t)TA);
   static constexpr size_t dsw2 = psibar + (FUSED ? al(4 * (size_t)TA * kS * kPacked) : 0);
   static constexpr size_t beta = dsw2 + (PERHEAD ? al(4 * (size_t)TM * (HP + 1)) : 0);
@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(kTileThreads)
   float* sEp = (float*)(lds + L::ep);
   float* sScale = (float*)(lds + L::rowsc);
   float* sShift = sScale + TM;
+  int* sStruct = (int*)(sShift + TM);
   float* sVir = (float*)(lds + L::vir);
   float* sPsibar = (float*)(lds + L::psibar);
   float* sDsw2 = (float*)(lds + L::dsw2);
@@ -196,13 +197,16 @@ __global__ void __launch_bounds__(kTileThreads)
   if (tid >= kTileThreads - 64 && tid - (kTileThreads - 64) < TM) {
     const int a = tid - (kTileThreads - 64);
     float sc = 0.0f, sh = 0.0f;
+    int b = 0;
     if (a < n_rows) {
       const int z = sys.species[row0 + a];
       sc = m.scale[z];
       sh = m.shift[z];
+      b = sys.atom_struct[row0 + a];
     }
     sScale[a] = sc;
     sShift[a] = sh;
+    sStruct[a] = b;
   }
   __syncthreads();
   contract_forward_b<TA, kTileThreads, BF16>(sPsi, sI, sG, NetStrides<HP, BF16>::G, tb, kGlo);
@@ -211,7 +215,10 @@ __global__ void __launch_bounds__(kTileThreads)
   // ---- network forward ---------------------------------------------------------
   floatx4 dsw1[Sh::TPW];
   network_forward<TM, HP, BF16, kTileWaves, !PERHEAD, kDepth>(m, sG, sGlo, sH, sHlo, sD2, sDsw2, sEp, sScale, sShift,
-                                                              row0, n_rows, atomic_e, sEa, dsw1, fring, ring);
+                                                              sStruct, row0, n_rows, atomic_e, sEa, dsw1, fring, ring);
+  // forward-only pass (the energies an uncertainty bias needs first): the
+  // readout tile stops here (uniform across the block)
+  if (!FUSED && m.fwd_only) return;
   constexpr int LDGB = NetStrides<HP, BF16>::GB;
   for (int hm = 0; hm < nh; ++hm) {
     // ---- network backward (head mean, or head hm) ------------------------------
