@@ -192,6 +192,7 @@ gmnn_status gmnn_model_prepare(gmnn_model* m, void* stream);
 #define GMNN_OP_NEIGHBORS 0
 #define GMNN_OP_ENERGY_FORCES 1
 #define GMNN_OP_BACKWARD 2
+#define GMNN_OP_FEATURES 3
 size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* sys,
                             const gmnn_neighbors* nl, uint32_t flags);
 
@@ -387,6 +388,38 @@ gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmn
                           const double* dL_dE, const float* dL_dF, uint32_t flags,
                           gmnn_param_grads* grads, float* dL_dpos,
                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batch active learning (Section 2.4).
+ *
+ * Last-layer gradient features (eq. lastlayer): phi[b] = the gradient of
+ * structure b's head-mean energy w.r.t. one head's last-layer weights and
+ * bias,
+ *   phi[b] = (1/M) [ sum_{i in b} sigma_Zi h2_i ,  sum_{i in b} sigma_Zi ],
+ * H2 + 1 values per structure (FP64, summed in atom order), h2_i the second
+ * hidden layer's activations of atom i (the network as in
+ * gmnn_energy_forces, GMNN_PREC_BF16 honoured).  The full gradient repeats
+ * this block once per head, which scales every distance by sqrt(M) and
+ * leaves the selection below unchanged.  phi: device [B][H2 + 1].
+ * Workspace: gmnn_workspace_bytes(GMNN_OP_FEATURES, ...).  Runs the readout
+ * forward only (split schedule). */
+gmnn_status gmnn_last_layer_features(const gmnn_model* m, const gmnn_system* sys,
+                                     const gmnn_neighbors* nl, uint32_t flags, double* phi,
+                                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Greedy maximum-distance selection (eq. maxdist): n_select indices of
+ * pool[n_pool][dim] (device, FP64), each the pool entry (not yet selected)
+ * whose smallest Euclidean distance to the training entries train[n_train]
+ * [dim] and to the entries selected before it is largest; ties go to the
+ * smaller index.  With no training entries the first pick is the entry of
+ * largest norm (reading: the paper's minimum runs over an empty set there).
+ * selected: device [n_select] int32, in selection order.  Distances in FP64.
+ * Workspace: gmnn_select_workspace_bytes(n_pool).  3 n_select + 1 launches,
+ * no host synchronisation. */
+size_t gmnn_select_workspace_bytes(int64_t n_pool);
+gmnn_status gmnn_select_max_distance(const double* pool, int64_t n_pool, int32_t dim, const double* train,
+                                     int64_t n_train, int32_t n_select, int32_t* selected,
+                                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Molecular dynamics on the device (Section 3.5: the whole simulation loop

@@ -15,6 +15,7 @@ GMNN_ERR_HIP = -4
 GMNN_ERR_DEVICE_FLAG = -5
 GMNN_ERR_WORKSPACE = -6
 GMNN_ERR_SCRATCH_LIMIT = -7
+GMNN_OP_FEATURES = 3
 GMNN_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 GMNN_FLAG_CAPACITY = 1
@@ -122,6 +123,11 @@ EXPORTS = {
     "gmnn_energy_forces_udd": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),
                                            C.c_uint32, C.POINTER(gmnn_plan), C.POINTER(gmnn_udd),
                                            C.POINTER(gmnn_outputs), vp, C.c_size_t, vp]),
+    "gmnn_last_layer_features": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
+                                             C.POINTER(gmnn_neighbors), C.c_uint32, vp, vp, C.c_size_t, vp]),
+    "gmnn_select_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "gmnn_select_max_distance": (C.c_int32, [vp, C.c_int64, C.c_int32, vp, C.c_int64, C.c_int32, vp, vp,
+                                             C.c_size_t, vp]),
     "gmnn_energy_forces_noalloc": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system),
                                                C.POINTER(gmnn_neighbors), C.c_uint32, C.POINTER(gmnn_outputs), vp]),
     "gmnn_energy_forces": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_system), C.POINTER(gmnn_neighbors),

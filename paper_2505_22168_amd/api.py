@@ -510,3 +510,40 @@ class EnergyForcesFunction(torch.autograd.Function):
         gF = torch.zeros((N, 3), dtype=torch.float32, device=ctx.system.device) if gF is None else gF.float()
         grads = param_grads(ctx.model, ctx.system, ctx.nl, gE, gF, precision=ctx.model.train_precision)
         return (None, None, None, *[grads[k] for k in PARAM_NAMES])
+
+
+# ---------------------------------------------------------------------------
+# batch active learning (gmnn_last_layer_features, gmnn_select_max_distance)
+def last_layer_features(model: Model, system: System, nl: NeighborList, precision: str = "fp32") -> torch.Tensor:
+    """Last-layer gradient features [B, H2 + 1] (float64, device) of every
+    structure: the gradient of its head-mean energy w.r.t. one head's
+    last-layer weights and bias."""
+    if precision not in ("fp32", "bf16"):
+        raise ValueError(precision)
+    flags = A.GMNN_PREC_BF16 if precision == "bf16" else A.GMNN_PREC_FP32
+    lib = A.load()
+    model.ensure_packed()
+    mc, sc, nc = model.c(), system.c(), nl.c()
+    nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_FEATURES, C.byref(mc), C.byref(sc), C.byref(nc), flags)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=system.device)
+    phi = torch.empty((system.n_structs, model.spec.hidden[1] + 1), dtype=torch.float64, device=system.device)
+    A.check(lib.gmnn_last_layer_features(C.byref(mc), C.byref(sc), C.byref(nc), flags, _ptr(phi), _ptr(ws), nbytes,
+                                         _stream()), "gmnn_last_layer_features")
+    return phi
+
+
+def select_max_distance(pool: torch.Tensor, n_select: int, train: torch.Tensor | None = None) -> torch.Tensor:
+    """Greedy maximum-distance selection of n_select rows of pool [n, d]
+    (float64 device tensor), against the training rows `train` [t, d]; the
+    picked row indices in order (int32 device tensor)."""
+    pool = pool.to(torch.float64).contiguous()
+    n, d = pool.shape
+    tr = None if train is None else train.to(device=pool.device, dtype=torch.float64).contiguous()
+    lib = A.load()
+    nbytes = lib.gmnn_select_workspace_bytes(n)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=pool.device)
+    out = torch.empty(max(n_select, 1), dtype=torch.int32, device=pool.device)
+    A.check(lib.gmnn_select_max_distance(_ptr(pool), n, d, None if tr is None else _ptr(tr),
+                                         0 if tr is None else tr.shape[0], n_select, _ptr(out), _ptr(ws), nbytes,
+                                         _stream()), "gmnn_select_max_distance")
+    return out[:n_select]

@@ -35,6 +35,7 @@ size_t stream_lds_bytes(int hp, bool bf16, int n_heads);
 size_t stream_g_bytes(int n_atoms, bool bf16);
 size_t stream_dg_bytes(int n_atoms);
 size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead);
+__global__ void ll_features(DevModel m, DevSystem sys, int H2, const float* h2, double* phi);
 bool train_supported(const DevModel& m);
 size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
 gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
@@ -238,6 +239,7 @@ static DevModel dev_model(const gmnn_model* m) {
   d.b3 = (const float*)(P + L.b3);
   d.head_w = nullptr;
   d.fwd_only = 0;
+  d.h2_out = nullptr;
   return d;
 }
 
@@ -438,6 +440,10 @@ size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* 
   }
   if (!m || !nl) return 0;
   if (op == GMNN_OP_ENERGY_FORCES) return ef_layout(m, sys, nl, flags).bytes;
+  if (op == GMNN_OP_FEATURES) {
+    const PackedLayout P = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+    return ef_layout(m, sys, nl, flags & GMNN_PREC_BF16).bytes + ((4 * (size_t)sys->n_atoms * P.HP2 + 255) & ~size_t(255));
+  }
   if (op == GMNN_OP_BACKWARD) {
     const PackedLayout P = packed_layout(m->hidden1, m->hidden2, m->n_heads);
     return train_workspace_bytes(sys->n_atoms, P.HP1, m->n_species);
@@ -811,6 +817,60 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
   st = gmnn_energy_forces_plan(m, sys, nl, flags, best, out, workspace, workspace_bytes, stream);
   if (st == GMNN_OK && hipStreamSynchronize(s) != hipSuccess) st = GMNN_ERR_HIP;
   return st;
+}
+
+gmnn_status gmnn_last_layer_features(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
+                                     uint32_t flags, double* phi, void* workspace, size_t workspace_bytes,
+                                     void* stream) {
+  gmnn_status st = check_model(m);
+  if (st != GMNN_OK) return st;
+  st = check_system(sys);
+  if (st != GMNN_OK) return st;
+  if (!nl || !nl->row_ptr || !nl->atom_struct || (nl->capacity > 0 && (!nl->j || !nl->shift || !nl->rev)) || !phi ||
+      !workspace)
+    return GMNN_ERR_INVALID_ARG;
+  if (nl->cutoff + 1e-6f < m->r_cut) return GMNN_ERR_INVALID_ARG;
+  const uint32_t f = flags & GMNN_PREC_BF16;
+  const EfLayout L = ef_layout(m, sys, nl, f);
+  if (workspace_bytes < gmnn_workspace_bytes(GMNN_OP_FEATURES, m, sys, nl, f)) return GMNN_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)workspace;
+  float* psi = (float*)(W + L.psi);
+  float* psibar = (float*)(W + L.psibar);
+  float* atomic_e = (float*)(W + L.atomic_e);
+  float* h2 = (float*)(W + L.bytes);
+  DevModel dm = dev_model(m);
+  dm.fwd_only = 1;  // the readout forward only, recording h2
+  dm.h2_out = h2;
+  const DevSystem ds = dev_system(sys, nl);
+  const bool bf16 = f != 0;
+  Plan P;
+  const gmnn_plan split{GMNN_SCHEDULE_SPLIT, 0, GMNN_READOUT_AUTO, 0};
+  st = resolve_plan(m, sys, f, &split, P);
+  if (st != GMNN_OK) return st;
+  const int N = sys->n_atoms;
+  if (N > 0) {
+    const int lpa = P.lpa;
+    const int nb = (N + kPairThreads / lpa - 1) / (kPairThreads / lpa);
+    const size_t beta_lds = sizeof(float) * (size_t)m->n_species * m->n_species * kS * kMaxBasis;
+#define MOMENTS(LPA) \
+  hipLaunchKernelGGL(pair_moments<LPA>, dim3(nb), dim3(kPairThreads), beta_lds, s, dm, ds, psi, (int*)nullptr, 0)
+    if (lpa == 64) MOMENTS(64);
+    else if (lpa == 32) MOMENTS(32);
+    else if (lpa == 16) MOMENTS(16);
+    else MOMENTS(8);
+#undef MOMENTS
+    if (P.stream)
+      st = launch_stream(dm, ds, bf16, psi, W + L.g, (float*)(W + L.dg), atomic_e, psibar, s, nullptr, 3);
+    else
+      st = launch_tile(false, false, 16, dm, ds, bf16, psi, atomic_e, psibar, nullptr, nullptr, nl->capacity, nullptr,
+                       s);
+    if (st != GMNN_OK) return st;
+  }
+  hipLaunchKernelGGL(ll_features, dim3(sys->n_structs), dim3(256), 0, s, dm, ds, m->hidden2, h2, phi);
+  if (hipGetLastError() != hipSuccess) return GMNN_ERR_HIP;
+  if ((flags & GMNN_SYNC) && hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
+  return GMNN_OK;
 }
 
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, const double* dL_dE,

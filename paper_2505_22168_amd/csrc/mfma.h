@@ -373,6 +373,7 @@ __device__ __forceinline__ void network_forward(const DevModel& m, const void* s
         float d;
         const float hv = swish_parts(acc[i][j] + b2v[i], d);
         acc[i][j] = hv;
+        if (m.h2_out && row < n_rows) m.h2_out[(int64_t)(row0 + row) * HP + col] = hv;
         if (MEAN)
           st_act<BF16>(sD2, row * St::H + col,
                        d * sScale[row] * (m.head_w ? m.head_w[(int64_t)sStruct[row] * HP + col] : wbv[i]));

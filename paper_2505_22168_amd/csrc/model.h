@@ -93,6 +93,7 @@ struct DevModel {
   // the head mean of W3 in the backward (sum_m c_m W3[:, m]); null: the mean
   const float* head_w;
   int fwd_only;         // readout kernels stop after the energies (no backward)
+  float* h2_out;        // [N][HP2] second hidden layer's activations, written when set
 };
 
 // System view shared by the energy kernels.

@@ -405,6 +405,7 @@ __global__ void __launch_bounds__(kRoThreads)
           const int row = r * 16 + 4 * (l >> 4) + j;
           float d;
           acc[r][i][j] = swish_parts(acc[r][i][j] + bias, d);
+          if (m.h2_out && row < n_rows) m.h2_out[(int64_t)(row0 + row) * HP + col] = acc[r][i][j];
           const float wr = m.head_w ? m.head_w[(int64_t)sStruct[row] * HP + col] : wb;
           st_act<BF16>(sB, row * St::H + col, d * sScale[row] * wr);
         }
