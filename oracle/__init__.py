@@ -10,13 +10,18 @@ network readout with per-element scale and shift; Section 3.3: forces and
 virials as gradients; Section 2.2: shallow-ensemble statistics; Section
 2.3: the uncertainty-driven bias; Section 2.4: last-layer gradient features
 and greedy maximum-distance selection; Section 2.1's Bessel-like basis as an
-alternative to the Gaussians).
+alternative to the Gaussians; Section 2.2's probabilistic losses with
+Section 3.4's loss terms, Adam parameter groups and learning-rate
+schedules).
 
 Every function here is pinned by tests under tests/ against closed forms,
 invariances, brute force or finite differences; none is "parity unpinned".
 """
 from .neighbors import brute_force_neighbors, NeighborList
 from .bal import last_layer_features, max_distance_selection
+from .ensemble_training import (
+    LossSpec, ensemble_loss, ensemble_loss_grads, ensemble_loss_and_param_grads, adam_step, lr_factor,
+)
 from .gmnn import (
     radial_basis, cutoff_fn, pair_vectors, moments, invariants, feature_index,
     mlp, atomic_energies, evaluate, OracleResult, loss_and_param_grads, udd_bias, evaluate_udd, UddResult,
@@ -27,4 +32,5 @@ __all__ = [
     "moments", "invariants", "feature_index", "mlp", "atomic_energies", "evaluate",
     "OracleResult", "loss_and_param_grads", "udd_bias", "evaluate_udd", "UddResult",
     "last_layer_features", "max_distance_selection",
+    "LossSpec", "ensemble_loss", "ensemble_loss_grads", "ensemble_loss_and_param_grads", "adam_step", "lr_factor",
 ]
