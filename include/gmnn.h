@@ -65,6 +65,7 @@ typedef int32_t gmnn_status;
 #define GMNN_SYNC 8u               /* synchronise and turn device flags into a status */
 #define GMNN_BACKWARD_LANES16 16u  /* gmnn_backward: 16 lanes per atom row in its pair kernels whatever
                                       the atom count (built-in: 64 below 8192 atoms, 16 from there) */
+#define GMNN_BACKWARD_PER_HEAD 32u /* gmnn_backward: per-head upstream gradients (shallow-ensemble losses) */
 
 /* A ragged batch of B structures with N atoms in total (Section 2.1: a
  * configuration is positions R and atomic numbers Z; Section 3.5: with a
@@ -167,6 +168,8 @@ typedef struct gmnn_outputs {
                            * separation, energy or force.  Bits are OR-ed and kept until the
                            * caller clears the word; with GMNN_SYNC a raised bit turns into
                            * GMNN_ERR_DEVICE_FLAG. */
+  float* forces_heads;    /* [n_heads, N, 3] per-head forces F^m = -dE^m/dx (eq. jacobian), with
+                           * GMNN_WANT_FORCE_VAR, may be NULL */
 } gmnn_outputs;
 
 /* ---------------------------------------------------------------------- */
@@ -371,23 +374,115 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
                           void* stream, int32_t reps, gmnn_plan* best, gmnn_tune_entry* entries,
                           int32_t max_entries, int32_t* n_entries);
 
-/* Gradients of a scalar loss L(E, F) w.r.t. the model parameters and the
- * positions, given the upstream gradients dL/dE (per structure, w.r.t. the
- * head-mean energy) and dL/dF [N,3] (Section 3.4: energy + force losses;
- * Section 3.3: forces are -dE/dx, so the force term needs the mixed second
- * derivative).  Every array of `grads` is overwritten; dL_dpos may be
- * NULL.  With GMNN_PREC_BF16 the network products of the forward and
- * reverse passes (primal and tangent rows) run in BF16 on MFMA with FP32
- * accumulation, the operands rounded as in gmnn_energy_forces; the products
- * that form the weight gradients split each FP32 operand into a BF16 high
- * and low part and add the three products hi.hi + hi.lo + lo.hi (about 16
- * significant bits per product).  Without it everything is FP32.  The
- * workspace must hold gmnn_workspace_bytes(GMNN_OP_BACKWARD, ...).
- * Recomputes the forward pass itself. */
+/* Gradients of a scalar loss L(E, F) w.r.t. the model parameters, given the
+ * upstream gradients dL/dE (per structure, w.r.t. the head-mean energy) and
+ * dL/dF [N,3] (Section 3.4: energy + force losses; Section 3.3: forces are
+ * -dE/dx, so the force term needs the mixed second derivative).  Every array
+ * of `grads` is overwritten.  dL_dpos must be NULL (position gradients:
+ * GMNN_ERR_UNSUPPORTED).  With GMNN_PREC_BF16 the network products of the
+ * forward and reverse passes (primal and tangent rows) run in BF16 on MFMA
+ * with FP32 accumulation, the operands rounded as in gmnn_energy_forces; the
+ * products that form the weight gradients split each FP32 operand into a
+ * BF16 high and low part and add the three products hi.hi + hi.lo + lo.hi
+ * (about 16 significant bits per product).  Without it everything is FP32.
+ *
+ * With GMNN_BACKWARD_PER_HEAD the upstream gradients are per head, as a loss
+ * over the members of a shallow ensemble needs (Section 2.2, eq. nll):
+ * dL_dE is [B, n_heads] (dL/dE_b^m) and dL_dF [n_heads, N, 3] (dL/dF^m with
+ * F^m = -dE^m/dx, eq. jacobian).  The call runs one double backward per
+ * head; the gradients of the shared parameters (beta, W1, b1, W2, b2, scale,
+ * shift) are added over the heads in head order, W3[:, m] and b3[m] take
+ * head m's alone.
+ *
+ * The workspace must hold gmnn_workspace_bytes(GMNN_OP_BACKWARD, ..., flags)
+ * for the same flags.  Recomputes the forward pass itself. */
 gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
                           const double* dL_dE, const float* dL_dF, uint32_t flags,
                           gmnn_param_grads* grads, float* dL_dpos,
                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Shallow-ensemble training step (Section 2.2, eq. nll; Section 3.4).
+ *
+ * Loss terms over the M heads' predictions.  The energy term scores x_b^m =
+ * E_b^m (or E_b^m / N_b with energy_per_atom) against x_b^ref, the force
+ * term every Cartesian component F_ia^m of the per-head forces
+ * (outputs->forces_heads) against F_ia^ref, through
+ *   GMNN_LOSS_MSE   (xbar - x_ref)^2
+ *   GMNN_LOSS_NLL   (1/2) [(xbar - x_ref)^2 / s2 + log(2 pi s2)]
+ *   GMNN_LOSS_CRPS  s [z (2 Phi(z) - 1) + 2 phi(z) - 1/sqrt(pi)],  z = |xbar - x_ref| / s
+ * where xbar is the mean over the heads and s2 = s^2 their population
+ * variance (1/M) plus var_floor;
+ *   L = w_energy (1/B) sum_b l_b + w_force (1/(3N)) sum_{i,a} l_ia.
+ * gmnn_ensemble_loss writes loss[0] (energy term) and loss[1] (force term)
+ * (device FP64, fixed-order sums) and the per-head gradients dL_dE [B, M]
+ * (FP64) and dL_dF [M, N, 3] (FP32) that gmnn_backward takes with
+ * GMNN_BACKWARD_PER_HEAD; dL_dE or dL_dF may be NULL.  All arrays device.
+ * energy [B, M] FP64 and forces_heads [M, N, 3] FP32 as gmnn_energy_forces
+ * writes them; energy_ref [B] FP64, forces_ref [N, 3] FP32.  Workspace:
+ * gmnn_loss_workspace_bytes(sys).  Non-finite inputs propagate into the
+ * outputs (no device flag). */
+#define GMNN_LOSS_MSE 0
+#define GMNN_LOSS_NLL 1
+#define GMNN_LOSS_CRPS 2
+typedef struct gmnn_loss {
+  int32_t energy_kind;      /* GMNN_LOSS_* */
+  int32_t force_kind;       /* GMNN_LOSS_* */
+  int32_t energy_per_atom;  /* 1: the energy term scores E_b / N_b */
+  int32_t reserved;
+  double w_energy;          /* weight of the energy term (0 drops it) */
+  double w_force;           /* weight of the force term (0 drops it) */
+  double var_floor;         /* added to every variance (units of x^2); NLL and CRPS need
+                               s2 > 0, which equal heads break without it */
+} gmnn_loss;
+size_t gmnn_loss_workspace_bytes(const gmnn_system* sys);
+gmnn_status gmnn_ensemble_loss(const gmnn_loss* spec, const gmnn_system* sys, int32_t n_heads,
+                               const double* energy, const float* forces_heads, const double* energy_ref,
+                               const float* forces_ref, double* loss, double* dL_dE, float* dL_dF,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* One Adam update (Kingma & Ba, Algorithm 1) of every parameter array of m,
+ * in place, with one learning rate per parameter group (Section 3.4:
+ * separate rates for the embedding, the neural network, the scales and the
+ * shifts; a rate of 0 freezes its group):
+ *   m1 = beta1 m1 + (1 - beta1) g;  m2 = beta2 m2 + (1 - beta2) g^2;
+ *   theta -= lr_group (m1 / (1 - beta1^t)) / (sqrt(m2 / (1 - beta2^t)) + eps).
+ * grads, m1, m2: device FP32 arrays shaped like the parameters (m1 and m2
+ * zero before the first step, updated in place).  The arrays m points to
+ * must be writable.  The packed copies (m->packed) are rebuilt afterwards,
+ * as gmnn_model_prepare does, so the next evaluation sees the new weights.
+ * FP32 arithmetic; the bias corrections are formed on the host in FP64. */
+#define GMNN_GROUP_EMBEDDING 0  /* beta */
+#define GMNN_GROUP_NN 1         /* W1, b1, W2, b2, W3, b3 */
+#define GMNN_GROUP_SCALE 2      /* scale */
+#define GMNN_GROUP_SHIFT 3      /* shift */
+typedef struct gmnn_adam {
+  double lr[4];             /* learning rate per GMNN_GROUP_* */
+  double beta1, beta2, eps;
+  int64_t step;             /* t >= 1, the index of this update */
+} gmnn_adam;
+gmnn_status gmnn_adam_step(gmnn_model* m, const gmnn_param_grads* grads, gmnn_param_grads* m1,
+                           gmnn_param_grads* m2, const gmnn_adam* opt, void* stream);
+
+/* Learning-rate schedules (Section 3.4): the factor every group's base rate
+ * is multiplied by at a (0-based) step.
+ *   GMNN_LR_CONSTANT  1
+ *   GMNN_LR_LINEAR    1 + (end_factor - 1) min(step, total_steps) / total_steps
+ *   GMNN_LR_COSINE    cyclic cosine: decay_factor^c (1 + cos(pi r / period)) / 2
+ *                     with c, r = step div/mod period
+ * Host function; NaN for an invalid schedule. */
+#define GMNN_LR_CONSTANT 0
+#define GMNN_LR_LINEAR 1
+#define GMNN_LR_COSINE 2
+typedef struct gmnn_lr_schedule {
+  int32_t kind;
+  int32_t reserved;
+  int64_t total_steps;      /* GMNN_LR_LINEAR, >= 1 */
+  double end_factor;        /* GMNN_LR_LINEAR */
+  int64_t period;           /* GMNN_LR_COSINE, >= 1 */
+  double decay_factor;      /* GMNN_LR_COSINE */
+} gmnn_lr_schedule;
+double gmnn_lr_factor(const gmnn_lr_schedule* s, int64_t step);
 
 /* ---------------------------------------------------------------------- */
 /* Batch active learning (Section 2.4).

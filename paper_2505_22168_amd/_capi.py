@@ -31,6 +31,10 @@ GMNN_WANT_STRESS = 2
 GMNN_WANT_FORCE_VAR = 4
 GMNN_SYNC = 8
 GMNN_BACKWARD_LANES16 = 16
+GMNN_BACKWARD_PER_HEAD = 32
+GMNN_LOSS_MSE, GMNN_LOSS_NLL, GMNN_LOSS_CRPS = 0, 1, 2
+GMNN_GROUP_EMBEDDING, GMNN_GROUP_NN, GMNN_GROUP_SCALE, GMNN_GROUP_SHIFT = 0, 1, 2, 3
+GMNN_LR_CONSTANT, GMNN_LR_LINEAR, GMNN_LR_COSINE = 0, 1, 2
 
 GMNN_SCHEDULE_AUTO = 0
 GMNN_SCHEDULE_FUSED = 1
@@ -107,10 +111,33 @@ class gmnn_tune_entry(C.Structure):
 
 class gmnn_outputs(C.Structure):
     _fields_ = [("energy", vp), ("forces", vp), ("stress", vp), ("energy_var", vp),
-                ("force_var", vp), ("atomic_energy", vp), ("energy_mean", vp), ("status", vp)]
+                ("force_var", vp), ("atomic_energy", vp), ("energy_mean", vp), ("status", vp),
+                ("forces_heads", vp)]
+
+
+class gmnn_loss(C.Structure):
+    _fields_ = [("energy_kind", C.c_int32), ("force_kind", C.c_int32), ("energy_per_atom", C.c_int32),
+                ("reserved", C.c_int32), ("w_energy", C.c_double), ("w_force", C.c_double),
+                ("var_floor", C.c_double)]
+
+
+class gmnn_adam(C.Structure):
+    _fields_ = [("lr", C.c_double * 4), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("step", C.c_int64)]
+
+
+class gmnn_lr_schedule(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("total_steps", C.c_int64),
+                ("end_factor", C.c_double), ("period", C.c_int64), ("decay_factor", C.c_double)]
 
 
 EXPORTS = {
+    "gmnn_loss_workspace_bytes": (C.c_size_t, [C.POINTER(gmnn_system)]),
+    "gmnn_ensemble_loss": (C.c_int32, [C.POINTER(gmnn_loss), C.POINTER(gmnn_system), C.c_int32, vp, vp, vp, vp,
+                                       vp, vp, vp, vp, C.c_size_t, vp]),
+    "gmnn_adam_step": (C.c_int32, [C.POINTER(gmnn_model), C.POINTER(gmnn_param_grads), C.POINTER(gmnn_param_grads),
+                                   C.POINTER(gmnn_param_grads), C.POINTER(gmnn_adam), vp]),
+    "gmnn_lr_factor": (C.c_double, [C.POINTER(gmnn_lr_schedule), C.c_int64]),
     "gmnn_status_string": (C.c_char_p, [C.c_int32]),
     "gmnn_num_features": (C.c_int32, [C.c_int32]),
     "gmnn_model_packed_bytes": (C.c_size_t, [C.POINTER(gmnn_model)]),

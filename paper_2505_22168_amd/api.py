@@ -214,6 +214,7 @@ class Outputs:
     energy_mean: torch.Tensor     # [B] float64, mean over heads
     status: torch.Tensor          # [1] int32 device status word (GMNN_FLAG_* bits)
     bias_energy: torch.Tensor | None = None  # [B] float64 uncertainty-driven bias (udd=)
+    forces_heads: torch.Tensor | None = None  # [heads, N, 3] float32 per-head forces (force_var=True)
 
 
 class EnergyForces:
@@ -247,7 +248,8 @@ class EnergyForces:
             force_var=torch.zeros(max(N, 1), dtype=torch.float32, device=dev) if force_var else None,
             atomic_energy=torch.zeros((max(N, 1), M), dtype=torch.float32, device=dev),
             energy_mean=torch.zeros(B, dtype=torch.float64, device=dev),
-            status=torch.zeros(1, dtype=torch.int32, device=dev))
+            status=torch.zeros(1, dtype=torch.int32, device=dev),
+            forces_heads=torch.zeros((M, max(N, 1), 3), dtype=torch.float32, device=dev) if force_var else None)
         lib = A.load()
         self._mc = model.c()
         self._sc = system.c()
@@ -258,7 +260,8 @@ class EnergyForces:
         self.ws_bytes = nbytes
         o = self.out
         self._oc = A.gmnn_outputs(_ptr(o.energy), _ptr(o.forces), _ptr(o.stress), _ptr(o.energy_var),
-                                  _ptr(o.force_var), _ptr(o.atomic_energy), _ptr(o.energy_mean), _ptr(o.status))
+                                  _ptr(o.force_var), _ptr(o.atomic_energy), _ptr(o.energy_mean), _ptr(o.status),
+                                  _ptr(o.forces_heads))
         self._plan = None
         self._udd = None
         if udd is not None:
@@ -447,23 +450,35 @@ def maxwell_boltzmann(masses, temperature: float, seed: int):
 
 # ---------------------------------------------------------------------------
 def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, workspace=None,
-                precision: str = "fp32", out=None, lanes16: bool = False):
+                precision: str = "fp32", out=None, lanes16: bool = False, per_head: bool = False):
     """Gradients of a loss w.r.t. every model parameter (gmnn_backward), given
     dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3];
     precision "bf16" runs the network products of the double backward in BF16
     and the weight-gradient products as three BF16 products of split FP32
-    operands (about 16 significant bits per product).
+    operands (about 16 significant bits per product).  per_head: the
+    upstream gradients are per head, dL/dE^m [B, heads] and dL/dF^m
+    [heads, N, 3] (shallow-ensemble losses; one double backward per head).
 
     `out` (a dict of FP32 device tensors shaped like model.tensors) receives
     the gradients; the call overwrites every element, so neither `out` nor a
     freshly allocated result needs clearing first."""
     if precision not in ("fp32", "bf16"):
         raise ValueError(precision)
-    flags = (A.GMNN_PREC_BF16 if precision == "bf16" else 0) | (A.GMNN_BACKWARD_LANES16 if lanes16 else 0)
+    flags = ((A.GMNN_PREC_BF16 if precision == "bf16" else 0) | (A.GMNN_BACKWARD_LANES16 if lanes16 else 0)
+             | (A.GMNN_BACKWARD_PER_HEAD if per_head else 0))
     lib = A.load()
     dev = system.device
+    B, N, M = system.n_structs, system.n_atoms, model.spec.n_heads
     dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=dev).contiguous()
-    dF = torch.as_tensor(dL_dF, dtype=torch.float32, device=dev).reshape(-1, 3).contiguous()
+    dF = torch.as_tensor(dL_dF, dtype=torch.float32, device=dev).contiguous()
+    if per_head:
+        dF = dF.reshape(M, -1, 3)
+        if dE.shape != (B, M) or dF.shape[1] < N:
+            raise ValueError(f"per-head gradients need dL_dE [{B}, {M}] and dL_dF [{M}, {N}, 3]")
+        if dF.shape[1] != N:
+            dF = dF[:, :N].contiguous()  # the library reads head m's rows at m * 3N
+    else:
+        dF = dF.reshape(-1, 3)
     if out is None:
         grads = {k: torch.empty_like(v) for k, v in model.tensors.items()}
     else:
@@ -475,7 +490,7 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
     gc = A.gmnn_param_grads(*[_ptr(grads[k]) for k in PARAM_NAMES])
     model.ensure_packed()
     mc, sc, nc = model.c(), system.c(), nl.c()
-    nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), 0)
+    nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), flags)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
     st = lib.gmnn_backward(C.byref(mc), C.byref(sc), C.byref(nc), _ptr(dE), _ptr(dF), flags, C.byref(gc), None,
@@ -547,3 +562,125 @@ def select_max_distance(pool: torch.Tensor, n_select: int, train: torch.Tensor |
                                          0 if tr is None else tr.shape[0], n_select, _ptr(out), _ptr(ws), nbytes,
                                          _stream()), "gmnn_select_max_distance")
     return out[:n_select]
+
+
+# ---------------------------------------------------------------------------
+# shallow-ensemble training step (gmnn_ensemble_loss, gmnn_backward per head,
+# gmnn_adam_step, gmnn_lr_factor)
+_LOSS_KIND = {"mse": A.GMNN_LOSS_MSE, "nll": A.GMNN_LOSS_NLL, "crps": A.GMNN_LOSS_CRPS}
+GROUPS = ("embedding", "nn", "scale", "shift")
+
+
+@dataclass
+class LossSpec:
+    """Energy and force loss terms over the heads: kinds "mse", "nll" or
+    "crps", weights, the energy term per atom or not, and the variance floor."""
+    energy: str = "crps"
+    force: str = "crps"
+    w_energy: float = 1.0
+    w_force: float = 1.0
+    energy_per_atom: bool = True
+    var_floor: float = 0.0
+
+    def c(self):
+        return A.gmnn_loss(_LOSS_KIND[self.energy], _LOSS_KIND[self.force], int(self.energy_per_atom), 0,
+                           float(self.w_energy), float(self.w_force), float(self.var_floor))
+
+
+def ensemble_loss(system: System, energy, forces_heads, energy_ref, forces_ref, spec: LossSpec, workspace=None):
+    """(loss [2] float64 = energy term, force term; dL/dE^m [B, heads] float64;
+    dL/dF^m [heads, N, 3] float32), all device tensors, from the per-head
+    energies and forces of an evaluation with force_var=True."""
+    lib = A.load()
+    dev = system.device
+    B, N = system.n_structs, system.n_atoms
+    energy = energy.to(torch.float64).contiguous()
+    M = energy.shape[1]
+    fh = forces_heads.to(torch.float32).contiguous()
+    if fh.shape[0] != M or fh.shape[1] < N:
+        raise ValueError("forces_heads must be [heads, N, 3]")
+    if fh.shape[1] != N:
+        fh = fh[:, :N].contiguous()
+    er = torch.as_tensor(energy_ref, dtype=torch.float64, device=dev).contiguous()
+    fr = torch.as_tensor(forces_ref, dtype=torch.float32, device=dev).reshape(-1, 3)[:N].contiguous()
+    sc = system.c()
+    nbytes = lib.gmnn_loss_workspace_bytes(C.byref(sc))
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    loss = torch.empty(2, dtype=torch.float64, device=dev)
+    dE = torch.empty((B, M), dtype=torch.float64, device=dev)
+    dF = torch.empty((M, max(N, 1), 3), dtype=torch.float32, device=dev)
+    lc = spec.c()
+    A.check(lib.gmnn_ensemble_loss(C.byref(lc), C.byref(sc), M, _ptr(energy), _ptr(fh), _ptr(er), _ptr(fr),
+                                   _ptr(loss), _ptr(dE), _ptr(dF), _ptr(workspace), nbytes, _stream()),
+            "gmnn_ensemble_loss")
+    return loss, dE, dF
+
+
+def lr_factor(kind: str = "constant", step: int = 0, total_steps: int = 1, end_factor: float = 0.0,
+              period: int = 1, decay_factor: float = 1.0) -> float:
+    """Learning-rate multiplier of a schedule at a 0-based step (gmnn_lr_factor)."""
+    k = {"constant": A.GMNN_LR_CONSTANT, "linear": A.GMNN_LR_LINEAR, "cosine": A.GMNN_LR_COSINE}[kind]
+    sc = A.gmnn_lr_schedule(k, 0, int(total_steps), float(end_factor), int(period), float(decay_factor))
+    return float(A.load().gmnn_lr_factor(C.byref(sc), int(step)))
+
+
+class Adam:
+    """On-device Adam (gmnn_adam_step) over a Model's parameters, one learning
+    rate per group ("embedding", "nn", "scale", "shift"), optionally scaled
+    by a schedule (a dict of lr_factor's keyword arguments).  Updates the
+    model's tensors in place and re-packs its weights."""
+
+    def __init__(self, model: Model, lr: dict, betas=(0.9, 0.999), eps: float = 1e-8, schedule: dict | None = None):
+        self.model = model
+        self.lr = {g: float(lr.get(g, 0.0)) for g in GROUPS}
+        self.betas, self.eps, self.schedule = betas, eps, schedule
+        self.t = 0
+        self.m1 = {k: torch.zeros_like(v) for k, v in model.tensors.items()}
+        self.m2 = {k: torch.zeros_like(v) for k, v in model.tensors.items()}
+        self._c1 = A.gmnn_param_grads(*[_ptr(self.m1[k]) for k in PARAM_NAMES])
+        self._c2 = A.gmnn_param_grads(*[_ptr(self.m2[k]) for k in PARAM_NAMES])
+
+    def step(self, grads: dict):
+        f = 1.0 if self.schedule is None else lr_factor(step=self.t, **self.schedule)
+        self.t += 1
+        opt = A.gmnn_adam((C.c_double * 4)(*[self.lr[g] * f for g in GROUPS]), self.betas[0], self.betas[1],
+                          self.eps, self.t)
+        gc = A.gmnn_param_grads(*[_ptr(grads[k]) for k in PARAM_NAMES])
+        self.model.ensure_packed()
+        mc = self.model.c()
+        A.check(A.load().gmnn_adam_step(C.byref(mc), C.byref(gc), C.byref(self._c1), C.byref(self._c2),
+                                        C.byref(opt), _stream()), "gmnn_adam_step")
+
+
+class EnsembleTrainer:
+    """One on-device training step of a shallow ensemble (Section 2.2 losses,
+    Section 3.4 optimiser): per-head energies and forces (force_var
+    evaluation), the loss terms and their per-head gradients, the per-head
+    double backward, the Adam update.  No host synchronisation; step()
+    returns the device loss terms of the evaluated (pre-update) parameters."""
+
+    def __init__(self, model: Model, system: System, nl: NeighborList, energy_ref, forces_ref, loss: LossSpec,
+                 adam: Adam, precision: str = "fp32", plan=None):
+        self.model, self.system, self.nl, self.loss, self.adam = model, system, nl, loss, adam
+        self.precision = precision
+        dev = system.device
+        self.energy_ref = torch.as_tensor(energy_ref, dtype=torch.float64, device=dev).contiguous()
+        self.forces_ref = torch.as_tensor(forces_ref, dtype=torch.float32, device=dev).reshape(-1, 3).contiguous()
+        self.ev = EnergyForces(model, system, nl, precision=precision, stress=False, force_var=True, plan=plan)
+        self.grads = {k: torch.empty_like(v) for k, v in model.tensors.items()}
+        lib = A.load()
+        mc, sc, nc = model.c(), system.c(), nl.c()
+        flags = A.GMNN_BACKWARD_PER_HEAD | (A.GMNN_PREC_BF16 if precision == "bf16" else 0)
+        nb = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), flags)
+        self._bws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        self._lws = torch.empty(max(lib.gmnn_loss_workspace_bytes(C.byref(sc)), 1), dtype=torch.uint8, device=dev)
+
+    def step(self):
+        out = self.ev()
+        loss, dE, dF = ensemble_loss(self.system, out.energy, out.forces_heads, self.energy_ref, self.forces_ref,
+                                     self.loss, workspace=self._lws)
+        param_grads(self.model, self.system, self.nl, dE, dF, workspace=self._bws, precision=self.precision,
+                    out=self.grads, per_head=True)
+        self.adam.step(self.grads)
+        return loss

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmnn.so")
-SOURCES = ["capi.hip", "neighbors.hip", "pairs.hip", "tile.hip", "readout.hip", "md.hip", "train.hip", "select.hip"]
+SOURCES = ["capi.hip", "neighbors.hip", "pairs.hip", "tile.hip", "readout.hip", "md.hip", "train.hip", "select.hip", "ensemble_train.hip"]
 ARCH = os.environ.get("GMNN_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",

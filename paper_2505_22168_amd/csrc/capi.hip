@@ -24,7 +24,8 @@ template <int LPA, bool VAR>
 __global__ void finish(int M, DevSystem sys, const float* gpair, const float* atomic_e, const float* virial,
                        int want_stress, int nb_gather, int64_t gstride, int nchunk, double* partial, int* counters,
                        float* forces, float* force_var, double* energy, double* energy_var, double* energy_mean,
-                       double* stress, const double* tile_part, int tile_atoms, const float* head_c);
+                       double* stress, const double* tile_part, int tile_atoms, const float* head_c,
+                       float* forces_heads);
 gmnn_status launch_tile(bool fused, bool perhead, int tile_atoms, const DevModel& m, const DevSystem& sys, bool bf16,
                         const float* psi, float* atomic_e, float* psibar, float* gpair, float* virial,
                         int64_t gstride, double* tile_rec, hipStream_t stream);
@@ -38,6 +39,10 @@ size_t tile_lds_bytes(int hp, bool bf16, bool fused, bool perhead);
 __global__ void ll_features(DevModel m, DevSystem sys, int H2, const float* h2, double* phi);
 bool train_supported(const DevModel& m);
 size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
+size_t heads_backward_extra_bytes(const DevModel& m, int H1, int H2, int n_structs);
+gmnn_status train_backward_heads(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
+                                 int n_structs, const double* dE, const float* dF, gmnn_param_grads* g, void* ws,
+                                 size_t ws_bytes, hipStream_t s);
 gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
                            const double* ebar, const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes,
                            hipStream_t s);
@@ -446,7 +451,10 @@ size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* 
   }
   if (op == GMNN_OP_BACKWARD) {
     const PackedLayout P = packed_layout(m->hidden1, m->hidden2, m->n_heads);
-    return train_workspace_bytes(sys->n_atoms, P.HP1, m->n_species);
+    const size_t tb = train_workspace_bytes(sys->n_atoms, P.HP1, m->n_species);
+    if (!(flags & GMNN_BACKWARD_PER_HEAD)) return tb;
+    if (check_model(m) != GMNN_OK) return 0;
+    return ((tb + 255) & ~size_t(255)) + heads_backward_extra_bytes(dev_model(m), m->hidden1, m->hidden2, sys->n_structs);
   }
   return 0;
 }
@@ -600,7 +608,7 @@ static gmnn_status ef_run(const gmnn_model* m, const gmnn_system* sys, const gmn
 #define FINISH_REDUCE(VAR)                                                                                      \
   hipLaunchKernelGGL((finish<64, VAR>), rgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial,  \
                      0, 0, gstride, nchunk, partial, counters, out->forces, out->force_var, out->energy,           \
-                     out->energy_var, out->energy_mean, out->stress, nullptr, 0, nullptr)
+                     out->energy_var, out->energy_mean, out->stress, nullptr, 0, nullptr, nullptr)
         if (var) FINISH_REDUCE(true);
         else FINISH_REDUCE(false);
 #undef FINISH_REDUCE
@@ -652,7 +660,7 @@ static gmnn_status ef_run(const gmnn_model* m, const gmnn_system* sys, const gmn
   hipLaunchKernelGGL((finish<LPA, VAR>), fgrid, dim3(kPairThreads), 0, s, m->n_heads, ds, gpair, atomic_e, virial, \
                      want_stress, nbg, gstride, nchunk, partial, counters, out->forces, out->force_var, out->energy, \
                      out->energy_var, out->energy_mean, out->stress, fused ? tilerec : nullptr, fused ? P.ta : 0, \
-                     (udd && var) ? head_c : nullptr)
+                     (udd && var) ? head_c : nullptr, var ? out->forces_heads : nullptr)
   if (lpa == 64) {
     if (var) FINISH(64, true);
     else FINISH(64, false);
@@ -885,14 +893,19 @@ gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmn
       !grads->b2 || !grads->W3 || !grads->b3 || !grads->scale || !grads->shift || !workspace)
     return GMNN_ERR_INVALID_ARG;
   if (nl->cutoff + 1e-6f < m->r_cut) return GMNN_ERR_INVALID_ARG;
-  // the head-mean loss only; positions gradients are not produced
+  // positions gradients are not produced
   if ((flags & GMNN_WANT_FORCE_VAR) || dL_dpos) return GMNN_ERR_UNSUPPORTED;
   const DevModel dm = dev_model(m);
   if (!train_supported(dm)) return GMNN_ERR_UNSUPPORTED;
   const DevSystem ds = dev_system(sys, nl);
   hipStream_t s = (hipStream_t)stream;
-  st = train_backward(dm, ds, (flags & GMNN_PREC_BF16) != 0, (flags & GMNN_BACKWARD_LANES16) != 0, m->hidden1,
-                      m->hidden2, dL_dE, dL_dF, grads, workspace, workspace_bytes, s);
+  const bool bf16 = (flags & GMNN_PREC_BF16) != 0, lanes16 = (flags & GMNN_BACKWARD_LANES16) != 0;
+  if (flags & GMNN_BACKWARD_PER_HEAD)
+    st = train_backward_heads(dm, ds, bf16, lanes16, m->hidden1, m->hidden2, sys->n_structs, dL_dE, dL_dF, grads,
+                              workspace, workspace_bytes, s);
+  else
+    st = train_backward(dm, ds, bf16, lanes16, m->hidden1, m->hidden2, dL_dE, dL_dF, grads, workspace,
+                        workspace_bytes, s);
   if (st != GMNN_OK) return st;
   if ((flags & GMNN_SYNC) && hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
   return GMNN_OK;

@@ -300,7 +300,8 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
                                                      double* __restrict__ energy_var,
                                                      double* __restrict__ energy_mean, double* __restrict__ stress,
                                                      const double* __restrict__ tile_part, int tile_atoms,
-                                                     const float* __restrict__ head_c) {
+                                                     const float* __restrict__ head_c,
+                                                     float* __restrict__ forces_heads) {
   const int n_red = (int)gridDim.x - nb_gather;
   if ((int)blockIdx.x >= n_red) {
     const int q = threadIdx.x & (LPA - 1);
@@ -379,6 +380,13 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
         forces[3 * (int64_t)i + 1] = fo[1];
         forces[3 * (int64_t)i + 2] = fo[2];
         force_var[i] = var * invM;
+        if (forces_heads) {
+#pragma unroll
+          for (int h = 0; h < kMaxHeads; ++h)
+            if (h < M)
+#pragma unroll
+              for (int k = 0; k < 3; ++k) forces_heads[((int64_t)h * sys.n_atoms + i) * 3 + k] = f[h][k];
+        }
         if (sys.status && !(fabsf(fo[0]) + fabsf(fo[1]) + fabsf(fo[2]) + var <= 3.402823466e38f))
           raise_flag(sys.status, GMNN_FLAG_NONFINITE);
       }
@@ -460,7 +468,7 @@ template __global__ void pair_backward<64>(DevModel, DevSystem, const float*, fl
 #define FIN(LPA, VAR)                                                                                         \
   template __global__ void finish<LPA, VAR>(int, DevSystem, const float*, const float*, const float*, int, int, \
                                             int64_t, int, double*, int*, float*, float*, double*, double*, double*, \
-                                            double*, const double*, int, const float*);
+                                            double*, const double*, int, const float*, float*);
 FIN(8, false) FIN(16, false) FIN(32, false) FIN(64, false) FIN(8, true) FIN(16, true) FIN(32, true) FIN(64, true)
 #undef FIN
 
