@@ -495,6 +495,58 @@ def run_train(args):
     print(json.dumps(line))
 
 
+def run_train_ensemble(args):
+    """One whole on-device training step of a shallow ensemble (Section 2.2,
+    Section 3.4): per-head energies and forces, CRPS loss terms on energies
+    per atom and force components, the per-head double backward, one Adam
+    update with four parameter groups.  Training batch of 32 structures of
+    U{100..600} atoms with the 16-head 2x256 shallow-ensemble network."""
+    import dataclasses
+    import torch
+    import paper_2505_22168_amd as g
+    from workloads import make_workload, make_params
+    batch, _, spec = make_workload("train")
+    ens = make_workload("ensemble", n_structs=1)[2]
+    mspec = dataclasses.replace(spec.model, hidden=ens.model.hidden, n_heads=ens.model.n_heads)
+    params = make_params(mspec, 31)
+    dev = torch.device("cuda:0")
+    system = g.System.from_batch(batch, dev)
+    nl = g.build_neighbors(system, mspec.r_cut, spec.skin)
+    rng = np.random.default_rng(7)
+    nb = np.diff(batch.atom_ptr)
+    Er = -3.0 * nb + rng.normal(size=batch.n_structs) * np.sqrt(nb) * 0.05
+    Fr = rng.normal(size=(batch.n_atoms, 3)).astype(np.float32)
+    res = {}
+    for prec in ("bf16", "fp32"):
+        model = g.Model(mspec, params.as_dict(), dev)
+        adam = g.Adam(model, {"embedding": 5e-4, "nn": 5e-4, "scale": 5e-4, "shift": 5e-4},
+                      schedule=dict(kind="linear", total_steps=1000, end_factor=0.1))
+        tr = g.EnsembleTrainer(model, system, nl, Er, Fr, g.LossSpec("crps", "crps", 1.0, 1.0, True, 1e-6), adam,
+                               precision=prec)
+        t = _wall(tr.step, args.steps, args.warmup)
+        t_fwd = _wall(tr.ev, args.steps, args.warmup)
+        out = tr.ev()
+        t_loss = _wall(lambda: g.ensemble_loss(system, out.energy, out.forces_heads, tr.energy_ref, tr.forces_ref,
+                                               tr.loss, workspace=tr._lws), args.steps, args.warmup)
+        loss, dE, dF = g.ensemble_loss(system, out.energy, out.forces_heads, tr.energy_ref, tr.forces_ref, tr.loss)
+        t_bwd = _wall(lambda: g.param_grads(model, system, nl, dE, dF, workspace=tr._bws, precision=prec,
+                                            out=tr.grads, per_head=True), args.steps, args.warmup)
+        t_adam = _wall(lambda: adam.step(tr.grads), args.steps, args.warmup)
+        l0 = tr.step().cpu().numpy()
+        res[prec] = {"value": batch.n_atoms / t, "ms_per_step": t * 1e3, "forward_ms": t_fwd * 1e3,
+                     "loss_ms": t_loss * 1e3, "backward_ms": t_bwd * 1e3, "adam_ms": t_adam * 1e3,
+                     "loss_terms_after_timing": [float(l0[0]), float(l0[1])]}
+        print(f"[bench-train-ensemble] {prec}: {res[prec]}", file=sys.stderr, flush=True)
+    line = {"metric": "shallow-ensemble training-step atom-evals/s (per-head forces, CRPS loss, per-head double "
+                      "backward, Adam)", "value": res["bf16"]["value"], "unit": "atom-evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["bf16"]["ms_per_step"], "dtype": "bf16",
+            "data": "synthetic", "bf16": res["bf16"], "fp32": res["fp32"],
+            "config": {"workload": "train batch, 16-head ensemble network", "n_atoms": batch.n_atoms,
+                       "n_structs": batch.n_structs, "n_pairs": nl.n_pairs, "mlp": list(mspec.hidden),
+                       "heads": mspec.n_heads}}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +568,8 @@ def main():
                     help="C5 mode: one batched launch (heads, energy/force variance) vs per-structure launches")
     ap.add_argument("--train", action="store_true",
                     help="training-gradient mode: energy+forces then gmnn_backward per step (FP32)")
+    ap.add_argument("--train-ensemble", action="store_true",
+                    help="whole shallow-ensemble training steps (per-head forces, CRPS loss, backward, Adam)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library runs on one GPU (no multi-GPU path)",
@@ -540,6 +594,8 @@ def main():
         return run_ensemble(args)
     if args.train:
         return run_train(args)
+    if args.train_ensemble:
+        return run_train_ensemble(args)
     import torch
     import paper_2505_22168_amd as g
     from paper_2505_22168_amd import _capi as A

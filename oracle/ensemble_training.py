@@ -112,6 +112,7 @@ class EnsembleStep:
     dL_dE: np.ndarray            # [B, M]
     dL_dF: np.ndarray            # [M, N, 3]
     grads: dict                  # parameter name -> dL/dtheta
+    dL_dpos: np.ndarray          # [N, 3] gradient of the loss in the positions
 
 
 def ensemble_loss_and_param_grads(batch, params, nl, E_ref, F_ref, spec: LossSpec) -> EnsembleStep:
@@ -133,13 +134,14 @@ def ensemble_loss_and_param_grads(batch, params, nl, E_ref, F_ref, spec: LossSpe
     nb = torch.as_tensor(np.diff(batch.atom_ptr), dtype=DT)
     LE, LF = ensemble_loss(Eb, Fh, torch.as_tensor(np.asarray(E_ref, dtype=np.float64)),
                            torch.as_tensor(np.asarray(F_ref, dtype=np.float64)), nb, spec)
-    out = torch.autograd.grad(LE + LF, [p[k] for k in PARAM_NAMES] + [Eb, Fh], allow_unused=True)
+    out = torch.autograd.grad(LE + LF, [p[k] for k in PARAM_NAMES] + [Eb, Fh, pos], allow_unused=True)
     grads = {k: (g.detach().numpy() if g is not None else np.zeros(p[k].shape)) for k, g in zip(PARAM_NAMES, out)}
     gE = out[len(PARAM_NAMES)]
     gF = out[len(PARAM_NAMES) + 1]
     return EnsembleStep(float(LE.detach()), float(LF.detach()), Eb.detach().numpy(), Fh.detach().numpy(),
                         np.zeros((B, M)) if gE is None else gE.detach().numpy(),
-                        np.zeros((M, N, 3)) if gF is None else gF.detach().numpy(), grads)
+                        np.zeros((M, N, 3)) if gF is None else gF.detach().numpy(), grads,
+                        out[len(PARAM_NAMES) + 2].detach().numpy())
 
 
 # ----------------------------------------------------------------------------

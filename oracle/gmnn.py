@@ -366,10 +366,13 @@ def evaluate_udd(batch, params, nl, A, B) -> UddResult:
 PARAM_NAMES = ("beta", "W1", "b1", "W2", "b2", "W3", "b3", "scale", "shift")
 
 
-def loss_and_param_grads(batch, params, nl, E_ref, F_ref, w_E=1.0, w_F=1.0):
+def loss_and_param_grads(batch, params, nl, E_ref, F_ref, w_E=1.0, w_F=1.0, want_pos=False):
     """L = w_E/B sum_b ((Ebar_b - E_ref_b)/N_b)^2 + w_F/(3N) sum |F - F_ref|^2
     and dL/dtheta for every parameter array (dict of numpy arrays), plus
-    dL/dE_b and dL/dF (the upstream gradients a caller feeds to a backward)."""
+    dL/dE_b and dL/dF (the upstream gradients a caller feeds to a backward);
+    with want_pos also dL/dx [N, 3], the loss's gradient in the positions
+    (through the energies and, with forces = -dE/dx, their second
+    derivatives)."""
     p, pos0, cell, soa, sp, i, j, S = _tensors(batch, params, nl)
     p = {k: v.clone().requires_grad_(True) for k, v in p.items()}
     spec = params.spec
@@ -387,8 +390,10 @@ def loss_and_param_grads(batch, params, nl, E_ref, F_ref, w_E=1.0, w_F=1.0):
     Er = torch.as_tensor(E_ref, dtype=DT)
     Fr = torch.as_tensor(F_ref, dtype=DT)
     L = w_E / B * (((Ebar - Er) / nb) ** 2).sum() + w_F / (3 * N) * ((F - Fr) ** 2).sum()
-    grads = torch.autograd.grad(L, [p[k] for k in PARAM_NAMES] + [Ebar, F], allow_unused=True)
+    grads = torch.autograd.grad(L, [p[k] for k in PARAM_NAMES] + [Ebar, F, pos], allow_unused=True)
     out = {k: (g.detach().numpy() if g is not None else np.zeros(p[k].shape)) for k, g in zip(PARAM_NAMES, grads)}
     dLdE = grads[len(PARAM_NAMES)].detach().numpy()
     dLdF = grads[len(PARAM_NAMES) + 1].detach().numpy()
+    if want_pos:
+        return float(L.detach()), out, dLdE, dLdF, grads[len(PARAM_NAMES) + 2].detach().numpy()
     return float(L.detach()), out, dLdE, dLdF

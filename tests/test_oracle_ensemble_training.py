@@ -218,3 +218,24 @@ def test_learning_rate_schedules_at_their_defining_points():
     assert abs(lr_factor("cosine", 80, period=40, decay_factor=0.95) - 0.95 ** 2) < 1e-15
     assert abs(lr_factor("cosine", 100, period=40, decay_factor=0.95) - 0.5 * 0.95 ** 2) < 1e-15
     assert lr_factor("cosine", 39, period=40) < 1e-2
+
+
+def test_position_gradient_of_the_ensemble_loss(heads_setup):
+    """dL/dx of the ensemble loss (per-head forces inside) against five-point
+    differences along a random displacement; zero net gradient."""
+    b, p, _, Er, Fr = heads_setup
+    nl = brute_force_neighbors(b, 5.5)
+    spec = LossSpec("crps", "nll", var_floor=1e-4)
+    st = ensemble_loss_and_param_grads(b, p, nl, Er, Fr, spec)
+    assert np.abs(st.dL_dpos.sum(0)).max() < 1e-10 * max(1.0, np.abs(st.dL_dpos).max())
+    v = np.random.default_rng(6).normal(size=b.pos.shape)
+    ana = float((st.dL_dpos * v).sum())
+
+    def L(t):
+        bt = dataclasses.replace(b, pos=b.pos.astype(np.float64) + t * v)
+        s2 = ensemble_loss_and_param_grads(bt, p, nl, Er, Fr, spec)
+        return s2.loss_energy + s2.loss_force
+
+    h = 1e-4
+    fd = (8 * (L(h) - L(-h)) - (L(2 * h) - L(-2 * h))) / (12 * h)
+    assert abs(fd - ana) < 1e-6 * max(1.0, abs(ana)), (fd, ana)

@@ -68,3 +68,26 @@ def test_shift_gradient_closed_form(setup):
     assert np.allclose(g["shift"], want, rtol=1e-10, atol=1e-14)
     assert np.allclose(dLdE, 2.0 / b.n_structs * (r.energy_mean - Er) / nb ** 2, rtol=1e-10)
     assert np.allclose(dLdF, 2.0 / (3 * b.n_atoms) * (r.forces - Fr), rtol=1e-10, atol=1e-16)
+
+
+def test_position_gradient_directional_differences(setup):
+    """dL/dx against five-point differences of the loss along random position
+    displacements (list built with a skin so no pair leaves it), and zero net
+    gradient (the loss is invariant under a rigid translation)."""
+    import dataclasses
+    b, p, _, Er, Fr = setup
+    nl = brute_force_neighbors(b, 5.5)
+    _, _, _, _, gx = loss_and_param_grads(b, p, nl, Er, Fr, want_pos=True)
+    assert np.abs(gx.sum(0)).max() < 1e-10 * max(1.0, np.abs(gx).max())
+    rng = np.random.default_rng(2)
+    h = 1e-4
+    for _ in range(2):
+        v = rng.normal(size=b.pos.shape)
+        ana = float((gx * v).sum())
+
+        def L(t):
+            bt = dataclasses.replace(b, pos=b.pos.astype(np.float64) + t * v)
+            return _loss(bt, p, nl, Er, Fr)
+
+        fd = (8 * (L(h) - L(-h)) - (L(2 * h) - L(-2 * h))) / (12 * h)
+        assert abs(fd - ana) < 1e-6 * max(1.0, abs(ana)), (fd, ana)
