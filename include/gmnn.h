@@ -374,12 +374,16 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
                           void* stream, int32_t reps, gmnn_plan* best, gmnn_tune_entry* entries,
                           int32_t max_entries, int32_t* n_entries);
 
-/* Gradients of a scalar loss L(E, F) w.r.t. the model parameters, given the
- * upstream gradients dL/dE (per structure, w.r.t. the head-mean energy) and
- * dL/dF [N,3] (Section 3.4: energy + force losses; Section 3.3: forces are
- * -dE/dx, so the force term needs the mixed second derivative).  Every array
- * of `grads` is overwritten.  dL_dpos must be NULL (position gradients:
- * GMNN_ERR_UNSUPPORTED).  With GMNN_PREC_BF16 the network products of the
+/* Gradients of a scalar loss L(E, F) w.r.t. the model parameters and,
+ * optionally, the positions, given the upstream gradients dL/dE (per
+ * structure, w.r.t. the head-mean energy) and dL/dF [N,3] (Section 3.4:
+ * energy + force losses; Section 3.3: forces are -dE/dx, so the force term
+ * needs the mixed second derivative).  Every array of `grads` is
+ * overwritten.  dL_dpos (device [N,3], may be NULL) receives
+ *   dL/dx = sum_b dL/dE_b dE_b/dx + sum_k dL/dF_k . dF_k/dx,
+ * the second term a Hessian-vector product of the energy along dL/dF,
+ * evaluated per pair in dual numbers and gathered like the forces.  With
+ * GMNN_PREC_BF16 the network products of the
  * forward and reverse passes (primal and tangent rows) run in BF16 on MFMA
  * with FP32 accumulation, the operands rounded as in gmnn_energy_forces; the
  * products that form the weight gradients split each FP32 operand into a
@@ -391,8 +395,8 @@ gmnn_status gmnn_autotune(const gmnn_model* m, const gmnn_system* sys, const gmn
  * dL_dE is [B, n_heads] (dL/dE_b^m) and dL_dF [n_heads, N, 3] (dL/dF^m with
  * F^m = -dE^m/dx, eq. jacobian).  The call runs one double backward per
  * head; the gradients of the shared parameters (beta, W1, b1, W2, b2, scale,
- * shift) are added over the heads in head order, W3[:, m] and b3[m] take
- * head m's alone.
+ * shift) and of the positions are added over the heads in head order,
+ * W3[:, m] and b3[m] take head m's alone.
  *
  * The workspace must hold gmnn_workspace_bytes(GMNN_OP_BACKWARD, ..., flags)
  * for the same flags.  Recomputes the forward pass itself. */

@@ -450,7 +450,8 @@ def maxwell_boltzmann(masses, temperature: float, seed: int):
 
 # ---------------------------------------------------------------------------
 def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, workspace=None,
-                precision: str = "fp32", out=None, lanes16: bool = False, per_head: bool = False):
+                precision: str = "fp32", out=None, lanes16: bool = False, per_head: bool = False,
+                dL_dpos=None):
     """Gradients of a loss w.r.t. every model parameter (gmnn_backward), given
     dL/dE per structure (head-mean energy, float64 [B]) and dL/dF [N,3];
     precision "bf16" runs the network products of the double backward in BF16
@@ -458,6 +459,8 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
     operands (about 16 significant bits per product).  per_head: the
     upstream gradients are per head, dL/dE^m [B, heads] and dL/dF^m
     [heads, N, 3] (shallow-ensemble losses; one double backward per head).
+    dL_dpos: an FP32 device tensor [N, 3] that receives the loss's gradient
+    in the positions (may be None).
 
     `out` (a dict of FP32 device tensors shaped like model.tensors) receives
     the gradients; the call overwrites every element, so neither `out` nor a
@@ -493,8 +496,11 @@ def param_grads(model: Model, system: System, nl: NeighborList, dL_dE, dL_dF, wo
     nbytes = lib.gmnn_workspace_bytes(A.GMNN_OP_BACKWARD, C.byref(mc), C.byref(sc), C.byref(nc), flags)
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    st = lib.gmnn_backward(C.byref(mc), C.byref(sc), C.byref(nc), _ptr(dE), _ptr(dF), flags, C.byref(gc), None,
-                           _ptr(workspace), nbytes, _stream())
+    if dL_dpos is not None and (dL_dpos.dtype != torch.float32 or not dL_dpos.is_contiguous()
+                                or dL_dpos.numel() < 3 * N or dL_dpos.device.type != "cuda"):
+        raise ValueError(f"dL_dpos must be a contiguous float32 device tensor of at least [{N}, 3]")
+    st = lib.gmnn_backward(C.byref(mc), C.byref(sc), C.byref(nc), _ptr(dE), _ptr(dF), flags, C.byref(gc),
+                           None if dL_dpos is None else _ptr(dL_dpos), _ptr(workspace), nbytes, _stream())
     A.check(st, "gmnn_backward")
     return grads
 

@@ -42,10 +42,11 @@ size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
 size_t heads_backward_extra_bytes(const DevModel& m, int H1, int H2, int n_structs);
 gmnn_status train_backward_heads(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
                                  int n_structs, const double* dE, const float* dF, gmnn_param_grads* g, void* ws,
-                                 size_t ws_bytes, hipStream_t s);
+                                 size_t train_bytes, char* head_ws, size_t head_bytes, float* dL_dpos, float* gpos,
+                                 hipStream_t s);
 gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
                            const double* ebar, const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes,
-                           hipStream_t s);
+                           float* dL_dpos, float* gpos, bool accumulate_pos, hipStream_t s);
 
 constexpr int kPairThreads = 256;
 // below this many atoms the built-in plan takes the fused (latency) schedule,
@@ -435,6 +436,29 @@ gmnn_status gmnn_model_prepare(gmnn_model* m, void* stream) {
   return hipGetLastError() == hipSuccess ? GMNN_OK : GMNN_ERR_HIP;
 }
 
+}  // extern "C"
+
+// workspace of gmnn_backward: the training workspace, the per-pair gradient
+// of the positions' pass ([capacity][3]), and with GMNN_BACKWARD_PER_HEAD
+// the per-head buffers
+struct BwLayout {
+  size_t train, gpos, heads, bytes;
+};
+static BwLayout bw_layout(const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl, uint32_t flags) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const PackedLayout P = packed_layout(m->hidden1, m->hidden2, m->n_heads);
+  BwLayout L;
+  L.train = al(train_workspace_bytes(sys->n_atoms, P.HP1, m->n_species));
+  L.gpos = L.train;
+  L.heads = L.gpos + al(12 * (size_t)std::max<int64_t>(nl->capacity, 0));
+  L.bytes = L.heads + ((flags & GMNN_BACKWARD_PER_HEAD)
+                           ? heads_backward_extra_bytes(dev_model(m), m->hidden1, m->hidden2, sys->n_structs)
+                           : 0);
+  return L;
+}
+
+extern "C" {
+
 size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* sys, const gmnn_neighbors* nl,
                             uint32_t flags) {
   (void)flags;
@@ -450,11 +474,8 @@ size_t gmnn_workspace_bytes(int32_t op, const gmnn_model* m, const gmnn_system* 
     return ef_layout(m, sys, nl, flags & GMNN_PREC_BF16).bytes + ((4 * (size_t)sys->n_atoms * P.HP2 + 255) & ~size_t(255));
   }
   if (op == GMNN_OP_BACKWARD) {
-    const PackedLayout P = packed_layout(m->hidden1, m->hidden2, m->n_heads);
-    const size_t tb = train_workspace_bytes(sys->n_atoms, P.HP1, m->n_species);
-    if (!(flags & GMNN_BACKWARD_PER_HEAD)) return tb;
     if (check_model(m) != GMNN_OK) return 0;
-    return ((tb + 255) & ~size_t(255)) + heads_backward_extra_bytes(dev_model(m), m->hidden1, m->hidden2, sys->n_structs);
+    return bw_layout(m, sys, nl, flags).bytes;
   }
   return 0;
 }
@@ -893,19 +914,22 @@ gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmn
       !grads->b2 || !grads->W3 || !grads->b3 || !grads->scale || !grads->shift || !workspace)
     return GMNN_ERR_INVALID_ARG;
   if (nl->cutoff + 1e-6f < m->r_cut) return GMNN_ERR_INVALID_ARG;
-  // positions gradients are not produced
-  if ((flags & GMNN_WANT_FORCE_VAR) || dL_dpos) return GMNN_ERR_UNSUPPORTED;
+  if (flags & GMNN_WANT_FORCE_VAR) return GMNN_ERR_UNSUPPORTED;
   const DevModel dm = dev_model(m);
   if (!train_supported(dm)) return GMNN_ERR_UNSUPPORTED;
+  const BwLayout L = bw_layout(m, sys, nl, flags);
+  if (workspace_bytes < L.bytes) return GMNN_ERR_WORKSPACE;
   const DevSystem ds = dev_system(sys, nl);
   hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)workspace;
+  float* gpos = (float*)(W + L.gpos);
   const bool bf16 = (flags & GMNN_PREC_BF16) != 0, lanes16 = (flags & GMNN_BACKWARD_LANES16) != 0;
   if (flags & GMNN_BACKWARD_PER_HEAD)
     st = train_backward_heads(dm, ds, bf16, lanes16, m->hidden1, m->hidden2, sys->n_structs, dL_dE, dL_dF, grads,
-                              workspace, workspace_bytes, s);
+                              W, L.train, W + L.heads, L.bytes - L.heads, dL_dpos, gpos, s);
   else
-    st = train_backward(dm, ds, bf16, lanes16, m->hidden1, m->hidden2, dL_dE, dL_dF, grads, workspace,
-                        workspace_bytes, s);
+    st = train_backward(dm, ds, bf16, lanes16, m->hidden1, m->hidden2, dL_dE, dL_dF, grads, W, L.train, dL_dpos,
+                        gpos, false, s);
   if (st != GMNN_OK) return st;
   if ((flags & GMNN_SYNC) && hipStreamSynchronize(s) != hipSuccess) return GMNN_ERR_HIP;
   return GMNN_OK;

@@ -215,8 +215,7 @@ __global__ void __launch_bounds__(256) head_accumulate(GradSegs g, int h, int M)
 
 gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
                            const double* ebar, const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes,
-                           hipStream_t s);
-size_t train_workspace_bytes(int n_atoms, int HP, int nsp);
+                           float* dL_dpos, float* gpos, bool accumulate_pos, hipStream_t s);
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -243,14 +242,15 @@ size_t heads_backward_extra_bytes(const DevModel& m, int H1, int H2, int n_struc
 
 // one double backward per head (gmnn_backward with GMNN_BACKWARD_PER_HEAD):
 // head h sees the model with W3[:, h], b3[h] alone, dL/dE[:, h] and
-// dL/dF[h]; the extra workspace after the training workspace holds the
-// head's gradients, its W3 column and its dL/dE column
+// dL/dF[h]; head_ws holds the head's gradients, its W3 column and its dL/dE
+// column.  The positions' gradient (dL_dpos, optional) is summed over the
+// heads in head order.
 gmnn_status train_backward_heads(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
                                  int n_structs, const double* dE, const float* dF, gmnn_param_grads* g, void* ws,
-                                 size_t ws_bytes, hipStream_t s) {
-  const size_t tb = align256(train_workspace_bytes(sys.n_atoms, m.HP1, m.n_species));
-  if (ws_bytes < tb + heads_backward_extra_bytes(m, H1, H2, n_structs)) return GMNN_ERR_WORKSPACE;
-  char* X = (char*)ws + tb;
+                                 size_t train_bytes, char* head_ws, size_t head_bytes, float* dL_dpos, float* gpos,
+                                 hipStream_t s) {
+  if (head_bytes < heads_backward_extra_bytes(m, H1, H2, n_structs)) return GMNN_ERR_WORKSPACE;
+  char* X = head_ws;
   int64_t n[9];
   head_grad_sizes(m, H1, H2, n);
   float* tmp[9];
@@ -282,7 +282,8 @@ gmnn_status train_backward_heads(const DevModel& m, const DevSystem& sys, bool b
     mh.w3 = w3h;
     mh.w3bar = w3h;
     mh.b3 = m.b3 + h;
-    const gmnn_status st = train_backward(mh, sys, bf16, lanes16, H1, H2, dEh, dF + h * n3, &hg, ws, tb, s);
+    const gmnn_status st =
+        train_backward(mh, sys, bf16, lanes16, H1, H2, dEh, dF + h * n3, &hg, ws, train_bytes, dL_dpos, gpos, h > 0, s);
     if (st != GMNN_OK) return st;
     const int nb = (int)std::min<int64_t>((nmax + 255) / 256, 512);
     hipLaunchKernelGGL(head_accumulate, dim3(nb, 9), dim3(256), 0, s, segs, h, M);

@@ -565,6 +565,213 @@ __global__ void __launch_bounds__(kBetaMaxThreads) pair_beta_grad(DevModel m, De
 }
 
 // ---------------------------------------------------------------------------
+// Gradient of Phi in the positions (the loss's dL/dx, Section 3.3).  Phi
+// depends on the pair vectors d_p through Psi_i (adjoint Psibar_i) and
+// through Psidot_i = sum_p dPsi_i/dd_p . delta_p (adjoint Psidotbar_i), so
+//   dPhi/dd_p = grad phi_{Psibar}(d_p) + D_delta grad phi_{Psidotbar}(d_p),
+// phi_w(d) = sum_s R_s(|d|) sum_t w[s][t] mono_t(d/|d|) being the pair's
+// moment contribution contracted with w.  The first term is the pair
+// backward of the energy; the second, a Hessian-vector product, is the
+// same gradient evaluated in dual numbers (value, derivative along
+// delta_p), which needs R_s'' besides R_s and R_s'.  The positions' gradient
+// then gathers these over the reverse index like the forces.
+struct Dual {
+  float v, t;
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.t + b.t}; }
+__device__ inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.t - b.t}; }
+__device__ inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.v * b.t + a.t * b.v}; }
+__device__ inline Dual operator*(float a, Dual b) { return {a * b.v, a * b.t}; }
+__device__ inline Dual operator*(Dual a, float b) { return {a.v * b, a.t * b}; }
+__device__ inline Dual& operator+=(Dual& a, Dual b) { a.v += b.v; a.t += b.t; return a; }
+
+// R_s, dR_s/dr and d^2R_s/dr^2 (the basis and cutoff of radial<true>):
+//   Gaussians    g_k'' = (4 gamma^2 (r - mu_k)^2 - 2 gamma) g_k
+//   Bessel-like  d^2/dr^2 sinc(k x) = -(k pi / r_c)^2 sinc(k x) - 2 (cos(k x) - sinc(k x)) / r^2
+//   cutoff       f_c'' = -(pi / r_c)^2 cos(pi r / r_c) / 2
+template <int BASIS>
+__device__ inline void radial2(const DevModel& m, const float* __restrict__ bz, float r, float (&R)[kS],
+                               float (&dR)[kS], float (&d2R)[kS]) {
+  float sn, cs;
+  cutoff_cos_sin(m, r, cs, sn);
+  const float w = 3.14159265358979f / m.r_cut;
+  const float fc = 0.5f * (cs + 1.0f) * m.psi_scale;
+  const float dfc = -0.5f * w * sn * m.psi_scale;
+  const float d2fc = -0.5f * w * w * cs * m.psi_scale;
+  float g[kMaxBasis], dg[kMaxBasis], d2g[kMaxBasis];
+  if (BASIS == GMNN_BASIS_BESSEL) {
+    const float ir = 1.0f / r;
+    const float ix = m.rc_over_pi * ir;
+    float sa = sn, ca = cs;
+    float sb = 2.0f * cs * sn, cb = 2.0f * cs * cs - 1.0f;
+    float sinc_a = sa * ix;
+#pragma unroll
+    for (int n = 0; n < kMaxBasis; ++n) {
+      const float ka = (float)(n + 1) * w, kb = (float)(n + 2) * w;
+      const float sinc_b = sb * ix * (1.0f / (float)(n + 2));
+      g[n] = m.ck[n] * (sinc_a + sinc_b);
+      dg[n] = m.ck[n] * ((ca - sinc_a) + (cb - sinc_b)) * ir;
+      d2g[n] = m.ck[n] * (-(ka * ka) * sinc_a - (kb * kb) * sinc_b - 2.0f * ((ca - sinc_a) + (cb - sinc_b)) * ir * ir);
+      const float sc = 2.0f * cs * sb - sa, cc = 2.0f * cs * cb - ca;
+      sa = sb; ca = cb; sb = sc; cb = cc;
+      sinc_a = sinc_b;
+    }
+  } else {
+    const float tau = r - m.r_min;
+    const float g0 = __expf(-m.gamma * tau * tau);
+    const float a = __expf(2.0f * m.gamma * m.delta * tau);
+    float p = g0;
+#pragma unroll
+    for (int k = 0; k < kMaxBasis; ++k) {
+      const float e = tau - (float)k * m.delta;  // r - mu_k
+      g[k] = p * m.ck[k];
+      dg[k] = -2.0f * m.gamma * e * g[k];
+      d2g[k] = (4.0f * m.gamma * m.gamma * e * e - 2.0f * m.gamma) * g[k];
+      p *= a;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    float B = 0.0f, dB = 0.0f, d2B = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxBasis; ++k) {
+      const float bk = bz[s * kMaxBasis + k];
+      B += bk * g[k];
+      dB += bk * dg[k];
+      d2B += bk * d2g[k];
+    }
+    R[s] = fc * B;
+    dR[s] = dfc * B + fc * dB;
+    d2R[s] = d2fc * B + 2.0f * dfc * dB + fc * d2B;
+  }
+}
+
+// grad phi_w at the pair in dual numbers: pair_gradient's formula,
+//   g = (sum_s dR_s P_s(u)) u + (grad Q - (grad Q . u) u) / r,
+// with u, 1/r, R_s, dR_s carrying their derivatives along delta
+__device__ inline void pair_gradient_dual(const float* __restrict__ w, const Dual (&R)[kS], const Dual (&dR)[kS],
+                                          Dual x, Dual y, Dual z, Dual ir, Dual& gx, Dual& gy, Dual& gz) {
+  Dual mo[kPacked];
+  mo[0] = {1.0f, 0.0f};
+  mo[1] = x; mo[2] = y; mo[3] = z;
+  mo[4] = x * x; mo[5] = x * y; mo[6] = x * z; mo[7] = y * y; mo[8] = y * z; mo[9] = z * z;
+  mo[10] = mo[4] * x; mo[11] = mo[4] * y; mo[12] = mo[4] * z; mo[13] = mo[7] * x; mo[14] = mo[5] * z;
+  mo[15] = mo[9] * x; mo[16] = mo[7] * y; mo[17] = mo[7] * z; mo[18] = mo[9] * y; mo[19] = mo[9] * z;
+  Dual radial_part = {0.0f, 0.0f};
+  Dual qc[kPacked];
+#pragma unroll
+  for (int t = 0; t < kPacked; ++t) qc[t] = {0.0f, 0.0f};
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    Dual A = {0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < kPacked; ++t) {
+      A += w[s * kPacked + t] * mo[t];
+      qc[t] += R[s] * w[s * kPacked + t];
+    }
+    radial_part += A * dR[s];
+  }
+  const Dual Gx = qc[1] + 2.0f * qc[4] * x + qc[5] * y + qc[6] * z + 3.0f * qc[10] * x * x + 2.0f * qc[11] * x * y +
+                  2.0f * qc[12] * x * z + qc[13] * y * y + qc[14] * y * z + qc[15] * z * z;
+  const Dual Gy = qc[2] + qc[5] * x + 2.0f * qc[7] * y + qc[8] * z + qc[11] * x * x + 2.0f * qc[13] * x * y +
+                  qc[14] * x * z + 3.0f * qc[16] * y * y + 2.0f * qc[17] * y * z + qc[18] * z * z;
+  const Dual Gz = qc[3] + qc[6] * x + qc[8] * y + 2.0f * qc[9] * z + qc[12] * x * x + qc[14] * x * y +
+                  2.0f * qc[15] * x * z + qc[17] * y * y + 2.0f * qc[18] * y * z + 3.0f * qc[19] * z * z;
+  const Dual gu = Gx * x + Gy * y + Gz * z;
+  gx = radial_part * x + (Gx - gu * x) * ir;
+  gy = radial_part * y + (Gy - gu * y) * ir;
+  gz = radial_part * z + (Gz - gu * z) * ir;
+}
+
+constexpr int kPosLanes = 64;  // lanes per atom row of the position-gradient kernels
+
+// dPhi/dd_p for every pair (gpos [P][3]); one 64-lane group per atom
+template <int BASIS>
+__global__ void __launch_bounds__(kPairBlock) pair_pos_grad(DevModel m, DevSystem sys, const float* __restrict__ lambda,
+                                                            const float* __restrict__ psibar,
+                                                            const float* __restrict__ psidotbar,
+                                                            float* __restrict__ gpos) {
+  extern __shared__ float s_beta[];
+  stage_beta(m, s_beta);
+  __syncthreads();
+  const int q = threadIdx.x & (kPosLanes - 1);
+  const int i = blockIdx.x * (kPairBlock / kPosLanes) + threadIdx.x / kPosLanes;
+  if (i >= sys.n_atoms) return;
+  AtomCtx c;
+  load_atom(sys, i, c);
+  const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
+  const float* pb = psibar + (int64_t)i * (kS * kPacked);
+  const float* pd = psidotbar + (int64_t)i * (kS * kPacked);
+  const float lix = lambda[3 * (int64_t)i], liy = lambda[3 * (int64_t)i + 1], liz = lambda[3 * (int64_t)i + 2];
+  for (int64_t p = c.p0 + q; p < c.p1; p += kPosLanes) {
+    int j;
+    float dx, dy, dz;
+    pair_vec(sys, c, p, j, dx, dy, dz);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    if (r2 < m.rc2 && r2 > 0.0f) {
+      float r, ir;
+      length_of(r2, r, ir);
+      const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+      const float* bz = bzi + sys.species[j] * kS * kMaxBasis;
+      // the energy's pair gradient with Psibar
+      Radial rad;
+      radial<true>(m, bz, r, rad);
+      float mo[20];
+      monomials(ux, uy, uz, mo);
+      pair_gradient(pb, rad, mo, ux, uy, uz, ir, gx, gy, gz);
+      // its derivative along delta_p with Psidotbar
+      const float ex = lambda[3 * (int64_t)j] - lix, ey = lambda[3 * (int64_t)j + 1] - liy,
+                  ez = lambda[3 * (int64_t)j + 2] - liz;
+      const float rdot = ux * ex + uy * ey + uz * ez;  // d|d|/dt
+      float R[kS], dR[kS], d2R[kS];
+      radial2<BASIS>(m, bz, r, R, dR, d2R);
+      Dual Rd[kS], dRd[kS];
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+        Rd[s] = {R[s], dR[s] * rdot};
+        dRd[s] = {dR[s], d2R[s] * rdot};
+      }
+      const Dual xd = {ux, (ex - ux * rdot) * ir}, yd = {uy, (ey - uy * rdot) * ir}, zd = {uz, (ez - uz * rdot) * ir};
+      const Dual ird = {ir, -rdot * ir * ir};
+      Dual hx, hy, hz;
+      pair_gradient_dual(pd, Rd, dRd, xd, yd, zd, ird, hx, hy, hz);
+      gx += hx.t;
+      gy += hy.t;
+      gz += hz.t;
+    }
+    gpos[3 * p] = gx;
+    gpos[3 * p + 1] = gy;
+    gpos[3 * p + 2] = gz;
+  }
+}
+
+// dL/dx_i = sum over the row of (gpos[rev p] - gpos[p]) (added to dL_dpos
+// with accumulate, for the per-head sum)
+__global__ void __launch_bounds__(kPairBlock) pos_gather(DevSystem sys, const float* __restrict__ gpos,
+                                                         float* __restrict__ dL_dpos, int accumulate) {
+  const int q = threadIdx.x & (kPosLanes - 1);
+  const int i = blockIdx.x * (kPairBlock / kPosLanes) + threadIdx.x / kPosLanes;
+  const bool live = i < sys.n_atoms;
+  float f[3] = {0.0f, 0.0f, 0.0f};
+  if (live) {
+    const int64_t p0 = sys.row_ptr[i], p1 = sys.row_ptr[i + 1];
+    for (int64_t p = p0 + q; p < p1; p += kPosLanes) {
+      const int64_t rp = sys.rev[p];
+      f[0] += gpos[3 * rp] - gpos[3 * p];
+      f[1] += gpos[3 * rp + 1] - gpos[3 * p + 1];
+      f[2] += gpos[3 * rp + 2] - gpos[3 * p + 2];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[k] = atom_sum<kPosLanes>(f[k]);
+  if (live && q == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dL_dpos[3 * (int64_t)i + k] = accumulate ? dL_dpos[3 * (int64_t)i + k] + f[k] : f[k];
+}
+
+// ---------------------------------------------------------------------------
 // C[M][N] = sum_k A[k][M]^T B[k][N] over the rows k of chunk blockIdx.y
 // (split-K; partial[chunk][M][N]).  Each wave owns a 64 x 64 block of C as
 // 4 x 4 MFMA tiles, so every value loaded feeds four (SPLIT: twelve) MFMAs.
@@ -1078,7 +1285,7 @@ size_t train_workspace_bytes(int n_atoms, int HP, int nsp) { return train_layout
 
 gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, bool lanes16, int H1, int H2,
                            const double* ebar, const float* lambda, gmnn_param_grads* g, void* ws, size_t ws_bytes,
-                           hipStream_t s) {
+                           float* dL_dpos, float* gpos, bool accumulate_pos, hipStream_t s) {
   const int HP = m.HP1;
   const int nsp = m.n_species;
   const TrainLayout L = train_layout(sys.n_atoms, HP, nsp);
@@ -1129,6 +1336,15 @@ gmnn_status train_backward(const DevModel& m, const DevSystem& sys, bool bf16, b
       default: return GMNN_ERR_UNSUPPORTED;
     }
     if (st != GMNN_OK) return st;
+  }
+  if (dL_dpos && N > 0) {
+    // the positions' gradient from the same adjoints as the beta gradient
+    const int nbp = (N + kPairBlock / kPosLanes - 1) / (kPairBlock / kPosLanes);
+    auto kp = m.basis == GMNN_BASIS_BESSEL ? pair_pos_grad<GMNN_BASIS_BESSEL> : pair_pos_grad<GMNN_BASIS_GAUSSIAN>;
+    const gmnn_status sp = ensure_lds_limit((const void*)kp, beta_lds);
+    if (sp != GMNN_OK) return sp;
+    hipLaunchKernelGGL(kp, dim3(nbp), dim3(kPairBlock), beta_lds, s, m, sys, lambda, psibar, psidotbar, gpos);
+    hipLaunchKernelGGL(pos_gather, dim3(nbp), dim3(kPairBlock), 0, s, sys, gpos, dL_dpos, accumulate_pos ? 1 : 0);
   }
   // waves per block: the beta table plus one gradient copy per wave in 160 KB
   const int beta_waves = (int)std::min<size_t>(kBetaMaxThreads / 64, std::max<size_t>(1, 160 * 1024 / beta_lds - 1));

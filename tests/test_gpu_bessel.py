@@ -79,3 +79,22 @@ def test_bessel_param_gradients_match_oracle():
         got = grads[k].cpu().numpy().astype(np.float64).reshape(np.shape(gref[k]))
         err = np.linalg.norm(got - gref[k]) / max(np.linalg.norm(gref[k]), 1e-30)
         assert err < 1e-4, (k, err)
+
+
+def test_bessel_position_gradients_match_oracle():
+    """The Hessian-vector product of the positions' gradient with the
+    Bessel-like basis (its second radial derivatives)."""
+    g = need_gpu()
+    batch, params, spec = _bessel("train", hidden=(64, 64), n_structs=3, n_lo=30, n_hi=70)
+    teacher = make_params(spec, 121)
+    onl = brute_force_neighbors(batch, spec.r_cut)
+    rt = evaluate(batch, teacher, onl)
+    L, gref, dLdE, dLdF, gx = loss_and_param_grads(batch, params, onl, rt.energy_mean, rt.forces, want_pos=True)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, spec.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    dpos = torch.empty((batch.n_atoms, 3), dtype=torch.float32, device="cuda")
+    g.param_grads(model, system, nl, dLdE, dLdF, dL_dpos=dpos)
+    torch.cuda.synchronize()
+    got = dpos.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - gx) / np.linalg.norm(gx) < 1e-4

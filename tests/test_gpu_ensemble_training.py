@@ -195,3 +195,17 @@ def test_training_step_matches_oracle(kind):
         clear = np.abs(ref.grads[k]) > 1e-3 * np.abs(ref.grads[k]).max()
         assert np.all(np.abs(got - p[k])[clear] <= 1e-6 + 1e-6 * np.abs(p[k])[clear]), k
         assert np.all(np.abs(got - start[k]) <= 1.0001e-3 + 1e-6 * np.abs(start[k])), k
+
+
+def test_per_head_position_gradients_match_oracle():
+    """dL/dx of the ensemble loss: the positions' gradients of the per-head
+    double backwards summed in head order, against the oracle's."""
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(n_structs=3, n_lo=30, n_hi=60)
+    ref = ensemble_loss_and_param_grads(batch, params, onl, Er, Fr, OracleLoss("crps", "nll", var_floor=1e-4))
+    system, nl, model = _setup(g, batch, params)
+    dpos = torch.empty((batch.n_atoms, 3), dtype=torch.float32, device="cuda")
+    g.param_grads(model, system, nl, ref.dL_dE, ref.dL_dF, per_head=True, dL_dpos=dpos)
+    torch.cuda.synchronize()
+    got = dpos.cpu().numpy().astype(np.float64)
+    assert _rel(got, ref.dL_dpos) < 1e-4, _rel(got, ref.dL_dpos)

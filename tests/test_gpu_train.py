@@ -191,3 +191,39 @@ def test_param_gradients_sixteen_lanes_per_row():
         assert e16 < 1e-4, (k, e16)
         d = np.linalg.norm((g16[k] - g64[k]).double().cpu().numpy()) / nrm
         assert d < 1e-5, (k, d)
+
+
+def _pos_err(got, ref):
+    got = got.cpu().numpy().astype(np.float64)[: ref.shape[0]]
+    return np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30), np.abs(got - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("hidden,kw,lanes16", [((32, 32), dict(n_structs=3, n_lo=30, n_hi=70), False),
+                                                ((512, 512), dict(n_structs=2, n_lo=40, n_hi=60), False),
+                                                ((64, 64), dict(n_structs=2, n_lo=330, n_hi=400), False),
+                                                ((64, 64), dict(n_structs=3, n_lo=30, n_hi=70), True)])
+def test_position_gradients_match_oracle(hidden, kw, lanes16):
+    """dL/dx (gmnn_backward's dL_dpos: the energy term plus the Hessian-vector
+    product along dL/dF) against the oracle's autograd gradient: FP32 within
+    1e-4 relative l2 and 1e-3 of the largest entry element by element;
+    the parameter gradients of the same call unchanged."""
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(hidden=hidden, **kw)
+    L, gref, dLdE, dLdF, gx = loss_and_param_grads(batch, params, onl, Er, Fr, want_pos=True)
+    system = g.System.from_batch(batch, "cuda")
+    nl = g.build_neighbors(system, params.spec.r_cut)
+    model = g.Model.from_params(params, "cuda")
+    dpos = torch.full((batch.n_atoms, 3), float("nan"), dtype=torch.float32, device="cuda")
+    grads = g.param_grads(model, system, nl, dLdE, dLdF, lanes16=lanes16, dL_dpos=dpos)
+    plain = g.param_grads(model, system, nl, dLdE, dLdF, lanes16=lanes16)
+    torch.cuda.synchronize()
+    rel, mx = _pos_err(dpos, gx)
+    print(f"{hidden} N={batch.n_atoms} lanes16={lanes16}: dL/dx rel l2 {rel:.2e}, max {mx:.2e}")
+    assert rel < 1e-4 and mx < 1e-3, (rel, mx)
+    for k in PARAM_NAMES:
+        assert torch.equal(grads[k], plain[k]), k
+    dp16 = torch.empty_like(dpos)
+    g.param_grads(model, system, nl, dLdE, dLdF, lanes16=lanes16, dL_dpos=dp16, precision="bf16")
+    torch.cuda.synchronize()
+    rel16, _ = _pos_err(dp16, gx)
+    assert rel16 < 3e-2, rel16
