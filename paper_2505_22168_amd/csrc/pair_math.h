@@ -546,4 +546,200 @@ __device__ inline void atom_pair_backward_heads(const DevModel& m, const DevSyst
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compacted pair loops (split schedule).  A list built with a skin holds
+// pairs beyond r_c (about a third of them at r_c 6 A + 1 A skin); in a
+// lane-per-pair loop their lanes would idle through the whole pair
+// computation.  Here each group of LPA lanes tests LPA candidates at a time
+// and appends the pairs inside r_c to the group's LDS ring of kRingBatches
+// LPA entries (ballot and prefix count, in candidate order).  The pair
+// computation runs on queued pairs when every group of the wave still in its
+// row has LPA of them (a full batch each: the wave's lanes all busy), or
+// when some group's ring could not take another chunk; the remainder runs
+// after the row.  The decision is wave-wide because the wave executes the
+// computation whenever any of its groups does.  A ring entry is (d, tag),
+// tag = zj | (p - p0) << 5.  The ring stays within one wave (the group's
+// lanes), so wave-level ordering of its LDS accesses is all it needs.
+constexpr int kRingTagBits = 5;  // species index bits of a ring tag (kMaxSpecies <= 32)
+constexpr int kRingBatches = 4;  // ring entries per lane of a group
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// the group's bits of a wave ballot, bit q = lane q of the group
+template <int LPA>
+__device__ inline uint64_t group_ballot(bool v) {
+  const uint64_t bal = __ballot(v);
+  if (LPA == 64) return bal;
+  const int shift = lane_id() & (64 - LPA);
+  return (bal >> shift) & ((1ull << LPA) - 1ull);
+}
+
+// Candidate chunks are fetched ahead: the pair backward keeps the neighbour
+// positions and species of chunk k + 1 and the neighbour indices of chunk
+// k + 2 in flight while chunk k is tested; the moments (short of registers)
+// the indices of chunk k + 1 only.
+struct Cand {
+  float x, y, z;
+  int sp;
+  int32_t sh;
+};
+struct CandIdx {
+  int j;
+  int32_t sh;
+};
+__device__ __forceinline__ CandIdx cand_index(const DevSystem& sys, const AtomCtx& c, int64_t p) {
+  CandIdx r{0, 0};
+  if (p < c.p1) {
+    r.j = sys.nj[p];
+    r.sh = sys.nshift[p];
+  }
+  return r;
+}
+__device__ __forceinline__ Cand cand_fetch(const DevSystem& sys, const AtomCtx& c, int64_t p, CandIdx ix) {
+  Cand r{0.0f, 0.0f, 0.0f, 0, ix.sh};
+  if (p < c.p1) {
+    r.x = sys.pos[3 * (int64_t)ix.j];
+    r.y = sys.pos[3 * (int64_t)ix.j + 1];
+    r.z = sys.pos[3 * (int64_t)ix.j + 2];
+    r.sp = sys.species[ix.j];
+  }
+  return r;
+}
+
+// one candidate chunk: lane q tests pair pc + q (its neighbour fetched
+// ahead); accepted pairs are appended to the ring (tail advances by their
+// count); rejected ones inside the row are reported through `rejected`.
+// Flags as atom_moments_from raises them.
+template <int LPA>
+__device__ __forceinline__ void ring_append(const DevModel& m, const DevSystem& sys, const AtomCtx& c, int q,
+                                            int64_t pc, const Cand& cd, float4* __restrict__ ring, int& tail,
+                                            bool& rejected) {
+  const bool have = pc + q < c.p1;
+  bool ok = false;
+  float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+  if (have) {
+    pair_vec_of(c, cd.x, cd.y, cd.z, cd.sh, dx, dy, dz);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    ok = r2 < m.rc2 && r2 > 0.0f;
+    if (sys.status && r2 == 0.0f) raise_flag(sys.status, GMNN_FLAG_COINCIDENT);
+    if (sys.status && !(r2 <= 3.402823466e38f)) raise_flag(sys.status, GMNN_FLAG_NONFINITE);
+  }
+  rejected = have && !ok;
+  const uint64_t gb = group_ballot<LPA>(ok);
+  const int pre = __popcll(gb & ((1ull << q) - 1ull));
+  if (ok)
+    ring[(tail + pre) & (kRingBatches * LPA - 1)] =
+        make_float4(dx, dy, dz, __int_as_float(cd.sp | (int)(pc + q - c.p0) << kRingTagBits));
+  tail += __popcll(gb);
+  wave_lds_sync();
+}
+
+// one batch of queued pairs if the wave-wide rule calls for it (or always,
+// with `flush`, for the remainder after the row): each group takes up to LPA
+// entries, lane q the q-th
+template <int LPA, class F>
+__device__ __forceinline__ void ring_drain(int q, const float4* __restrict__ ring, int& head, int tail, bool flush,
+                                           F&& process) {
+  const int avail = tail - head;
+  if (!flush) {
+    const bool some_short = __ballot(avail < LPA) != 0;
+    const bool some_full = __ballot(avail > (kRingBatches - 1) * LPA) != 0;
+    if (some_short && !some_full) return;
+  }
+  const int take = avail < LPA ? avail : LPA;
+  if (q < take) process(ring[(head + q) & (kRingBatches * LPA - 1)]);
+  head += take;
+  wave_lds_sync();
+}
+
+// moment partial sums of lane q of an atom over the pairs inside r_c (the
+// accumulation of atom_moments_from, on compacted pairs)
+template <int LPA>
+__device__ inline void atom_moments_compact(const DevModel& m, const DevSystem& sys, const float* __restrict__ s_beta,
+                                            const AtomCtx& c, int q, float4* __restrict__ ring, float (&v)[128]) {
+  const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
+  auto process = [&](float4 e) {
+    const float dx = e.x, dy = e.y, dz = e.z;
+    const int zj = __float_as_int(e.w) & ((1 << kRingTagBits) - 1);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    float r, ir;
+    length_of(r2, r, ir);
+    Radial rad;
+    radial<false>(m, bzi + zj * kS * kMaxBasis, r, rad);
+    float mo[20];
+    monomials(dx * ir, dy * ir, dz * ir, mo);
+#pragma unroll
+    for (int s = 0; s < kS; ++s)
+#pragma unroll
+      for (int t = 0; t < kPacked; ++t) v[s * kPacked + t] += rad.R[s] * mo[t];
+  };
+  // one stage of prefetch only (the neighbour indices of the next chunk): the
+  // deeper pipeline of the backward costs this kernel a wave per SIMD
+  int head = 0, tail = 0;
+  CandIdx nxt = cand_index(sys, c, c.p0 + q);
+  for (int64_t pc = c.p0; pc < c.p1; pc += LPA) {
+    const Cand cd = cand_fetch(sys, c, pc + q, nxt);
+    nxt = cand_index(sys, c, pc + LPA + q);
+    bool rejected;
+    ring_append<LPA>(m, sys, c, q, pc, cd, ring, tail, rejected);
+    ring_drain<LPA>(q, ring, head, tail, false, process);
+  }
+  while (tail > head) ring_drain<LPA>(q, ring, head, tail, true, process);
+}
+
+// dE/dd_p for every pair of an atom's row on compacted pairs (the arithmetic
+// of atom_pair_backward): pairs outside r_c get g_p = 0 at once, the others
+// when their batch runs.  Accumulates lane q's share of the virial.
+template <int LPA>
+__device__ inline void atom_pair_backward_compact(const DevModel& m, const DevSystem& sys,
+                                                  const float* __restrict__ s_beta, const AtomCtx& c, int q,
+                                                  const float (&pb)[kS * kPacked], float4* __restrict__ ring,
+                                                  float* __restrict__ gpair, float (&vir)[9]) {
+  const float* bzi = s_beta + c.zsp * m.n_species * kS * kMaxBasis;
+  auto process = [&](float4 e) {
+    const float dx = e.x, dy = e.y, dz = e.z;
+    const int tag = __float_as_int(e.w);
+    const int zj = tag & ((1 << kRingTagBits) - 1);
+    const int64_t p = c.p0 + (tag >> kRingTagBits);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    float r, ir;
+    length_of(r2, r, ir);
+    const float ux = dx * ir, uy = dy * ir, uz = dz * ir;
+    Radial rad;
+    radial<true>(m, bzi + zj * kS * kMaxBasis, r, rad);
+    float mo[20];
+    monomials(ux, uy, uz, mo);
+    float gx, gy, gz;
+    pair_gradient(pb, rad, mo, ux, uy, uz, ir, gx, gy, gz);
+    vir[0] += gx * dx; vir[1] += gx * dy; vir[2] += gx * dz;
+    vir[3] += gy * dx; vir[4] += gy * dy; vir[5] += gy * dz;
+    vir[6] += gz * dx; vir[7] += gz * dy; vir[8] += gz * dz;
+    gpair[3 * p] = gx;
+    gpair[3 * p + 1] = gy;
+    gpair[3 * p + 2] = gz;
+  };
+  int head = 0, tail = 0;
+  Cand cur = cand_fetch(sys, c, c.p0 + q, cand_index(sys, c, c.p0 + q));
+  CandIdx nxt = cand_index(sys, c, c.p0 + LPA + q);
+  for (int64_t pc = c.p0; pc < c.p1; pc += LPA) {
+    const Cand cd = cur;
+    cur = cand_fetch(sys, c, pc + LPA + q, nxt);
+    nxt = cand_index(sys, c, pc + 2 * LPA + q);
+    bool rejected;
+    ring_append<LPA>(m, sys, c, q, pc, cd, ring, tail, rejected);
+    if (rejected) {
+      const int64_t p = pc + q;
+      gpair[3 * p] = 0.0f;
+      gpair[3 * p + 1] = 0.0f;
+      gpair[3 * p + 2] = 0.0f;
+    }
+    ring_drain<LPA>(q, ring, head, tail, false, process);
+  }
+  while (tail > head) ring_drain<LPA>(q, ring, head, tail, true, process);
+}
+
 }  // namespace gmnn

@@ -19,6 +19,8 @@
 // Each atom row is processed by LPA lanes (8, 16, 32 or 64: eight, four, two or
 // one atom per wave, chosen by the execution plan); the 100 moment accumulators of a lane are
 // combined by a reduce-scatter (permlane swaps and DPP, no LDS, no atomics).
+// pair_moments and pair_backward take the row's pairs inside r_c only, queued
+// per lane group in LDS (the list's skin pairs do not occupy lanes).
 #include "common.h"
 #include "model.h"
 #include "pair_math.h"
@@ -41,10 +43,15 @@ __global__ void __launch_bounds__(kPairBlock) pair_moments(DevModel m, DevSystem
   const int q = threadIdx.x & (LPA - 1);
   const int i = xcd_block(blockIdx.x, gridDim.x) * (kPairBlock / LPA) + threadIdx.x / LPA;
   const bool live = i < sys.n_atoms;
+  __shared__ float4 s_ring[kRingBatches * kPairBlock];  // per LPA-lane group: kRingBatches LPA queued pairs
   float v[128];
 #pragma unroll
   for (int k = 0; k < 128; ++k) v[k] = 0.0f;
-  if (live) atom_moments<LPA>(m, sys, s_beta, i, q, v);
+  if (live) {
+    AtomCtx c;
+    load_atom(sys, i, c);
+    atom_moments_compact<LPA>(m, sys, s_beta, c, q, s_ring + (threadIdx.x / LPA) * kRingBatches * LPA, v);
+  }
   reduce_scatter_128<LPA>(v, q);
   constexpr int OWN = 128 / LPA;
   if (live) {
@@ -68,6 +75,7 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
   const int q = threadIdx.x & (LPA - 1);
   const int i = xcd_block(blockIdx.x, gridDim.x) * (kPairBlock / LPA) + threadIdx.x / LPA;
   const bool live = i < sys.n_atoms;
+  __shared__ float4 s_ring[kRingBatches * kPairBlock];  // per LPA-lane group: kRingBatches LPA queued pairs
   float vir[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) vir[k] = 0.0f;
@@ -76,7 +84,9 @@ __global__ void __launch_bounds__(kPairBlock) pair_backward(DevModel m, DevSyste
     const float* src = psibar + (int64_t)i * (kS * kPacked);
 #pragma unroll
     for (int k = 0; k < kS * kPacked; ++k) pb[k] = src[k];
-    atom_pair_backward<LPA>(m, sys, s_beta, i, q, pb, gpair, vir);
+    AtomCtx c;
+    load_atom(sys, i, c);
+    atom_pair_backward_compact<LPA>(m, sys, s_beta, c, q, pb, s_ring + (threadIdx.x / LPA) * kRingBatches * LPA, gpair, vir);
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) vir[k] = atom_sum<LPA>(vir[k]);
