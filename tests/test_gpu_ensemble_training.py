@@ -209,3 +209,22 @@ def test_per_head_position_gradients_match_oracle():
     torch.cuda.synchronize()
     got = dpos.cpu().numpy().astype(np.float64)
     assert _rel(got, ref.dL_dpos) < 1e-4, _rel(got, ref.dL_dpos)
+
+
+@pytest.mark.parametrize("lanes16", [False, True])
+def test_per_head_backward_multi_chunk(lanes16):
+    """Above 600 atoms (several split-K chunks and species blocks per head)
+    and with the 16-lane pair kernels: per-head parameter and position
+    gradients against the oracle."""
+    g = need_gpu()
+    batch, params, onl, Er, Fr = _case(n_structs=2, n_lo=330, n_hi=400)
+    assert batch.n_atoms > 600
+    ref = ensemble_loss_and_param_grads(batch, params, onl, Er, Fr, OracleLoss("crps", "crps", var_floor=1e-6))
+    system, nl, model = _setup(g, batch, params)
+    dpos = torch.empty((batch.n_atoms, 3), dtype=torch.float32, device="cuda")
+    grads = g.param_grads(model, system, nl, ref.dL_dE, ref.dL_dF, per_head=True, lanes16=lanes16, dL_dpos=dpos)
+    torch.cuda.synchronize()
+    for k in PARAM_NAMES:
+        err = _rel(grads[k].cpu().numpy().astype(np.float64).reshape(np.shape(ref.grads[k])), ref.grads[k])
+        assert err < 1e-4, (k, err)
+    assert _rel(dpos.cpu().numpy().astype(np.float64), ref.dL_dpos) < 1e-4
