@@ -417,7 +417,9 @@ gmnn_status gmnn_backward(const gmnn_model* m, const gmnn_system* sys, const gmn
  *   GMNN_LOSS_CRPS  s [z (2 Phi(z) - 1) + 2 phi(z) - 1/sqrt(pi)],  z = |xbar - x_ref| / s
  * where xbar is the mean over the heads and s2 = s^2 their population
  * variance (1/M) plus var_floor;
- *   L = w_energy (1/B) sum_b l_b + w_force (1/(3N)) sum_{i,a} l_ia.
+ *   L = w_energy (1/B) sum_b l_b + w_force (1/(3N)) sum_{i,a} l_ia
+ * (with energy_per_atom a structure without atoms adds nothing to the
+ * energy term and gets zero gradients; B still counts it).
  * gmnn_ensemble_loss writes loss[0] (energy term) and loss[1] (force term)
  * (device FP64, fixed-order sums) and the per-head gradients dL_dE [B, M]
  * (FP64) and dL_dF [M, N, 3] (FP32) that gmnn_backward takes with

@@ -12,7 +12,8 @@ infrastructure only: the product path never imports this module).
   with x_b^m = E_b^m (or E_b^m / N_b) and F^m = -dE^m/dx the per-head forces
   of eq. (jacobian).  Readings: forces are scored per Cartesian component,
   each with its own ensemble variance; var_floor is added to every
-  variance (the paper leaves sigma -> 0 undefined).
+  variance (the paper leaves sigma -> 0 undefined); a structure without
+  atoms adds nothing to a per-atom energy term.
 * Adam (Kingma & Ba 2015, Algorithm 1) with the parameter groups of Section
   3.4 (embedding = beta, neural network = W1, b1, W2, b2, W3, b3, scale,
   shift: one learning rate each), and the learning-rate schedules Section
@@ -81,10 +82,16 @@ def ensemble_loss(E_heads, F_heads, E_ref, F_ref, n_atoms, spec: LossSpec):
     B = E_heads.shape[0]
     N = F_heads.shape[1]
     xE, xr = E_heads, E_ref
+    keep = torch.ones(B, dtype=torch.bool)
     if spec.energy_per_atom:
-        xE, xr = E_heads / n_atoms[:, None], E_ref / n_atoms
+        # a structure without atoms has no per-atom energy: it adds nothing
+        # to the per-atom term (B still counts it)
+        keep = n_atoms > 0
+        na = torch.where(keep, n_atoms, torch.ones_like(n_atoms))
+        xE, xr = E_heads / na[:, None], E_ref / na
     mE, vE = ensemble_mean_var(xE)
-    LE = spec.w_energy / B * LOSSES[spec.energy](mE, xr, vE + spec.var_floor).sum()
+    lE = LOSSES[spec.energy](mE, xr, vE + spec.var_floor)
+    LE = spec.w_energy / B * torch.where(keep, lE, torch.zeros_like(lE)).sum()
     mF, vF = ensemble_mean_var(F_heads.permute(1, 2, 0))             # [N, 3]
     LF = spec.w_force / (3 * N) * LOSSES[spec.force](mF, F_ref, vF + spec.var_floor).sum() if N else 0.0 * LE
     return LE, LF

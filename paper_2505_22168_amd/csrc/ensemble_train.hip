@@ -82,8 +82,12 @@ __global__ void __launch_bounds__(kLossBlock) loss_energy(gmnn_loss spec, int B,
                                                           double* __restrict__ part) {
   const int b = blockIdx.x * kLossBlock + threadIdx.x;
   double l = 0.0;
-  if (b < B) {
-    const double na = (double)(atom_ptr[b + 1] - atom_ptr[b]);
+  // a structure without atoms has no per-atom energy: with energy_per_atom
+  // it adds nothing (and gets zero gradients)
+  const double na = b < B ? (double)(atom_ptr[b + 1] - atom_ptr[b]) : 0.0;
+  if (b < B && spec.energy_per_atom && na == 0.0 && dE)
+    for (int h = 0; h < M; ++h) dE[(int64_t)b * M + h] = 0.0;
+  if (b < B && !(spec.energy_per_atom && na == 0.0)) {
     const double div = spec.energy_per_atom ? na : 1.0;
     double x[kMaxHeads];
     double mean = 0.0;

@@ -228,3 +228,30 @@ def test_per_head_backward_multi_chunk(lanes16):
         err = _rel(grads[k].cpu().numpy().astype(np.float64).reshape(np.shape(ref.grads[k])), ref.grads[k])
         assert err < 1e-4, (k, err)
     assert _rel(dpos.cpu().numpy().astype(np.float64), ref.dL_dpos) < 1e-4
+
+
+def test_loss_with_an_empty_structure_matches_oracle():
+    """A structure without atoms in the batch: no per-atom energy term, zero
+    gradients for its heads, the other terms unchanged."""
+    g = need_gpu()
+    rng = np.random.default_rng(31)
+    ptr = np.array([0, 5, 5, 12, 20], dtype=np.int64)
+    B, N, M = 4, 20, 5
+    nb = np.diff(ptr).astype(np.float64)
+    E = (-3.0 * nb)[:, None] + rng.normal(size=(B, M)) * 0.1
+    E[1] = 0.0
+    Er = -3.0 * nb + rng.normal(size=B) * 0.1
+    F = rng.normal(size=(M, N, 3)).astype(np.float32)
+    Fr = rng.normal(size=(N, 3)).astype(np.float32)
+    system = g.System(np.zeros((N, 3), np.float32), np.zeros(N, np.int32), np.tile(np.eye(3) * 10.0, (B, 1, 1)),
+                      np.zeros((B, 3), np.uint8), ptr, "cuda")
+    loss, dE, dF = g.ensemble_loss(system, torch.tensor(E, device="cuda"), torch.tensor(F, device="cuda"), Er, Fr,
+                                   g.LossSpec("nll", "crps", 1.0, 1.0, True, 1e-4))
+    torch.cuda.synchronize()
+    LE, LF, gE, gF = ensemble_loss_grads(E, F.astype(np.float64), Er, Fr.astype(np.float64), nb,
+                                         OracleLoss("nll", "crps", 1.0, 1.0, True, 1e-4))
+    loss = loss.cpu().numpy()
+    assert np.isfinite(loss).all()
+    assert abs(loss[0] - LE) <= 1e-12 * max(1.0, abs(LE)) and abs(loss[1] - LF) <= 1e-12 * max(1.0, abs(LF))
+    assert np.all(dE.cpu().numpy()[1] == 0.0)
+    assert np.abs(dE.cpu().numpy() - gE).max() <= 1e-11 * np.abs(gE).max()

@@ -239,3 +239,22 @@ def test_position_gradient_of_the_ensemble_loss(heads_setup):
     h = 1e-4
     fd = (8 * (L(h) - L(-h)) - (L(2 * h) - L(-2 * h))) / (12 * h)
     assert abs(fd - ana) < 1e-6 * max(1.0, abs(ana)), (fd, ana)
+
+
+def test_empty_structure_adds_nothing_to_the_per_atom_energy_term():
+    """Dropping a structure without atoms from the batch changes the per-atom
+    energy term only through the 1/B prefactor."""
+    rng = np.random.default_rng(12)
+    E = rng.normal(size=(4, 3)) - 5.0
+    E[2] = 0.0
+    Er = rng.normal(size=4) - 5.0
+    F = rng.normal(size=(3, 6, 3))
+    Fr = rng.normal(size=(6, 3))
+    nb = np.array([2.0, 3.0, 0.0, 1.0])
+    spec = LossSpec("crps", "nll", var_floor=1e-3)
+    LE, LF, gE, _ = ensemble_loss_grads(E, F, Er, Fr, nb, spec)
+    keep = [0, 1, 3]
+    LE3, LF3, gE3, _ = ensemble_loss_grads(E[keep], F, Er[keep], Fr, nb[keep], spec)
+    assert np.isfinite(LE) and abs(LE * 4 - LE3 * 3) < 1e-12
+    assert abs(LF - LF3) < 1e-15
+    assert np.all(gE[2] == 0.0) and np.allclose(gE[keep] * 4, gE3 * 3, rtol=1e-12, atol=0)
