@@ -90,6 +90,15 @@ __device__ inline float split_low(float v, __bf16 hi) {
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return __lane_id(); }
 
+// a block barrier that orders LDS accesses only: global loads in flight
+// (operands prefetched for a later phase) stay in flight across it, where
+// __syncthreads() would wait for them
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // The value held by lane l ^ 32 (lane_xor32) or l ^ 16 (lane_xor16), in
 // registers: a permlane swap of the value with itself hands every lane its
 // partner's copy in one of the two outputs (no LDS round trip, unlike a

@@ -99,15 +99,63 @@ __global__ void __launch_bounds__(kRoThreads) readout_features(DevSystem sys, co
 
 // ---------------------------------------------------------------------------
 // 2. network on row tiles of TM atoms.  Wave w owns the 16-column blocks
-// w, w + 8, ... of every product, for all TM/16 row blocks; each B fragment
-// loaded from L2 feeds TM/16 MFMAs.
+// w, w + 8, ... of every product, for all TM/16 row blocks; each weight
+// fragment loaded from L2 feeds TM/16 MFMAs.  Every product runs transposed:
+// the weight fragment is the MFMA's A operand and the activation fragment
+// its B operand (the A and B fragment layouts of the 16x16x32 BF16 and
+// 16x16x4 FP32 MFMAs coincide, so the packed weights and the LDS reads are
+// those of the plain orientation).  A lane's accumulator then holds four
+// consecutive hidden units (or features) of one atom, and every epilogue
+// store is one 8-byte (BF16) or 16-byte (FP32) write instead of four
+// scattered ones.  The block's barriers order LDS only (lds_barrier), so
+// the weight fragments prefetched for the next product stay in flight
+// through them.
+constexpr int kPfPlain = 3;  // k-steps of B in flight, plain BF16 products (measured best on the 2x512 network)
+constexpr int kPfSplit = 2;  // k-steps of B (high and low fragments) in flight, split products
+
+// the first kPfPlain k-steps of a plain product's B fragments, issued ahead
+// of the product (their latency then overlaps the previous phase)
+template <int TPW>
+__device__ inline void plain_pre(bf16x8 (&b)[kPfPlain][TPW], const bf16x8* __restrict__ Bp, int KB, int nb0, int nbs,
+                                 int NB) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < kPfPlain; ++s)
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB && s < KB) b[s][i] = Bp[((size_t)nb * KB + s) * 64 + l];
+    }
+}
+
+// the same for a split product (high and low parts, kPfSplit k-steps)
+template <int TPW>
+__device__ inline void split_pre(bf16x8 (&bh)[kPfSplit][TPW], bf16x8 (&bl)[kPfSplit][TPW],
+                                 const bf16x8* __restrict__ Bhi, const bf16x8* __restrict__ Blo, int KB, int nb0,
+                                 int nbs, int NB) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < kPfSplit; ++s)
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int nb = nb0 + i * nbs;
+      if (nb < NB && s < KB) {
+        const size_t o = ((size_t)nb * KB + s) * 64 + l;
+        bh[s][i] = Bhi[o];
+        bl[s][i] = Blo[o];
+      }
+    }
+}
+
+// plain BF16 rows product, acc += A B, with b holding the first kPfPlain
+// k-steps (plain_pre)
 template <int MB, int TPW>
 __device__ inline void mma_rows_bf16(const __bf16* __restrict__ A, int lda, const bf16x8* __restrict__ Bp, int KB,
-                                     int nb0, int nbs, int NB, floatx4 (&acc)[MB][TPW]) {
-  constexpr int PF = 3;  // k-steps of B in flight (measured best on the 2x512 network)
+                                     int nb0, int nbs, int NB, floatx4 (&acc)[MB][TPW],
+                                     bf16x8 (&b)[kPfPlain][TPW]) {
+  constexpr int PF = kPfPlain;
   const int l = threadIdx.x & 63;
   const __bf16* abase = A + (l & 15) * lda + (l >> 4) * 8;
-  bf16x8 b[PF][TPW];
   auto load = [&](bf16x8 (&dst)[TPW], int kb) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
@@ -124,11 +172,9 @@ __device__ inline void mma_rows_bf16(const __bf16* __restrict__ A, int lda, cons
       const int nb = nb0 + i * nbs;
       if (nb < NB)
 #pragma unroll
-        for (int r = 0; r < MB; ++r) acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bb[i], acc[r][i], 0, 0, 0);
+        for (int r = 0; r < MB; ++r) acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bb[i], a[r], acc[r][i], 0, 0, 0);
     }
   };
-#pragma unroll
-  for (int s = 0; s < PF; ++s) load(b[s], s);
   for (int kb = 0; kb < KB; kb += PF) {
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
@@ -143,14 +189,15 @@ __device__ inline void mma_rows_bf16(const __bf16* __restrict__ A, int lda, cons
 // split-BF16 rows product (the forward products of the BF16 network):
 // acc += Ahi Bhi + Ahi Blo + Alo Bhi per k-step, in the order of fwd_mma,
 // with the low part of A at A + alo elements
+// (bh, bl hold the first kPfSplit k-steps: split_pre)
 template <int MB, int TPW>
 __device__ inline void mma_rows_split(const __bf16* __restrict__ A, int alo, int lda, const bf16x8* __restrict__ Bhi,
                                       const bf16x8* __restrict__ Blo, int KB, int nb0, int nbs, int NB,
-                                      floatx4 (&acc)[MB][TPW]) {
-  constexpr int PF = 2;  // k-steps of B (high and low fragments) in flight
+                                      floatx4 (&acc)[MB][TPW], bf16x8 (&bh)[kPfSplit][TPW],
+                                      bf16x8 (&bl)[kPfSplit][TPW]) {
+  constexpr int PF = kPfSplit;
   const int l = threadIdx.x & 63;
   const __bf16* abase = A + (l & 15) * lda + (l >> 4) * 8;
-  bf16x8 bh[PF][TPW], bl[PF][TPW];
   auto load = [&](bf16x8 (&dh)[TPW], bf16x8 (&dl)[TPW], int kb) {
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
@@ -172,14 +219,12 @@ __device__ inline void mma_rows_split(const __bf16* __restrict__ A, int alo, int
       for (int i = 0; i < TPW; ++i) {
         const int nb = nb0 + i * nbs;
         if (nb >= NB) continue;
-        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, h[i], acc[r][i], 0, 0, 0);
-        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, lo[i], acc[r][i], 0, 0, 0);
-        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, h[i], acc[r][i], 0, 0, 0);
+        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h[i], ah, acc[r][i], 0, 0, 0);
+        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[i], ah, acc[r][i], 0, 0, 0);
+        acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h[i], al, acc[r][i], 0, 0, 0);
       }
     }
   };
-#pragma unroll
-  for (int s = 0; s < PF; ++s) load(bh[s], bl[s], s);
   for (int kb = 0; kb < KB; kb += PF) {
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
@@ -215,10 +260,10 @@ __device__ inline void mma_rows_f32(const float* __restrict__ A, int lda, const 
       if (nb < NB)
 #pragma unroll
         for (int r = 0; r < MB; ++r) {
-          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].x, bb[i].x, acc[r][i], 0, 0, 0);
-          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].y, bb[i].y, acc[r][i], 0, 0, 0);
-          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].z, bb[i].z, acc[r][i], 0, 0, 0);
-          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r].w, bb[i].w, acc[r][i], 0, 0, 0);
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[i].x, a[r].x, acc[r][i], 0, 0, 0);
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[i].y, a[r].y, acc[r][i], 0, 0, 0);
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[i].z, a[r].z, acc[r][i], 0, 0, 0);
+          acc[r][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(bb[i].w, a[r].w, acc[r][i], 0, 0, 0);
         }
     }
   };
@@ -235,28 +280,32 @@ __device__ inline void mma_rows_f32(const float* __restrict__ A, int lda, const 
   }
 }
 
-template <bool BF16, int MB, int TPW>
-__device__ inline void mma_rows(const void* A, int lda, const void* Bbf, const void* Bf, int K, int nb0, int nbs,
-                                int NB, floatx4 (&acc)[MB][TPW]) {
+template <int MB, int TPW>
+__device__ inline void zero_rows(floatx4 (&acc)[MB][TPW]) {
 #pragma unroll
   for (int r = 0; r < MB; ++r)
 #pragma unroll
     for (int i = 0; i < TPW; ++i) acc[r][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  if (BF16) mma_rows_bf16<MB, TPW>((const __bf16*)A, lda, (const bf16x8*)Bbf, K / 32, nb0, nbs, NB, acc);
-  else mma_rows_f32<MB, TPW>((const float*)A, lda, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
 }
 
-// forward product: split-BF16 (low parts `alo` elements after the high ones)
-// or FP32
-template <bool BF16, int MB, int TPW>
-__device__ inline void mma_rows_fwd(const void* A, int alo, int lda, const bf16x8* Bhi, const bf16x8* Blo,
-                                    const float* Bf, int K, int nb0, int nbs, int NB, floatx4 (&acc)[MB][TPW]) {
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
+// four consecutive activations of one row: FP32, or BF16 (high parts at
+// base, and with LO the low parts bf16(v - bf16(v)) at lo)
+template <bool BF16, bool LO = false>
+__device__ inline void st4(void* base, void* lo, int idx, floatx4 v) {
+  if constexpr (BF16) {
+    bf16x4 h, t;
 #pragma unroll
-  for (int r = 0; r < MB; ++r)
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) acc[r][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  if (BF16) mma_rows_split<MB, TPW>((const __bf16*)A, alo, lda, Bhi, Blo, K / 32, nb0, nbs, NB, acc);
-  else mma_rows_f32<MB, TPW>((const float*)A, lda, (const float4*)Bf, K / 16, nb0, nbs, NB, acc);
+    for (int j = 0; j < 4; ++j) {
+      h[j] = (__bf16)v[j];
+      if constexpr (LO) t[j] = (__bf16)split_low(v[j], h[j]);
+    }
+    *(bf16x4*)((__bf16*)base + idx) = h;
+    if constexpr (LO) *(bf16x4*)((__bf16*)lo + idx) = t;
+  } else {
+    *(floatx4*)((float*)base + idx) = v;
+  }
 }
 
 // rows per network block: as many 16-row MFMA blocks as the register file
@@ -307,6 +356,17 @@ __global__ void __launch_bounds__(kRoThreads)
   const int row0 = xcd_block(blockIdx.x, gridDim.x) * TM;
   const int n_rows = min(TM, sys.n_atoms - row0);
   const int M = m.M;
+  // a lane's accumulator entries j = 0..3 of a 16 x 16 block: unit (or
+  // feature) uq + j of the column block, atom ar of the row block
+  const int ar = l & 15, uq = 4 * (l >> 4);
+
+  // BF16: the B fragments of each product's first k-steps are issued one
+  // phase ahead (W1's before the tile's G rows, W2's before the first
+  // epilogue, W2^T's and W1^T's before the second and third), so their
+  // latency overlaps loads, barriers and epilogues instead of the products
+  bf16x8 ph[kPfSplit][TPW], pl[kPfSplit][TPW];
+  bf16x8 pb[kPfPlain][TPW], pg[kPfPlain][TPW_G];
+  if constexpr (BF16) split_pre<TPW>(ph, pl, m.w1_bf16, m.w1lo_bf16, kFP / 32, w, NW, NBH);
 
   // G rows (each part) -> region A (row stride St::G), zero rows beyond the
   // system; every load of the tile is issued before the first store
@@ -344,94 +404,110 @@ __global__ void __launch_bounds__(kRoThreads)
       sStruct[a] = b;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // z1 = G W1 + b1 (split-BF16 or FP32), h1 = swish(z1) -> region A once every
   // wave is done with G; swish'(z1) stays in registers
   floatx4 dsw1[MB][TPW];
   {
     floatx4 acc[MB][TPW];
-    mma_rows_fwd<BF16, MB, TPW>(sA, L::GLO, St::G, m.w1_bf16, m.w1lo_bf16, m.w1_f32, kFP, w, NW, NBH, acc);
+    zero_rows(acc);
+    if constexpr (BF16) {
+      mma_rows_split<MB, TPW>((const __bf16*)sA, L::GLO, St::G, m.w1_bf16, m.w1lo_bf16, kFP / 32, w, NW, NBH, acc,
+                              ph, pl);
+      split_pre<TPW>(ph, pl, m.w2_bf16, m.w2lo_bf16, HP / 32, w, NW, NBH);
+    } else {
+      mma_rows_f32<MB, TPW>((const float*)sA, St::G, (const float4*)m.w1_f32, kFP / 16, w, NW, NBH, acc);
+    }
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = w + i * NW;
       if (nb >= NBH) continue;
-      const int col = nb * 16 + (l & 15);
-      const float bias = m.b1[col];
+      const floatx4 bias = *(const floatx4*)(m.b1 + nb * 16 + uq);
 #pragma unroll
       for (int r = 0; r < MB; ++r)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float d;
-          acc[r][i][j] = swish_parts(acc[r][i][j] + bias, d);
+          acc[r][i][j] = swish_parts(acc[r][i][j] + bias[j], d);
           dsw1[r][i][j] = d;
         }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = w + i * NW;
       if (nb >= NBH) continue;
-      const int col = nb * 16 + (l & 15);
 #pragma unroll
       for (int r = 0; r < MB; ++r)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int row = r * 16 + 4 * (l >> 4) + j;
-          st_split<BF16>(sA, (__bf16*)sA + L::HLO, row * St::H + col, acc[r][i][j]);
-        }
+        st4<BF16, BF16>(sA, (__bf16*)sA + L::HLO, (r * 16 + ar) * St::H + nb * 16 + uq, acc[r][i]);
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // z2 = h1 W2 + b2, h2 = swish(z2); delta2 = swish'(z2) sigma wbar -> region
   // B; per-wave partial sums of h2 . W3[:,m] -> sEp (in region A, once every
   // wave is done with h1)
   {
     floatx4 acc[MB][TPW];
-    mma_rows_fwd<BF16, MB, TPW>(sA, L::HLO, St::H, m.w2_bf16, m.w2lo_bf16, m.w2_f32, HP, w, NW, NBH, acc);
-    __syncthreads();
+    zero_rows(acc);
+    if constexpr (BF16) {
+      mma_rows_split<MB, TPW>((const __bf16*)sA, L::HLO, St::H, m.w2_bf16, m.w2lo_bf16, HP / 32, w, NW, NBH, acc, ph,
+                              pl);
+      plain_pre<TPW>(pb, m.w2t_bf16, HP / 32, w, NW, NBH);
+    } else {
+      mma_rows_f32<MB, TPW>((const float*)sA, St::H, (const float4*)m.w2_f32, HP / 16, w, NW, NBH, acc);
+    }
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = w + i * NW;
       if (nb >= NBH) continue;
-      const int col = nb * 16 + (l & 15);
-      const float bias = m.b2[col];
-      const float wb = m.w3bar[col];
+      const int col = nb * 16 + uq;
+      const floatx4 bias = *(const floatx4*)(m.b2 + col);
+      const floatx4 wb = *(const floatx4*)(m.w3bar + col);
 #pragma unroll
-      for (int r = 0; r < MB; ++r)
+      for (int r = 0; r < MB; ++r) {
+        const int row = r * 16 + ar;
+        floatx4 d;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int row = r * 16 + 4 * (l >> 4) + j;
-          float d;
-          acc[r][i][j] = swish_parts(acc[r][i][j] + bias, d);
-          if (m.h2_out && row < n_rows) m.h2_out[(int64_t)(row0 + row) * HP + col] = acc[r][i][j];
-          const float wr = m.head_w ? m.head_w[(int64_t)sStruct[row] * HP + col] : wb;
-          st_act<BF16>(sB, row * St::H + col, d * sScale[row] * wr);
+          float dj;
+          acc[r][i][j] = swish_parts(acc[r][i][j] + bias[j], dj);
+          d[j] = dj;
         }
+        if (m.h2_out && row < n_rows) *(floatx4*)(m.h2_out + (int64_t)(row0 + row) * HP + col) = acc[r][i];
+        const floatx4 wr = m.head_w ? *(const floatx4*)(m.head_w + (int64_t)sStruct[row] * HP + col) : wb;
+        st4<BF16>(sB, nullptr, row * St::H + col, d * sScale[row] * wr);
+      }
     }
     for (int hm = 0; hm < M; ++hm) {
 #pragma unroll
       for (int r = 0; r < MB; ++r) {
+        // per unit c = uq + j of the 16-column blocks: the sum over the
+        // wave's blocks; then an xor butterfly over the 16 units (bits 3 and
+        // 2 of c across the lane groups, bits 1 and 0 inside the lane), the
+        // tree the tile readout's row sums take, so both readouts agree bit
+        // for bit
         float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
           const int nb = w + i * NW;
           if (nb >= NBH) continue;
-          const float w3 = m.w3[(nb * 16 + (l & 15)) * M + hm];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) part[j] += acc[r][i][j] * w3;
+          for (int j = 0; j < 4; ++j) part[j] += acc[r][i][j] * m.w3[(nb * 16 + uq + j) * M + hm];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          float v = part[j];
-          v = row16_rot_sum(v);  // lane 0 of the row: the xor-butterfly sum
-          if ((l & 15) == 0) sEp[(w * TM + r * 16 + 4 * (l >> 4) + j) * M + hm] = v;
+          part[j] += __shfl_xor(part[j], 32);
+          part[j] += __shfl_xor(part[j], 16);
         }
+        const float v = (part[0] + part[2]) + (part[1] + part[3]);
+        if (l < 16) sEp[(w * TM + r * 16 + ar) * M + hm] = v;
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
   for (int t = tid; t < TM * M; t += kRoThreads) {
     const int a = t / M, hm = t % M;
     if (a < n_rows) {
@@ -447,39 +523,41 @@ __global__ void __launch_bounds__(kRoThreads)
   // delta1 = swish'(z1) (delta2 W2^T) -> region A (h1 is dead)
   {
     floatx4 acc[MB][TPW];
-    mma_rows<BF16, MB, TPW>(sB, St::H, m.w2t_bf16, m.w2t_f32, HP, w, NW, NBH, acc);
+    zero_rows(acc);
+    if constexpr (BF16) {
+      mma_rows_bf16<MB, TPW>((const __bf16*)sB, St::H, m.w2t_bf16, HP / 32, w, NW, NBH, acc, pb);
+      plain_pre<TPW_G>(pg, m.w1t_bf16, HP / 32, w, NW, NBG);
+    } else {
+      mma_rows_f32<MB, TPW>((const float*)sB, St::H, (const float4*)m.w2t_f32, HP / 16, w, NW, NBH, acc);
+    }
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int nb = w + i * NW;
       if (nb >= NBH) continue;
-      const int col = nb * 16 + (l & 15);
 #pragma unroll
-      for (int r = 0; r < MB; ++r)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int row = r * 16 + 4 * (l >> 4) + j;
-          st_act<BF16>(sA, row * St::H + col, acc[r][i][j] * dsw1[r][i][j]);
-        }
+      for (int r = 0; r < MB; ++r) st4<BF16>(sA, nullptr, (r * 16 + ar) * St::H + nb * 16 + uq, acc[r][i] * dsw1[r][i]);
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // dE/dG = delta1 W1^T -> HBM [N][kFP] (FP32)
   {
     floatx4 acc[MB][TPW_G];
-    mma_rows<BF16, MB, TPW_G>(sA, St::H, m.w1t_bf16, m.w1t_f32, HP, w, NW, NBG, acc);
+    zero_rows(acc);
+    if constexpr (BF16) {
+      mma_rows_bf16<MB, TPW_G>((const __bf16*)sA, St::H, m.w1t_bf16, HP / 32, w, NW, NBG, acc, pg);
+    } else {
+      mma_rows_f32<MB, TPW_G>((const float*)sA, St::H, (const float4*)m.w1t_f32, HP / 16, w, NW, NBG, acc);
+    }
 #pragma unroll
     for (int i = 0; i < TPW_G; ++i) {
       const int nb = w + i * NW;
       if (nb >= NBG) continue;
-      const int col = nb * 16 + (l & 15);
 #pragma unroll
-      for (int r = 0; r < MB; ++r)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int row = r * 16 + 4 * (l >> 4) + j;
-          if (row < n_rows) dG[(int64_t)(row0 + row) * kFP + col] = acc[r][i][j];
-        }
+      for (int r = 0; r < MB; ++r) {
+        const int row = r * 16 + ar;
+        if (row < n_rows) *(floatx4*)(dG + (int64_t)(row0 + row) * kFP + nb * 16 + uq) = acc[r][i];
+      }
     }
   }
 }

@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(kPairBlock) pair_tangent(DevModel m, DevSystem
 
 // ---------------------------------------------------------------------------
 __device__ inline void swish_d2(float z, float& s, float& d1, float& d2) {
-  const float sg = 1.0f / (1.0f + __expf(-z));
+  const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-z));  // hardware reciprocal, as swish_parts
   s = z * sg;
   d1 = sg * (1.0f + z * (1.0f - sg));
   d2 = sg * (1.0f - sg) * (2.0f + z * (1.0f - 2.0f * sg));
