@@ -361,12 +361,11 @@ __global__ void __launch_bounds__(kRoThreads)
   const int ar = l & 15, uq = 4 * (l >> 4);
 
   // BF16: the B fragments of each product's first k-steps are issued one
-  // phase ahead (W1's before the tile's G rows, W2's before the first
+  // phase ahead (W1's with the tile's G rows, W2's before the first
   // epilogue, W2^T's and W1^T's before the second and third), so their
   // latency overlaps loads, barriers and epilogues instead of the products
   bf16x8 ph[kPfSplit][TPW], pl[kPfSplit][TPW];
   bf16x8 pb[kPfPlain][TPW], pg[kPfPlain][TPW_G];
-  if constexpr (BF16) split_pre<TPW>(ph, pl, m.w1_bf16, m.w1lo_bf16, kFP / 32, w, NW, NBH);
 
   // G rows (each part) -> region A (row stride St::G), zero rows beyond the
   // system; every load of the tile is issued before the first store
@@ -383,6 +382,9 @@ __global__ void __launch_bounds__(kRoThreads)
       if (part < L::NS && tt < n_rows * C16)
         v[u] = ((const uint4*)(gbase + ((size_t)part * sys.n_atoms + row0) * kFP * L::ESZ))[tt];
     }
+    // W1's first k-steps after the tile's rows: the LDS stores below wait
+    // for the rows only
+    if constexpr (BF16) split_pre<TPW>(ph, pl, m.w1_bf16, m.w1lo_bf16, kFP / 32, w, NW, NBH);
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int t = tid + u * kRoThreads;
@@ -494,8 +496,15 @@ __global__ void __launch_bounds__(kRoThreads)
         for (int i = 0; i < TPW; ++i) {
           const int nb = w + i * NW;
           if (nb >= NBH) continue;
+          floatx4 w3;
+          if (M == 1) {
+            w3 = *(const floatx4*)(m.w3 + nb * 16 + uq);
+          } else {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) part[j] += acc[r][i][j] * m.w3[(nb * 16 + uq + j) * M + hm];
+            for (int j = 0; j < 4; ++j) w3[j] = m.w3[(nb * 16 + uq + j) * M + hm];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) part[j] += acc[r][i][j] * w3[j];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
