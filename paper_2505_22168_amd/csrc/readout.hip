@@ -22,8 +22,12 @@
 
 namespace gmnn {
 
-constexpr int kRoAtoms = 16;     // atoms per contraction block
-constexpr int kRoThreads = 512;  // threads of every readout block
+// invariant blocks: 6 atoms and 256 threads (about 25 KB of LDS: six
+// blocks per CU, whose load and barrier waits overlap one another; the
+// arithmetic of an atom's invariants does not depend on the block size)
+constexpr int kRoAtoms = 6;      // atoms per invariant (features) block
+constexpr int kFtThreads = 256;  // threads of an invariant block
+constexpr int kRoThreads = 512;  // threads of a network block
 constexpr int kRoWaves = kRoThreads / 64;
 
 static constexpr size_t ro_al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -33,17 +37,17 @@ static constexpr size_t ro_al(size_t x) { return (x + 255) & ~size_t(255); }
 __device__ inline void ro_load_moments(const float* __restrict__ psi, int row0, int n_rows, float* __restrict__ sPsi,
                                        const Tables& tb) {
   constexpr int NP = kS * kPacked;
-  constexpr int NU = (kRoAtoms * NP + kRoThreads - 1) / kRoThreads;
+  constexpr int NU = (kRoAtoms * NP + kFtThreads - 1) / kFtThreads;
   const int tid = threadIdx.x;
   float v[NU];
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    const int t = tid + u * kRoThreads;
+    const int t = tid + u * kFtThreads;
     v[u] = t < n_rows * NP ? psi[(int64_t)row0 * NP + t] : 0.0f;
   }
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    const int t = tid + u * kRoThreads;
+    const int t = tid + u * kFtThreads;
     if (t < kRoAtoms * NP) {
       const int a = t / NP, e = t % NP;
       const int s = e / kPacked, c = e % kPacked;
@@ -66,7 +70,7 @@ struct FeatLds {
 };
 
 template <bool BF16>
-__global__ void __launch_bounds__(kRoThreads) readout_features(DevSystem sys, const float* __restrict__ psi,
+__global__ void __launch_bounds__(kFtThreads) readout_features(DevSystem sys, const float* __restrict__ psi,
                                                                void* __restrict__ G) {
   using L = FeatLds<BF16>;
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -81,19 +85,19 @@ __global__ void __launch_bounds__(kRoThreads) readout_features(DevSystem sys, co
   ro_load_moments(psi, row0, n_rows, sPsi, tb);
   __syncthreads();
   constexpr int glo = BF16 ? kRoAtoms * kFP : 0;  // low parts after the high ones
-  contract_forward_a<kRoAtoms, kRoThreads, BF16, true, ISF>(sPsi, sI, sG, kFP, tb, glo);
+  contract_forward_a<kRoAtoms, kFtThreads, BF16, true, ISF>(sPsi, sI, sG, kFP, tb, glo);
   __syncthreads();
-  contract_forward_b<kRoAtoms, kRoThreads, BF16, ISF>(sPsi, sI, sG, kFP, tb, glo);
+  contract_forward_b<kRoAtoms, kFtThreads, BF16, ISF>(sPsi, sI, sG, kFP, tb, glo);
   __syncthreads();
   // rows of G are contiguous: 16-byte copies (BF16: the high plane, then the
   // low plane N rows further)
   const int n16 = n_rows * kFP * L::ESZ / 16;
   uint4* dst = (uint4*)((char*)G + (size_t)row0 * kFP * L::ESZ);
-  for (int t = threadIdx.x; t < n16; t += kRoThreads) dst[t] = ((const uint4*)sG)[t];
+  for (int t = threadIdx.x; t < n16; t += kFtThreads) dst[t] = ((const uint4*)sG)[t];
   if (BF16) {
     uint4* dlo = (uint4*)((char*)G + ((size_t)sys.n_atoms + row0) * kFP * L::ESZ);
     const uint4* slo = (const uint4*)(sG + (size_t)glo * L::ESZ);
-    for (int t = threadIdx.x; t < n16; t += kRoThreads) dlo[t] = slo[t];
+    for (int t = threadIdx.x; t < n16; t += kFtThreads) dlo[t] = slo[t];
   }
 }
 
@@ -573,11 +577,12 @@ __global__ void __launch_bounds__(kRoThreads)
 
 // ---------------------------------------------------------------------------
 // 3. invariant backward: dE/dG and the moments -> dE/dPsi (packed).  Blocks of
-// 8 atoms and 512 threads: the first forward pass runs each task's two
-// independent halves on two threads; two blocks per CU, so one block's loads
-// overlap the other's arithmetic.
-constexpr int kBkAtoms = 8;
-constexpr int kBkThreads = 512;
+// 4 atoms and 256 threads: the first forward pass runs each task's two
+// independent halves on two threads; about 29 KB of LDS, so five blocks per
+// CU, and each block's load and barrier waits overlap the others' arithmetic
+// (the time per block is latency: few tasks per atom between barriers).
+constexpr int kBkAtoms = 4;
+constexpr int kBkThreads = 256;
 
 struct BackLds {
   static constexpr int LDGB = kFP + 1;
@@ -682,7 +687,7 @@ static gmnn_status launch_stream_t(const DevModel& m, const DevSystem& sys, cons
   const int gb = (N + kBkAtoms - 1) / kBkAtoms;
   mark(0);
   if (phases & 1)
-    hipLaunchKernelGGL(readout_features<BF16>, dim3(g16), dim3(kRoThreads), FeatLds<BF16>::bytes, s, sys, psi, G);
+    hipLaunchKernelGGL(readout_features<BF16>, dim3(g16), dim3(kFtThreads), FeatLds<BF16>::bytes, s, sys, psi, G);
   mark(1);
   mark(2);
   if (phases & 2)
