@@ -321,7 +321,26 @@ __global__ void __launch_bounds__(kPairBlock) finish(int M, DevSystem sys, const
       float f[3] = {0.0f, 0.0f, 0.0f};
       if (live) {
         const int64_t p0 = sys.row_ptr[i], p1 = sys.row_ptr[i + 1];
-        for (int64_t p = p0 + q; p < p1; p += LPA) {
+        int64_t p = p0 + q;
+        // four of the lane's pairs per pass: every index and gradient load
+        // of the pass is issued before the first sum, and the sums run in
+        // the pairs' order (the same result as one pair per pass)
+        constexpr int U = 4;
+        for (; p + (U - 1) * LPA < p1; p += U * LPA) {
+          int64_t rp[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) rp[u] = sys.rev[p + u * LPA];
+          float d[U][3];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[u][k] = gpair[3 * (p + u * LPA) + k] - gpair[3 * rp[u] + k];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) f[k] += d[u][k];
+        }
+        for (; p < p1; p += LPA) {
           const int64_t rp = sys.rev[p];
           f[0] += gpair[3 * p] - gpair[3 * rp];
           f[1] += gpair[3 * p + 1] - gpair[3 * rp + 1];
