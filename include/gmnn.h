@@ -439,7 +439,8 @@ typedef struct gmnn_loss {
   double w_energy;          /* weight of the energy term (0 drops it) */
   double w_force;           /* weight of the force term (0 drops it) */
   double var_floor;         /* added to every variance (units of x^2); NLL and CRPS need
-                               s2 > 0, which equal heads break without it */
+                               s2 > 0, which equal heads break without it; with one head a
+                               weighted NLL or CRPS term and var_floor 0 is INVALID_ARG */
 } gmnn_loss;
 size_t gmnn_loss_workspace_bytes(const gmnn_system* sys);
 gmnn_status gmnn_ensemble_loss(const gmnn_loss* spec, const gmnn_system* sys, int32_t n_heads,

@@ -318,6 +318,12 @@ gmnn_status gmnn_ensemble_loss(const gmnn_loss* spec, const gmnn_system* sys, in
   for (int k : {spec->energy_kind, spec->force_kind})
     if (k != GMNN_LOSS_MSE && k != GMNN_LOSS_NLL && k != GMNN_LOSS_CRPS) return GMNN_ERR_INVALID_ARG;
   if (!(spec->var_floor >= 0.0)) return GMNN_ERR_INVALID_ARG;
+  // one head has no spread: a NLL or CRPS term without a floor would divide
+  // by a zero variance
+  if (n_heads == 1 && spec->var_floor == 0.0)
+    for (int k : {spec->w_energy != 0.0 ? spec->energy_kind : GMNN_LOSS_MSE,
+                  spec->w_force != 0.0 ? spec->force_kind : GMNN_LOSS_MSE})
+      if (k != GMNN_LOSS_MSE) return GMNN_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < gmnn_loss_workspace_bytes(sys)) return GMNN_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int B = sys->n_structs;
