@@ -85,7 +85,10 @@ __global__ void __launch_bounds__(kFtThreads) readout_features(DevSystem sys, co
   ro_load_moments(psi, row0, n_rows, sPsi, tb);
   __syncthreads();
   constexpr int glo = BF16 ? kRoAtoms * kFP : 0;  // low parts after the high ones
-  contract_forward_a<kRoAtoms, kFtThreads, BF16, true, ISF>(sPsi, sI, sG, kFP, tb, glo);
+  // the first pass runs each task's two independent halves on two threads
+  // when the block has threads for both (no change to any arithmetic)
+  constexpr int KSF = 2 * ((kRoAtoms * 20 + 63) / 64 * 64) <= kFtThreads ? 2 : 1;
+  contract_forward_a<kRoAtoms, kFtThreads, BF16, true, ISF, KSF>(sPsi, sI, sG, kFP, tb, glo);
   __syncthreads();
   contract_forward_b<kRoAtoms, kFtThreads, BF16, ISF>(sPsi, sI, sG, kFP, tb, glo);
   __syncthreads();
