@@ -524,12 +524,23 @@ __device__ inline void contract_forward_b_dual(const float* __restrict__ P, cons
 //   task (a, s2, b):  U8[(s1, s2)][b, c] for every s1, c, and the five Qv
 //                     entries [x = s2][s3][i] with 3 s3 + i in [5b, 5b + 5)
 //   task (a, p = (x <= s')):  Y[(x, s')] and its mirror Y[(s', x)]
-template <int TM, int NT>
+// KS = 2 (a block with twice as many threads as tasks) runs each task's two
+// independent output groups on two threads: U8 | Qv, and the Y entries
+// ab < 5 | ab >= 5.  Every output keeps its single writer and its order of
+// operations, so the split changes no result.
+template <int TM, int NT, int KS = 1>
 __device__ inline void contract_backward_a(const float* __restrict__ P, const float* __restrict__ Gb, int ldgb,
                                            float* __restrict__ I, const Tables& tb) {
+  static_assert(KS == 1 || KS == 2, "one or two halves");
   constexpr int ISTR = IS;
   constexpr int nu = TM * 15, ny = TM * 15;
-  for (int t = threadIdx.x; t < nu + ny; t += NT) {
+  // with KS = 2 each half's tasks start on a wave boundary
+  constexpr int NTASK = nu + ny, NHALF = KS == 1 ? NTASK : (NTASK + 63) / 64 * 64;
+  for (int tt = threadIdx.x; tt < KS * NHALF; tt += NT) {
+    const int half = KS == 1 ? 0 : tt / NHALF;
+    const int t = KS == 1 ? tt : tt % NHALF;
+    if (t >= NTASK) continue;
+    const bool h0 = KS == 1 || half == 0, h1 = KS == 1 || half == 1;
     if (t < nu) {
       const int a = t % TM, e = t / TM;
       const int s2 = e / 3, b = e % 3;
@@ -538,27 +549,31 @@ __device__ inline void contract_backward_a(const float* __restrict__ P, const fl
       for (int s1 = 0; s1 < kS; ++s1)
 #pragma unroll
         for (int i = 0; i < 3; ++i) p1[s1][i] = GM_P1(a, s1, i);
+      if (h0) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p3[i][c] = GM_P3(a, s2, i * 9 + b * 3 + c);
+          for (int c = 0; c < 3; ++c) p3[i][c] = GM_P3(a, s2, i * 9 + b * 3 + c);
 #pragma unroll
-      for (int s1 = 0; s1 < kS; ++s1)
+        for (int s1 = 0; s1 < kS; ++s1)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+          for (int c = 0; c < 3; ++c) {
+            float v = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) v += p1[s1][i] * p3[i][c];
+            GM_I(a, kU8 + (s1 * 5 + s2) * 9 + b * 3 + c) = v;
+          }
+      }
+      if (h1) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const int lin = 5 * b + q;
+          const int s3 = lin / 3, i = lin % 3;
           float v = 0.0f;
 #pragma unroll
-          for (int i = 0; i < 3; ++i) v += p1[s1][i] * p3[i][c];
-          GM_I(a, kU8 + (s1 * 5 + s2) * 9 + b * 3 + c) = v;
+          for (int s1 = 0; s1 < kS; ++s1) v += GM_GB(a, kFam8 + s1 * 25 + s2 * 5 + s3) * GM_P1(a, s1, i);
+          GM_I(a, kQv + (s2 * 5 + s3) * 3 + i) = v;
         }
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        const int lin = 5 * b + q;
-        const int s3 = lin / 3, i = lin % 3;
-        float v = 0.0f;
-#pragma unroll
-        for (int s1 = 0; s1 < kS; ++s1) v += GM_GB(a, kFam8 + s1 * 25 + s2 * 5 + s3) * GM_P1(a, s1, i);
-        GM_I(a, kQv + (s2 * 5 + s3) * 3 + i) = v;
       }
     } else {
       const int u = t - nu;
@@ -570,6 +585,7 @@ __device__ inline void contract_backward_a(const float* __restrict__ P, const fl
       const float f = (x == sp) ? 2.0f : 1.0f;
 #pragma unroll
       for (int ab = 0; ab < 9; ++ab) {
+        if (!(ab < 5 ? h0 : h1)) continue;
         float v = 0.0f;
 #pragma unroll
         for (int s1 = 0; s1 < kS; ++s1) v += g[s1] * GM_P2(a, s1, ab);

@@ -658,7 +658,9 @@ __global__ void __launch_bounds__(kBkThreads) readout_backward(DevSystem sys, co
   constexpr int KS = 1;
   contract_forward_a<TB, NT, false, false, IS, KSF>(sPsi, sI, nullptr, 0, tb);
   __syncthreads();
-  contract_backward_a<TB, NT>(sPsi, sGb, L::LDGB, sI, tb);
+  // phase A: each task's two output groups on two threads (no result changes)
+  constexpr int KSA = 2 * ((TB * 30 + 63) / 64 * 64) <= NT ? 2 : 1;
+  contract_backward_a<TB, NT, KSA>(sPsi, sGb, L::LDGB, sI, tb);
   __syncthreads();
   contract_backward_b<TB, NT, KS>(sPsi, sGb, L::LDGB, sI, sPb, tb);
   __syncthreads();

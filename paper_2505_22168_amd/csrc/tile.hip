@@ -229,7 +229,10 @@ __global__ void __launch_bounds__(kTileThreads)
     }
     network_backward<TM, HP, BF16, kTileWaves, kDepth>(m, sD2, sH, sGb, dsw1, ring);
     // ---- invariants backward ---------------------------------------------------
-    contract_backward_a<TA, kTileThreads>(sPsi, sGb, LDGB, sI, tb);
+    // phase A: each task's two output groups on two threads when the tile has
+    // the threads (8-atom tiles; no result changes)
+    constexpr int KSA = 2 * ((TA * 30 + 63) / 64 * 64) <= kTileThreads ? 2 : 1;
+    contract_backward_a<TA, kTileThreads, KSA>(sPsi, sGb, LDGB, sI, tb);
     __syncthreads();
     // an 8-atom tile has threads for both halves of every task; the second
     // half's gradient lands in the rows of sPb past the tile's atoms

@@ -38,6 +38,9 @@ namespace gmnn {
 constexpr int kTrainThreads = 512;
 constexpr int kTrainWaves = kTrainThreads / 64;
 constexpr int kTA = 8;  // atoms per training tile (16 MFMA rows: primal + tangent)
+// phase A of the invariant backward: each task's two output groups on two
+// threads when the tile has the threads (no result changes)
+constexpr int kTrainKSA = 2 * ((kTA * 30 + 63) / 64 * 64) <= kTrainThreads ? 2 : 1;
 // 8 atoms leave threads for both halves of every task of the invariants' first pass
 constexpr int kFwdSplit = 2 * ((kTA * 20 + 63) / 64 * 64) <= kTrainThreads ? 2 : 1;
 
@@ -420,7 +423,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   // Psidotbar = B(Psi; Gdotbar)
   contract_forward_a<TA, kTrainThreads, false, false, IS, kFwdSplit>(sPsi, sI, nullptr, 0, tb);  // intermediates of Psi
   __syncthreads();
-  contract_backward_a<TA, kTrainThreads>(sPsi, Gdbar, L::LDGB, sI, tb);
+  contract_backward_a<TA, kTrainThreads, kTrainKSA>(sPsi, Gdbar, L::LDGB, sI, tb);
   __syncthreads();
   contract_backward_b<TA, kTrainThreads, KS>(sPsi, Gdbar, L::LDGB, sI, sPbS, tb, sPbS2);
   __syncthreads();
@@ -429,7 +432,7 @@ __global__ void __launch_bounds__(kTrainThreads)
   };
   fold_packed<TA, kTrainThreads, decltype(to_psidotbar), KS == 2>(sPbS, tb, to_psidotbar, sPbS2);
   // Psibar = B(Psi; Gbar) + [B(Psi + t Psidot; Gdotbar) - B(Psi - t Psidot; Gdotbar)] / (2t)
-  contract_backward_a<TA, kTrainThreads>(sPsi, Gbar, L::LDGB, sI, tb);
+  contract_backward_a<TA, kTrainThreads, kTrainKSA>(sPsi, Gbar, L::LDGB, sI, tb);
   __syncthreads();
   contract_backward_b<TA, kTrainThreads, KS>(sPsi, Gbar, L::LDGB, sI, sPbA, tb, sPbA2);
   __syncthreads();
@@ -442,7 +445,7 @@ __global__ void __launch_bounds__(kTrainThreads)
     __syncthreads();
     contract_forward_a<TA, kTrainThreads, false, false, IS, kFwdSplit>(sPt, sI, nullptr, 0, tb);  // intermediates of Psi +- t Psidot
     __syncthreads();
-    contract_backward_a<TA, kTrainThreads>(sPt, Gdbar, L::LDGB, sI, tb);
+    contract_backward_a<TA, kTrainThreads, kTrainKSA>(sPt, Gdbar, L::LDGB, sI, tb);
     __syncthreads();
     contract_backward_b<TA, kTrainThreads, KS>(sPt, Gdbar, L::LDGB, sI, sPbS, tb, sPbS2);
     __syncthreads();
