@@ -55,7 +55,7 @@ def test_zero_atoms():
     nl = g.build_neighbors(system, spec.model.r_cut)
     assert nl.n_pairs == 0
     model = g.Model.from_params(params, "cuda")
-    for plan in (None, (2, 16, 1)):
+    for plan in (None, (2, 16, 1), (2, 16, 2)):
         out = g.EnergyForces(model, system, nl, precision="fp32", stress=True, plan=plan)(sync=True)
         assert np.all(out.energy.cpu().numpy() == 0.0)
 
